@@ -1,0 +1,99 @@
+"""Dynamics, tracking controller and particle deviations (oracle, FP64).
+
+Sec. II, eq. (1)-(2): linear dynamics with Gaussian process noise, discretised
+with a zero-order hold at the tracking step dt; a linear-quadratic tracking
+controller acts on the deviation from the nominal trajectory.  Sec. V-A fixes
+the model: a 6-D double integrator (x'' = u) in a 3-D workspace, so every axis
+is an independent 2-state (position, velocity) system and all matrices below
+are per axis.
+
+Readings (the paper leaves these open): the process noise intensity is
+V_c = sigma^2 * I on the 6 state derivatives; the tracking law is the
+steady-state discrete LQR gain with full-state feedback (du = -K dx),
+Q = diag(q_pos, q_vel), R = r_track; the deviation process starts at zero at
+the start state and its noise is indexed by (tracking step, particle), shared by
+every plan, so the deviation at plan step s does not depend on the plan; the
+deviation table is stored in FP32 (the kernel's storage precision), which is
+the one place the oracle rounds.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def discretize(dt: float, sigma: float):
+    """Eq. (2) per axis for A_c = [[0,1],[0,0]], B_c = [0,1]^T, V_c = sigma^2 I.
+
+    A = exp(A_c dt) = [[1, dt], [0, 1]]
+    B = (int_0^dt exp(A_c s) ds) B_c = [dt^2/2, dt]^T
+    V = int_0^dt exp(A_c s) V_c exp(A_c^T s) ds
+      = sigma^2 [[dt + dt^3/3, dt^2/2], [dt^2/2, dt]]
+    (exp(A_c s) exp(A_c^T s) = [[1 + s^2, s], [s, 1]], integrated term by term.)
+    """
+    dt = float(dt)
+    s2 = float(sigma) ** 2
+    A = np.array([[1.0, dt], [0.0, 1.0]])
+    B = np.array([[dt * dt / 2.0], [dt]])
+    V = s2 * np.array([[dt + dt ** 3 / 3.0, dt * dt / 2.0],
+                       [dt * dt / 2.0, dt]])
+    return A, B, V
+
+
+def lqr_gain(A, B, Q, R, tol=1e-14, max_iter=1_000_000):
+    """Steady-state discrete LQR gain (Sec. II tracking controller; reading:
+    infinite-horizon, full-state feedback).
+
+    Iterates the Riccati difference equation
+        P <- Q + A^T P A - A^T P B (R + B^T P B)^-1 B^T P A
+    from P = Q until the relative change is below `tol`; returns
+    K = (R + B^T P B)^-1 B^T P A and P.  The control is du = -K dx."""
+    A = np.asarray(A, float)
+    B = np.asarray(B, float)
+    Q = np.asarray(Q, float)
+    R = np.atleast_2d(np.asarray(R, float))
+    P = Q.copy()
+    for _ in range(max_iter):
+        G = R + B.T @ P @ B
+        PB = P @ B
+        Pn = Q + A.T @ P @ A - A.T @ PB @ np.linalg.solve(G, PB.T @ A)
+        delta = np.max(np.abs(Pn - P)) / max(np.max(np.abs(Pn)), 1e-300)
+        P = Pn
+        if delta < tol:
+            break
+    K = np.linalg.solve(R + B.T @ P @ B, B.T @ P @ A)
+    return K, P
+
+
+def closed_loop(dt, sigma, q_pos, q_vel, r_track):
+    """A_cl = A - B K and L = chol(V) for one axis."""
+    A, B, V = discretize(dt, sigma)
+    K, _ = lqr_gain(A, B, np.diag([q_pos, q_vel]), [[r_track]])
+    A_cl = A - B @ K
+    L = np.linalg.cholesky(V)
+    return A_cl, L, K
+
+
+def deviation_states(A_cl, L, noise, steps):
+    """Particle deviations dx_s for s = 0..steps (FP64).
+
+    noise: [>= steps, 6, P] standard normals; component 2a and 2a+1 drive axis a.
+    dx_0 = 0 and dx_{s+1} = A_cl dx_s + L (xi_{s,2a}, xi_{s,2a+1})^T  (eq. (2)
+    closed loop: dx_{t+1} = A dx_t + B du_t + v_t with du_t = -K dx_t and
+    v_t ~ N(0, V) drawn as L xi).
+    Returns an array [steps+1, 3, 2, P] of (position, velocity) deviations."""
+    noise = np.asarray(noise, dtype=np.float64)
+    P = noise.shape[2]
+    out = np.zeros((steps + 1, 3, 2, P))
+    for s in range(steps):
+        for a in range(3):
+            x = out[s, a]
+            w = L @ noise[s, 2 * a:2 * a + 2, :]
+            out[s + 1, a] = A_cl @ x + w
+    return out
+
+
+def deviation_table(A_cl, L, noise, steps):
+    """Position part of the deviations, D[s][a][j], rounded to FP32 storage."""
+    dev = deviation_states(A_cl, L, noise, steps)
+    return dev[:, :, 0, :].astype(np.float32)

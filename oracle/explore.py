@@ -1,0 +1,196 @@
+"""Explore (Alg. 4): the bucketed multiobjective search (oracle, FP64).
+
+Plans are records (head, path, cost, cp_hat) (Sec. IV); cp_hat is the particle
+estimate: N particle trajectories follow the plan, and a particle counts as
+invalid once any of its waypoint positions lies in an obstacle; cp_hat is the
+number of invalid particles over N (Sec. III-B: per-particle checks, an OR
+over the trajectory, a count).  A plan carries its particles' invalid bits, so
+extending it by one edge ORs in the new edge's hits.
+
+Readings used here:
+  * particles: the deviation of particle j at plan step s is the shared table
+    D[s][.][j] (plan-independent; see dynamics.py); an edge of duration tau* gets
+    K_e = max(1, ceil(tau*/dt)) waypoints at t_k = k tau*/K_e, k = 1..K_e, at
+    plan steps s_p + k, and particle j's position there is nominal(t_k) + D[s_p+k].
+  * the per-waypoint predicate is "position inside a closed box";
+  * a candidate whose step count exceeds S_max is dropped (and counted);
+  * RemoveDominated acts on every plan still open at that point, including
+    the group just expanded, against all plans with the same head; closed
+    plans are never removed; dominance is strict on cost and non-strict on
+    cp_hat, so plans with equal (cost, cp_hat) coexist;
+  * every (p in B, x in N(p.head)) pair formed counts as one partial plan.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List
+
+import numpy as np
+
+from . import steer as st
+
+EPS_FLAG = 1e-5
+
+
+@dataclasses.dataclass
+class Plan:
+    nodes: tuple        # path + head (node indices from x_init)
+    cost: float
+    step: int           # tracking steps covered so far
+    mask: np.ndarray    # bool [N]: particle j invalid
+    parent: int
+    pop: int = dataclasses.field(init=False)   # number of invalid particles
+
+    def __post_init__(self):
+        self.pop = int(self.mask.sum())
+
+    @property
+    def head(self) -> int:
+        return self.nodes[-1]
+
+
+def extend_batch(V, graph, D, boxes, dt, S_max, parents: List[Plan], edges: np.ndarray,
+                 chunk=256):
+    """q = (x, p.path + p.head, p.cost + Cost(p.head, x), CP_hat(x, p)) for many
+    (p, edge) pairs (Alg. 4, the line that forms q).
+
+    Returns (x, cost, step, mask [m, N], over_steps [m], flagged [m])."""
+    V = np.asarray(V, np.float64)
+    b = np.asarray(boxes, np.float64)
+    m = len(parents)
+    N = D.shape[2]
+    x = graph["col"][edges]
+    tau = graph["tau"][edges]
+    cst = graph["cost"][edges]
+    K = st.waypoint_count(tau, dt)
+    s_p = np.array([p.step for p in parents], np.int64)
+    heads = np.array([p.head for p in parents], np.int64)
+    cost = np.array([p.cost for p in parents]) + cst
+    step = s_p + K
+    over = step > S_max
+    mask = np.stack([p.mask for p in parents]) if m else np.zeros((0, N), bool)
+    mask = mask.copy()
+    flagged = np.zeros(m, np.int64)
+    Dd = D.astype(np.float64)
+    for c0 in range(0, m, chunk):
+        sl = slice(c0, min(m, c0 + chunk))
+        idx = np.arange(sl.start, sl.stop)
+        idx = idx[~over[idx]]
+        if idx.shape[0] == 0:
+            continue
+        coef = st.hermite(V[heads[idx]], V[x[idx]], tau[idx])
+        Kmax = int(K[idx].max())
+        k = np.arange(1, Kmax + 1)
+        live = k[None, :] <= K[idx][:, None]                       # [c, Kmax]
+        t = (k[None, :] * tau[idx][:, None]) / K[idx][:, None]
+        nom = st.hermite_eval(coef[:, None, :, :], t)              # [c, Kmax, 3]
+        srow = np.minimum(s_p[idx][:, None] + k[None, :], S_max)
+        y = nom[..., None] + Dd[srow]                               # [c, Kmax, 3, N]
+        hit = np.zeros((idx.shape[0], N), bool)
+        best = np.full((idx.shape[0], N), -np.inf)                  # max depth
+        near = np.zeros((idx.shape[0], N), bool)
+        for j in range(b.shape[0]):
+            lo = b[j, :3][None, None, :, None]
+            hi = b[j, 3:][None, None, :, None]
+            inside = np.all((y >= lo) & (y <= hi), axis=2)         # [c, Kmax, N]
+            inside &= live[..., None]
+            hit |= inside.any(axis=1)
+            depth = np.minimum(y - lo, hi - y).min(axis=2)         # [c, Kmax, N]
+            depth = np.where(live[..., None], depth, -np.inf)
+            best = np.maximum(best, depth.max(axis=1))
+            near |= ((np.abs(depth) < EPS_FLAG) & live[..., None]).any(axis=1)
+        par = mask[idx]
+        flagged[idx] = ((~par) & near & (best < EPS_FLAG)).sum(axis=1)
+        mask[idx] = par | hit
+    return x, cost, step, mask, over, flagged
+
+
+def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
+            S_max, record=False):
+    """Alg. 4.  Returns (plans, P, stats, rounds) where P maps head -> plan ids
+    still in P(head) at exit and `rounds` holds per-round snapshots if `record`."""
+    N = D.shape[2]
+    root = Plan(nodes=(0,), cost=0.0, step=0, mask=np.zeros(N, bool), parent=-1)
+    plans: List[Plan] = [root]
+    P: Dict[int, List[int]] = {0: [0]}
+    P_open = {0}
+    B = [0]
+    i = 0
+    h = float(lam) * float(r_n)
+    goal = np.zeros(V.shape[0], bool)
+    goal[np.asarray(goal_nodes, np.int64)] = True
+    stats = dict(partial_plans=0, inserted=0, rounds=0, iterations=0,
+                 dropped_steps=0, flagged_particles=0)
+    rounds = []
+
+    def stop_now():
+        return any(goal[plans[g].head] and plans[g].pop / N < alpha_min for g in B)
+
+    while P_open and not stop_now():
+        stats["iterations"] += 1
+        snap = dict(i=i, B=[plans[p].nodes for p in B]) if record else None
+        parents, edges, parent_ids = [], [], []
+        for p in sorted(B):
+            u = plans[p].head
+            for e in range(graph["row_ptr"][u], graph["row_ptr"][u + 1]):
+                parents.append(plans[p])
+                parent_ids.append(p)
+                edges.append(e)
+        edges = np.asarray(edges, np.int64)
+        if B:
+            stats["rounds"] += 1
+        x, cost, step, mask, over, flagged = extend_batch(
+            V, graph, D, boxes, dt, S_max, parents, edges)
+        stats["partial_plans"] += len(parents)
+        stats["dropped_steps"] += int(over.sum())
+        stats["flagged_particles"] += int(flagged.sum())
+        inserted = []
+        for q in range(len(parents)):
+            if over[q]:
+                continue
+            cp_hat = mask[q].sum() / N
+            if cp_hat < alpha_max:                      # CP cutoff
+                plan = Plan(nodes=parents[q].nodes + (int(x[q]),), cost=float(cost[q]),
+                            step=int(step[q]), mask=mask[q].copy(), parent=parent_ids[q])
+                plans.append(plan)
+                pid = len(plans) - 1
+                P.setdefault(int(x[q]), []).append(pid)
+                P_open.add(pid)
+                inserted.append(pid)
+        stats["inserted"] += len(inserted)
+        # RemoveDominated(P, P_open)
+        dominated = set()
+        for p in P_open:
+            pp = plans[p]
+            for d in P[pp.head]:
+                dd = plans[d]
+                if pp.cost > dd.cost and pp.pop >= dd.pop:
+                    dominated.add(p)
+                    break
+        for p in dominated:
+            P[plans[p].head].remove(p)
+            P_open.discard(p)
+        P_open -= set(B)
+        if record:
+            snap["candidates"] = {plans[p].nodes: (plans[p].cost, plans[p].pop,
+                                                   np.packbits(plans[p].mask, bitorder="little"))
+                                  for p in inserted}
+            snap["survivors"] = sorted(plans[p].nodes for p in inserted if p not in dominated)
+            snap["removed"] = sorted(plans[p].nodes for p in dominated)
+            snap["open"] = sorted(plans[p].nodes for p in P_open)
+            snap["pairs"] = len(parents)
+            rounds.append(snap)
+        i += 1
+        B = sorted(p for p in P_open if plans[p].cost <= i * h)
+    stats["final_i"] = i
+    stats["stopped_at_goal"] = bool(P_open) and stop_now()
+    return plans, P, stats, rounds
+
+
+def goal_plans(plans, P, goal_nodes):
+    """P_goal = {p in P(v) : v in X_goal} (Alg. 4 return)."""
+    out = []
+    for v in goal_nodes:
+        out.extend(P.get(int(v), []))
+    return [plans[p] for p in out]

@@ -1,0 +1,291 @@
+"""Pins for Explore (Alg. 4), the particle CP estimate, MC(p) and
+PlanSelection (Alg. 5) in the oracle."""
+
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse
+import scipy.sparse.csgraph
+import scipy.stats
+
+from oracle import dynamics, explore as ex, graph as gr, pump, select as sel, steer as st
+from paper_1607_06886_amd import scenes
+
+CFG = pump.Config()
+
+
+def _small_scene(seed, n=150, N=32, sigma=0.02, alpha=0.05, n_obs=3, side=(0.1, 0.3)):
+    spec = dict(n=n, n_obs=n_obs, side=side, N=N, sigma=sigma, alpha=alpha, indoor=False)
+    return scenes.make_scene(spec, seed, M=2000, S_max=256)
+
+
+def _resimulate_mask(V, nodes, D, boxes, dt):
+    """From-scratch particle hits along a whole path, one waypoint at a time."""
+    N = D.shape[2]
+    hit = np.zeros(N, bool)
+    s = 0
+    for u, v in zip(nodes[:-1], nodes[1:]):
+        tau, c = st.steer(V[u][None], V[v][None], CFG.r_steer)
+        K = int(st.waypoint_count(tau, dt)[0])
+        coef = st.hermite(V[u][None], V[v][None], tau)[0]
+        for k in range(1, K + 1):
+            p = st.hermite_eval(coef, (k * tau[0]) / K)
+            y = p[:, None] + D[s + k].astype(np.float64)          # [3, N]
+            for b in boxes:
+                hit |= np.all((y >= b[:3, None]) & (y <= b[3:, None]), axis=0)
+        s += K
+    return hit, s
+
+
+@pytest.mark.parametrize("seed", [101, 102])
+def test_explore_invariants(seed):
+    sc = _small_scene(seed)
+    out = pump.run(sc, CFG, with_selection=False)
+    plans, P, V, D = out["plans"], out["P"], out["V"], out["D"]
+    c_cut = math.ceil(out["alpha_max"] * sc.N)
+    rp, col, cost = out["graph"]["row_ptr"], out["graph"]["col"], out["graph"]["cost"]
+    assert out["stats"]["partial_plans"] > 500
+    checked = 0
+    for pid, p in enumerate(plans[1:], start=1):
+        par = plans[p.parent]
+        # cp_hat never decreases along a plan: the child's bits contain the parent's
+        assert np.all(p.mask >= par.mask)
+        assert p.nodes[:-1] == par.nodes
+        e = rp[par.head] + int(np.searchsorted(col[rp[par.head]:rp[par.head + 1]], p.head))
+        assert abs(p.cost - (par.cost + cost[e])) <= 1e-12 * max(1.0, p.cost)
+        assert p.pop < c_cut
+        if pid % 7 == 0:
+            hit, s = _resimulate_mask(V, p.nodes, D, sc.obstacles, CFG.dt)
+            np.testing.assert_array_equal(hit, p.mask)
+            assert s == p.step
+            checked += 1
+    assert checked > 20
+    # at most c_cut distinct cp_hat levels per head (pops are < c_cut)
+    for x, ids in P.items():
+        assert len({plans[q].pop for q in ids}) <= c_cut
+
+
+def test_no_open_plan_is_dominated_after_each_round():
+    sc = _small_scene(103)
+    out = pump.run(sc, CFG, record=True, with_selection=False)
+    plans = out["plans"]
+    by_nodes = {p.nodes: p for p in plans}
+    for snap in out["rounds"]:
+        heads = {}
+        for nodes in snap["open"]:
+            heads.setdefault(nodes[-1], []).append(by_nodes[nodes])
+        for h, lst in heads.items():
+            for p in lst:
+                assert not any(p.cost > d.cost and p.pop >= d.pop for d in lst)
+
+
+def test_zero_noise_reduces_to_dijkstra():
+    """sigma = 0: every particle sits on the collision-free nominal waypoints,
+    all masks are empty, and with the early exit disabled (alpha_min = 0) the
+    best goal cost equals the shortest-path distance on the same graph."""
+    sc = _small_scene(104, n=120, sigma=0.0)
+    V = np.concatenate([sc.x_init[None], sc.samples]).astype(np.float64)
+    D = np.zeros((sc.S_max + 1, 3, sc.N), np.float32)
+    g = gr.build_graph(V, sc.obstacles, CFG.r_conn, CFG.r_steer)
+    gl = sc.goal.astype(np.float64)
+    goal_nodes = np.nonzero(np.all((V[:, :3] >= gl[:3]) & (V[:, :3] <= gl[3:]), 1))[0]
+    plans, P, stats, _ = ex.explore(V, g, D, sc.obstacles, goal_nodes, 0.0, 0.1, CFG.lam,
+                                    CFG.r_conn, CFG.dt, sc.S_max)
+    assert all(p.pop == 0 for p in plans)
+    n = V.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(g["row_ptr"]))
+    Gm = scipy.sparse.csr_matrix((g["cost"], (rows, g["col"])), shape=(n, n))
+    dist = scipy.sparse.csgraph.dijkstra(Gm, directed=True, indices=0)
+    best_ref = dist[goal_nodes].min()
+    assert np.isfinite(best_ref)
+    best = min(plans[q].cost for v in goal_nodes for q in P.get(int(v), []))
+    assert abs(best - best_ref) <= 1e-9 * best_ref
+    # every node's cheapest surviving plan is its shortest-path distance
+    for v, ids in P.items():
+        assert abs(min(plans[q].cost for q in ids) - dist[v]) <= 1e-9 * max(1.0, dist[v])
+
+
+def _tiny_instance(seed):
+    rng = np.random.default_rng(seed)
+    n = 8
+    pos = np.concatenate([[[0.1, 0.1, 0.1]], rng.uniform(0.15, 0.55, (n - 1, 3))])
+    vel = np.concatenate([[[0, 0, 0]], rng.uniform(-0.3, 0.3, (n - 1, 3))])
+    V = np.concatenate([pos, vel], 1)
+    boxes = np.array([[0.3, 0.3, 0.25, 0.36, 0.36, 0.45]])
+    return V, boxes
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_tiny_graph_exhaustive_enumeration(seed):
+    """n = 8: every simple path from x_init is enumerated and its (cost, pop)
+    computed from scratch; each PUMP plan's values equal the enumerator's for the
+    same node sequence, and PUMP's best goal cost is no better than the
+    enumerated optimum among paths with cp_hat < alpha_max."""
+    V, boxes = _tiny_instance(seed)
+    N = 64
+    rng = np.random.default_rng(100 + seed)
+    noise = rng.standard_normal((256, 6, N)).astype(np.float32)
+    A_cl, L, _ = dynamics.closed_loop(CFG.dt, 0.03, CFG.q_pos, CFG.q_vel, CFG.r_track)
+    D = dynamics.deviation_table(A_cl, L, noise, 256)
+    g = gr.build_graph(V, boxes, 1.2, CFG.r_steer)
+    assert g["col"].shape[0] >= 15
+    goal_nodes = np.array([5, 6, 7])
+    alpha_max = 0.2
+    plans, P, stats, _ = ex.explore(V, g, D, boxes, goal_nodes, 0.0, alpha_max, CFG.lam,
+                                    1.2, CFG.dt, 256)
+    adj = {v: list(g["col"][g["row_ptr"][v]:g["row_ptr"][v + 1]]) for v in range(V.shape[0])}
+    enum = {}
+
+    def walk(path):
+        if len(path) > 1:
+            hit, _ = _resimulate_mask(V, path, D, boxes, CFG.dt)
+            cost = sum(st.steer(V[a][None], V[b][None], CFG.r_steer)[1][0]
+                       for a, b in zip(path[:-1], path[1:]))
+            enum[tuple(path)] = (cost, int(hit.sum()))
+        for x in adj[path[-1]]:
+            if x not in path:
+                walk(path + [x])
+
+    walk([0])
+    for p in plans[1:]:
+        if len(set(p.nodes)) == len(p.nodes):
+            c, k = enum[p.nodes]
+            assert abs(c - p.cost) <= 1e-12 * max(1.0, c)
+            assert k == p.pop
+    best_enum = min((c for path, (c, k) in enum.items()
+                     if path[-1] in goal_nodes and k / N < alpha_max), default=np.inf)
+    got = [plans[q].cost for v in goal_nodes for q in P.get(int(v), [])]
+    if got:
+        assert best_enum <= min(got) + 1e-12
+
+
+def test_single_waypoint_cp_matches_gaussian_box_probability():
+    """One waypoint (K_e = 1) at plan step 11: particle positions are Gaussian
+    with the Lyapunov covariance, so the hit fraction is a product of normal CDF
+    differences (scipy.stats.norm), within a 4.5-sigma binomial band."""
+    N = 40_000
+    sigma = 0.02
+    A_cl, L, _ = dynamics.closed_loop(CFG.dt, sigma, CFG.q_pos, CFG.q_vel, CFG.r_track)
+    rng = np.random.default_rng(31)
+    noise = rng.standard_normal((12, 6, N)).astype(np.float32)
+    D = dynamics.deviation_table(A_cl, L, noise, 12)
+    Sig = np.zeros((2, 2))
+    for _ in range(11):
+        Sig = A_cl @ Sig @ A_cl.T + L @ L.T
+    s = math.sqrt(Sig[0, 0])
+    x0 = np.array([0.5, 0.5, 0.5, 0.25, 0.0, 0.0])      # coasting: tau* < 0.04
+    x1 = np.array([0.51, 0.5, 0.5, 0.25, 0.0, 0.0])
+    tau, c = st.steer(x0[None], x1[None], CFG.r_steer)
+    assert tau[0] <= CFG.dt                        # a single waypoint
+    V = np.stack([x0, x1])
+    graph = dict(col=np.array([1]), tau=tau, cost=c, row_ptr=np.array([0, 1, 1]))
+    box = np.array([[0.51 + 0.3 * s, 0.5 - 2 * s, 0.5 - 1 * s, 0.6, 0.5 + 1 * s, 0.6]])
+    parent = ex.Plan(nodes=(0,), cost=0.0, step=10, mask=np.zeros(N, bool), parent=-1)
+    _, _, step, mask, over, _ = ex.extend_batch(V, graph, D, box, CFG.dt, 12, [parent],
+                                                np.array([0]))
+    assert step[0] == 11 and not over[0]
+    mu = np.array([0.51, 0.5, 0.5])
+    p = 1.0
+    for a in range(3):
+        p *= (scipy.stats.norm.cdf((box[0, 3 + a] - mu[a]) / s)
+              - scipy.stats.norm.cdf((box[0, a] - mu[a]) / s))
+    frac = mask[0].mean()
+    assert 0.05 < p < 0.5
+    assert abs(frac - p) <= 4.5 * math.sqrt(p * (1 - p) / N), (frac, p)
+
+
+def _near_miss_plan():
+    V = np.array([[0.1, 0.5, 0.5, 0.0, 0.0, 0.0], [0.9, 0.5, 0.5, 0.0, 0.0, 0.0]])
+    boxes = np.array([[0.45, 0.515, 0.0, 0.55, 0.8, 1.0]])
+    return V, boxes
+
+
+def test_mc_converges_at_the_binomial_rate():
+    V, boxes = _near_miss_plan()
+    A_cl, L, _ = dynamics.closed_loop(CFG.dt, 0.02, CFG.q_pos, CFG.q_vel, CFG.r_track)
+    rng = np.random.default_rng(41)
+    big = rng.standard_normal((64, 6, 200_000)).astype(np.float32)
+    ref = sel.mc_count(V, (0, 1), boxes, A_cl, L, big, CFG.r_steer, CFG.dt) / 200_000
+    assert 0.02 < ref < 0.5
+    for M in (512, 4096, 16384):
+        xi = rng.standard_normal((64, 6, M)).astype(np.float32)
+        p = sel.mc_count(V, (0, 1), boxes, A_cl, L, xi, CFG.r_steer, CFG.dt) / M
+        assert abs(p - ref) <= 4 * math.sqrt(ref * (1 - ref) / M) + 4 * math.sqrt(ref * (1 - ref) / 200_000)
+
+
+def test_segment_check_dominates_waypoint_check():
+    """On the same particles, the swept (polyline) test finds every collision the
+    waypoint-only test finds."""
+    V, boxes = _near_miss_plan()
+    A_cl, L, _ = dynamics.closed_loop(CFG.dt, 0.02, CFG.q_pos, CFG.q_vel, CFG.r_track)
+    rng = np.random.default_rng(42)
+    M = 5000
+    xi = rng.standard_normal((64, 6, M)).astype(np.float32)
+    W = sel.plan_waypoints(V, (0, 1), CFG.r_steer, CFG.dt)
+    dev = dynamics.deviation_states(A_cl, L, xi, W.shape[0] - 1)
+    pts = W[:, :, None] + dev[:, :, 0, :]                      # [S+1, 3, M]
+    way = np.zeros(M, bool)
+    for b in boxes:
+        way |= np.any(np.all((pts >= b[None, :3, None]) & (pts <= b[None, 3:, None]), axis=1), axis=0)
+    swept = sel.mc_count(V, (0, 1), boxes, A_cl, L, xi, CFG.r_steer, CFG.dt)
+    assert way.sum() > 50
+    assert swept >= way.sum()
+
+
+def test_segment_box_slab_test_matches_dense_sampling():
+    rng = np.random.default_rng(43)
+    m = 3000
+    a = rng.uniform(0.2, 0.9, (m, 3))
+    b = a + rng.uniform(-0.3, 0.3, (m, 3))
+    lo = rng.uniform(0.3, 0.5, 3)
+    hi = lo + 0.2
+    got = sel.segments_hit_box(a, b, lo, hi)
+    t = np.linspace(0, 1, 4001)[:, None, None]
+    pts = a[None] + t * (b - a)[None]
+    dense = np.any(np.all((pts >= lo) & (pts <= hi), axis=2), axis=0)
+    assert got.sum() > 100
+    assert np.all(got | ~dense)             # dense hits are always found
+    assert (got != dense).sum() <= 3        # only grazes can differ
+
+
+def test_bisection_on_a_monotone_certificate_is_a_linear_scan():
+    class Pl:
+        def __init__(self, pop, cost, i):
+            self.pop, self.cost, self.nodes = pop, cost, (0, i)
+
+    for n in range(1, 12):
+        plans = [Pl(k, 10.0 - k, k) for k in range(n)]
+        for thresh in range(-1, n + 1):
+            mc = lambda p: (None, 0.0 if p.pop <= thresh else 1.0)
+            best, front, _ = sel.plan_selection(plans, 0.5, mc)
+            feasible = [p for p in front if p.pop <= thresh]
+            if feasible:
+                assert best is feasible[-1]
+            else:
+                assert best is None
+
+
+def test_pareto_front_keeps_exact_ties():
+    class Pl:
+        def __init__(self, pop, cost):
+            self.pop, self.cost = pop, cost
+
+    a, b, c, d = Pl(0, 2.0), Pl(0, 2.0), Pl(1, 1.5), Pl(1, 2.5)
+    front = sel.pareto_front([a, b, c, d])
+    assert front == [a, b, c]
+
+
+def test_pump_end_to_end_on_the_three_box_workload():
+    """The certified plan's MC estimate is within alpha and it lies on the
+    sorted Pareto front of P_goal."""
+    sc = scenes.make_scene("cfg1", scenes.workload_seed(1, 0), M=2000, S_max=256)
+    out = pump.run(sc, CFG)
+    assert out["status"] == 0
+    best = out["best"]
+    assert best in out["front"]
+    count, frac = out["evals"][out["front"].index(best) + 1]
+    assert frac <= sc.alpha
+    assert best.nodes[0] == 0 and best.head in set(out["goal_nodes"].tolist())
+    assert out["stats"]["partial_plans"] >= out["stats"]["inserted"] > 0
