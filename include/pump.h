@@ -1,0 +1,216 @@
+/*
+ * pump.h -- C ABI of libpump, an MI355X (gfx950) implementation of the hot
+ * path of PUMP (Parallel Uncertainty-aware Multiobjective Planning; Ichter,
+ * Schmerling, Agha-mohammadi, Pavone, arXiv 1607.06886).
+ *
+ * The planning problem is the stochastic kinodynamic motion planning problem
+ * of Sec. II, eq. (3): find the lowest-cost nominal trajectory from x_init to a
+ * goal region whose collision probability (CP) under an LQ tracking controller
+ * and Gaussian process noise is at most alpha.  The robot is the 6-D double
+ * integrator of Sec. V-A; obstacles are unions of axis-aligned boxes (Sec. V-C).
+ * pump_plan() runs Alg. 2: BuildGraph (Alg. 3), Explore (Alg. 4), PlanSelection
+ * (Alg. 5).
+ *
+ * Conventions for every call:
+ *   - A state is 6 floats (px, py, pz, vx, vy, vz).  Positions must lie within
+ *     [-16, 16] on every axis.
+ *   - Every function returns a status code (PUMP_OK, a positive algorithmic
+ *     outcome, or a negative error) unless stated otherwise; on a negative
+ *     code pump_last_error() describes the failure.
+ *   - The caller owns every buffer it passes.  The library never keeps a
+ *     caller pointer after a call returns.  Pointers flagged PUMP_MEM_DEVICE
+ *     are read on the context's HIP stream; calls return only after their
+ *     device work has finished.
+ *   - The context owns its device workspace (allocated once in pump_create,
+ *     sized by the pump_config capacities) and every result it reports; those
+ *     stay valid until the next call on the same context.  A context is used
+ *     by one host thread at a time.
+ *   - Same inputs, configuration and build give bit-identical outputs.
+ */
+#ifndef PUMP_H
+#define PUMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes.  Positive values are outcomes of the algorithm, not errors. */
+#define PUMP_OK            0
+#define PUMP_INFEASIBLE    1   /* Alg. 5: no plan of the front is certified (MC > alpha) */
+#define PUMP_NO_GOAL_PLAN  2   /* Explore ended with no plan reaching the goal region */
+#define PUMP_E_ARG        -1   /* invalid argument (see pump_last_error) */
+#define PUMP_E_CAPACITY   -2   /* a workspace capacity was exceeded; pump_last_error names it */
+#define PUMP_E_HIP        -3   /* a HIP runtime call failed */
+#define PUMP_E_STATE      -4   /* call out of order (e.g. a round before setup) */
+
+#define PUMP_MEM_HOST      0
+#define PUMP_MEM_DEVICE    1
+
+/* A closed axis-aligned box {p : lo <= p <= hi} (Sec. V-C: obstacles are
+ * unions of such boxes). */
+typedef struct pump_aabb {
+    float lo[3];
+    float hi[3];
+} pump_aabb;
+
+/* Planner configuration.  Fill with pump_config_default() and override.
+ * The paper fixes N = 128, eta and lambda (Sec. V-A); the other model
+ * parameters are left open by the paper and default to the values below. */
+typedef struct pump_config {
+    int32_t n_particles;   /* N exploration particles: 32, 64, 128 or 256          */
+    int32_t max_nodes;     /* capacity: samples + 1 (x_init is node 0)              */
+    int32_t max_obstacles; /* capacity: obstacle boxes, <= 256                      */
+    int32_t max_steps;     /* S_max: tracking steps a plan may span; also the step
+                              extent of both noise arrays                          */
+    int32_t mc_particles;  /* M certification particles (Alg. 5 MC(p))             */
+    int32_t preprune;      /* 1: skip simulating a pair whose parent cp_hat already
+                              makes it dominated (exact; results unchanged)       */
+    float dt;              /* tracking step of eq. (2), default 0.05                */
+    float q_pos, q_vel;    /* LQR state weights per axis, default 100, 10           */
+    float r_track;         /* LQR input weight, default 1                           */
+    float r_steer;         /* control-effort weight r_u in the cost c, default 0.1  */
+    float r_conn;          /* connection radius r_n of Near (Alg. 3), default 1.0   */
+    float eta;             /* CP approximation factor of Alg. 2; 0 = 2 above 1%,
+                              10 at 0.1%, log-linear between                      */
+    float lambda;          /* group cost factor of Alg. 4, default 0.5             */
+    int64_t cap_edges;     /* capacity: graph edges                                 */
+    int64_t cap_plans;     /* capacity: plan records over a whole query             */
+    int64_t cap_pairs;     /* capacity: (plan, neighbour) pairs in one round        */
+} pump_config;
+
+/* One planning query: Alg. 2's inputs plus the noise the particle models
+ * consume.  `samples`, `obstacles`, `noise` and `noise_mc` live in host or
+ * device memory as `mem` says.
+ *   samples   [n][6]          SampleFree(n) states (Alg. 3); a sample whose
+ *                             position lies in an obstacle is dropped
+ *   obstacles [n_obs]         closed boxes
+ *   noise     [S_max][6][N]   standard normals for the exploration particles;
+ *                             component 2a and 2a+1 drive axis a at step s
+ *   noise_mc  [S_max][6][M]   standard normals for certification
+ * alpha in (0, 1) is the CP bound of eq. (3); sigma is the process-noise
+ * intensity (V_c = sigma^2 I in eq. (1)). */
+typedef struct pump_problem {
+    const float* samples;
+    int32_t n;
+    const pump_aabb* obstacles;
+    int32_t n_obs;
+    float x_init[6];
+    pump_aabb goal;          /* X_goal: closed position box, velocity free */
+    float alpha;
+    float sigma;
+    const float* noise;
+    const float* noise_mc;
+    int32_t mem;             /* PUMP_MEM_HOST or PUMP_MEM_DEVICE */
+} pump_problem;
+
+/* Outcome of a query (Alg. 2 output plus counters). */
+typedef struct pump_result {
+    int32_t status;          /* PUMP_OK, PUMP_INFEASIBLE or PUMP_NO_GOAL_PLAN */
+    int32_t n_goal_plans;    /* |P_goal| (Alg. 4 return)                      */
+    int32_t n_front;         /* Pareto front of P_goal (cost, cp_hat)         */
+    int32_t best;            /* index of p* in the sorted front, -1 if none  */
+    int32_t best_plan;       /* plan id of p* (see pump_get_plans), -1       */
+    int32_t best_pop;        /* invalid exploration particles of p*           */
+    int32_t best_mc_count;   /* certification particles of p* that collide    */
+    int32_t best_len;        /* nodes on p* including x_init                  */
+    double best_cost;        /* c of p*                                        */
+    double best_cp_mc;       /* MC(p*) = best_mc_count / M                     */
+    int64_t partial_plans;   /* (plan, neighbour) pairs formed in Explore     */
+    int64_t simulated;       /* pairs whose particles were propagated         */
+    int64_t preprune;        /* pairs resolved as dominated before simulation */
+    int64_t inserted;        /* pairs passing the CP cutoff and not pre-pruned*/
+    int64_t survivors;       /* plans added to the plan store                 */
+    int64_t dropped_steps;   /* pairs dropped for exceeding S_max             */
+    int64_t flagged;         /* particle decisions within 1e-5 of a box face  */
+    int32_t rounds;          /* Explore iterations with a non-empty group     */
+    int32_t final_i;         /* group index i at exit                          */
+    int32_t n_plans;         /* plan records created                          */
+    int32_t n_edges;         /* graph edges                                    */
+    int32_t n_valid_nodes;   /* nodes not inside an obstacle                   */
+    int32_t c_cut;           /* keep a pair iff pop < c_cut (= ceil(alpha_max N)) */
+    int32_t c_min;           /* goal stop iff pop < c_min (= ceil(alpha_min N))   */
+    int32_t pad;
+    float ms_setup;          /* deviation table + graph build (Alg. 3)        */
+    float ms_explore;        /* Alg. 4                                          */
+    float ms_select;         /* Alg. 5                                          */
+    float ms_total;          /* whole pump_plan call                            */
+} pump_result;
+
+typedef struct pump_ctx pump_ctx;
+
+/* Defaults: N = 128, dt = 0.05, q = (100, 10), r_track = 1, r_steer = 0.1,
+ * r_conn = 1, eta = 0 (rule), lambda = 0.5, M = 10000, S_max = 512,
+ * preprune = 1, capacities for 4001 nodes / 64 obstacles. */
+void pump_config_default(pump_config* cfg);
+
+/* Create a context on the current HIP device.  `hip_stream` is a
+ * hipStream_t to run on, or NULL for a stream the context creates.  All
+ * device memory is allocated here.  Errors: PUMP_E_ARG for an unsupported
+ * configuration, PUMP_E_HIP if allocation fails (*out is then NULL). */
+int pump_create(const pump_config* cfg, void* hip_stream, pump_ctx** out);
+
+/* Free the context and its device memory.  NULL is accepted. */
+int pump_destroy(pump_ctx* ctx);
+
+/* Alg. 2 end to end: setup (deviation table, BuildGraph), Explore,
+ * PlanSelection.  Fills *out (which may be NULL).  Returns the status. */
+int pump_plan(pump_ctx* ctx, const pump_problem* prob, pump_result* out);
+
+/* Step hooks (the same work pump_plan does, one stage at a time). */
+/* Upload the problem, compute the tracking constants, the particle deviation
+ * table and BuildGraph (Alg. 3). */
+int pump_setup(pump_ctx* ctx, const pump_problem* prob);
+/* Alg. 4 initialisation: P_open = B = {root}, i = 0. */
+int pump_explore_begin(pump_ctx* ctx);
+/* One iteration of Alg. 4's while loop; *done = 1 once the loop test fails
+ * (no open plan, or a goal plan of the group has cp_hat < alpha_min). */
+int pump_explore_round(pump_ctx* ctx, int32_t* done);
+/* Rounds until done. */
+int pump_explore_run(pump_ctx* ctx);
+/* Alg. 5 on the explored plans; fills *out (status and p*). */
+int pump_select(pump_ctx* ctx, pump_result* out);
+
+/* Readers (host output buffers; sizes in elements). */
+/* Particle deviation table D[s][a][j] (position part), (S_max+1)*3*N floats. */
+int pump_get_deviation(pump_ctx* ctx, float* out, int64_t cap);
+/* Graph: row_ptr [n+2] (node v's neighbours are col[row_ptr[v]..row_ptr[v+1]),
+ * sorted), col/tau/cost [n_edges]; valid [n+1] (node not in an obstacle).
+ * Any pointer may be NULL. */
+int pump_get_graph(pump_ctx* ctx, int32_t* row_ptr, int32_t* col, double* tau,
+                   double* cost, uint8_t* valid, int64_t cap_edges, int64_t* n_edges);
+/* Plan store: for plans 0..n-1 their head node, parent plan (-1 for the root),
+ * graph edge (-1 for the root), cost, tracking steps, pop (invalid particles),
+ * group index of the round that created them, state (0 open, 1 closed,
+ * 2 removed by RemoveDominated) and particle bits (N/32 words per plan, bit j
+ * of word j/32 = particle j invalid).  Any pointer may be NULL. */
+int pump_get_plans(pump_ctx* ctx, int32_t* head, int32_t* parent, int32_t* edge,
+                   double* cost, int32_t* step, int32_t* pop, int32_t* round,
+                   uint8_t* state, uint32_t* mask, int64_t cap, int64_t* n_plans);
+/* Candidates of the last round, one per (plan, neighbour) pair in pair order:
+ * flag (0 dropped, 1 kept and not dominated, 2 kept but dominated),
+ * pop (-1 pre-pruned before simulation, -2 over S_max), and for kept ones
+ * parent plan, head, cost and particle bits.  Any pointer may be NULL. */
+int pump_get_candidates(pump_ctx* ctx, uint8_t* flag, int32_t* pop, int32_t* parent,
+                        int32_t* head, double* cost, uint32_t* mask, int64_t cap,
+                        int64_t* n_pairs);
+/* The sorted Pareto front of P_goal used by Alg. 5: plan ids and the MC
+ * certification counts (out of M). */
+int pump_get_front(pump_ctx* ctx, int32_t* plan_ids, int32_t* mc_counts, int32_t cap,
+                   int32_t* n_front);
+/* Node sequence (x_init first) of a plan. */
+int pump_get_path(pump_ctx* ctx, int32_t plan, int32_t* nodes, int32_t cap, int32_t* len);
+/* MC(p) (Sec. IV) for an arbitrary node sequence (nodes[0] must be 0):
+ * number of the M certification particles whose path meets an obstacle. */
+int pump_mc_path(pump_ctx* ctx, const int32_t* nodes, int32_t len, int32_t* count);
+
+/* Status text for a code, and the last error message of a context. */
+const char* pump_status_str(int status);
+const char* pump_last_error(const pump_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PUMP_H */

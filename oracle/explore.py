@@ -180,6 +180,10 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
             snap["removed"] = sorted(plans[p].nodes for p in dominated)
             snap["open"] = sorted(plans[p].nodes for p in P_open)
             snap["pairs"] = len(parents)
+            snap["pairs_all"] = {
+                parents[q].nodes + (int(x[q]),): (float(cost[q]), -2 if over[q] else int(mask[q].sum()),
+                                                  np.packbits(mask[q], bitorder="little"))
+                for q in range(len(parents))}
             rounds.append(snap)
         i += 1
         B = sorted(p for p in P_open if plans[p].cost <= i * h)

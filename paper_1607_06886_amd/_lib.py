@@ -1,0 +1,330 @@
+"""ctypes binding of libpump (include/pump.h): argument marshalling only.
+
+Every step of the planner runs in the HIP library; this module converts numpy
+arrays (host memory) or torch CUDA tensors (device memory) into the C
+structures and reads results back.  It raises if the built library is absent.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpump.so")
+
+PUMP_OK = 0
+PUMP_INFEASIBLE = 1
+PUMP_NO_GOAL_PLAN = 2
+PUMP_E_ARG = -1
+PUMP_E_CAPACITY = -2
+PUMP_E_HIP = -3
+PUMP_E_STATE = -4
+MEM_HOST = 0
+MEM_DEVICE = 1
+
+_f = ctypes.c_float
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+_p = ctypes.c_void_p
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_particles", _i32), ("max_nodes", _i32), ("max_obstacles", _i32),
+                ("max_steps", _i32), ("mc_particles", _i32), ("preprune", _i32),
+                ("dt", _f), ("q_pos", _f), ("q_vel", _f), ("r_track", _f), ("r_steer", _f),
+                ("r_conn", _f), ("eta", _f), ("lambda_", _f),
+                ("cap_edges", _i64), ("cap_plans", _i64), ("cap_pairs", _i64)]
+
+
+class AABB(ctypes.Structure):
+    _fields_ = [("lo", _f * 3), ("hi", _f * 3)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("samples", _p), ("n", _i32), ("obstacles", _p), ("n_obs", _i32),
+                ("x_init", _f * 6), ("goal", AABB), ("alpha", _f), ("sigma", _f),
+                ("noise", _p), ("noise_mc", _p), ("mem", _i32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", _i32), ("n_goal_plans", _i32), ("n_front", _i32), ("best", _i32),
+                ("best_plan", _i32), ("best_pop", _i32), ("best_mc_count", _i32),
+                ("best_len", _i32), ("best_cost", _d), ("best_cp_mc", _d),
+                ("partial_plans", _i64), ("simulated", _i64), ("preprune", _i64),
+                ("inserted", _i64), ("survivors", _i64), ("dropped_steps", _i64),
+                ("flagged", _i64), ("rounds", _i32), ("final_i", _i32), ("n_plans", _i32),
+                ("n_edges", _i32), ("n_valid_nodes", _i32), ("c_cut", _i32), ("c_min", _i32),
+                ("pad", _i32), ("ms_setup", _f), ("ms_explore", _f), ("ms_select", _f),
+                ("ms_total", _f)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class PumpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libpump status {code}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+# exported symbols (must match include/pump.h)
+EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "pump_setup",
+           "pump_explore_begin", "pump_explore_round", "pump_explore_run", "pump_select",
+           "pump_get_deviation", "pump_get_graph", "pump_get_plans", "pump_get_candidates",
+           "pump_get_front", "pump_get_path", "pump_mc_path", "pump_status_str",
+           "pump_last_error"]
+
+
+def load(path: Optional[str] = None):
+    """Load libpump (built in-tree); raises if it is missing."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"{p} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    P = ctypes.POINTER
+    sig = {
+        "pump_config_default": (None, [P(Config)]),
+        "pump_create": (_i32, [P(Config), _p, P(_p)]),
+        "pump_destroy": (_i32, [_p]),
+        "pump_plan": (_i32, [_p, P(Problem), P(Result)]),
+        "pump_setup": (_i32, [_p, P(Problem)]),
+        "pump_explore_begin": (_i32, [_p]),
+        "pump_explore_round": (_i32, [_p, P(_i32)]),
+        "pump_explore_run": (_i32, [_p]),
+        "pump_select": (_i32, [_p, P(Result)]),
+        "pump_get_deviation": (_i32, [_p, _p, _i64]),
+        "pump_get_graph": (_i32, [_p, _p, _p, _p, _p, _p, _i64, P(_i64)]),
+        "pump_get_plans": (_i32, [_p] + [_p] * 9 + [_i64, P(_i64)]),
+        "pump_get_candidates": (_i32, [_p] + [_p] * 6 + [_i64, P(_i64)]),
+        "pump_get_front": (_i32, [_p, _p, _p, _i32, P(_i32)]),
+        "pump_get_path": (_i32, [_p, _i32, _p, _i32, P(_i32)]),
+        "pump_mc_path": (_i32, [_p, _p, _i32, P(_i32)]),
+        "pump_status_str": (ctypes.c_char_p, [_i32]),
+        "pump_last_error": (ctypes.c_char_p, [_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _LIB = lib
+    return lib
+
+
+def default_config(**over) -> Config:
+    lib = load()
+    c = Config()
+    lib.pump_config_default(ctypes.byref(c))
+    for k, v in over.items():
+        setattr(c, "lambda_" if k == "lam" else k, v)
+    return c
+
+
+def _ptr(a):
+    """Data pointer of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class Planner:
+    """One libpump context.  Inputs may be numpy arrays (host) or torch CUDA
+    tensors (device); `stream` is a torch.cuda.Stream or raw hipStream_t."""
+
+    def __init__(self, stream=None, **cfg):
+        self.lib = load()
+        self.cfg = default_config(**cfg)
+        s = None
+        if stream is not None:
+            s = getattr(stream, "cuda_stream", stream)
+        self.ctx = _p()
+        rc = self.lib.pump_create(ctypes.byref(self.cfg), s, ctypes.byref(self.ctx))
+        if rc != 0:
+            raise PumpError(rc, "pump_create failed")
+        self._keep = []
+
+    def close(self):
+        if self.ctx:
+            self.lib.pump_destroy(self.ctx)
+            self.ctx = _p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_positive=False):
+        if rc < 0 or (rc > 0 and not allow_positive):
+            msg = self.lib.pump_last_error(self.ctx) or b""
+            raise PumpError(rc, msg.decode())
+        return rc
+
+    # -- problem -------------------------------------------------------------
+    def problem(self, samples, obstacles, x_init, goal, alpha, sigma, noise, noise_mc):
+        """Build the C problem struct.  Array arguments are numpy (host) or
+        torch CUDA tensors (device), all of the same kind."""
+        dev = not isinstance(samples, np.ndarray)
+        if not dev:
+            samples = _np(samples, np.float32)
+            obstacles = _np(obstacles, np.float32).reshape(-1, 6)
+            noise = _np(noise, np.float32)
+            noise_mc = _np(noise_mc, np.float32)
+        self._keep = [samples, obstacles, noise, noise_mc]
+        pr = Problem()
+        pr.samples = _ptr(samples)
+        pr.n = int(samples.shape[0])
+        pr.obstacles = _ptr(obstacles) if int(obstacles.shape[0]) else None
+        pr.n_obs = int(obstacles.shape[0])
+        xi = np.asarray(x_init, np.float32)
+        for k in range(6):
+            pr.x_init[k] = float(xi[k])
+        g = np.asarray(goal, np.float32)
+        for k in range(3):
+            pr.goal.lo[k] = float(g[k])
+            pr.goal.hi[k] = float(g[3 + k])
+        pr.alpha = float(alpha)
+        pr.sigma = float(sigma)
+        pr.noise = _ptr(noise)
+        pr.noise_mc = _ptr(noise_mc)
+        pr.mem = MEM_DEVICE if dev else MEM_HOST
+        return pr
+
+    def scene_problem(self, sc, device=False):
+        if device:
+            import torch
+            t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+            return self.problem(t(sc.samples), t(sc.obstacles), sc.x_init, sc.goal, sc.alpha,
+                                sc.sigma, t(sc.noise), t(sc.noise_mc))
+        return self.problem(sc.samples, sc.obstacles, sc.x_init, sc.goal, sc.alpha, sc.sigma,
+                            sc.noise, sc.noise_mc)
+
+    # -- whole query and stages ----------------------------------------------
+    def plan(self, pr) -> dict:
+        res = Result()
+        rc = self.lib.pump_plan(self.ctx, ctypes.byref(pr), ctypes.byref(res))
+        self._check(rc, allow_positive=True)
+        return res.as_dict()
+
+    def setup(self, pr):
+        self._check(self.lib.pump_setup(self.ctx, ctypes.byref(pr)))
+
+    def explore_begin(self):
+        self._check(self.lib.pump_explore_begin(self.ctx))
+
+    def explore_round(self) -> bool:
+        d = _i32(0)
+        self._check(self.lib.pump_explore_round(self.ctx, ctypes.byref(d)))
+        return bool(d.value)
+
+    def explore_run(self):
+        self._check(self.lib.pump_explore_run(self.ctx))
+
+    def select(self) -> dict:
+        res = Result()
+        rc = self.lib.pump_select(self.ctx, ctypes.byref(res))
+        self._check(rc, allow_positive=True)
+        return res.as_dict()
+
+    # -- readers ---------------------------------------------------------------
+    def deviation(self):
+        N = self.cfg.n_particles
+        S = self.cfg.max_steps
+        out = np.zeros((S + 1, 3, N), np.float32)
+        self._check(self.lib.pump_get_deviation(self.ctx, out.ctypes.data, out.size))
+        return out
+
+    def graph(self, n_nodes):
+        ne = _i64(0)
+        self._check(self.lib.pump_get_graph(self.ctx, None, None, None, None, None, 0,
+                                            ctypes.byref(ne)))
+        E = ne.value
+        row = np.zeros(n_nodes + 1, np.int32)
+        col = np.zeros(max(E, 1), np.int32)
+        tau = np.zeros(max(E, 1), np.float64)
+        cost = np.zeros(max(E, 1), np.float64)
+        valid = np.zeros(n_nodes, np.uint8)
+        self._check(self.lib.pump_get_graph(self.ctx, row.ctypes.data, col.ctypes.data,
+                                            tau.ctypes.data, cost.ctypes.data, valid.ctypes.data,
+                                            max(E, 1), ctypes.byref(ne)))
+        return dict(row_ptr=row, col=col[:E], tau=tau[:E], cost=cost[:E], valid=valid.astype(bool))
+
+    def plans(self):
+        n = _i64(0)
+        self._check(self.lib.pump_get_plans(self.ctx, *([None] * 9), 0, ctypes.byref(n)))
+        n = n.value
+        W = self.cfg.n_particles // 32
+        out = dict(head=np.zeros(n, np.int32), parent=np.zeros(n, np.int32),
+                   edge=np.zeros(n, np.int32), cost=np.zeros(n, np.float64),
+                   step=np.zeros(n, np.int32), pop=np.zeros(n, np.int32),
+                   round=np.zeros(n, np.int32), state=np.zeros(n, np.uint8),
+                   mask=np.zeros((n, W), np.uint32))
+        ks = ["head", "parent", "edge", "cost", "step", "pop", "round", "state", "mask"]
+        self._check(self.lib.pump_get_plans(self.ctx, *[out[k].ctypes.data for k in ks], n,
+                                            ctypes.byref(_i64(0))))
+        return out
+
+    def candidates(self):
+        n = _i64(0)
+        self._check(self.lib.pump_get_candidates(self.ctx, *([None] * 6), 0, ctypes.byref(n)))
+        n = n.value
+        W = self.cfg.n_particles // 32
+        out = dict(flag=np.zeros(n, np.uint8), pop=np.zeros(n, np.int32),
+                   parent=np.zeros(n, np.int32), head=np.zeros(n, np.int32),
+                   cost=np.zeros(n, np.float64), mask=np.zeros((n, W), np.uint32))
+        ks = ["flag", "pop", "parent", "head", "cost", "mask"]
+        self._check(self.lib.pump_get_candidates(self.ctx, *[out[k].ctypes.data for k in ks],
+                                                 n, ctypes.byref(_i64(0))))
+        return out
+
+    def front(self):
+        n = _i32(0)
+        self._check(self.lib.pump_get_front(self.ctx, None, None, 0, ctypes.byref(n)))
+        ids = np.zeros(max(n.value, 1), np.int32)
+        mc = np.zeros(max(n.value, 1), np.int32)
+        self._check(self.lib.pump_get_front(self.ctx, ids.ctypes.data, mc.ctypes.data,
+                                            ids.size, ctypes.byref(n)))
+        return ids[:n.value], mc[:n.value]
+
+    def path(self, plan):
+        cap = self.cfg.max_steps + 1
+        buf = np.zeros(cap, np.int32)
+        ln = _i32(0)
+        self._check(self.lib.pump_get_path(self.ctx, int(plan), buf.ctypes.data, cap,
+                                           ctypes.byref(ln)))
+        return tuple(int(v) for v in buf[:ln.value])
+
+    def mc_path(self, nodes):
+        nd = np.ascontiguousarray(np.asarray(nodes, np.int32))
+        c = _i32(0)
+        self._check(self.lib.pump_mc_path(self.ctx, nd.ctypes.data, int(nd.shape[0]),
+                                          ctypes.byref(c)))
+        return int(c.value)
+
+
+def plan_paths(pl: dict):
+    """Node sequences of every plan from the plan-store arrays (host side)."""
+    head, parent = pl["head"], pl["parent"]
+    paths = [None] * head.shape[0]
+    for p in range(head.shape[0]):
+        if parent[p] < 0:
+            paths[p] = (int(head[p]),)
+        else:
+            paths[p] = paths[parent[p]] + (int(head[p]),)
+    return paths

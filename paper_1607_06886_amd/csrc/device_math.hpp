@@ -1,0 +1,223 @@
+// FP64 device math of the double-integrator connection (Sec. II cost c,
+// Sec. IV Cost / Collision primitives).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace pump {
+
+// Boundary sums of a connection x0 -> x1:
+//   S_PP = sum P_a^2, S_Pv = sum P_a (v0_a + v1_a), S_vv = sum v0^2 + v0 v1 + v1^2
+// with P = p1 - p0.  The minimum-effort cost of duration tau is
+//   c(tau) = tau + r (12 S_PP / tau^3 - 12 S_Pv / tau^2 + 4 S_vv / tau).
+struct BSums {
+    double pp, pv, vv;
+};
+
+__device__ __forceinline__ BSums boundary_sums(const float* x0, const float* x1) {
+    BSums s{0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double P = (double)x1[a] - (double)x0[a];
+        double v0 = (double)x0[3 + a];
+        double v1 = (double)x1[3 + a];
+        s.pp += P * P;
+        s.pv += P * (v0 + v1);
+        s.vv += v0 * v0 + v0 * v1 + v1 * v1;
+    }
+    return s;
+}
+
+__device__ __forceinline__ double cost_of(double t, const BSums& s, double r) {
+    return t + r * (12.0 * s.pp / (t * t * t) - 12.0 * s.pv / (t * t) + 4.0 * s.vv / t);
+}
+
+// Stationarity of c: f(t) = t^4 + a2 t^2 + a1 t + a0 with a2 = -4 r S_vv <= 0,
+// a1 = 24 r S_Pv, a0 = -36 r S_PP <= 0; f' = 4 t^3 + 2 a2 t + a1, f'' = 12 t^2 + 2 a2.
+struct Quartic {
+    double a2, a1, a0;
+    __device__ double f(double t) const { return ((t * t + a2) * t + a1) * t + a0; }
+    __device__ double g(double t) const { return (4.0 * t * t + 2.0 * a2) * t + a1; }
+    __device__ double gp(double t) const { return 12.0 * t * t + 2.0 * a2; }
+};
+
+// Root of a function monotone on [lo, hi] whose values at the ends have
+// opposite signs: Newton steps kept inside the shrinking bracket, bisection
+// when a step leaves it.  `which` selects f (0) or f' (1) of the quartic.
+__device__ __forceinline__ double bracket_root(const Quartic& q, int which, double lo, double hi) {
+    double flo = which ? q.g(lo) : q.f(lo);
+    double fhi = which ? q.g(hi) : q.f(hi);
+    if (flo == 0.0) return lo;
+    if (fhi == 0.0) return hi;
+    if ((flo < 0.0) == (fhi < 0.0)) return fabs(flo) < fabs(fhi) ? lo : hi;
+    const bool rising = flo < 0.0;
+    double t = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        double v = which ? q.g(t) : q.f(t);
+        if (v == 0.0) return t;
+        if ((v < 0.0) == rising) lo = t; else hi = t;
+        double d = which ? q.gp(t) : q.g(t);
+        double tn = t - v / d;
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (tn == t || !(hi > lo)) break;
+        // stop once the bracket is down to a few ulps
+        if (hi - lo <= 4.0 * 2.220446049250313e-16 * hi) { t = tn; break; }
+        t = tn;
+    }
+    return t;
+}
+
+// Optimal duration and cost of the connection x0 -> x1 (FP64).  The global
+// minimiser of c over tau > 0 is one of the upward zero crossings of f
+// (local minima of c).  f is concave on (0, ti) and convex on (ti, inf) with
+// ti = sqrt(-a2/6), so f' has at most one zero t1 on (0, ti) (only when
+// f'(0) = a1 > 0) and one zero t2 on (ti, inf); the upward crossings lie in
+// (0, t1) and (t2, inf).  Identical states give tau = cost = 0.
+__device__ __forceinline__ void steer64(const float* x0, const float* x1, double r,
+                                        double& tau, double& cost) {
+    BSums s = boundary_sums(x0, x1);
+    if (s.pp == 0.0 && s.vv == 0.0) { tau = 0.0; cost = 0.0; return; }
+    Quartic q{-4.0 * r * s.vv, 24.0 * r * s.pv, -36.0 * r * s.pp};
+    // Fujiwara bound on the roots of f and of f'/4
+    double Bf = 2.0 * fmax(fmax(sqrt(fabs(q.a2)), cbrt(fabs(q.a1))), sqrt(sqrt(0.5 * fabs(q.a0))));
+    double Bg = 2.0 * fmax(sqrt(0.5 * fabs(q.a2)), cbrt(0.25 * fabs(q.a1)));
+    double ti = sqrt(-q.a2 / 6.0);
+    double cand[2];
+    int nc = 0;
+    if (q.g(ti) >= 0.0) {
+        cand[nc++] = bracket_root(q, 0, 0.0, Bf);
+    } else {
+        double t2 = bracket_root(q, 1, ti, fmax(Bg, ti));
+        if (q.f(t2) < 0.0) cand[nc++] = bracket_root(q, 0, t2, fmax(Bf, t2));
+        if (q.a1 > 0.0) {
+            double t1 = bracket_root(q, 1, 0.0, ti);
+            if (q.f(t1) > 0.0) cand[nc++] = bracket_root(q, 0, 0.0, t1);
+        }
+    }
+    double bt = 0.0, bc = INFINITY;
+    for (int k = 0; k < nc; ++k) {
+        double t = cand[k];
+        if (!(t > 0.0)) continue;
+        double c = cost_of(t, s, r);
+        if (c < bc || (c == bc && t < bt)) { bc = c; bt = t; }
+    }
+    tau = bt;
+    cost = bc;
+}
+
+// Minimum-effort nominal trajectory per axis (cubic Hermite):
+//   p(t) = p0 + v0 t + c2 t^2 + c3 t^3,
+//   c2 = (3P - (2 v0 + v1) tau) / tau^2,  c3 = (-2P + (v0 + v1) tau) / tau^3.
+struct Cubic {
+    double c0, c1, c2, c3;
+    __device__ double at(double t) const { return c0 + t * (c1 + t * (c2 + t * c3)); }
+};
+
+__device__ __forceinline__ void hermite(const float* x0, const float* x1, double tau, Cubic* out) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double p0 = (double)x0[a], v0 = (double)x0[3 + a], v1 = (double)x1[3 + a];
+        double P = (double)x1[a] - p0;
+        out[a].c0 = p0;
+        out[a].c1 = v0;
+        out[a].c2 = (3.0 * P - (2.0 * v0 + v1) * tau) / (tau * tau);
+        out[a].c3 = (-2.0 * P + (v0 + v1) * tau) / (tau * tau * tau);
+    }
+}
+
+// Interior stationary points of a cubic on (0, tau), ascending; returns count.
+__device__ __forceinline__ int stationary_points(const Cubic& c, double tau, double* br) {
+    double A = 3.0 * c.c3, B = 2.0 * c.c2, C = c.c1;
+    double r0 = NAN, r1 = NAN;
+    if (A == 0.0) {
+        if (B != 0.0) r0 = -C / B;
+    } else {
+        double disc = B * B - 4.0 * A * C;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double qv = -0.5 * (B + (B >= 0.0 ? sq : -sq));
+            if (qv != 0.0) { r0 = qv / A; r1 = C / qv; }
+            else { r0 = 0.0; }
+        }
+    }
+    int n = 0;
+    if (r0 > 0.0 && r0 < tau) br[n++] = r0;
+    if (r1 > 0.0 && r1 < tau) br[n++] = r1;
+    if (n == 2 && br[1] < br[0]) { double t = br[0]; br[0] = br[1]; br[1] = t; }
+    return n;
+}
+
+// On a monotone piece [ta, tb] bracketing `level`: bisection for the crossing.
+// Returns the bracket (lo, hi) with p(lo) on the start side of the level.
+__device__ __forceinline__ void crossing(const Cubic& c, double ta, double tb, double level,
+                                         bool rising, double& lo, double& hi) {
+    lo = ta; hi = tb;
+    for (int it = 0; it < 64; ++it) {
+        double mid = 0.5 * (lo + hi);
+        bool below = c.at(mid) < level;
+        bool right = rising ? below : !below;
+        if (right) lo = mid; else hi = mid;
+    }
+}
+
+// The set {t in [0, tau] : lo <= p(t) <= hi} as <= 3 closed intervals.
+__device__ __forceinline__ int slab_set(const Cubic& c, double tau, double lo, double hi,
+                                        double* s, double* e) {
+    double br[2];
+    int nb = stationary_points(c, tau, br);
+    double edges[4];
+    edges[0] = 0.0;
+    for (int k = 0; k < nb; ++k) edges[1 + k] = br[k];
+    edges[1 + nb] = tau;
+    int n = 0;
+    for (int k = 0; k <= nb; ++k) {
+        double ta = edges[k], tb = edges[k + 1];
+        double pa = c.at(ta), pb = c.at(tb);
+        bool rising = pb >= pa;
+        double pmin = fmin(pa, pb), pmax = fmax(pa, pb);
+        if (!(pmax >= lo && pmin <= hi)) continue;
+        double l0, l1, h0, h1;
+        double st, en;
+        if (rising) {
+            if (pmin >= lo) st = ta; else { crossing(c, ta, tb, lo, true, l0, l1); st = l1; }
+            if (pmax <= hi) en = tb; else { crossing(c, ta, tb, hi, true, h0, h1); en = h0; }
+        } else {
+            if (pmax <= hi) st = ta; else { crossing(c, ta, tb, hi, false, h0, h1); st = h1; }
+            if (pmin >= lo) en = tb; else { crossing(c, ta, tb, lo, false, l0, l1); en = l0; }
+        }
+        s[n] = st; e[n] = en; ++n;
+    }
+    return n;
+}
+
+// Range of a cubic over [0, tau] (endpoints and stationary points).
+__device__ __forceinline__ void cubic_range(const Cubic& c, double tau, double& mn, double& mx) {
+    double br[2];
+    int nb = stationary_points(c, tau, br);
+    double p0 = c.at(0.0), p1 = c.at(tau);
+    mn = fmin(p0, p1); mx = fmax(p0, p1);
+    for (int k = 0; k < nb; ++k) { double v = c.at(br[k]); mn = fmin(mn, v); mx = fmax(mx, v); }
+}
+
+// Does the nominal trajectory (three axis cubics on [0, tau]) meet the closed
+// box? It is inside at time t iff all three coordinates are in their slabs,
+// so it meets the box iff the three per-axis in-slab sets intersect.
+__device__ __forceinline__ bool trajectory_hits_box(const Cubic* cs, double tau, const float* box) {
+    double s[3][3], e[3][3];
+    int n[3];
+    for (int a = 0; a < 3; ++a) {
+        n[a] = slab_set(cs[a], tau, (double)box[a], (double)box[3 + a], s[a], e[a]);
+        if (n[a] == 0) return false;
+    }
+    for (int i = 0; i < n[0]; ++i)
+        for (int j = 0; j < n[1]; ++j)
+            for (int k = 0; k < n[2]; ++k) {
+                double st = fmax(fmax(s[0][i], s[1][j]), s[2][k]);
+                double en = fmin(fmin(e[0][i], e[1][j]), e[2][k]);
+                if (st <= en) return true;
+            }
+    return false;
+}
+
+}  // namespace pump

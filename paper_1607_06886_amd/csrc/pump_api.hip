@@ -1,0 +1,804 @@
+// C ABI of libpump: context, problem setup, the Explore loop and
+// PlanSelection (Alg. 2-5).  Host code only orchestrates; every step of the
+// planner runs in the kernels of kernels_*.hip.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "pump_internal.hpp"
+
+using namespace pump;
+
+struct pump_ctx {
+    pump_config cfg;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int N = 0, W = 0;
+    int words_per_row = 0;  // edge bit-matrix row length (u32)
+    // problem
+    float* X = nullptr;
+    uint8_t* valid = nullptr;
+    uint8_t* goal = nullptr;
+    float* obs = nullptr;
+    float* noise_buf = nullptr;
+    float* noise_mc_buf = nullptr;
+    const float* noise = nullptr;
+    const float* noise_mc = nullptr;
+    float* D = nullptr;
+    float* cloud = nullptr;
+    float* gcloud = nullptr;
+    int32_t* dev_ints = nullptr;  // [0] n_nodes, [1] bad-input flag
+    // graph
+    uint32_t* ebits = nullptr;
+    int32_t* deg = nullptr;
+    int32_t* row_ptr = nullptr;
+    int32_t* col = nullptr;
+    double* etau = nullptr;
+    double* ecost = nullptr;
+    // plans
+    int32_t *p_head = nullptr, *p_parent = nullptr, *p_edge = nullptr, *p_step = nullptr,
+            *p_pop = nullptr, *p_round = nullptr;
+    double* p_cost = nullptr;
+    uint32_t* p_mask = nullptr;
+    uint8_t* p_state = nullptr;
+    unsigned long long* stair = nullptr;
+    int32_t *open_a = nullptr, *open_b = nullptr, *o_keep = nullptr;
+    uint8_t* o_inB = nullptr;
+    int32_t *b_ids = nullptr, *b_off = nullptr, *b_deg = nullptr;
+    // candidates
+    int32_t *c_head = nullptr, *c_parent = nullptr, *c_edge = nullptr, *c_step = nullptr,
+            *c_pop = nullptr, *c_pos = nullptr;
+    double* c_cost = nullptr;
+    uint32_t* c_mask = nullptr;
+    uint8_t* c_flag = nullptr;
+    int32_t* blk = nullptr;
+    Ctl* ctl = nullptr;
+    Ctl* ctl_h = nullptr;  // pinned mirror
+    // selection
+    int32_t *goal_ids = nullptr, *front_ids = nullptr, *paths = nullptr, *path_len = nullptr,
+            *wp_len = nullptr, *mc_counts = nullptr;
+    double* wp = nullptr;
+    // query state
+    int n_nodes = 0, n_obs = 0, M = 0, S_max = 0;
+    double alpha = 0, eta = 0, alpha_min = 0, alpha_max = 0, h = 0, dt = 0;
+    int c_cut = 0, c_min = 0;
+    double Acl[4] = {0, 0, 0, 0}, L[4] = {0, 0, 0, 0}, K[2] = {0, 0};
+    int n_edges = 0, n_valid = 0;
+    bool have_setup = false, have_explore = false, explore_done = false;
+    int32_t* open_cur = nullptr;
+    int32_t* open_next = nullptr;
+    long long partial_plans = 0;
+    int32_t last_pairs = 0;
+    int rounds = 0;
+    float ms_setup = 0, ms_explore = 0, ms_select = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::string err;
+};
+
+namespace {
+
+int fail(pump_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(ctx, PUMP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+    if (n == 0) n = 1;
+    return hipMalloc((void**)p, n * sizeof(T));
+}
+
+// Steady-state discrete LQR for one axis of the double integrator: iterate
+// P <- Q + A'PA - A'PB (R + B'PB)^-1 B'PA to a relative change below 1e-14,
+// K = (R + B'PB)^-1 B'PA, du = -K dx.
+void lqr_axis(double dt, double q_pos, double q_vel, double r, double K[2]) {
+    const double A[2][2] = {{1.0, dt}, {0.0, 1.0}};
+    const double B[2] = {0.5 * dt * dt, dt};
+    double P[2][2] = {{q_pos, 0.0}, {0.0, q_vel}};
+    for (int it = 0; it < 1000000; ++it) {
+        double PA[2][2], PB[2];
+        for (int i = 0; i < 2; ++i) {
+            for (int j = 0; j < 2; ++j) PA[i][j] = P[i][0] * A[0][j] + P[i][1] * A[1][j];
+            PB[i] = P[i][0] * B[0] + P[i][1] * B[1];
+        }
+        const double G = r + B[0] * PB[0] + B[1] * PB[1];
+        double BPA[2];  // B'PA
+        for (int j = 0; j < 2; ++j) BPA[j] = B[0] * PA[0][j] + B[1] * PA[1][j];
+        double Pn[2][2];
+        double dmax = 0.0, pmax = 0.0;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                const double APA = A[0][i] * PA[0][j] + A[1][i] * PA[1][j];
+                const double v = (i == j ? (i == 0 ? q_pos : q_vel) : 0.0) + APA - BPA[i] * BPA[j] / G;
+                Pn[i][j] = v;
+                dmax = std::max(dmax, fabs(v - P[i][j]));
+                pmax = std::max(pmax, fabs(v));
+            }
+        memcpy(P, Pn, sizeof(P));
+        if (dmax <= 1e-14 * pmax) break;
+    }
+    double PA[2][2], PB[2];
+    for (int i = 0; i < 2; ++i) {
+        for (int j = 0; j < 2; ++j) PA[i][j] = P[i][0] * A[0][j] + P[i][1] * A[1][j];
+        PB[i] = P[i][0] * B[0] + P[i][1] * B[1];
+    }
+    const double G = r + B[0] * PB[0] + B[1] * PB[1];
+    for (int j = 0; j < 2; ++j) K[j] = (B[0] * PA[0][j] + B[1] * PA[1][j]) / G;
+}
+
+double eta_rule(double alpha) {
+    if (alpha >= 0.01) return 2.0;
+    if (alpha <= 0.001) return 10.0;
+    const double w = (log(0.01) - log(alpha)) / (log(0.01) - log(0.001));
+    return exp(log(2.0) + w * (log(10.0) - log(2.0)));
+}
+
+RoundArgs round_args(pump_ctx* c) {
+    RoundArgs a;
+    memset(&a, 0, sizeof(a));
+    a.X = c->X;
+    a.goal = c->goal;
+    a.obs = c->obs;
+    a.n_obs = c->n_obs;
+    a.D = c->D;
+    a.cloud = c->cloud;
+    a.gcloud = c->gcloud;
+    a.S_max = c->S_max;
+    a.dt = c->dt;
+    a.c_cut = c->c_cut;
+    a.c_min = c->c_min;
+    a.h = c->h;
+    a.preprune = c->cfg.preprune;
+    a.row_ptr = c->row_ptr;
+    a.col = c->col;
+    a.etau = c->etau;
+    a.ecost = c->ecost;
+    a.p_head = c->p_head;
+    a.p_parent = c->p_parent;
+    a.p_edge = c->p_edge;
+    a.p_step = c->p_step;
+    a.p_pop = c->p_pop;
+    a.p_round = c->p_round;
+    a.p_cost = c->p_cost;
+    a.p_mask = c->p_mask;
+    a.p_state = c->p_state;
+    a.cap_plans = c->cfg.cap_plans;
+    a.stair = c->stair;
+    a.stair_w = c->N + 1;
+    a.open_in = c->open_cur;
+    a.open_out = c->open_next;
+    a.o_inB = c->o_inB;
+    a.o_keep = c->o_keep;
+    a.b_ids = c->b_ids;
+    a.b_off = c->b_off;
+    a.c_head = c->c_head;
+    a.c_parent = c->c_parent;
+    a.c_edge = c->c_edge;
+    a.c_step = c->c_step;
+    a.c_pop = c->c_pop;
+    a.c_cost = c->c_cost;
+    a.c_mask = c->c_mask;
+    a.c_flag = c->c_flag;
+    a.c_pos = c->c_pos;
+    a.ctl = c->ctl;
+    return a;
+}
+
+SelectArgs select_args(pump_ctx* c) {
+    SelectArgs a;
+    memset(&a, 0, sizeof(a));
+    a.X = c->X;
+    a.obs = c->obs;
+    a.n_obs = c->n_obs;
+    a.goal = c->goal;
+    a.p_head = c->p_head;
+    a.p_parent = c->p_parent;
+    a.p_pop = c->p_pop;
+    a.p_cost = c->p_cost;
+    a.p_state = c->p_state;
+    a.n_plans = c->ctl_h->n_plans;
+    a.goal_ids = c->goal_ids;
+    a.front_ids = c->front_ids;
+    a.paths = c->paths;
+    a.path_len = c->path_len;
+    a.wp = c->wp;
+    a.wp_len = c->wp_len;
+    a.mc_counts = c->mc_counts;
+    a.noise_mc = c->noise_mc;
+    a.M = c->M;
+    a.S_max = c->S_max;
+    a.dt = c->dt;
+    a.r_steer = (double)c->cfg.r_steer;
+    for (int k = 0; k < 4; ++k) { a.Acl[k] = c->Acl[k]; a.L[k] = c->L[k]; }
+    a.ctl = c->ctl;
+    return a;
+}
+
+int read_ctl(pump_ctx* ctx) {
+    HIPCHK(hipMemcpyAsync(ctx->ctl_h, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return PUMP_OK;
+}
+
+bool finite6(const float* x) {
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(x[k])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pump_config_default(pump_config* c) {
+    if (!c) return;
+    memset(c, 0, sizeof(*c));
+    c->n_particles = 128;
+    c->max_nodes = 4001;
+    c->max_obstacles = 64;
+    c->max_steps = 512;
+    c->mc_particles = 10000;
+    c->preprune = 1;
+    c->dt = 0.05f;
+    c->q_pos = 100.0f;
+    c->q_vel = 10.0f;
+    c->r_track = 1.0f;
+    c->r_steer = 0.1f;
+    c->r_conn = 1.0f;
+    c->eta = 0.0f;
+    c->lambda = 0.5f;
+    c->cap_edges = 4 << 20;
+    c->cap_plans = 1 << 20;
+    c->cap_pairs = 4 << 20;
+}
+
+const char* pump_status_str(int s) {
+    switch (s) {
+        case PUMP_OK: return "ok";
+        case PUMP_INFEASIBLE: return "infeasible: no plan of the front certified";
+        case PUMP_NO_GOAL_PLAN: return "no plan reached the goal region";
+        case PUMP_E_ARG: return "invalid argument";
+        case PUMP_E_CAPACITY: return "capacity exceeded";
+        case PUMP_E_HIP: return "HIP runtime error";
+        case PUMP_E_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+const char* pump_last_error(const pump_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int pump_destroy(pump_ctx* ctx) {
+    if (!ctx) return PUMP_OK;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    void* ptrs[] = {ctx->X, ctx->valid, ctx->goal, ctx->obs, ctx->noise_buf, ctx->noise_mc_buf,
+                    ctx->D, ctx->cloud, ctx->gcloud, ctx->dev_ints, ctx->ebits, ctx->deg,
+                    ctx->row_ptr, ctx->col, ctx->etau, ctx->ecost, ctx->p_head, ctx->p_parent,
+                    ctx->p_edge, ctx->p_step, ctx->p_pop, ctx->p_round, ctx->p_cost, ctx->p_mask,
+                    ctx->p_state, ctx->stair, ctx->open_a, ctx->open_b, ctx->o_keep, ctx->o_inB,
+                    ctx->b_ids, ctx->b_off, ctx->b_deg, ctx->c_head, ctx->c_parent, ctx->c_edge,
+                    ctx->c_step, ctx->c_pop, ctx->c_pos, ctx->c_cost, ctx->c_mask, ctx->c_flag,
+                    ctx->blk, ctx->ctl, ctx->goal_ids, ctx->front_ids, ctx->paths,
+                    ctx->path_len, ctx->wp_len, ctx->mc_counts, ctx->wp};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (ctx->ctl_h) (void)hipHostFree(ctx->ctl_h);
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return PUMP_OK;
+}
+
+int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
+    if (!out) return PUMP_E_ARG;
+    *out = nullptr;
+    pump_config cfg;
+    if (cfg_in) cfg = *cfg_in; else pump_config_default(&cfg);
+    const int N = cfg.n_particles;
+    if (!(N == 32 || N == 64 || N == 128 || N == 256)) return PUMP_E_ARG;
+    if (cfg.max_nodes < 2 || cfg.max_nodes > 65535) return PUMP_E_ARG;
+    if (cfg.max_obstacles < 0 || cfg.max_obstacles > kMaxObs) return PUMP_E_ARG;
+    if (cfg.max_steps < 1 || cfg.max_steps > 4096 || cfg.mc_particles < 1) return PUMP_E_ARG;
+    if (!(cfg.dt > 0) || !(cfg.r_conn > 0) || !(cfg.lambda > 0) || !(cfg.r_steer > 0) ||
+        !(cfg.r_track > 0) || !(cfg.q_pos >= 0) || !(cfg.q_vel >= 0))
+        return PUMP_E_ARG;
+    if (ceil((double)cfg.r_conn / (double)cfg.dt) > kMaxWaypoints) return PUMP_E_ARG;
+    if (cfg.cap_pairs < 1 || cfg.cap_pairs > (1ll << 26) || cfg.cap_plans < 1 ||
+        cfg.cap_plans > (1ll << 26) || cfg.cap_edges < 1 || cfg.cap_edges > (1ll << 31) - 1)
+        return PUMP_E_ARG;
+    pump_ctx* ctx = new pump_ctx();
+    ctx->cfg = cfg;
+    ctx->N = N;
+    ctx->W = N / 32;
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&ctx->stream) != hipSuccess) { delete ctx; return PUMP_E_HIP; }
+        ctx->own_stream = true;
+    }
+    const size_t nn = (size_t)cfg.max_nodes;
+    const size_t S = (size_t)cfg.max_steps;
+    const size_t M = (size_t)cfg.mc_particles;
+    const size_t P = (size_t)cfg.cap_plans;
+    const size_t Q = (size_t)cfg.cap_pairs;
+    const size_t E = (size_t)cfg.cap_edges;
+    ctx->words_per_row = (int)(((nn + 63) / 64) * 2);
+    bool ok = true;
+    auto A = [&](hipError_t e) { ok = ok && (e == hipSuccess); };
+    A(dalloc(&ctx->X, nn * 6));
+    A(dalloc(&ctx->valid, nn));
+    A(dalloc(&ctx->goal, nn));
+    A(dalloc(&ctx->obs, (size_t)kMaxObs * 6));
+    A(dalloc(&ctx->noise_buf, S * 6 * N));
+    A(dalloc(&ctx->noise_mc_buf, S * 6 * M));
+    A(dalloc(&ctx->D, (S + 1) * 3 * N));
+    A(dalloc(&ctx->cloud, (S + 1) * 6));
+    A(dalloc(&ctx->gcloud, 8));
+    A(dalloc(&ctx->dev_ints, 8));
+    A(dalloc(&ctx->ebits, nn * ctx->words_per_row));
+    A(dalloc(&ctx->deg, nn + 1));
+    A(dalloc(&ctx->row_ptr, nn + 2));
+    A(dalloc(&ctx->col, E));
+    A(dalloc(&ctx->etau, E));
+    A(dalloc(&ctx->ecost, E));
+    A(dalloc(&ctx->p_head, P));
+    A(dalloc(&ctx->p_parent, P));
+    A(dalloc(&ctx->p_edge, P));
+    A(dalloc(&ctx->p_step, P));
+    A(dalloc(&ctx->p_pop, P));
+    A(dalloc(&ctx->p_round, P));
+    A(dalloc(&ctx->p_cost, P));
+    A(dalloc(&ctx->p_mask, P * ctx->W));
+    A(dalloc(&ctx->p_state, P));
+    A(dalloc(&ctx->stair, nn * (N + 1)));
+    A(dalloc(&ctx->open_a, P));
+    A(dalloc(&ctx->open_b, P));
+    A(dalloc(&ctx->o_keep, P));
+    A(dalloc(&ctx->o_inB, P));
+    A(dalloc(&ctx->b_ids, P + 1));
+    A(dalloc(&ctx->b_off, P + 1));
+    A(dalloc(&ctx->b_deg, P + 1));
+    A(dalloc(&ctx->c_head, Q));
+    A(dalloc(&ctx->c_parent, Q));
+    A(dalloc(&ctx->c_edge, Q));
+    A(dalloc(&ctx->c_step, Q));
+    A(dalloc(&ctx->c_pop, Q));
+    A(dalloc(&ctx->c_pos, Q));
+    A(dalloc(&ctx->c_cost, Q));
+    A(dalloc(&ctx->c_mask, Q * ctx->W));
+    A(dalloc(&ctx->c_flag, Q));
+    A(dalloc(&ctx->blk, (size_t)2 * 65536));
+    A(dalloc(&ctx->ctl, 1));
+    A(dalloc(&ctx->goal_ids, (size_t)kMaxGoal));
+    A(dalloc(&ctx->front_ids, (size_t)kMaxFront));
+    A(dalloc(&ctx->paths, (size_t)kMaxFront * (S + 1)));
+    A(dalloc(&ctx->path_len, (size_t)kMaxFront));
+    A(dalloc(&ctx->wp_len, (size_t)kMaxFront));
+    A(dalloc(&ctx->mc_counts, (size_t)kMaxFront));
+    A(dalloc(&ctx->wp, (size_t)kMaxFront * (S + 1) * 3));
+    A(hipHostMalloc((void**)&ctx->ctl_h, sizeof(Ctl), hipHostMallocDefault));
+    for (auto& e : ctx->ev) A(hipEventCreate(&e));
+    if (!ok) {
+        pump_destroy(ctx);
+        return PUMP_E_HIP;
+    }
+    memset(ctx->ctl_h, 0, sizeof(Ctl));
+    *out = ctx;
+    return PUMP_OK;
+}
+
+int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
+    if (!ctx || !pr) return PUMP_E_ARG;
+    ctx->have_setup = ctx->have_explore = ctx->explore_done = false;
+    const pump_config& cfg = ctx->cfg;
+    if (pr->n < 1 || pr->n + 1 > cfg.max_nodes) return fail(ctx, PUMP_E_ARG, "n out of range for max_nodes");
+    if (pr->n_obs < 0 || pr->n_obs > cfg.max_obstacles) return fail(ctx, PUMP_E_ARG, "n_obs exceeds max_obstacles");
+    if (!pr->samples || (pr->n_obs > 0 && !pr->obstacles) || !pr->noise || !pr->noise_mc)
+        return fail(ctx, PUMP_E_ARG, "null input pointer");
+    if (!(pr->alpha > 0.0f && pr->alpha < 1.0f)) return fail(ctx, PUMP_E_ARG, "alpha must lie in (0, 1)");
+    if (!(pr->sigma >= 0.0f) || !std::isfinite(pr->sigma)) return fail(ctx, PUMP_E_ARG, "sigma must be finite and >= 0");
+    if (!finite6(pr->x_init)) return fail(ctx, PUMP_E_ARG, "x_init not finite");
+    for (int k = 0; k < 3; ++k) {
+        if (fabsf(pr->x_init[k]) > 16.0f) return fail(ctx, PUMP_E_ARG, "x_init outside [-16, 16]");
+        if (!(pr->goal.lo[k] <= pr->goal.hi[k])) return fail(ctx, PUMP_E_ARG, "goal box empty");
+    }
+    if (pr->mem != PUMP_MEM_HOST && pr->mem != PUMP_MEM_DEVICE) return fail(ctx, PUMP_E_ARG, "mem flag");
+    const hipMemcpyKind kind = pr->mem == PUMP_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    if (pr->mem == PUMP_MEM_HOST) {
+        for (int o = 0; o < pr->n_obs; ++o) {
+            const pump_aabb& b = pr->obstacles[o];
+            for (int k = 0; k < 3; ++k) {
+                if (!std::isfinite(b.lo[k]) || !std::isfinite(b.hi[k]) || !(b.lo[k] <= b.hi[k]) ||
+                    fabsf(b.lo[k]) > 16.0f || fabsf(b.hi[k]) > 16.0f)
+                    return fail(ctx, PUMP_E_ARG, "obstacle box invalid or outside [-16, 16]");
+            }
+            bool in = true;
+            for (int k = 0; k < 3; ++k) in = in && pr->x_init[k] >= b.lo[k] && pr->x_init[k] <= b.hi[k];
+            if (in) return fail(ctx, PUMP_E_ARG, "x_init lies in an obstacle");
+        }
+    }
+    const int N = ctx->N;
+    ctx->n_nodes = pr->n + 1;
+    ctx->n_obs = pr->n_obs;
+    ctx->M = cfg.mc_particles;
+    ctx->S_max = cfg.max_steps;
+    ctx->dt = (double)cfg.dt;
+    ctx->alpha = (double)pr->alpha;
+    ctx->eta = cfg.eta > 0.0f ? (double)cfg.eta : eta_rule(ctx->alpha);
+    ctx->alpha_min = ctx->alpha / ctx->eta;
+    ctx->alpha_max = ctx->eta * ctx->alpha;
+    // integer forms of the cp_hat tests (pop / N is exact for N a power of 2)
+    ctx->c_cut = (int)std::min<double>(ceil(ctx->alpha_max * N), (double)(N + 1));
+    ctx->c_min = (int)std::min<double>(ceil(ctx->alpha_min * N), (double)(N + 1));
+    ctx->h = (double)cfg.lambda * (double)cfg.r_conn;
+    // tracking constants (eq. (2) for the double integrator; LQR)
+    lqr_axis(ctx->dt, (double)cfg.q_pos, (double)cfg.q_vel, (double)cfg.r_track, ctx->K);
+    const double dt = ctx->dt, s2 = (double)pr->sigma * (double)pr->sigma;
+    const double Bd[2] = {0.5 * dt * dt, dt};
+    ctx->Acl[0] = 1.0 - Bd[0] * ctx->K[0];
+    ctx->Acl[1] = dt - Bd[0] * ctx->K[1];
+    ctx->Acl[2] = -Bd[1] * ctx->K[0];
+    ctx->Acl[3] = 1.0 - Bd[1] * ctx->K[1];
+    const double V00 = s2 * (dt + dt * dt * dt / 3.0), V10 = s2 * (0.5 * dt * dt), V11 = s2 * dt;
+    ctx->L[0] = sqrt(V00);
+    ctx->L[1] = 0.0;
+    ctx->L[2] = ctx->L[0] > 0.0 ? V10 / ctx->L[0] : 0.0;
+    ctx->L[3] = sqrt(std::max(0.0, V11 - ctx->L[2] * ctx->L[2]));
+
+    HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
+    // uploads: x_init is node 0, sample i is node i + 1
+    HIPCHK(hipMemcpyAsync(ctx->X, pr->x_init, 6 * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->X + 6, pr->samples, (size_t)pr->n * 6 * sizeof(float), kind, ctx->stream));
+    if (pr->n_obs > 0)
+        HIPCHK(hipMemcpyAsync(ctx->obs, pr->obstacles, (size_t)pr->n_obs * 6 * sizeof(float), kind, ctx->stream));
+    if (pr->mem == PUMP_MEM_HOST) {
+        HIPCHK(hipMemcpyAsync(ctx->noise_buf, pr->noise, (size_t)ctx->S_max * 6 * N * sizeof(float),
+                              hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(ctx->noise_mc_buf, pr->noise_mc,
+                              (size_t)ctx->S_max * 6 * ctx->M * sizeof(float), hipMemcpyHostToDevice,
+                              ctx->stream));
+        ctx->noise = ctx->noise_buf;
+        ctx->noise_mc = ctx->noise_mc_buf;
+    } else {
+        ctx->noise = pr->noise;
+        ctx->noise_mc = pr->noise_mc;
+    }
+    float gb[6] = {pr->goal.lo[0], pr->goal.lo[1], pr->goal.lo[2],
+                   pr->goal.hi[0], pr->goal.hi[1], pr->goal.hi[2]};
+    launch_deviation_table(ctx->stream, ctx->noise, ctx->D, ctx->cloud, ctx->gcloud, N, ctx->S_max,
+                           ctx->Acl, ctx->L);
+    HIPCHK(hipMemsetAsync(ctx->dev_ints, 0, 8 * sizeof(int32_t), ctx->stream));
+    launch_mark_valid(ctx->stream, ctx->X, ctx->n_nodes, ctx->obs, ctx->n_obs, gb, ctx->valid, ctx->goal,
+                      ctx->dev_ints + 1);
+    HIPCHK(hipMemsetAsync(ctx->deg, 0, (size_t)(ctx->n_nodes + 1) * sizeof(int32_t), ctx->stream));
+    launch_graph_mark(ctx->stream, ctx->X, ctx->valid, ctx->n_nodes, ctx->obs, ctx->n_obs,
+                      (double)cfg.r_steer, (double)cfg.r_conn, ctx->ebits, ctx->deg, ctx->words_per_row);
+    int32_t nn = ctx->n_nodes;
+    HIPCHK(hipMemcpyAsync(ctx->dev_ints, &nn, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    scan_exclusive(ctx->stream, ctx->deg, ctx->row_ptr, ctx->dev_ints, nn, &ctx->ctl->scan_total[4],
+                   ctx->blk);
+    HIPCHK(hipMemcpyAsync(ctx->ctl_h, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+    int32_t flags[2];
+    HIPCHK(hipMemcpyAsync(flags, ctx->dev_ints, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (flags[1] & 1) return fail(ctx, PUMP_E_ARG, "a sample or obstacle is not finite or lies outside [-16, 16]");
+    if (flags[1] & 2) return fail(ctx, PUMP_E_ARG, "x_init lies in an obstacle");
+    ctx->n_edges = ctx->ctl_h->scan_total[4];
+    if ((long long)ctx->n_edges > cfg.cap_edges)
+        return fail(ctx, PUMP_E_CAPACITY, "graph edges " + std::to_string(ctx->n_edges) +
+                                              " exceed cap_edges");
+    HIPCHK(hipMemcpyAsync(ctx->row_ptr + nn, &ctx->n_edges, sizeof(int32_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+    launch_graph_fill(ctx->stream, ctx->X, ctx->n_nodes, (double)cfg.r_steer, ctx->ebits, ctx->row_ptr,
+                      ctx->col, ctx->etau, ctx->ecost, ctx->words_per_row);
+    HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
+    HIPCHK(hipEventSynchronize(ctx->ev[1]));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventElapsedTime(&ctx->ms_setup, ctx->ev[0], ctx->ev[1]));
+    ctx->have_setup = true;
+    return PUMP_OK;
+}
+
+int pump_explore_begin(pump_ctx* ctx) {
+    if (!ctx) return PUMP_E_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUMP_E_STATE, "pump_setup first");
+    ctx->open_cur = ctx->open_b;
+    ctx->open_next = ctx->open_a;
+    RoundArgs a = round_args(ctx);
+    HIPCHK(hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream));
+    launch_explore_init(ctx->stream, a, ctx->n_nodes, ctx->N);  // writes open_next
+    std::swap(ctx->open_cur, ctx->open_next);
+    int r = read_ctl(ctx);
+    if (r) return r;
+    HIPCHK(hipGetLastError());
+    ctx->partial_plans = 0;
+    ctx->rounds = 0;
+    ctx->ms_explore = 0.0f;
+    ctx->have_explore = true;
+    ctx->explore_done = ctx->ctl_h->done != 0;
+    return PUMP_OK;
+}
+
+int pump_explore_round(pump_ctx* ctx, int32_t* done) {
+    if (!ctx) return PUMP_E_ARG;
+    if (!ctx->have_explore) return fail(ctx, PUMP_E_STATE, "pump_explore_begin first");
+    if (ctx->explore_done) {
+        if (done) *done = 1;
+        return PUMP_OK;
+    }
+    const int32_t n_pairs = ctx->ctl_h->n_pairs;
+    const int32_t n_open = ctx->ctl_h->n_open;
+    if ((long long)n_pairs > ctx->cfg.cap_pairs)
+        return fail(ctx, PUMP_E_CAPACITY, "round pairs " + std::to_string(n_pairs) + " exceed cap_pairs");
+    RoundArgs a = round_args(ctx);
+    launch_expand(ctx->stream, a, ctx->N, n_pairs);
+    launch_prune(ctx->stream, a, ctx->N, n_pairs, n_open);
+    launch_compact(ctx->stream, a, ctx->N, n_pairs, n_open, ctx->blk);
+    long long upper = std::min<long long>((long long)n_open + n_pairs, ctx->cfg.cap_plans);
+    launch_next_group(ctx->stream, a, (int32_t)upper, ctx->b_deg, ctx->blk);
+    HIPCHK(hipGetLastError());
+    int r = read_ctl(ctx);
+    if (r) return r;
+    ctx->partial_plans += n_pairs;
+    ctx->last_pairs = n_pairs;
+    ctx->rounds += 1;
+    std::swap(ctx->open_cur, ctx->open_next);
+    if (ctx->ctl_h->err == 3) return fail(ctx, PUMP_E_STATE, "open plans without a finite cost");
+    if (ctx->ctl_h->err)
+        return fail(ctx, PUMP_E_CAPACITY, "plan store exceeds cap_plans");
+    if (ctx->rounds > (1 << 24)) return fail(ctx, PUMP_E_STATE, "Explore did not terminate");
+    ctx->explore_done = ctx->ctl_h->done != 0;
+    if (done) *done = ctx->explore_done ? 1 : 0;
+    return PUMP_OK;
+}
+
+int pump_explore_run(pump_ctx* ctx) {
+    if (!ctx) return PUMP_E_ARG;
+    HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
+    int32_t done = ctx->explore_done ? 1 : 0;
+    while (!done) {
+        int r = pump_explore_round(ctx, &done);
+        if (r) return r;
+    }
+    HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
+    HIPCHK(hipEventSynchronize(ctx->ev[2]));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+    ctx->ms_explore = ms;
+    return PUMP_OK;
+}
+
+static void fill_counters(pump_ctx* ctx, pump_result* o) {
+    const Ctl* c = ctx->ctl_h;
+    o->partial_plans = ctx->partial_plans;
+    o->simulated = c->simulated;
+    o->preprune = c->preprune;
+    o->inserted = c->inserted;
+    o->survivors = c->n_plans - 1;
+    o->dropped_steps = c->dropped_steps;
+    o->flagged = c->flagged;
+    o->rounds = ctx->rounds;
+    o->final_i = c->i;
+    o->n_plans = c->n_plans;
+    o->n_edges = ctx->n_edges;
+    o->c_cut = ctx->c_cut;
+    o->c_min = ctx->c_min;
+    o->ms_setup = ctx->ms_setup;
+    o->ms_explore = ctx->ms_explore;
+    o->ms_select = ctx->ms_select;
+}
+
+int pump_select(pump_ctx* ctx, pump_result* out) {
+    if (!ctx) return PUMP_E_ARG;
+    if (!ctx->have_explore || !ctx->explore_done) return fail(ctx, PUMP_E_STATE, "explore not finished");
+    pump_result res;
+    memset(&res, 0, sizeof(res));
+    res.best = -1;
+    res.best_plan = -1;
+    HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
+    SelectArgs a = select_args(ctx);
+    HIPCHK(hipMemsetAsync(ctx->mc_counts, 0, kMaxFront * sizeof(int32_t), ctx->stream));
+    launch_select_front(ctx->stream, a);
+    int r = read_ctl(ctx);
+    if (r) return r;
+    if (ctx->ctl_h->err == 2) return fail(ctx, PUMP_E_CAPACITY, "Pareto front exceeds 256 plans");
+    if (ctx->ctl_h->n_goal > kMaxGoal) return fail(ctx, PUMP_E_CAPACITY, "P_goal exceeds 65536 plans");
+    const int nf = ctx->ctl_h->n_front;
+    res.n_goal_plans = ctx->ctl_h->n_goal;
+    res.n_front = nf;
+    if (ctx->ctl_h->n_goal == 0) {
+        res.status = PUMP_NO_GOAL_PLAN;
+    } else {
+        launch_waypoints(ctx->stream, a, nf);
+        launch_mc(ctx->stream, a, nf);
+        HIPCHK(hipGetLastError());
+        std::vector<int32_t> ids(nf), mc(nf), wl(nf), plen(nf);
+        HIPCHK(hipMemcpyAsync(ids.data(), ctx->front_ids, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(mc.data(), ctx->mc_counts, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(wl.data(), ctx->wp_len, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(plen.data(), ctx->path_len, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        for (int f = 0; f < nf; ++f)
+            if (wl[f] < 0) return fail(ctx, PUMP_E_STATE, "front plan longer than max_steps");
+        // Alg. 5 bisection (1-based) on MC(P_m) > alpha
+        auto mc_gt = [&](int m) { return (double)mc[m - 1] / (double)ctx->M > ctx->alpha; };
+        int l = 1, u = nf, m = (l + u + 1) / 2;
+        while (l != u) {
+            if (mc_gt(m)) u = m - 1; else l = m;
+            m = (l + u + 1) / 2;
+        }
+        if (mc_gt(m)) {
+            res.status = PUMP_INFEASIBLE;
+        } else {
+            res.status = PUMP_OK;
+            res.best = m - 1;
+            res.best_plan = ids[m - 1];
+            res.best_mc_count = mc[m - 1];
+            res.best_cp_mc = (double)mc[m - 1] / (double)ctx->M;
+            res.best_len = plen[m - 1];
+            HIPCHK(hipMemcpy(&res.best_cost, ctx->p_cost + ids[m - 1], sizeof(double), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(&res.best_pop, ctx->p_pop + ids[m - 1], sizeof(int32_t), hipMemcpyDeviceToHost));
+        }
+    }
+    HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
+    HIPCHK(hipEventSynchronize(ctx->ev[3]));
+    HIPCHK(hipEventElapsedTime(&ctx->ms_select, ctx->ev[2], ctx->ev[3]));
+    fill_counters(ctx, &res);
+    int32_t nv = 0;
+    {
+        std::vector<uint8_t> v(ctx->n_nodes);
+        HIPCHK(hipMemcpy(v.data(), ctx->valid, ctx->n_nodes, hipMemcpyDeviceToHost));
+        for (uint8_t b : v) nv += b;
+    }
+    res.n_valid_nodes = nv;
+    if (out) *out = res;
+    return res.status;
+}
+
+int pump_plan(pump_ctx* ctx, const pump_problem* pr, pump_result* out) {
+    if (!ctx || !pr) return PUMP_E_ARG;
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    HIPCHK(hipEventRecord(t0, ctx->stream));
+    int r = pump_setup(ctx, pr);
+    if (r == PUMP_OK) r = pump_explore_begin(ctx);
+    if (r == PUMP_OK) r = pump_explore_run(ctx);
+    pump_result res;
+    memset(&res, 0, sizeof(res));
+    if (r == PUMP_OK) r = pump_select(ctx, &res);
+    HIPCHK(hipEventRecord(t1, ctx->stream));
+    HIPCHK(hipEventSynchronize(t1));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    res.ms_total = ms;
+    if (out) *out = res;
+    return r;
+}
+
+int pump_get_deviation(pump_ctx* ctx, float* out, int64_t cap) {
+    if (!ctx || !out) return PUMP_E_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUMP_E_STATE, "pump_setup first");
+    size_t n = (size_t)(ctx->S_max + 1) * 3 * ctx->N;
+    if ((int64_t)n > cap) return fail(ctx, PUMP_E_ARG, "output too small");
+    HIPCHK(hipMemcpy(out, ctx->D, n * sizeof(float), hipMemcpyDeviceToHost));
+    return PUMP_OK;
+}
+
+int pump_get_graph(pump_ctx* ctx, int32_t* row_ptr, int32_t* col, double* tau, double* cost,
+                   uint8_t* valid, int64_t cap_edges, int64_t* n_edges) {
+    if (!ctx) return PUMP_E_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUMP_E_STATE, "pump_setup first");
+    if (n_edges) *n_edges = ctx->n_edges;
+    if (row_ptr) HIPCHK(hipMemcpy(row_ptr, ctx->row_ptr, (ctx->n_nodes + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (valid) HIPCHK(hipMemcpy(valid, ctx->valid, ctx->n_nodes, hipMemcpyDeviceToHost));
+    if ((col || tau || cost) && cap_edges < ctx->n_edges) return fail(ctx, PUMP_E_ARG, "output too small");
+    if (col) HIPCHK(hipMemcpy(col, ctx->col, (size_t)ctx->n_edges * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (tau) HIPCHK(hipMemcpy(tau, ctx->etau, (size_t)ctx->n_edges * sizeof(double), hipMemcpyDeviceToHost));
+    if (cost) HIPCHK(hipMemcpy(cost, ctx->ecost, (size_t)ctx->n_edges * sizeof(double), hipMemcpyDeviceToHost));
+    return PUMP_OK;
+}
+
+int pump_get_plans(pump_ctx* ctx, int32_t* head, int32_t* parent, int32_t* edge, double* cost,
+                   int32_t* step, int32_t* pop, int32_t* round, uint8_t* state, uint32_t* mask,
+                   int64_t cap, int64_t* n_plans) {
+    if (!ctx) return PUMP_E_ARG;
+    if (!ctx->have_explore) return fail(ctx, PUMP_E_STATE, "pump_explore_begin first");
+    const size_t n = (size_t)ctx->ctl_h->n_plans;
+    if (n_plans) *n_plans = (int64_t)n;
+    if ((head || parent || edge || cost || step || pop || round || state || mask) && (int64_t)n > cap)
+        return fail(ctx, PUMP_E_ARG, "output too small");
+    if (head) HIPCHK(hipMemcpy(head, ctx->p_head, n * 4, hipMemcpyDeviceToHost));
+    if (parent) HIPCHK(hipMemcpy(parent, ctx->p_parent, n * 4, hipMemcpyDeviceToHost));
+    if (edge) HIPCHK(hipMemcpy(edge, ctx->p_edge, n * 4, hipMemcpyDeviceToHost));
+    if (cost) HIPCHK(hipMemcpy(cost, ctx->p_cost, n * 8, hipMemcpyDeviceToHost));
+    if (step) HIPCHK(hipMemcpy(step, ctx->p_step, n * 4, hipMemcpyDeviceToHost));
+    if (pop) HIPCHK(hipMemcpy(pop, ctx->p_pop, n * 4, hipMemcpyDeviceToHost));
+    if (round) HIPCHK(hipMemcpy(round, ctx->p_round, n * 4, hipMemcpyDeviceToHost));
+    if (state) HIPCHK(hipMemcpy(state, ctx->p_state, n, hipMemcpyDeviceToHost));
+    if (mask) HIPCHK(hipMemcpy(mask, ctx->p_mask, n * ctx->W * 4, hipMemcpyDeviceToHost));
+    return PUMP_OK;
+}
+
+int pump_get_candidates(pump_ctx* ctx, uint8_t* flag, int32_t* pop, int32_t* parent, int32_t* head,
+                        double* cost, uint32_t* mask, int64_t cap, int64_t* n_pairs) {
+    if (!ctx) return PUMP_E_ARG;
+    if (!ctx->have_explore) return fail(ctx, PUMP_E_STATE, "pump_explore_begin first");
+    // the pair count of the round just run is the previous round's n_pairs;
+    // kept as the number the caller saw before the round
+    const int32_t n = ctx->last_pairs;
+    if (n_pairs) *n_pairs = n;
+    if ((int64_t)n > cap && (flag || pop || parent || head || cost || mask))
+        return fail(ctx, PUMP_E_ARG, "output too small");
+    if (flag) HIPCHK(hipMemcpy(flag, ctx->c_flag, (size_t)n, hipMemcpyDeviceToHost));
+    if (pop) HIPCHK(hipMemcpy(pop, ctx->c_pop, (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (parent) HIPCHK(hipMemcpy(parent, ctx->c_parent, (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (head) HIPCHK(hipMemcpy(head, ctx->c_head, (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (cost) HIPCHK(hipMemcpy(cost, ctx->c_cost, (size_t)n * 8, hipMemcpyDeviceToHost));
+    if (mask) HIPCHK(hipMemcpy(mask, ctx->c_mask, (size_t)n * ctx->W * 4, hipMemcpyDeviceToHost));
+    return PUMP_OK;
+}
+
+int pump_get_front(pump_ctx* ctx, int32_t* plan_ids, int32_t* mc_counts, int32_t cap, int32_t* n_front) {
+    if (!ctx) return PUMP_E_ARG;
+    const int nf = ctx->ctl_h->n_front;
+    if (n_front) *n_front = nf;
+    if ((plan_ids || mc_counts) && nf > cap) return fail(ctx, PUMP_E_ARG, "output too small");
+    if (plan_ids && nf) HIPCHK(hipMemcpy(plan_ids, ctx->front_ids, nf * 4, hipMemcpyDeviceToHost));
+    if (mc_counts && nf) HIPCHK(hipMemcpy(mc_counts, ctx->mc_counts, nf * 4, hipMemcpyDeviceToHost));
+    return PUMP_OK;
+}
+
+int pump_get_path(pump_ctx* ctx, int32_t plan, int32_t* nodes, int32_t cap, int32_t* len) {
+    if (!ctx || !nodes || !len) return PUMP_E_ARG;
+    if (!ctx->have_explore) return fail(ctx, PUMP_E_STATE, "pump_explore_begin first");
+    const int n = ctx->ctl_h->n_plans;
+    if (plan < 0 || plan >= n) return fail(ctx, PUMP_E_ARG, "plan id out of range");
+    std::vector<int32_t> par(n), head(n);
+    HIPCHK(hipMemcpy(par.data(), ctx->p_parent, (size_t)n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(head.data(), ctx->p_head, (size_t)n * 4, hipMemcpyDeviceToHost));
+    std::vector<int32_t> rev;
+    for (int q = plan; q >= 0; q = par[q]) {
+        rev.push_back(head[q]);
+        if ((int)rev.size() > n) return fail(ctx, PUMP_E_STATE, "parent cycle");
+    }
+    if ((int)rev.size() > cap) return fail(ctx, PUMP_E_ARG, "output too small");
+    *len = (int32_t)rev.size();
+    for (size_t i = 0; i < rev.size(); ++i) nodes[i] = rev[rev.size() - 1 - i];
+    return PUMP_OK;
+}
+
+int pump_mc_path(pump_ctx* ctx, const int32_t* nodes, int32_t len, int32_t* count) {
+    if (!ctx || !nodes || !count) return PUMP_E_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUMP_E_STATE, "pump_setup first");
+    if (len < 1 || len > ctx->S_max + 1 || nodes[0] != 0) return fail(ctx, PUMP_E_ARG, "bad path");
+    for (int i = 0; i < len; ++i)
+        if (nodes[i] < 0 || nodes[i] >= ctx->n_nodes) return fail(ctx, PUMP_E_ARG, "node out of range");
+    HIPCHK(hipMemcpyAsync(ctx->paths, nodes, (size_t)len * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->path_len, &len, 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->mc_counts, 0, 4, ctx->stream));
+    SelectArgs a = select_args(ctx);
+    launch_waypoints(ctx->stream, a, 1);
+    launch_mc(ctx->stream, a, 1);
+    HIPCHK(hipGetLastError());
+    int32_t wl = 0;
+    HIPCHK(hipMemcpyAsync(&wl, ctx->wp_len, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(count, ctx->mc_counts, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (wl < 0) return fail(ctx, PUMP_E_ARG, "path longer than max_steps");
+    return PUMP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// Internal declarations shared by the libpump translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "pump.h"
+
+namespace pump {
+
+constexpr int kMaxObs = 256;          // obstacle boxes per query
+constexpr int kMaxWaypoints = 32;     // ceil(r_n / dt) bound (u32 waypoint masks)
+constexpr int kScanBlock = 1024;      // items per block in the device-wide scans
+constexpr int kMaxFront = 256;        // Pareto front entries handled by selection
+constexpr int kMaxGoal = 1 << 16;     // goal plans gathered for selection
+// FP32 guard band of the particle test: a particle whose FP32 position is
+// within kGuard of a face is re-tested in FP64 (2^-14, far above the FP32
+// error of a position of magnitude <= 16).
+constexpr float kGuard = 6.103515625e-05f;
+constexpr double kFlagEps = 1e-5;     // face distance counted as a flagged decision
+constexpr double kTauMin = 1e-6;      // connections shorter than this are skipped
+
+enum PlanState : uint8_t { kOpen = 0, kClosed = 1, kRemoved = 2 };
+
+// Device-resident control block of the Explore loop.
+struct Ctl {
+    int32_t n_plans;
+    int32_t n_open;
+    int32_t n_B;
+    int32_t n_pairs;
+    int32_t i;
+    int32_t done;
+    int32_t goal_stop;
+    int32_t err;
+    int32_t n_keep_open;
+    int32_t n_surv;
+    int32_t n_goal;
+    int32_t n_front;
+    unsigned long long min_cost_bits;
+    long long simulated;
+    long long preprune;
+    long long inserted;
+    long long dropped_steps;
+    long long flagged;
+    int32_t scan_total[8];
+};
+
+// Kernel arguments of one Explore round.
+struct RoundArgs {
+    // problem
+    const float* X;            // [n_nodes][6]
+    const uint8_t* goal;       // [n_nodes]
+    const float* obs;          // [n_obs][6]
+    int32_t n_obs;
+    const float* D;            // [S_max+1][3][N]
+    const float* cloud;        // [S_max+1][6] (lo xyz, hi xyz) of D over particles
+    const float* gcloud;       // [6] union of cloud over all steps
+    int32_t S_max;
+    double dt;
+    int32_t c_cut, c_min;
+    double h;                  // lambda * r_n
+    int32_t preprune;
+    // graph
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const double* etau;
+    const double* ecost;
+    // plans
+    int32_t* p_head;
+    int32_t* p_parent;
+    int32_t* p_edge;
+    int32_t* p_step;
+    int32_t* p_pop;
+    int32_t* p_round;
+    double* p_cost;
+    uint32_t* p_mask;
+    uint8_t* p_state;
+    int64_t cap_plans;
+    unsigned long long* stair; // [n_nodes][N+1] min cost with pop <= c (FP64 bits)
+    int32_t stair_w;
+    // open list and group
+    const int32_t* open_in;
+    int32_t* open_out;
+    uint8_t* o_inB;
+    int32_t* o_keep;           // scan input/output over the open list
+    int32_t* b_ids;
+    int32_t* b_off;            // [n_B + 1]
+    // candidates (slot = pair index)
+    int32_t* c_head;
+    int32_t* c_parent;
+    int32_t* c_edge;
+    int32_t* c_step;
+    int32_t* c_pop;
+    double* c_cost;
+    uint32_t* c_mask;
+    uint8_t* c_flag;
+    int32_t* c_pos;            // scan input/output over the pairs
+    Ctl* ctl;
+};
+
+// ---- launchers (kernels_*.hip) ----
+void launch_deviation_table(hipStream_t s, const float* noise, float* D, float* cloud,
+                            float* gcloud, int N, int S_max, const double* Acl,
+                            const double* L);
+void launch_mark_valid(hipStream_t s, const float* X, int n_nodes, const float* obs,
+                       int n_obs, const float* goal_box, uint8_t* valid, uint8_t* goal,
+                       int32_t* bad);
+void launch_graph_mark(hipStream_t s, const float* X, const uint8_t* valid, int n_nodes,
+                       const float* obs, int n_obs, double r_steer, double r_conn,
+                       uint32_t* ebits, int32_t* deg, int words);
+void launch_graph_fill(hipStream_t s, const float* X, int n_nodes, double r_steer,
+                       const uint32_t* ebits, const int32_t* row_ptr, int32_t* col,
+                       double* etau, double* ecost, int words);
+
+void scan_exclusive(hipStream_t s, const int32_t* in, int32_t* out, const int32_t* n_dev,
+                    int32_t n_upper, int32_t* total_dev, int32_t* blk_scratch);
+
+void launch_explore_init(hipStream_t s, const RoundArgs& a, int n_nodes, int N);
+void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs);
+void launch_prune(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, int32_t n_open);
+void launch_compact(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs,
+                    int32_t n_open, int32_t* blk_scratch);
+void launch_next_group(hipStream_t s, const RoundArgs& a, int32_t n_open_upper,
+                       int32_t* deg_scratch, int32_t* blk_scratch);
+
+struct SelectArgs {
+    const float* X;
+    const float* obs;
+    int32_t n_obs;
+    const uint8_t* goal;
+    const int32_t* p_head;
+    const int32_t* p_parent;
+    const int32_t* p_pop;
+    const double* p_cost;
+    const uint8_t* p_state;
+    int32_t n_plans;
+    int32_t* goal_ids;     // [kMaxGoal]
+    int32_t* front_ids;    // [kMaxFront]
+    int32_t* paths;        // [kMaxFront][S_max+1] node sequences
+    int32_t* path_len;     // [kMaxFront]
+    double* wp;            // [kMaxFront][S_max+1][3] nominal waypoints
+    int32_t* wp_len;       // [kMaxFront] steps
+    int32_t* mc_counts;    // [kMaxFront]
+    const float* noise_mc; // [S_max][6][M]
+    int32_t M;
+    int32_t S_max;
+    double dt;
+    double r_steer;
+    double Acl[4];
+    double L[4];
+    Ctl* ctl;
+};
+
+void launch_select_front(hipStream_t s, const SelectArgs& a);
+void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths);
+void launch_mc(hipStream_t s, const SelectArgs& a, int32_t n_paths);
+
+}  // namespace pump

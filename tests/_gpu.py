@@ -1,0 +1,47 @@
+"""Helpers shared by the GPU parity tests (not collected by pytest)."""
+
+from __future__ import annotations
+
+import numpy as np
+
+from paper_1607_06886_amd import _lib, scenes
+
+
+def small_spec(n=150, N=32, sigma=0.02, alpha=0.05, n_obs=3, side=(0.1, 0.3)):
+    return dict(n=n, n_obs=n_obs, side=side, N=N, sigma=sigma, alpha=alpha, indoor=False)
+
+
+def planner_for(sc, **over):
+    kw = dict(n_particles=sc.N, max_nodes=sc.n + 1, max_obstacles=max(sc.n_obs, 1),
+              max_steps=sc.S_max, mc_particles=sc.M, cap_plans=1 << 20, cap_pairs=1 << 22,
+              cap_edges=1 << 24)
+    kw.update(over)
+    return _lib.Planner(**kw)
+
+
+def gpu_plans(pl):
+    st = pl.plans()
+    st["paths"] = _lib.plan_paths(st)
+    return st
+
+
+def unpack_mask(words, N):
+    """uint32 words -> bool[N] (bit j of word j // 32)."""
+    w = np.asarray(words, np.uint32)
+    bits = (w[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1
+    return bits.reshape(-1)[:N].astype(bool)
+
+
+def oracle_mask_bool(packed, N):
+    return np.unpackbits(packed, bitorder="little")[:N].astype(bool)
+
+
+def mask_words_from_bool(m):
+    m = np.asarray(m, bool)
+    pad = (-m.shape[0]) % 32
+    m = np.concatenate([m, np.zeros(pad, bool)]).reshape(-1, 32)
+    return (m.astype(np.uint64) << np.arange(32, dtype=np.uint64)).sum(1).astype(np.uint32)
+
+
+def print_case(name, **kw):
+    print(f"[gpu case] {name} {kw}", flush=True)

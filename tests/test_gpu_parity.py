@@ -1,0 +1,247 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact for particle bitmasks, graph adjacency, plan sets, Pareto fronts,
+the selected plan and Monte Carlo counts; costs and durations within 1e-12
+relative (both sides decide in FP64; the HIP particle test runs in FP32 with
+an FP64 re-test inside a 2^-14 guard band, so its decisions equal the FP64
+ones).  Flagged decisions (a particle within 1e-5 of a face) are counted and
+printed; the tests require exact agreement regardless.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import dynamics, graph as ogr, pump as opump, select as osel
+from paper_1607_06886_amd import _lib, scenes
+from tests._gpu import (gpu_plans, oracle_mask_bool, planner_for, print_case, small_spec,
+                        unpack_mask)
+
+pytestmark = pytest.mark.gpu
+
+CFG = opump.Config()
+REL = 1e-12
+
+
+def _scene(kind, seed):
+    if kind == "cfg1":
+        return scenes.make_scene("cfg1", scenes.workload_seed(1, seed), M=2000, S_max=256)
+    if kind == "boxes20":
+        return scenes.make_scene(small_spec(n=400, N=128, sigma=0.02, alpha=0.01, n_obs=20,
+                                            side=(0.05, 0.25)), 500 + seed, M=2000, S_max=256)
+    if kind == "indoor":
+        return scenes.make_scene(dict(n=450, n_obs=60, side=None, N=128, sigma=0.02, alpha=0.05,
+                                      indoor=True), 700 + seed, M=2000, S_max=256)
+    if kind == "n64":
+        return scenes.make_scene(small_spec(n=250, N=64, sigma=0.03, alpha=0.05, n_obs=8),
+                                 900 + seed, M=2000, S_max=256)
+    if kind == "n256":
+        return scenes.make_scene(small_spec(n=300, N=256, sigma=0.02, alpha=0.02, n_obs=12,
+                                            side=(0.05, 0.25)), 950 + seed, M=2000, S_max=256)
+    raise ValueError(kind)
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle(kind, seed):
+    return opump.run(_scene(kind, seed), CFG, record=True)
+
+
+@pytest.mark.parametrize("N", [32, 64, 128, 256])
+def test_deviation_table(N):
+    print_case("deviation_table", N=N)
+    sc = scenes.make_scene(small_spec(n=20, N=N, sigma=0.02), 11, M=64, S_max=300)
+    pl = planner_for(sc)
+    pl.setup(pl.scene_problem(sc))
+    D = pl.deviation()
+    A_cl, L, _ = dynamics.closed_loop(CFG.dt, sc.sigma, CFG.q_pos, CFG.q_vel, CFG.r_track)
+    Dref = dynamics.deviation_table(A_cl, L, sc.noise, sc.S_max)
+    assert D.shape == Dref.shape
+    diff = D != Dref
+    # FP64 recurrences with independently computed gains may round to a
+    # neighbouring FP32 value in rare entries; states agree far inside 1e-5
+    assert diff.mean() < 1e-4, diff.sum()
+    np.testing.assert_allclose(D, Dref, rtol=0, atol=1e-5 * max(1.0, float(np.abs(Dref).max())))
+    ulp = np.abs(D.view(np.int32)[diff].astype(np.int64) - Dref.view(np.int32)[diff])
+    assert ulp.size == 0 or ulp.max() <= 1
+    pl.close()
+
+
+@pytest.mark.parametrize("kind,seed", [("cfg1", 0), ("boxes20", 1), ("indoor", 2)])
+def test_graph(kind, seed):
+    print_case("graph", kind=kind, seed=seed)
+    sc = _scene(kind, seed)
+    pl = planner_for(sc)
+    pl.setup(pl.scene_problem(sc))
+    g = pl.graph(sc.n + 1)
+    V = np.concatenate([sc.x_init[None], sc.samples]).astype(np.float64)
+    ref = ogr.build_graph(V, sc.obstacles, CFG.r_conn, CFG.r_steer)
+    np.testing.assert_array_equal(g["valid"], ref["valid"])
+    np.testing.assert_array_equal(g["row_ptr"], ref["row_ptr"])
+    np.testing.assert_array_equal(g["col"], ref["col"])
+    np.testing.assert_allclose(g["tau"], ref["tau"], rtol=REL)
+    np.testing.assert_allclose(g["cost"], ref["cost"], rtol=REL)
+    assert g["col"].shape[0] > 1000
+    pl.close()
+
+
+def _compare_end_state(pl, ref, sc):
+    st = gpu_plans(pl)
+    N = sc.N
+    alive = st["state"] != 2
+    gpu_P = {st["paths"][p]: p for p in np.nonzero(alive)[0]}
+    ref_P = {ref["plans"][q].nodes: ref["plans"][q] for ids in ref["P"].values() for q in ids}
+    assert set(gpu_P) == set(ref_P)
+    for nodes, p in gpu_P.items():
+        rp = ref_P[nodes]
+        assert abs(st["cost"][p] - rp.cost) <= REL * max(1.0, rp.cost)
+        assert st["pop"][p] == rp.pop
+        assert st["step"][p] == rp.step
+        np.testing.assert_array_equal(unpack_mask(st["mask"][p], N), rp.mask)
+    # plans created per group index
+    by_round = {}
+    for p in range(1, st["head"].shape[0]):
+        by_round.setdefault(int(st["round"][p]), set()).add(st["paths"][p])
+    for snap in ref["rounds"]:
+        assert by_round.get(snap["i"], set()) == set(snap["survivors"]), snap["i"]
+    return st
+
+
+@pytest.mark.parametrize("preprune", [0, 1])
+@pytest.mark.parametrize("kind,seed", [("cfg1", 0), ("cfg1", 3), ("boxes20", 1), ("n64", 4),
+                                       ("n256", 5), ("indoor", 2)])
+def test_plan_end_to_end(kind, seed, preprune):
+    print_case("plan", kind=kind, seed=seed, preprune=preprune)
+    sc = _scene(kind, seed)
+    ref = _oracle(kind, seed)
+    pl = planner_for(sc, preprune=preprune)
+    res = pl.plan(pl.scene_problem(sc))
+    print("  gpu", {k: res[k] for k in ("status", "partial_plans", "simulated", "preprune",
+                                        "rounds", "flagged", "ms_total")},
+          "oracle flagged", ref["stats"]["flagged_particles"], flush=True)
+    assert res["partial_plans"] == ref["stats"]["partial_plans"]
+    assert res["rounds"] == ref["stats"]["rounds"]
+    assert res["final_i"] == ref["stats"]["final_i"]
+    assert res["dropped_steps"] == ref["stats"]["dropped_steps"]
+    if preprune == 0:
+        assert res["inserted"] == ref["stats"]["inserted"]
+        assert res["flagged"] == ref["stats"]["flagged_particles"]
+    st = _compare_end_state(pl, ref, sc)
+    assert res["status"] == ref["status"]
+    assert res["n_goal_plans"] == len(ref["goal_plans"])
+    ids, mc = pl.front()
+    assert [st["paths"][p] for p in ids] == [p.nodes for p in ref["front"]]
+    for m, cnt in ref["evals"].items():
+        assert mc[m - 1] == cnt[0]
+    if ref["status"] == 0:
+        assert pl.path(res["best_plan"]) == ref["best"].nodes
+        assert res["best_pop"] == ref["best"].pop
+        assert abs(res["best_cost"] - ref["best"].cost) <= REL * ref["best"].cost
+        k = ref["front"].index(ref["best"]) + 1
+        assert res["best_mc_count"] == ref["evals"][k][0]
+    pl.close()
+
+
+def test_rounds_candidate_by_candidate():
+    """Round by round with pre-pruning off: every formed pair's particle
+    count, and every kept pair's cost and bits, equal the oracle's."""
+    print_case("rounds", kind="cfg1", seed=0)
+    sc = _scene("cfg1", 0)
+    ref = _oracle("cfg1", 0)
+    snaps = [s for s in ref["rounds"] if s["B"]]
+    pl = planner_for(sc, preprune=0)
+    pl.setup(pl.scene_problem(sc))
+    pl.explore_begin()
+    done = False
+    r = 0
+    while not done:
+        done = pl.explore_round()
+        cand = pl.candidates()
+        st = gpu_plans(pl)
+        snap = snaps[r]
+        assert cand["flag"].shape[0] == snap["pairs"]
+        seen = set()
+        for q in range(cand["flag"].shape[0]):
+            nodes = st["paths"][cand["parent"][q]] + (int(cand["head"][q]),)
+            seen.add(nodes)
+            cost, pop, packed = snap["pairs_all"][nodes]
+            assert cand["pop"][q] == pop, (r, nodes)
+            if cand["flag"][q]:
+                assert abs(cand["cost"][q] - cost) <= REL * max(1.0, cost)
+                np.testing.assert_array_equal(unpack_mask(cand["mask"][q], sc.N),
+                                              oracle_mask_bool(packed, sc.N))
+        assert seen == set(snap["pairs_all"])
+        r += 1
+    assert r == len(snaps)
+    pl.close()
+
+
+def test_mc_on_given_paths():
+    print_case("mc_path")
+    sc = _scene("cfg1", 0)
+    ref = _oracle("cfg1", 0)
+    pl = planner_for(sc)
+    pl.setup(pl.scene_problem(sc))
+    V = ref["V"]
+    rng = np.random.default_rng(5)
+    plans = [p for p in ref["plans"] if len(p.nodes) >= 3]
+    picks = [plans[i] for i in rng.choice(len(plans), 12, replace=False)]
+    for p in picks:
+        c_ref = osel.mc_count(V, p.nodes, sc.obstacles, ref["A_cl"], ref["L"], sc.noise_mc,
+                              CFG.r_steer, CFG.dt)
+        assert pl.mc_path(p.nodes) == c_ref, p.nodes
+    pl.close()
+
+
+def test_mc_near_obstacle_counts():
+    """A path that grazes a box: a substantial count, equal to the oracle's."""
+    print_case("mc_near")
+    samples = np.array([[0.9, 0.5, 0.5, 0.0, 0.0, 0.0]], np.float32)
+    boxes = np.array([[0.45, 0.515, 0.0, 0.55, 0.8, 1.0]], np.float32)
+    rng = np.random.default_rng(8)
+    N, M, S = 32, 4000, 64
+    noise = rng.standard_normal((S, 6, N), dtype=np.float32)
+    noise_mc = rng.standard_normal((S, 6, M), dtype=np.float32)
+    x0 = np.array([0.1, 0.5, 0.5, 0, 0, 0], np.float32)
+    pl = _lib.Planner(n_particles=N, max_nodes=2, max_obstacles=1, max_steps=S, mc_particles=M,
+                      cap_plans=1024, cap_pairs=1024, cap_edges=1024, r_conn=1.5)
+    pl.setup(pl.problem(samples, boxes, x0, [0.8, 0.4, 0.4, 1, 0.6, 0.6], 0.05, 0.02, noise,
+                        noise_mc))
+    got = pl.mc_path([0, 1])
+    V = np.concatenate([x0[None], samples]).astype(np.float64)
+    A_cl, L, _ = dynamics.closed_loop(CFG.dt, float(np.float32(0.02)), CFG.q_pos, CFG.q_vel,
+                                      CFG.r_track)
+    want = osel.mc_count(V, (0, 1), boxes, A_cl, L, noise_mc, CFG.r_steer, CFG.dt)
+    assert want > 100
+    assert got == want
+    pl.close()
+
+
+def test_determinism():
+    print_case("determinism")
+    sc = _scene("boxes20", 1)
+    pl = planner_for(sc)
+    pr = pl.scene_problem(sc)
+    a = pl.plan(pr)
+    sa = pl.plans()
+    b = pl.plan(pr)
+    sb = pl.plans()
+    for k in ("status", "partial_plans", "best_plan", "best_cost", "best_mc_count", "n_plans"):
+        assert a[k] == b[k]
+    for k in sa:
+        np.testing.assert_array_equal(sa[k], sb[k])
+    pl.close()
+
+
+def test_device_inputs_match_host_inputs():
+    print_case("device_inputs")
+    sc = _scene("cfg1", 3)
+    pl = planner_for(sc)
+    a = pl.plan(pl.scene_problem(sc))
+    sa = pl.plans()
+    b = pl.plan(pl.scene_problem(sc, device=True))
+    sb = pl.plans()
+    assert a["best_plan"] == b["best_plan"] and a["best_cost"] == b["best_cost"]
+    for k in sa:
+        np.testing.assert_array_equal(sa[k], sb[k])
+    pl.close()
