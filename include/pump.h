@@ -205,6 +205,20 @@ int pump_get_path(pump_ctx* ctx, int32_t plan, int32_t* nodes, int32_t cap, int3
  * number of the M certification particles whose path meets an obstacle. */
 int pump_mc_path(pump_ctx* ctx, const int32_t* nodes, int32_t len, int32_t* count);
 
+/* Per-kernel timing.  When on, every launch of the kernels below is
+ * bracketed by HIP events on the context's stream and the elapsed times are
+ * accumulated per kind:
+ *   0 deviation table   1 graph pass 1 (all pairs)   2 graph pass 2 (fill)
+ *   3 expand            4 prune (staircase update + mark)
+ *   5 compact (scans + scatter)   6 next group (min, flags, scans)
+ *   7 front selection   8 MC certification
+ * pump_set_timing(ctx, on) switches it and clears the totals;
+ * pump_get_timing copies min(n, PUMP_TIMING_KINDS) totals (ms) and launch
+ * counts (either pointer may be NULL). */
+#define PUMP_TIMING_KINDS 9
+int pump_set_timing(pump_ctx* ctx, int32_t on);
+int pump_get_timing(pump_ctx* ctx, double* ms, int64_t* launches, int32_t n);
+
 /* Status text for a code, and the last error message of a context. */
 const char* pump_status_str(int status);
 const char* pump_last_error(const pump_ctx* ctx);

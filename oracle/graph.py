@@ -147,39 +147,44 @@ def trajectory_hits_boxes(coef, tau, boxes):
     return hit
 
 
+def graph_rows(V, valid, obstacles, r_n, r_u, rows):
+    """N(v) for the source nodes `rows` (Alg. 3 inner loop): returns flat
+    arrays (src, dst, tau, cost), each row's neighbours ascending."""
+    V = np.asarray(V, np.float64)
+    ids = np.nonzero(valid)[0]
+    vs = np.asarray([v for v in rows if valid[v]], np.int64)
+    src = np.repeat(vs, ids.shape[0])
+    dst = np.tile(ids, vs.shape[0])
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    tau, c = st.steer(V[src], V[dst], r_u)
+    near = (c < r_n) & (tau > TAU_MIN)
+    src, dst, tau, c = src[near], dst[near], tau[near], c[near]
+    if src.shape[0]:
+        coef = st.hermite(V[src], V[dst], tau)
+        free = ~trajectory_hits_boxes(coef, tau, obstacles)
+        src, dst, tau, c = src[free], dst[free], tau[free], c[free]
+    return src, dst, tau, c
+
+
 def build_graph(V, obstacles, r_n, r_u, chunk=1 << 18):
     """Alg. 3.  V: [n+1, 6] states with V[0] = x_init.
 
     Returns CSR arrays (row_ptr, col, tau, cost) of the out-neighbour lists,
     each row sorted by neighbour index, and `valid` [n+1] (sample not in an
-    obstacle).  All ordered pairs are evaluated in chunks of rows."""
+    obstacle).  All ordered pairs are evaluated, a chunk of rows at a time."""
     V = np.asarray(V, np.float64)
     nv = V.shape[0]
     valid = ~points_in_boxes(V[:, :3], obstacles)
     ids = np.nonzero(valid)[0]
     rows_per = max(1, chunk // max(1, ids.shape[0]))
-    cols, taus, costs, srcs = [], [], [], []
-    for r0 in range(0, ids.shape[0], rows_per):
-        vs = ids[r0:r0 + rows_per]
-        src = np.repeat(vs, ids.shape[0])
-        dst = np.tile(ids, vs.shape[0])
-        keep = src != dst
-        src, dst = src[keep], dst[keep]
-        tau, c = st.steer(V[src], V[dst], r_u)
-        near = (c < r_n) & (tau > TAU_MIN)
-        src, dst, tau, c = src[near], dst[near], tau[near], c[near]
-        if src.shape[0]:
-            coef = st.hermite(V[src], V[dst], tau)
-            free = ~trajectory_hits_boxes(coef, tau, obstacles)
-            src, dst, tau, c = src[free], dst[free], tau[free], c[free]
-        srcs.append(src)
-        cols.append(dst)
-        taus.append(tau)
-        costs.append(c)
-    src = np.concatenate(srcs) if srcs else np.zeros(0, np.int64)
-    col = np.concatenate(cols) if cols else np.zeros(0, np.int64)
-    tau = np.concatenate(taus) if taus else np.zeros(0)
-    cost = np.concatenate(costs) if costs else np.zeros(0)
+    parts = [graph_rows(V, valid, obstacles, r_n, r_u, ids[r0:r0 + rows_per])
+             for r0 in range(0, ids.shape[0], rows_per)]
+    if parts:
+        src, col, tau, cost = (np.concatenate([p[k] for p in parts]) for k in range(4))
+    else:
+        src, col, tau, cost = (np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0),
+                               np.zeros(0))
     order = np.lexsort((col, src))
     src, col, tau, cost = src[order], col[order], tau[order], cost[order]
     row_ptr = np.zeros(nv + 1, np.int64)

@@ -78,8 +78,11 @@ _LIB = None
 EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "pump_setup",
            "pump_explore_begin", "pump_explore_round", "pump_explore_run", "pump_select",
            "pump_get_deviation", "pump_get_graph", "pump_get_plans", "pump_get_candidates",
-           "pump_get_front", "pump_get_path", "pump_mc_path", "pump_status_str",
-           "pump_last_error"]
+           "pump_get_front", "pump_get_path", "pump_mc_path", "pump_set_timing",
+           "pump_get_timing", "pump_status_str", "pump_last_error"]
+
+TIMING_KINDS = ["deviation", "graph_mark", "graph_fill", "expand", "prune", "compact",
+                "next_group", "select_front", "mc"]
 
 
 def load(path: Optional[str] = None):
@@ -90,6 +93,13 @@ def load(path: Optional[str] = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise FileNotFoundError(f"{p} is not built; run __graft_entry__.build()")
+    # Load torch's HIP runtime first so libpump binds to the same runtime
+    # instance (same soname); device pointers and streams from torch are then
+    # valid in the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(p)
     P = ctypes.POINTER
     sig = {
@@ -109,6 +119,8 @@ def load(path: Optional[str] = None):
         "pump_get_front": (_i32, [_p, _p, _p, _i32, P(_i32)]),
         "pump_get_path": (_i32, [_p, _i32, _p, _i32, P(_i32)]),
         "pump_mc_path": (_i32, [_p, _p, _i32, P(_i32)]),
+        "pump_set_timing": (_i32, [_p, _i32]),
+        "pump_get_timing": (_i32, [_p, _p, _p, _i32]),
         "pump_status_str": (ctypes.c_char_p, [_i32]),
         "pump_last_error": (ctypes.c_char_p, [_p]),
     }
@@ -309,6 +321,16 @@ class Planner:
         self._check(self.lib.pump_get_path(self.ctx, int(plan), buf.ctypes.data, cap,
                                            ctypes.byref(ln)))
         return tuple(int(v) for v in buf[:ln.value])
+
+    def set_timing(self, on: bool):
+        self._check(self.lib.pump_set_timing(self.ctx, 1 if on else 0))
+
+    def timing(self) -> dict:
+        n = len(TIMING_KINDS)
+        ms = np.zeros(n, np.float64)
+        cnt = np.zeros(n, np.int64)
+        self._check(self.lib.pump_get_timing(self.ctx, ms.ctypes.data, cnt.ctypes.data, n))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(TIMING_KINDS)}
 
     def mc_path(self, nodes):
         nd = np.ascontiguousarray(np.asarray(nodes, np.int32))

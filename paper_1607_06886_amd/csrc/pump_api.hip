@@ -76,6 +76,13 @@ struct pump_ctx {
     float ms_setup = 0, ms_explore = 0, ms_select = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::string err;
+    // per-kernel timing
+    bool timing = false;
+    double t_ms[PUMP_TIMING_KINDS] = {0};
+    long long t_n[PUMP_TIMING_KINDS] = {0};
+    struct Pend { int kind; hipEvent_t a, b; };
+    std::vector<Pend> pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
 };
 
 namespace {
@@ -224,9 +231,43 @@ SelectArgs select_args(pump_ctx* c) {
     return a;
 }
 
+// Timing brackets: tbeg/tend around a launch group when timing is on.
+void tbeg(pump_ctx* c, int kind) {
+    if (!c->timing) return;
+    if (c->pool.empty()) {
+        hipEvent_t a = nullptr, b = nullptr;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        c->pool.push_back({a, b});
+    }
+    auto pr = c->pool.back();
+    c->pool.pop_back();
+    (void)hipEventRecord(pr.first, c->stream);
+    c->pending.push_back({kind, pr.first, pr.second});
+}
+
+void tend(pump_ctx* c) {
+    if (!c->timing || c->pending.empty()) return;
+    (void)hipEventRecord(c->pending.back().b, c->stream);
+}
+
+// After a stream synchronisation: accumulate the finished brackets.
+void tresolve(pump_ctx* c) {
+    for (auto& p : c->pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->t_ms[p.kind] += ms;
+            c->t_n[p.kind] += 1;
+        }
+        c->pool.push_back({p.a, p.b});
+    }
+    c->pending.clear();
+}
+
 int read_ctl(pump_ctx* ctx) {
     HIPCHK(hipMemcpyAsync(ctx->ctl_h, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    tresolve(ctx);
     return PUMP_OK;
 }
 
@@ -294,6 +335,11 @@ int pump_destroy(pump_ctx* ctx) {
     if (ctx->ctl_h) (void)hipHostFree(ctx->ctl_h);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& p : ctx->pending) ctx->pool.push_back({p.a, p.b});
+    for (auto& p : ctx->pool) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return PUMP_OK;
@@ -475,14 +521,18 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
     }
     float gb[6] = {pr->goal.lo[0], pr->goal.lo[1], pr->goal.lo[2],
                    pr->goal.hi[0], pr->goal.hi[1], pr->goal.hi[2]};
+    tbeg(ctx, 0);
     launch_deviation_table(ctx->stream, ctx->noise, ctx->D, ctx->cloud, ctx->gcloud, N, ctx->S_max,
                            ctx->Acl, ctx->L);
+    tend(ctx);
     HIPCHK(hipMemsetAsync(ctx->dev_ints, 0, 8 * sizeof(int32_t), ctx->stream));
     launch_mark_valid(ctx->stream, ctx->X, ctx->n_nodes, ctx->obs, ctx->n_obs, gb, ctx->valid, ctx->goal,
                       ctx->dev_ints + 1);
     HIPCHK(hipMemsetAsync(ctx->deg, 0, (size_t)(ctx->n_nodes + 1) * sizeof(int32_t), ctx->stream));
+    tbeg(ctx, 1);
     launch_graph_mark(ctx->stream, ctx->X, ctx->valid, ctx->n_nodes, ctx->obs, ctx->n_obs,
                       (double)cfg.r_steer, (double)cfg.r_conn, ctx->ebits, ctx->deg, ctx->words_per_row);
+    tend(ctx);
     int32_t nn = ctx->n_nodes;
     HIPCHK(hipMemcpyAsync(ctx->dev_ints, &nn, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
     scan_exclusive(ctx->stream, ctx->deg, ctx->row_ptr, ctx->dev_ints, nn, &ctx->ctl->scan_total[4],
@@ -499,10 +549,13 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
                                               " exceed cap_edges");
     HIPCHK(hipMemcpyAsync(ctx->row_ptr + nn, &ctx->n_edges, sizeof(int32_t), hipMemcpyHostToDevice,
                           ctx->stream));
+    tbeg(ctx, 2);
     launch_graph_fill(ctx->stream, ctx->X, ctx->n_nodes, (double)cfg.r_steer, ctx->ebits, ctx->row_ptr,
                       ctx->col, ctx->etau, ctx->ecost, ctx->words_per_row);
+    tend(ctx);
     HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev[1]));
+    tresolve(ctx);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventElapsedTime(&ctx->ms_setup, ctx->ev[0], ctx->ev[1]));
     ctx->have_setup = true;
@@ -541,11 +594,19 @@ int pump_explore_round(pump_ctx* ctx, int32_t* done) {
     if ((long long)n_pairs > ctx->cfg.cap_pairs)
         return fail(ctx, PUMP_E_CAPACITY, "round pairs " + std::to_string(n_pairs) + " exceed cap_pairs");
     RoundArgs a = round_args(ctx);
+    tbeg(ctx, 3);
     launch_expand(ctx->stream, a, ctx->N, n_pairs);
+    tend(ctx);
+    tbeg(ctx, 4);
     launch_prune(ctx->stream, a, ctx->N, n_pairs, n_open);
+    tend(ctx);
+    tbeg(ctx, 5);
     launch_compact(ctx->stream, a, ctx->N, n_pairs, n_open, ctx->blk);
+    tend(ctx);
     long long upper = std::min<long long>((long long)n_open + n_pairs, ctx->cfg.cap_plans);
+    tbeg(ctx, 6);
     launch_next_group(ctx->stream, a, (int32_t)upper, ctx->b_deg, ctx->blk);
+    tend(ctx);
     HIPCHK(hipGetLastError());
     int r = read_ctl(ctx);
     if (r) return r;
@@ -608,7 +669,9 @@ int pump_select(pump_ctx* ctx, pump_result* out) {
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
     SelectArgs a = select_args(ctx);
     HIPCHK(hipMemsetAsync(ctx->mc_counts, 0, kMaxFront * sizeof(int32_t), ctx->stream));
+    tbeg(ctx, 7);
     launch_select_front(ctx->stream, a);
+    tend(ctx);
     int r = read_ctl(ctx);
     if (r) return r;
     if (ctx->ctl_h->err == 2) return fail(ctx, PUMP_E_CAPACITY, "Pareto front exceeds 256 plans");
@@ -620,7 +683,9 @@ int pump_select(pump_ctx* ctx, pump_result* out) {
         res.status = PUMP_NO_GOAL_PLAN;
     } else {
         launch_waypoints(ctx->stream, a, nf);
+        tbeg(ctx, 8);
         launch_mc(ctx->stream, a, nf);
+        tend(ctx);
         HIPCHK(hipGetLastError());
         std::vector<int32_t> ids(nf), mc(nf), wl(nf), plen(nf);
         HIPCHK(hipMemcpyAsync(ids.data(), ctx->front_ids, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
@@ -628,6 +693,7 @@ int pump_select(pump_ctx* ctx, pump_result* out) {
         HIPCHK(hipMemcpyAsync(wl.data(), ctx->wp_len, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipMemcpyAsync(plen.data(), ctx->path_len, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
+        tresolve(ctx);
         for (int f = 0; f < nf; ++f)
             if (wl[f] < 0) return fail(ctx, PUMP_E_STATE, "front plan longer than max_steps");
         // Alg. 5 bisection (1-based) on MC(P_m) > alpha
@@ -686,6 +752,26 @@ int pump_plan(pump_ctx* ctx, const pump_problem* pr, pump_result* out) {
     res.ms_total = ms;
     if (out) *out = res;
     return r;
+}
+
+int pump_set_timing(pump_ctx* ctx, int32_t on) {
+    if (!ctx) return PUMP_E_ARG;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    tresolve(ctx);
+    ctx->timing = on != 0;
+    for (int k = 0; k < PUMP_TIMING_KINDS; ++k) { ctx->t_ms[k] = 0.0; ctx->t_n[k] = 0; }
+    return PUMP_OK;
+}
+
+int pump_get_timing(pump_ctx* ctx, double* ms, int64_t* launches, int32_t n) {
+    if (!ctx || n < 0) return PUMP_E_ARG;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    tresolve(ctx);
+    for (int k = 0; k < n && k < PUMP_TIMING_KINDS; ++k) {
+        if (ms) ms[k] = ctx->t_ms[k];
+        if (launches) launches[k] = ctx->t_n[k];
+    }
+    return PUMP_OK;
 }
 
 int pump_get_deviation(pump_ctx* ctx, float* out, int64_t cap) {
