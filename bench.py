@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--batch-queries", type=int, default=256,
+                    help="queries in the batched-engine leg (0 skips the leg)")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--tune-queries", type=int, default=32)
     return ap.parse_args()
 
 
@@ -117,6 +121,73 @@ def cpu_baseline(seconds):
                    f"({t_ex:.1f} s); BuildGraph rows for the same heads: "
                    f"{graph_pairs} pairs in {t1 - t0:.1f} s = {graph_pairs / (t1 - t0):.3g} pairs/s"),
         "graph_pairs_per_s": graph_pairs / (t1 - t0),
+    }
+
+
+def batched_inputs(q, seed, S_max=512, M=10_000):
+    """q uneven queries (scenes.batch_specs) with device-resident inputs; the
+    particle noise is drawn on the device from a per-query seed."""
+    import torch
+
+    from paper_1607_06886_amd import scenes
+    specs = scenes.batch_specs(seed, q)
+    g = torch.Generator(device="cuda")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = []
+    for i, sp in enumerate(specs):
+        qs = scenes.workload_seed(4, 1000 * seed + i)
+        x0, goal, boxes, smp = scenes.batch_map(sp, qs)
+        g.manual_seed(qs)
+        noise = torch.randn((S_max, 6, sp["N"]), generator=g, device="cuda")
+        noise_mc = torch.randn((S_max, 6, M), generator=g, device="cuda")
+        out.append((dev(smp), dev(boxes), x0, goal, float(np.float32(sp["alpha"])),
+                    float(np.float32(sp["sigma"])), noise, noise_mc))
+    return specs, out
+
+
+def batched_leg(q, seed, steps, tune_q, S_max=512, M=10_000):
+    """The batched engine on q uneven queries: the autotuner picks the
+    persistent kernel's shape on the first tune_q queries, then whole batches
+    are timed (device inputs resident, one graph launch per batch)."""
+    import torch
+
+    from paper_1607_06886_amd import _lib
+    specs, queries = batched_inputs(q, seed, S_max, M)
+    b = _lib.Batch(q, n_particles=256, max_nodes=max(s["n"] for s in specs) + 1,
+                   max_obstacles=60, max_steps=S_max, mc_particles=M, cap_plans=1 << 20,
+                   cap_pairs=1 << 21, cap_edges=1 << 22)
+    t0 = time.perf_counter()
+    best, tune_ms = b.tune(queries[:tune_q])
+    t_tune = time.perf_counter() - t0
+    best["use_graph"] = 1
+    res = b.plan(queries, tuning=best)          # warm-up (and the reference results)
+    times = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r = b.plan(queries, tuning=best)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ta)
+        assert [x["partial_plans"] for x in r] == [x["partial_plans"] for x in res]
+    b.close()
+    total = sum(times)
+    pairs = sum(x["partial_plans"] for x in res)
+    st = [x["status"] for x in res]
+    return {
+        "workload": f"{q} queries: samples U{{1000..8000}}, particles {{64,128,256}}, "
+                    "boxes U{5..60} (sides U[0.05,0.25]), alpha {0.01,0.05}, sigma 0.02, "
+                    f"M {M}, S_max {S_max}",
+        "queries": q,
+        "steps": steps,
+        "ms_per_batch": 1e3 * total / steps,
+        "queries_per_s": q * steps / total,
+        "partial_plans_per_s": pairs * steps / total,
+        "partial_plans_per_batch": pairs,
+        "status_counts": {str(k): st.count(k) for k in sorted(set(st))},
+        "tuning": best,
+        "tune_queries": tune_q,
+        "tune_best_ms": tune_ms,
+        "tune_s": t_tune,
     }
 
 
@@ -202,9 +273,12 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
         "roofline": roofline,
     }
+    pl.close()
+    if args.batch_queries > 0:
+        line["batched"] = batched_leg(args.batch_queries, args.seed, args.batch_steps,
+                                      min(args.tune_queries, args.batch_queries))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
-    pl.close()
     print(json.dumps(line), flush=True)
 
 

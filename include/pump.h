@@ -219,6 +219,104 @@ int pump_mc_path(pump_ctx* ctx, const int32_t* nodes, int32_t len, int32_t* coun
 int pump_set_timing(pump_ctx* ctx, int32_t on);
 int pump_get_timing(pump_ctx* ctx, double* ms, int64_t* launches, int32_t n);
 
+/* ---------------------------------------------------------------------------
+ * Learned sampling proposal.  The paper draws SampleFree(n) uniformly (Alg. 3;
+ * Halton in Sec. V-A); a learned proposal only changes that sample set (half
+ * learned, half uniform), and every plan is still certified by MC(p) in
+ * Alg. 5.  Network: condition vector of 396 floats (start state 6, goal box
+ * centre 3 and half-size 3, then up to 64 obstacle boxes as lo xyz, hi xyz,
+ * zero padded) -> 4 hidden layers of 256 with ReLU -> 208 outputs: 16 mixture
+ * logits, then 16 x 6 means, then 16 x 6 log standard deviations (clamped to
+ * [-7, 2]) of a diagonal Gaussian mixture over the 6-D state.  Weights are
+ * kept as FP32 masters with BF16 copies; matrix products take BF16 operands
+ * with FP32 accumulation.  Parameters are one flat FP32 array: for each layer
+ * W [out][in] row-major, then b [out].
+ * Array arguments are host or device memory as `mem` says; every call returns
+ * after its device work has finished.  Errors: PUMP_E_ARG (sizes), PUMP_E_HIP.
+ * ------------------------------------------------------------------------- */
+typedef struct pump_mlp pump_mlp;
+#define PUMP_MLP_IN  396
+#define PUMP_MLP_OUT 208
+
+/* Create a network workspace for batches up to max_batch rows. */
+int pump_mlp_create(int32_t max_batch, void* hip_stream, pump_mlp** out);
+int pump_mlp_destroy(pump_mlp* m);
+/* Number of parameters (352464). */
+int pump_mlp_num_params(void);
+/* Load FP32 parameters from the host (resets the Adam moments) / read them. */
+int pump_mlp_set_params(pump_mlp* m, const float* params, int64_t n);
+int pump_mlp_get_params(pump_mlp* m, float* params, int64_t n);
+/* out [B][208] = network outputs for cond [B][396]. */
+int pump_mlp_forward(pump_mlp* m, const float* cond, int32_t B, float* out, int32_t mem);
+/* Mean mixture negative log-likelihood of target states [B][6] and its
+ * gradient (flat, same layout as the parameters; grads may be NULL). */
+int pump_mlp_loss_grad(pump_mlp* m, const float* cond, const float* target, int32_t B,
+                       float* loss, float* grads, int32_t mem);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean NLL of the batch. */
+int pump_mlp_train_step(pump_mlp* m, const float* cond, const float* target, int32_t B,
+                        float lr, float* loss, int32_t mem);
+/* Condition vectors [q][396] from device arrays: x_init [q][6], goal boxes
+ * [q][6] (lo xyz, hi xyz), boxes [q][max_boxes_in][6], n_obs [q]. */
+int pump_mlp_condition(pump_mlp* m, const float* x_init, const float* goal, const float* boxes,
+                       const int32_t* n_obs, int32_t q, int32_t max_boxes_in, float* cond);
+/* n draws per query from the mixture: the component is chosen by inverse CDF
+ * of softmax(logits) at u [q][n] (uniform in [0, 1)), the state is
+ * mean + exp(log-std) * eps [q][n][6] (standard normals), clamped to the
+ * state box (positions [0, 1], velocities [-0.5, 0.5]); out [q][n][6]. */
+int pump_mlp_sample(pump_mlp* m, const float* cond, int32_t q, const float* u, const float* eps,
+                    int32_t n, float* out, int32_t mem);
+const char* pump_mlp_last_error(const pump_mlp* m);
+
+/* -------------------------------------------------------------------------
+ * Batched engine.  Many independent queries (Alg. 2 each: BuildGraph, Explore,
+ * PlanSelection), of uneven sizes, planned by one sequence of device launches
+ * with no host round trip between them, captured in one HIP graph.  Setup
+ * and selection run as batched kernels with the query index as a grid
+ * dimension; Explore runs in one persistent kernel whose workgroups take
+ * whole queries from a device queue and run all of a query's rounds with
+ * workgroup barriers only.  Each query's results equal those of pump_plan on
+ * the same inputs (same per-element code, same orders).  Selection certifies
+ * at most 32 Pareto-front plans per query (a larger front makes that query
+ * report PUMP_E_CAPACITY).
+ * ------------------------------------------------------------------------- */
+typedef struct pump_batch pump_batch;
+
+/* Shape of the persistent Explore kernel. */
+typedef struct pump_batch_tuning {
+    int32_t explore_threads; /* 256 or 512 threads per workgroup */
+    int32_t blocks_per_cu;   /* 1..8 persistent workgroups per compute unit */
+    int32_t order;           /* 0: queue in input order; 1: largest query first */
+    int32_t use_graph;       /* 1: capture the launches in a HIP graph and launch it */
+} pump_batch_tuning;
+
+/* Allocate per-query workspaces for up to max_queries queries, each sized by
+ * *cfg (n_particles is the largest particle count a query may use, max_nodes
+ * the largest n + 1, and so on).  hip_stream NULL creates a private stream.
+ * Errors: PUMP_E_ARG (unsupported configuration), PUMP_E_HIP (allocation). */
+int pump_batch_create(const pump_config* cfg, int32_t max_queries, void* hip_stream,
+                      pump_batch** out);
+int pump_batch_destroy(pump_batch* b);
+/* Plan q queries.  probs[i] must have mem == PUMP_MEM_DEVICE (every array on
+ * the device, read only, kept alive until the call returns); n_particles[i]
+ * is that query's N (32/64/128/256, at most cfg.n_particles; noise arrays are
+ * [S_max][6][N] for that N).  tune may be NULL (512 threads, 2 per CU,
+ * largest first, graph on).  out[i] receives query i's result; the returned
+ * code is PUMP_OK or the first negative per-query status.  ms_total holds the
+ * wall time of the whole batch. */
+int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_particles,
+                    int32_t q, const pump_batch_tuning* tune, pump_result* out);
+/* Node ids (x_init = 0, sample k = k + 1) of plan `plan` of query `query`
+ * from the last pump_batch_plan call, root first. */
+int pump_batch_get_path(pump_batch* b, int32_t query, int32_t plan, int32_t* nodes, int32_t cap,
+                        int32_t* len);
+/* Autotuner: time every persistent-kernel shape (threads x workgroups per CU x
+ * order, graph on) on these queries, check that every shape returns the same
+ * per-query results, write the timings as JSON to json_path (if not NULL)
+ * and return the fastest shape and its time. */
+int pump_batch_tune(pump_batch* b, const pump_problem* probs, const int32_t* n_particles,
+                    int32_t q, pump_batch_tuning* best, double* best_ms, const char* json_path);
+const char* pump_batch_last_error(const pump_batch* b);
+
 /* Status text for a code, and the last error message of a context. */
 const char* pump_status_str(int status);
 const char* pump_last_error(const pump_ctx* ctx);

@@ -66,6 +66,11 @@ class Result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("explore_threads", _i32), ("blocks_per_cu", _i32), ("order", _i32),
+                ("use_graph", _i32)]
+
+
 class PumpError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libpump status {code}: {msg}")
@@ -79,7 +84,13 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
            "pump_explore_begin", "pump_explore_round", "pump_explore_run", "pump_select",
            "pump_get_deviation", "pump_get_graph", "pump_get_plans", "pump_get_candidates",
            "pump_get_front", "pump_get_path", "pump_mc_path", "pump_set_timing",
-           "pump_get_timing", "pump_status_str", "pump_last_error"]
+           "pump_get_timing", "pump_status_str", "pump_last_error", "pump_mlp_create",
+           "pump_mlp_destroy", "pump_mlp_num_params", "pump_mlp_set_params",
+           "pump_mlp_get_params", "pump_mlp_forward", "pump_mlp_loss_grad",
+           "pump_mlp_train_step", "pump_mlp_condition", "pump_mlp_sample",
+           "pump_mlp_last_error", "pump_batch_create", "pump_batch_destroy",
+           "pump_batch_plan", "pump_batch_get_path", "pump_batch_tune",
+           "pump_batch_last_error"]
 
 TIMING_KINDS = ["deviation", "graph_mark", "graph_fill", "expand", "prune", "compact",
                 "next_group", "select_front", "mc"]
@@ -123,6 +134,24 @@ def load(path: Optional[str] = None):
         "pump_get_timing": (_i32, [_p, _p, _p, _i32]),
         "pump_status_str": (ctypes.c_char_p, [_i32]),
         "pump_last_error": (ctypes.c_char_p, [_p]),
+        "pump_mlp_create": (_i32, [_i32, _p, P(_p)]),
+        "pump_mlp_destroy": (_i32, [_p]),
+        "pump_mlp_num_params": (_i32, []),
+        "pump_mlp_set_params": (_i32, [_p, _p, _i64]),
+        "pump_mlp_get_params": (_i32, [_p, _p, _i64]),
+        "pump_mlp_forward": (_i32, [_p, _p, _i32, _p, _i32]),
+        "pump_mlp_loss_grad": (_i32, [_p, _p, _p, _i32, P(_f), _p, _i32]),
+        "pump_mlp_train_step": (_i32, [_p, _p, _p, _i32, _f, P(_f), _i32]),
+        "pump_mlp_condition": (_i32, [_p, _p, _p, _p, _p, _i32, _i32, _p]),
+        "pump_mlp_sample": (_i32, [_p, _p, _i32, _p, _p, _i32, _p, _i32]),
+        "pump_mlp_last_error": (ctypes.c_char_p, [_p]),
+        "pump_batch_create": (_i32, [P(Config), _i32, _p, P(_p)]),
+        "pump_batch_destroy": (_i32, [_p]),
+        "pump_batch_plan": (_i32, [_p, P(Problem), P(_i32), _i32, P(Tuning), P(Result)]),
+        "pump_batch_get_path": (_i32, [_p, _i32, _i32, _p, _i32, P(_i32)]),
+        "pump_batch_tune": (_i32, [_p, P(Problem), P(_i32), _i32, P(Tuning), P(_d),
+                                   ctypes.c_char_p]),
+        "pump_batch_last_error": (ctypes.c_char_p, [_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -350,3 +379,203 @@ def plan_paths(pl: dict):
         else:
             paths[p] = paths[parent[p]] + (int(head[p]),)
     return paths
+
+
+class MLP:
+    """The learned proposal network (pump_mlp_*).  Arrays are numpy (host) or
+    torch CUDA tensors (device)."""
+
+    def __init__(self, max_batch, stream=None):
+        self.lib = load()
+        s = None if stream is None else getattr(stream, "cuda_stream", stream)
+        self.m = _p()
+        rc = self.lib.pump_mlp_create(int(max_batch), s, ctypes.byref(self.m))
+        if rc != 0:
+            raise PumpError(rc, "pump_mlp_create failed")
+        self.n_params = self.lib.pump_mlp_num_params()
+        self.max_batch = int(max_batch)
+
+    def close(self):
+        if self.m:
+            self.lib.pump_mlp_destroy(self.m)
+            self.m = _p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PumpError(rc, (self.lib.pump_mlp_last_error(self.m) or b"").decode())
+
+    @staticmethod
+    def _mem(a):
+        return MEM_HOST if isinstance(a, np.ndarray) else MEM_DEVICE
+
+    def set_params(self, flat):
+        f = _np(flat, np.float32)
+        self._check(self.lib.pump_mlp_set_params(self.m, f.ctypes.data, f.size))
+
+    def get_params(self):
+        f = np.zeros(self.n_params, np.float32)
+        self._check(self.lib.pump_mlp_get_params(self.m, f.ctypes.data, f.size))
+        return f
+
+    def forward(self, cond):
+        if isinstance(cond, np.ndarray):
+            cond = _np(cond, np.float32)
+            out = np.zeros((cond.shape[0], 208), np.float32)
+        else:
+            import torch
+            out = torch.empty((cond.shape[0], 208), dtype=torch.float32, device=cond.device)
+        self._check(self.lib.pump_mlp_forward(self.m, _ptr(cond), int(cond.shape[0]), _ptr(out),
+                                              self._mem(cond)))
+        return out
+
+    def loss_grad(self, cond, target):
+        cond = _np(cond, np.float32)
+        target = _np(target, np.float32)
+        g = np.zeros(self.n_params, np.float32)
+        loss = _f(0)
+        self._check(self.lib.pump_mlp_loss_grad(self.m, cond.ctypes.data, target.ctypes.data,
+                                                int(cond.shape[0]), ctypes.byref(loss),
+                                                g.ctypes.data, MEM_HOST))
+        return float(loss.value), g
+
+    def train_step(self, cond, target, lr):
+        if isinstance(cond, np.ndarray):
+            cond = _np(cond, np.float32)
+            target = _np(target, np.float32)
+        loss = _f(0)
+        self._check(self.lib.pump_mlp_train_step(self.m, _ptr(cond), _ptr(target),
+                                                 int(cond.shape[0]), float(lr),
+                                                 ctypes.byref(loss), self._mem(cond)))
+        return float(loss.value)
+
+    def condition(self, x_init, goal, boxes, n_obs):
+        """Device tensors in, device tensor [q][396] out."""
+        import torch
+        q = int(x_init.shape[0])
+        out = torch.empty((q, 396), dtype=torch.float32, device=x_init.device)
+        self._check(self.lib.pump_mlp_condition(self.m, _ptr(x_init), _ptr(goal), _ptr(boxes),
+                                                _ptr(n_obs), q, int(boxes.shape[1]), _ptr(out)))
+        return out
+
+    def sample(self, cond, u, eps):
+        q, n = int(u.shape[0]), int(u.shape[1])
+        if isinstance(cond, np.ndarray):
+            cond, u, eps = _np(cond, np.float32), _np(u, np.float32), _np(eps, np.float32)
+            out = np.zeros((q, n, 6), np.float32)
+        else:
+            import torch
+            out = torch.empty((q, n, 6), dtype=torch.float32, device=cond.device)
+        self._check(self.lib.pump_mlp_sample(self.m, _ptr(cond), q, _ptr(u), _ptr(eps), n,
+                                             _ptr(out), self._mem(cond)))
+        return out
+
+
+class Batch:
+    """The batched engine: many device-resident queries in one graph launch.
+    Queries are (samples, obstacles, x_init, goal, alpha, sigma, noise,
+    noise_mc) with torch CUDA tensors for the arrays; N is taken from
+    noise.shape[2]."""
+
+    def __init__(self, max_queries, stream=None, **cfg):
+        self.lib = load()
+        self.cfg = default_config(**cfg)
+        s = getattr(stream, "cuda_stream", stream) if stream is not None else None
+        self.b = _p()
+        rc = self.lib.pump_batch_create(ctypes.byref(self.cfg), int(max_queries), s,
+                                        ctypes.byref(self.b))
+        if rc != 0:
+            raise PumpError(rc, "pump_batch_create failed")
+        self._keep = []
+
+    def close(self):
+        if self.b:
+            self.lib.pump_batch_destroy(self.b)
+            self.b = _p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, rc):
+        msg = self.lib.pump_batch_last_error(self.b) or b""
+        raise PumpError(rc, msg.decode())
+
+    def _problems(self, queries):
+        q = len(queries)
+        arr = (Problem * q)()
+        ns = (_i32 * q)()
+        keep = []
+        for i, (smp, obs, x0, goal, alpha, sigma, noise, noise_mc) in enumerate(queries):
+            keep += [smp, obs, noise, noise_mc]
+            pr = arr[i]
+            pr.samples = _ptr(smp)
+            pr.n = int(smp.shape[0])
+            pr.obstacles = _ptr(obs) if int(obs.shape[0]) else None
+            pr.n_obs = int(obs.shape[0])
+            xi = np.asarray(x0, np.float32)
+            for k in range(6):
+                pr.x_init[k] = float(xi[k])
+            g = np.asarray(goal, np.float32)
+            for k in range(3):
+                pr.goal.lo[k] = float(g[k])
+                pr.goal.hi[k] = float(g[3 + k])
+            pr.alpha = float(alpha)
+            pr.sigma = float(sigma)
+            pr.noise = _ptr(noise)
+            pr.noise_mc = _ptr(noise_mc)
+            pr.mem = MEM_DEVICE
+            ns[i] = int(noise.shape[2])
+        self._keep = keep
+        return arr, ns
+
+    @staticmethod
+    def _sync_torch():
+        # inputs written on torch's stream must be complete before the
+        # library's stream reads them
+        import torch
+        torch.cuda.current_stream().synchronize()
+
+    def plan(self, queries, tuning=None, raise_on_error=True):
+        arr, ns = self._problems(queries)
+        self._sync_torch()
+        q = len(queries)
+        out = (Result * q)()
+        t = None
+        if tuning is not None:
+            t = Tuning(*[int(tuning[k]) for k in ("explore_threads", "blocks_per_cu", "order",
+                                                  "use_graph")])
+        rc = self.lib.pump_batch_plan(self.b, arr, ns, q, ctypes.byref(t) if t else None, out)
+        if rc < 0 and raise_on_error:
+            self._err(rc)
+        return [r.as_dict() for r in out]
+
+    def path(self, query, plan):
+        cap = self.cfg.max_steps + 1
+        buf = np.zeros(cap, np.int32)
+        n = _i32(0)
+        rc = self.lib.pump_batch_get_path(self.b, int(query), int(plan), buf.ctypes.data, cap,
+                                          ctypes.byref(n))
+        if rc != 0:
+            self._err(rc)
+        return tuple(int(v) for v in buf[:n.value])
+
+    def tune(self, queries, json_path=None):
+        arr, ns = self._problems(queries)
+        self._sync_torch()
+        best = Tuning()
+        ms = _d(0.0)
+        rc = self.lib.pump_batch_tune(self.b, arr, ns, len(queries), ctypes.byref(best),
+                                      ctypes.byref(ms),
+                                      json_path.encode() if json_path else None)
+        if rc != 0:
+            self._err(rc)
+        return dict(explore_threads=best.explore_threads, blocks_per_cu=best.blocks_per_cu,
+                    order=best.order, use_graph=best.use_graph), ms.value

@@ -106,6 +106,47 @@ __device__ __forceinline__ void steer64(const float* x0, const float* x1, double
     cost = bc;
 }
 
+// Exact rejection test for Near: true only if c(tau) > R for every tau > 0,
+// so the pair cannot be an edge with c* < R.  For tau >= R, c(tau) >= tau >= R.
+// On (0, R), c(tau) < R iff g(tau) = tau^3 (c(tau) - R) < 0 with
+//   g(tau) = tau^4 - R tau^3 + 4 r S_vv tau^2 - 12 r S_Pv tau + 12 r S_PP.
+// A polynomial whose Bernstein coefficients on an interval are all positive is
+// positive there; the test splits [0, R] into halves and quarters (de
+// Casteljau) where needed and demands a margin far above the rounding error.
+__device__ __forceinline__ bool bern_pos(const double* b, double m) {
+    return fmin(fmin(fmin(b[0], b[1]), fmin(b[2], b[3])), b[4]) > m;
+}
+
+__device__ __forceinline__ void bern_split(const double* b, double* L, double* Rr) {
+    double c[5] = {b[0], b[1], b[2], b[3], b[4]};
+    L[0] = c[0];
+    Rr[4] = c[4];
+    for (int lvl = 1; lvl <= 4; ++lvl) {
+        for (int i = 0; i <= 4 - lvl; ++i) c[i] = 0.5 * (c[i] + c[i + 1]);
+        L[lvl] = c[0];
+        Rr[4 - lvl] = c[4 - lvl];
+    }
+}
+
+__device__ __forceinline__ bool surely_not_near(const BSums& s, double r, double R) {
+    const double R2 = R * R, R4 = R2 * R2;
+    const double a0 = 12.0 * r * s.pp, a1 = -12.0 * r * s.pv * R, a2 = 4.0 * r * s.vv * R2;
+    const double a3 = -R4, a4 = R4;
+    const double m = 1e-9 * (fabs(a0) + fabs(a1) + fabs(a2) + fabs(a3) + fabs(a4));
+    double b[5] = {a0, a0 + 0.25 * a1, a0 + 0.5 * a1 + a2 / 6.0,
+                   a0 + 0.75 * a1 + 0.5 * a2 + 0.25 * a3, a0 + a1 + a2 + a3 + a4};
+    if (bern_pos(b, m)) return true;
+    double h[2][5];
+    bern_split(b, h[0], h[1]);
+    for (int k = 0; k < 2; ++k) {
+        if (bern_pos(h[k], m)) continue;
+        double q0[5], q1[5];
+        bern_split(h[k], q0, q1);
+        if (!(bern_pos(q0, m) && bern_pos(q1, m))) return false;
+    }
+    return true;
+}
+
 // Minimum-effort nominal trajectory per axis (cubic Hermite):
 //   p(t) = p0 + v0 t + c2 t^2 + c3 t^3,
 //   c2 = (3P - (2 v0 + v1) tau) / tau^2,  c3 = (-2P + (v0 + v1) tau) / tau^3.

@@ -1,0 +1,434 @@
+// Per-element operations of one Explore round (Alg. 4), shared by the
+// single-query kernels (one launch per phase, whole device) and the batched
+// engine (one workgroup per query).  Both drivers run these same bodies, in
+// the same orders, so they produce identical plan stores.
+#pragma once
+
+#include "device_math.hpp"
+#include "pump_internal.hpp"
+
+namespace pump {
+
+__device__ __forceinline__ double stair_get(const unsigned long long* st, int w, int x, int c) {
+    return __longlong_as_double((long long)st[(size_t)x * w + c]);
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
+    return lane ? ((1ull << lane) - 1ull) : 0ull;
+}
+
+__device__ __forceinline__ bool boxes_overlap(const float* lo3, const float* hi3, const float* b) {
+    return (lo3[0] <= b[3]) & (hi3[0] >= b[0]) & (lo3[1] <= b[4]) & (hi3[1] >= b[1]) &
+           (lo3[2] <= b[5]) & (hi3[2] >= b[2]);
+}
+
+// Obstacles as stored (raw), shrunk by the guard band (in) and grown by it (out).
+__device__ __forceinline__ void stage_obstacles_block(const float* obs, int n_obs, float* s_raw,
+                                                      float* s_in, float* s_out) {
+    for (int t = threadIdx.x; t < n_obs * 6; t += blockDim.x) {
+        const float v = obs[t];
+        const bool is_lo = (t % 6) < 3;
+        if (s_raw) s_raw[t] = v;
+        if (s_in) s_in[t] = is_lo ? v + kGuard : v - kGuard;
+        s_out[t] = is_lo ? v - kGuard : v + kGuard;
+    }
+}
+
+// Root plan and empty staircases (Alg. 4 first lines).  `t0`/`stride`
+// distribute the staircase fill; the root itself is written by thread t0 == 0.
+__device__ __forceinline__ void explore_init_fill(const RoundArgs& a, int n_nodes, size_t t0,
+                                                  size_t stride) {
+    const size_t n = (size_t)n_nodes * a.stair_w;
+    for (size_t t = t0; t < n; t += stride) a.stair[t] = 0x7FF0000000000000ull;
+}
+
+__device__ __forceinline__ void explore_init_root(const RoundArgs& a, int N) {
+    const int W = N / 32;
+    a.p_head[0] = 0;
+    a.p_parent[0] = -1;
+    a.p_edge[0] = -1;
+    a.p_step[0] = 0;
+    a.p_pop[0] = 0;
+    a.p_round[0] = 0;
+    a.p_cost[0] = 0.0;
+    a.p_state[0] = kOpen;
+    for (int w = 0; w < W; ++w) a.p_mask[w] = 0u;
+    for (int c = 0; c < a.c_cut && c < a.stair_w; ++c) a.stair[c] = 0ull;  // 0.0 bits
+    a.open_out[0] = 0;  // the initial open list is written to open_out
+    a.o_inB[0] = 1;
+    a.b_ids[0] = 0;
+    const int deg = a.row_ptr[1] - a.row_ptr[0];
+    a.b_off[0] = 0;
+    a.b_off[1] = deg;
+    Ctl* c = a.ctl;
+    c->n_plans = 1;
+    c->n_open = 1;
+    c->n_B = 1;
+    c->n_pairs = deg;
+    c->i = 0;
+    c->goal_stop = (a.goal[0] && 0 < a.c_min) ? 1 : 0;
+    c->done = c->goal_stop;
+    c->err = 0;
+    c->n_tasks = 0;
+    c->simulated = c->preprune = c->inserted = c->dropped_steps = c->flagged = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Expansion, first part (one pair per lane): locate pair q (q < n_pairs), its
+// edge and parent plan; cost, step count and K_e waypoints; drop it past
+// S_max; resolve it if the parent's own cp_hat already makes it dominated;
+// otherwise evaluate the nominal trajectory and mark the waypoints where the
+// particle cloud's bounding box, shifted onto the nominal point and widened by
+// the guard band, touches an obstacle.  Returns 1 if q keeps the parent's
+// bits (written here), 2 if its particles must be simulated, 0 if resolved.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int n_B, const float* s_out,
+                                           const float* gl, const float* gh, long long& n_sim,
+                                           long long& n_pre, long long& n_drop) {
+    constexpr int W = N / 32;
+    const int n_obs = a.n_obs;
+    int lo = 0, hi = n_B;  // b_off[lo] <= q < b_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.b_off[mid] <= q) lo = mid; else hi = mid;
+    }
+    const int p = a.b_ids[lo];
+    const int head = a.p_head[p];
+    const int e = a.row_ptr[head] + (q - a.b_off[lo]);
+    const int x = a.col[e];
+    a.c_parent[q] = p;   // every formed pair records its identity
+    a.c_head[q] = x;
+    const double tau = a.etau[e];
+    const double cost = a.p_cost[p] + a.ecost[e];
+    const int K = max(1, (int)ceil(tau / a.dt));
+    const int s_p = a.p_step[p];
+    const int pop_p = a.p_pop[p];
+    if (s_p + K > a.S_max) {
+        a.c_flag[q] = 0;
+        a.c_pop[q] = -2;
+        ++n_drop;
+        return 0;
+    }
+    if (a.preprune && stair_get(a.stair, a.stair_w, x, pop_p) < cost) {
+        a.c_flag[q] = 0;
+        a.c_pop[q] = -1;
+        ++n_pre;
+        return 0;
+    }
+    ++n_sim;
+    Cubic cs[3];
+    hermite(a.X + (size_t)head * 6, a.X + (size_t)x * 6, tau, cs);
+    // obstacles the cloud can reach anywhere along the edge
+    float elo[3], ehi[3];
+    for (int k = 0; k < 3; ++k) {
+        double mn, mx;
+        cubic_range(cs[k], tau, mn, mx);
+        elo[k] = (float)mn + gl[k] - 1e-6f;
+        ehi[k] = (float)mx + gh[k] + 1e-6f;
+    }
+    unsigned long long cand[kMaxObs / 64];
+    bool any = false;
+    for (int c = 0; c < kMaxObs / 64; ++c) cand[c] = 0ull;
+    for (int o = 0; o < n_obs; ++o) {
+        if (boxes_overlap(elo, ehi, s_out + o * 6)) {
+            cand[o >> 6] |= 1ull << (o & 63);
+            any = true;
+        }
+    }
+    unsigned near = 0u;
+    if (any) {
+        for (int k = 1; k <= K; ++k) {
+            const double t = ((double)k * tau) / (double)K;
+            const float* cl = a.cloud + (size_t)(s_p + k) * 6;
+            float lo3[3], hi3[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                const float nom = (float)cs[ax].at(t);
+                lo3[ax] = nom + cl[ax] - 1e-6f;
+                hi3[ax] = nom + cl[3 + ax] + 1e-6f;
+            }
+            bool hitk = false;
+            for (int c = 0; c < (n_obs + 63) / 64 && !hitk; ++c) {
+                unsigned long long m = cand[c];
+                while (m && !hitk) {
+                    const int o = c * 64 + __ffsll((long long)m) - 1;
+                    m &= m - 1ull;
+                    hitk = boxes_overlap(lo3, hi3, s_out + o * 6);
+                }
+            }
+            if (hitk) near |= 1u << (k - 1);
+        }
+    }
+    a.c_edge[q] = e;
+    a.c_cost[q] = cost;
+    a.c_step[q] = s_p + K;
+    if (near == 0u) {
+        // no particle can touch an obstacle on this edge: q keeps p's bits
+        a.c_flag[q] = 1;
+        a.c_pop[q] = pop_p;
+        for (int w = 0; w < W; ++w) a.c_mask[(size_t)q * W + w] = a.p_mask[(size_t)p * W + w];
+        return 1;
+    }
+    a.c_pos[q] = (int)near;   // waypoint mask for the simulation
+    return 2;
+}
+
+// Append the wave's pairs with st == 2 to the simulation queue.
+__device__ __forceinline__ void queue_pairs(const RoundArgs& a, int q, int st) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long need = __ballot(st == 2);
+    int base = 0;
+    if (lane == 0 && need) base = atomicAdd(&a.ctl->n_tasks, (int)__popcll(need));
+    base = __shfl(base, 0, 64);
+    if (st == 2) a.tasks[base + (int)__popcll(need & lanemask_lt(lane))] = q;
+}
+
+// ---------------------------------------------------------------------------
+// Expansion, second part (one queued pair per wave, particles across lanes):
+// at each marked waypoint, lanes test their particles against the obstacles
+// the cloud touches (FP32 with an FP64 re-test inside the guard band); hits
+// are gathered with ballots into the N-bit mask, ORed with the parent's bits
+// and counted; the pair is cut if pop >= c_cut.  Counters are wave-uniform.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void simulate_pair(const RoundArgs& a, int qj, const float* s_raw,
+                                              const float* s_in, const float* s_out,
+                                              long long& n_pre, long long& n_flag) {
+    constexpr int W = N / 32;                      // u32 mask words
+    constexpr int PPL = N >= 64 ? N / 64 : 1;      // particles per lane
+    const int n_obs = a.n_obs;
+    const int lane = threadIdx.x & 63;
+    const bool valid_lane = (N >= 64) || (lane < N);
+    const int pj = a.c_parent[qj], xj = a.c_head[qj], ej = a.c_edge[qj];
+    const double tj = a.etau[ej], cj = a.c_cost[qj];
+    const int Kj = max(1, (int)ceil(tj / a.dt));
+    const int spj = a.c_step[qj] - Kj;
+    const int hj = a.p_head[pj];
+    const unsigned nj = (unsigned)a.c_pos[qj];
+    Cubic cs[3];
+    hermite(a.X + (size_t)hj * 6, a.X + (size_t)xj * 6, tj, cs);
+    bool hit[PPL], deep[PPL], nearp[PPL];
+    for (int r = 0; r < PPL; ++r) { hit[r] = false; deep[r] = false; nearp[r] = false; }
+    unsigned wm = nj;
+    while (wm) {
+        const int k = __ffs((int)wm);
+        wm &= wm - 1u;
+        const int s = spj + k;
+        const double t = ((double)k * tj) / (double)Kj;
+        double nom64[3];
+        float nom32[3];
+        for (int ax = 0; ax < 3; ++ax) { nom64[ax] = cs[ax].at(t); nom32[ax] = (float)nom64[ax]; }
+        const float* cl = a.cloud + (size_t)s * 6;
+        float lo3[3], hi3[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            lo3[ax] = nom32[ax] + cl[ax] - 1e-6f;
+            hi3[ax] = nom32[ax] + cl[3 + ax] + 1e-6f;
+        }
+        float y[PPL][3];
+        bool loaded = false;
+        for (int c0 = 0; c0 < n_obs; c0 += 64) {
+            const int o = c0 + lane;
+            const bool ov = o < n_obs && boxes_overlap(lo3, hi3, s_out + o * 6);
+            unsigned long long om = __ballot(ov);
+            if (om && !loaded) {
+                for (int r = 0; r < PPL; ++r) {
+                    const int jj = valid_lane ? r * 64 + lane : 0;
+                    for (int ax = 0; ax < 3; ++ax)
+                        y[r][ax] = nom32[ax] + a.D[((size_t)s * 3 + ax) * N + jj];
+                }
+                loaded = true;
+            }
+            while (om) {
+                const int ob = c0 + __ffsll((long long)om) - 1;
+                om &= om - 1ull;
+                const float* bi = s_in + ob * 6;
+                const float* bo = s_out + ob * 6;
+                for (int r = 0; r < PPL; ++r) {
+                    const float y0 = y[r][0], y1 = y[r][1], y2 = y[r][2];
+                    const bool inner = (y0 >= bi[0]) & (y0 <= bi[3]) & (y1 >= bi[1]) &
+                                       (y1 <= bi[4]) & (y2 >= bi[2]) & (y2 <= bi[5]);
+                    const bool outer = (y0 >= bo[0]) & (y0 <= bo[3]) & (y1 >= bo[1]) &
+                                       (y1 <= bo[4]) & (y2 >= bo[2]) & (y2 <= bo[5]);
+                    if (inner) {
+                        hit[r] = true;
+                        deep[r] = true;
+                    } else if (outer && valid_lane) {
+                        // within the guard band of a face: decide in FP64
+                        const int jj = r * 64 + lane;
+                        const float* br = s_raw + ob * 6;
+                        double dmin = INFINITY;
+                        for (int ax = 0; ax < 3; ++ax) {
+                            const double yy = nom64[ax] + (double)a.D[((size_t)s * 3 + ax) * N + jj];
+                            dmin = fmin(dmin, fmin(yy - (double)br[ax], (double)br[3 + ax] - yy));
+                        }
+                        if (dmin >= 0.0) hit[r] = true;
+                        if (dmin >= kFlagEps) deep[r] = true;
+                        if (fabs(dmin) < kFlagEps) nearp[r] = true;
+                    }
+                }
+            }
+        }
+    }
+    // gather hits into the N-bit mask and OR with the parent's bits
+    uint32_t words[W];
+    int popc = 0;
+    long long flg = 0;
+    for (int r = 0; r < PPL; ++r) {
+        const unsigned long long hb = __ballot(hit[r] && valid_lane);
+        const unsigned long long fb = __ballot(nearp[r] && !deep[r] && valid_lane);
+        if (N >= 64) {
+            const uint32_t pm0 = a.p_mask[(size_t)pj * W + 2 * r];
+            const uint32_t pm1 = a.p_mask[(size_t)pj * W + 2 * r + 1];
+            words[2 * r] = pm0 | (uint32_t)hb;
+            words[2 * r + 1] = pm1 | (uint32_t)(hb >> 32);
+            flg += __popc((uint32_t)fb & ~pm0) + __popc((uint32_t)(fb >> 32) & ~pm1);
+        } else {
+            const uint32_t pm0 = a.p_mask[(size_t)pj * W];
+            words[0] = pm0 | (uint32_t)hb;
+            flg += __popc((uint32_t)fb & ~pm0);
+        }
+    }
+    for (int w = 0; w < W; ++w) popc += __popc(words[w]);
+    bool keep = popc < a.c_cut;
+    if (keep && a.preprune && stair_get(a.stair, a.stair_w, xj, popc) < cj) {
+        keep = false;
+        ++n_pre;
+    }
+    if (lane == 0) {
+        a.c_flag[qj] = keep ? 1 : 0;
+        a.c_pop[qj] = popc;
+    }
+    if (keep && lane < W) {
+        uint32_t v = 0;
+        for (int w = 0; w < W; ++w)
+            if (w == lane) v = words[w];
+        a.c_mask[(size_t)qj * W + lane] = v;
+    }
+    n_flag += flg;
+}
+
+// ---------------------------------------------------------------------------
+// RemoveDominated (Sec. IV): remove every open plan p for which some plan d
+// with the same head has d.cost < p.cost and d.cp_hat <= p.cp_hat.  Per node
+// the library keeps the staircase M_x(c) = min{cost of plans in P(x) with
+// pop <= c}; p is dominated iff M_{p.head}(p.pop) < p.cost.  Plans removed as
+// dominated never change M (their dominator is counted with a lower cost), so
+// M needs only insertions: one atomic minimum per kept candidate and level.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void stair_update_pair(const RoundArgs& a, int q) {
+    if (a.c_flag[q] != 1) return;
+    const int x = a.c_head[q];
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(a.c_cost[q]);
+    for (int c = a.c_pop[q]; c < a.c_cut; ++c) atomicMin(&a.stair[(size_t)x * a.stair_w + c], bits);
+}
+
+// Candidate q: dominated -> flag 2; scan input = survivor.  Returns whether q
+// was kept before the test (counts toward `inserted`).
+__device__ __forceinline__ bool mark_pair(const RoundArgs& a, int t) {
+    uint8_t f = a.c_flag[t];
+    bool kept = false;
+    if (f == 1) {
+        kept = true;
+        if (stair_get(a.stair, a.stair_w, a.c_head[t], a.c_pop[t]) < a.c_cost[t]) {
+            f = 2;
+            a.c_flag[t] = 2;
+        }
+    }
+    a.c_pos[t] = (f == 1) ? 1 : 0;
+    return kept;
+}
+
+// Open entry i: removed if dominated, closed if in B (P_open \ B), else kept.
+__device__ __forceinline__ void mark_open(const RoundArgs& a, int i) {
+    const int p = a.open_in[i];
+    const bool dom = stair_get(a.stair, a.stair_w, a.p_head[p], a.p_pop[p]) < a.p_cost[p];
+    const bool inB = a.o_inB[i] != 0;
+    const uint8_t stt = dom ? kRemoved : (inB ? kClosed : kOpen);
+    a.p_state[p] = stt;
+    a.o_keep[i] = (stt == kOpen) ? 1 : 0;
+}
+
+// Compaction: survivors are appended to the plan store in pair order after
+// the kept open plans (c_pos / o_keep hold exclusive scans).
+template <int W>
+__device__ __forceinline__ void compact_pair(const RoundArgs& a, int t, int n_plans, int n_keep,
+                                             int i_round) {
+    if (a.c_flag[t] != 1) return;
+    const int r = a.c_pos[t];
+    const int id = n_plans + r;
+    a.p_head[id] = a.c_head[t];
+    a.p_parent[id] = a.c_parent[t];
+    a.p_edge[id] = a.c_edge[t];
+    a.p_step[id] = a.c_step[t];
+    a.p_pop[id] = a.c_pop[t];
+    a.p_round[id] = i_round;
+    a.p_cost[id] = a.c_cost[t];
+    a.p_state[id] = kOpen;
+    for (int w = 0; w < W; ++w) a.p_mask[(size_t)id * W + w] = a.c_mask[(size_t)t * W + w];
+    a.open_out[n_keep + r] = id;
+}
+
+__device__ __forceinline__ void compact_open(const RoundArgs& a, int i) {
+    const int p = a.open_in[i];
+    if (a.p_state[p] == kOpen) a.open_out[a.o_keep[i]] = p;
+}
+
+// After compaction (one thread): publish the new counts; err on overflow.
+__device__ __forceinline__ void compact_finalize(Ctl* c, int64_t cap) {
+    const int n_surv = c->scan_total[0];
+    const int n_keep = c->scan_total[1];
+    if ((long long)c->n_plans + n_surv > cap) {
+        c->err = 1;
+        c->done = 1;
+        return;
+    }
+    c->n_plans += n_surv;
+    c->n_open = n_keep + n_surv;
+    c->min_cost_bits = 0x7FF0000000000000ull;
+    c->goal_stop = 0;
+}
+
+// Next group (one thread): i <- i + 1; when that group would be empty the
+// loop only advances i, so i jumps to the first value admitting the cheapest
+// open plan (cost <= i lambda r_n).
+__device__ __forceinline__ void pick_next_i(Ctl* c, double h) {
+    if (c->err) return;
+    if (c->n_open == 0) {
+        c->done = 1;
+        c->i = c->i + 1;
+        return;
+    }
+    const double mc = __longlong_as_double((long long)c->min_cost_bits);
+    if (!(mc >= 0.0 && mc < 1e300) || !(mc / h < 2.0e9)) {  // no finite cheapest open plan
+        c->err = 3;
+        c->done = 1;
+        return;
+    }
+    long long k = (long long)ceil(mc / h);
+    if (k < 0) k = 0;
+    while (k > 0 && mc <= (double)(k - 1) * h) --k;
+    while (!(mc <= (double)k * h)) ++k;
+    const long long inext = c->i + 1;
+    c->i = (int)(k > inext ? k : inext);
+}
+
+// Open entry i of the new list: in B?  (scan input in o_keep).  Returns
+// whether it stops the loop (a goal plan of B with cp_hat < alpha_min).
+__device__ __forceinline__ bool flag_group_one(const RoundArgs& a, int i, double thr) {
+    const int p = a.open_out[i];
+    const bool inB = a.p_cost[p] <= thr;
+    a.o_inB[i] = inB ? 1 : 0;
+    a.o_keep[i] = inB ? 1 : 0;
+    return inB && a.goal[a.p_head[p]] && a.p_pop[p] < a.c_min;
+}
+
+__device__ __forceinline__ void scatter_group_one(const RoundArgs& a, int i, int32_t* deg) {
+    if (!a.o_inB[i]) return;
+    const int p = a.open_out[i];
+    const int pos = a.o_keep[i];
+    const int h = a.p_head[p];
+    a.b_ids[pos] = p;
+    deg[pos] = a.row_ptr[h + 1] - a.row_ptr[h];
+}
+
+}  // namespace pump

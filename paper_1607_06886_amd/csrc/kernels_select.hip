@@ -1,205 +1,34 @@
 // PlanSelection (Alg. 5): gather P_goal, reduce it to its Pareto front, sort
-// by cp_hat, and certify with Monte Carlo (MC(p), Sec. IV).
-#include "device_math.hpp"
-#include "pump_internal.hpp"
+// by cp_hat, and certify with Monte Carlo (MC(p), Sec. IV).  The bodies live
+// in select_ops.hpp.
+#include "select_ops.hpp"
 
 namespace pump {
 
-// P_goal = plans still in P(v) for goal nodes v (Alg. 4 return), in id order.
-// One block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_goal_collect(SelectArgs a) {
-    __shared__ int s_w[16];
-    __shared__ int s_base;
-    if (threadIdx.x == 0) s_base = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int b0 = 0; b0 < a.n_plans; b0 += 1024) {
-        const int p = b0 + threadIdx.x;
-        const bool f = p < a.n_plans && a.p_state[p] != kRemoved && a.goal[a.p_head[p]];
-        const unsigned long long m = __ballot(f);
-        if (lane == 0) s_w[wave] = __popcll(m);
-        __syncthreads();
-        int off = s_base;
-        for (int w = 0; w < wave; ++w) off += s_w[w];
-        const int pos = off + (int)__popcll(m & (lane ? ((1ull << lane) - 1ull) : 0ull));
-        if (f && pos < kMaxGoal) a.goal_ids[pos] = p;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int t = 0;
-            for (int w = 0; w < 16; ++w) t += s_w[w];
-            s_base += t;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) a.ctl->n_goal = s_base;
-}
+__global__ __launch_bounds__(1024) void k_goal_collect(SelectArgs a) { goal_collect_block(a); }
 
-// Pareto front of P_goal (d dominates p iff p.cost > d.cost and
-// p.pop >= d.pop), sorted by pop ascending, cost descending, then node
-// sequence.  Paths are reconstructed from the parent links.
-__device__ int path_of(const SelectArgs& a, int p, int* out, int cap) {
-    int n = 0;
-    for (int q = p; q >= 0 && n < cap; q = a.p_parent[q]) out[n++] = a.p_head[q];
-    for (int i = 0; i < n / 2; ++i) { int t = out[i]; out[i] = out[n - 1 - i]; out[n - 1 - i] = t; }
-    return n;
-}
-
-__device__ bool front_less(const SelectArgs& a, int fa, int fb) {
-    const int pa = a.front_ids[fa], pb = a.front_ids[fb];
-    if (a.p_pop[pa] != a.p_pop[pb]) return a.p_pop[pa] < a.p_pop[pb];
-    if (a.p_cost[pa] != a.p_cost[pb]) return a.p_cost[pa] > a.p_cost[pb];
-    const int stride = a.S_max + 1;
-    const int* xa = a.paths + (size_t)fa * stride;
-    const int* xb = a.paths + (size_t)fb * stride;
-    const int la = a.path_len[fa], lb = a.path_len[fb];
-    for (int i = 0; i < la && i < lb; ++i)
-        if (xa[i] != xb[i]) return xa[i] < xb[i];
-    return la < lb;
-}
-
-__global__ __launch_bounds__(256) void k_front(SelectArgs a) {
-    __shared__ int s_flag[kMaxFront];
-    __shared__ int s_n;
-    const int G = a.ctl->n_goal < kMaxGoal ? a.ctl->n_goal : kMaxGoal;
-    if (threadIdx.x == 0) s_n = 0;
-    __syncthreads();
-    // front membership, then compaction in goal order (thread 0, deterministic)
-    for (int g = threadIdx.x; g < G; g += blockDim.x) {
-        const int p = a.goal_ids[g];
-        const double c = a.p_cost[p];
-        const int k = a.p_pop[p];
-        bool dom = false;
-        for (int h = 0; h < G && !dom; ++h) {
-            const int d = a.goal_ids[h];
-            dom = (c > a.p_cost[d]) && (k >= a.p_pop[d]);
-        }
-        if (!dom) {
-            int slot = atomicAdd(&s_n, 1);
-            if (slot < kMaxFront) s_flag[slot] = g;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    int n = s_n < kMaxFront ? s_n : kMaxFront;
-    if (s_n > kMaxFront) a.ctl->err = 2;
-    // deterministic order of discovery: sort slots by goal index
-    for (int i = 1; i < n; ++i) {
-        int v = s_flag[i], j = i - 1;
-        while (j >= 0 && s_flag[j] > v) { s_flag[j + 1] = s_flag[j]; --j; }
-        s_flag[j + 1] = v;
-    }
-    const int stride = a.S_max + 1;
-    for (int f = 0; f < n; ++f) {
-        a.front_ids[f] = a.goal_ids[s_flag[f]];
-        a.path_len[f] = path_of(a, a.front_ids[f], a.paths + (size_t)f * stride, stride);
-    }
-    // insertion sort of the front (entries carry their paths)
-    for (int i = 1; i < n; ++i) {
-        int j = i;
-        while (j > 0 && front_less(a, j, j - 1)) {
-            int t = a.front_ids[j]; a.front_ids[j] = a.front_ids[j - 1]; a.front_ids[j - 1] = t;
-            int l = a.path_len[j]; a.path_len[j] = a.path_len[j - 1]; a.path_len[j - 1] = l;
-            int* xa = a.paths + (size_t)j * stride;
-            int* xb = a.paths + (size_t)(j - 1) * stride;
-            for (int k = 0; k < stride; ++k) { int u = xa[k]; xa[k] = xb[k]; xb[k] = u; }
-            --j;
-        }
-    }
-    a.ctl->n_front = n;
-}
+__global__ __launch_bounds__(256) void k_front(SelectArgs a) { front_block(a, kMaxFront); }
 
 void launch_select_front(hipStream_t s, const SelectArgs& a) {
     k_goal_collect<<<1, 1024, 0, s>>>(a);
     k_front<<<1, 256, 0, s>>>(a);
 }
 
-// Nominal tracking waypoints of a path (step 0 = the first node's position):
-// each connection (u, v) contributes K_e = max(1, ceil(tau*/dt)) waypoints at
-// t_k = k tau*/K_e.  One thread per path.
 __global__ void k_waypoints(SelectArgs a, int n_paths) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n_paths) return;
-    const int stride = a.S_max + 1;
-    const int* nodes = a.paths + (size_t)f * stride;
-    const int len = a.path_len[f];
-    double* wp = a.wp + (size_t)f * stride * 3;
-    const float* x0 = a.X + (size_t)nodes[0] * 6;
-    for (int ax = 0; ax < 3; ++ax) wp[ax] = (double)x0[ax];
-    int s = 0;
-    bool ok = true;
-    for (int l = 1; l < len && ok; ++l) {
-        const float* xu = a.X + (size_t)nodes[l - 1] * 6;
-        const float* xv = a.X + (size_t)nodes[l] * 6;
-        double tau, c;
-        steer64(xu, xv, a.r_steer, tau, c);
-        const int K = max(1, (int)ceil(tau / a.dt));
-        if (s + K > a.S_max) { ok = false; break; }
-        Cubic cs[3];
-        hermite(xu, xv, tau, cs);
-        for (int k = 1; k <= K; ++k) {
-            const double t = ((double)k * tau) / (double)K;
-            for (int ax = 0; ax < 3; ++ax) wp[(size_t)(s + k) * 3 + ax] = cs[ax].at(t);
-        }
-        s += K;
-    }
-    a.wp_len[f] = ok ? s : -1;
+    if (f < n_paths) waypoints_one(a, f);
 }
 
 void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths) {
     k_waypoints<<<(n_paths + 63) / 64, 64, 0, s>>>(a, n_paths);
 }
 
-// MC(p): M certification particles per path, one thread each.  A particle's
-// deviation follows the closed-loop recurrence from zero at step 0 with its
-// own noise; its workspace path is the polyline through the waypoint
-// positions; it collides iff a segment meets a closed obstacle box (slab
-// clipping, FP64).
 __global__ __launch_bounds__(256) void k_mc(SelectArgs a) {
     __shared__ float s_obs[kMaxObs * 6];
     for (int t = threadIdx.x; t < a.n_obs * 6; t += blockDim.x) s_obs[t] = a.obs[t];
     __syncthreads();
     const int f = blockIdx.y;
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    const int S = a.wp_len[f];
-    bool hit = false;
-    if (m < a.M && S >= 0) {
-        const int stride = a.S_max + 1;
-        const double* wp = a.wp + (size_t)f * stride * 3;
-        double dp[3] = {0.0, 0.0, 0.0}, dv[3] = {0.0, 0.0, 0.0};
-        double prev[3] = {wp[0], wp[1], wp[2]};
-        const double a00 = a.Acl[0], a01 = a.Acl[1], a10 = a.Acl[2], a11 = a.Acl[3];
-        const double l00 = a.L[0], l10 = a.L[2], l11 = a.L[3];
-        for (int s = 0; s < S && !hit; ++s) {
-            double cur[3];
-            for (int ax = 0; ax < 3; ++ax) {
-                const double w0 = (double)a.noise_mc[((size_t)s * 6 + 2 * ax) * a.M + m];
-                const double w1 = (double)a.noise_mc[((size_t)s * 6 + 2 * ax + 1) * a.M + m];
-                const double pn = a00 * dp[ax] + a01 * dv[ax] + l00 * w0;
-                const double vn = a10 * dp[ax] + a11 * dv[ax] + (l10 * w0 + l11 * w1);
-                dp[ax] = pn;
-                dv[ax] = vn;
-                cur[ax] = wp[(size_t)(s + 1) * 3 + ax] + pn;
-            }
-            for (int o = 0; o < a.n_obs && !hit; ++o) {
-                const float* b = s_obs + o * 6;
-                double t0 = 0.0, t1 = 1.0;
-                bool miss = false;
-                for (int ax = 0; ax < 3; ++ax) {
-                    const double d = cur[ax] - prev[ax];
-                    const double lo = (double)b[ax], hi = (double)b[3 + ax];
-                    if (d == 0.0) {
-                        miss |= (prev[ax] < lo) | (prev[ax] > hi);
-                    } else {
-                        const double ta = (lo - prev[ax]) / d, tb = (hi - prev[ax]) / d;
-                        t0 = fmax(t0, fmin(ta, tb));
-                        t1 = fmin(t1, fmax(ta, tb));
-                    }
-                }
-                hit = !miss && (t0 <= t1);
-            }
-            prev[0] = cur[0]; prev[1] = cur[1]; prev[2] = cur[2];
-        }
-    }
+    const bool hit = mc_particle(a, f, blockIdx.x * blockDim.x + threadIdx.x, s_obs);
     const unsigned long long b = __ballot(hit);
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(&a.mc_counts[f], (int)__popcll(b));
 }

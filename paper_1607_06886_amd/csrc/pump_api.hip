@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "host_consts.hpp"
 #include "pump_internal.hpp"
 
 using namespace pump;
@@ -36,6 +37,7 @@ struct pump_ctx {
     int32_t* deg = nullptr;
     int32_t* row_ptr = nullptr;
     int32_t* col = nullptr;
+    int32_t* esrc = nullptr;
     double* etau = nullptr;
     double* ecost = nullptr;
     // plans
@@ -50,7 +52,7 @@ struct pump_ctx {
     int32_t *b_ids = nullptr, *b_off = nullptr, *b_deg = nullptr;
     // candidates
     int32_t *c_head = nullptr, *c_parent = nullptr, *c_edge = nullptr, *c_step = nullptr,
-            *c_pop = nullptr, *c_pos = nullptr;
+            *c_pop = nullptr, *c_pos = nullptr, *tasks = nullptr;
     double* c_cost = nullptr;
     uint32_t* c_mask = nullptr;
     uint8_t* c_flag = nullptr;
@@ -105,51 +107,6 @@ hipError_t dalloc(T** p, size_t n) {
     return hipMalloc((void**)p, n * sizeof(T));
 }
 
-// Steady-state discrete LQR for one axis of the double integrator: iterate
-// P <- Q + A'PA - A'PB (R + B'PB)^-1 B'PA to a relative change below 1e-14,
-// K = (R + B'PB)^-1 B'PA, du = -K dx.
-void lqr_axis(double dt, double q_pos, double q_vel, double r, double K[2]) {
-    const double A[2][2] = {{1.0, dt}, {0.0, 1.0}};
-    const double B[2] = {0.5 * dt * dt, dt};
-    double P[2][2] = {{q_pos, 0.0}, {0.0, q_vel}};
-    for (int it = 0; it < 1000000; ++it) {
-        double PA[2][2], PB[2];
-        for (int i = 0; i < 2; ++i) {
-            for (int j = 0; j < 2; ++j) PA[i][j] = P[i][0] * A[0][j] + P[i][1] * A[1][j];
-            PB[i] = P[i][0] * B[0] + P[i][1] * B[1];
-        }
-        const double G = r + B[0] * PB[0] + B[1] * PB[1];
-        double BPA[2];  // B'PA
-        for (int j = 0; j < 2; ++j) BPA[j] = B[0] * PA[0][j] + B[1] * PA[1][j];
-        double Pn[2][2];
-        double dmax = 0.0, pmax = 0.0;
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j) {
-                const double APA = A[0][i] * PA[0][j] + A[1][i] * PA[1][j];
-                const double v = (i == j ? (i == 0 ? q_pos : q_vel) : 0.0) + APA - BPA[i] * BPA[j] / G;
-                Pn[i][j] = v;
-                dmax = std::max(dmax, fabs(v - P[i][j]));
-                pmax = std::max(pmax, fabs(v));
-            }
-        memcpy(P, Pn, sizeof(P));
-        if (dmax <= 1e-14 * pmax) break;
-    }
-    double PA[2][2], PB[2];
-    for (int i = 0; i < 2; ++i) {
-        for (int j = 0; j < 2; ++j) PA[i][j] = P[i][0] * A[0][j] + P[i][1] * A[1][j];
-        PB[i] = P[i][0] * B[0] + P[i][1] * B[1];
-    }
-    const double G = r + B[0] * PB[0] + B[1] * PB[1];
-    for (int j = 0; j < 2; ++j) K[j] = (B[0] * PA[0][j] + B[1] * PA[1][j]) / G;
-}
-
-double eta_rule(double alpha) {
-    if (alpha >= 0.01) return 2.0;
-    if (alpha <= 0.001) return 10.0;
-    const double w = (log(0.01) - log(alpha)) / (log(0.01) - log(0.001));
-    return exp(log(2.0) + w * (log(10.0) - log(2.0)));
-}
-
 RoundArgs round_args(pump_ctx* c) {
     RoundArgs a;
     memset(&a, 0, sizeof(a));
@@ -197,6 +154,7 @@ RoundArgs round_args(pump_ctx* c) {
     a.c_mask = c->c_mask;
     a.c_flag = c->c_flag;
     a.c_pos = c->c_pos;
+    a.tasks = c->tasks;
     a.ctl = c->ctl;
     return a;
 }
@@ -323,11 +281,11 @@ int pump_destroy(pump_ctx* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     void* ptrs[] = {ctx->X, ctx->valid, ctx->goal, ctx->obs, ctx->noise_buf, ctx->noise_mc_buf,
                     ctx->D, ctx->cloud, ctx->gcloud, ctx->dev_ints, ctx->ebits, ctx->deg,
-                    ctx->row_ptr, ctx->col, ctx->etau, ctx->ecost, ctx->p_head, ctx->p_parent,
+                    ctx->row_ptr, ctx->col, ctx->esrc, ctx->etau, ctx->ecost, ctx->p_head, ctx->p_parent,
                     ctx->p_edge, ctx->p_step, ctx->p_pop, ctx->p_round, ctx->p_cost, ctx->p_mask,
                     ctx->p_state, ctx->stair, ctx->open_a, ctx->open_b, ctx->o_keep, ctx->o_inB,
                     ctx->b_ids, ctx->b_off, ctx->b_deg, ctx->c_head, ctx->c_parent, ctx->c_edge,
-                    ctx->c_step, ctx->c_pop, ctx->c_pos, ctx->c_cost, ctx->c_mask, ctx->c_flag,
+                    ctx->c_step, ctx->c_pop, ctx->c_pos, ctx->tasks, ctx->c_cost, ctx->c_mask, ctx->c_flag,
                     ctx->blk, ctx->ctl, ctx->goal_ids, ctx->front_ids, ctx->paths,
                     ctx->path_len, ctx->wp_len, ctx->mc_counts, ctx->wp};
     for (void* p : ptrs)
@@ -395,6 +353,7 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     A(dalloc(&ctx->deg, nn + 1));
     A(dalloc(&ctx->row_ptr, nn + 2));
     A(dalloc(&ctx->col, E));
+    A(dalloc(&ctx->esrc, E));
     A(dalloc(&ctx->etau, E));
     A(dalloc(&ctx->ecost, E));
     A(dalloc(&ctx->p_head, P));
@@ -420,6 +379,7 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     A(dalloc(&ctx->c_step, Q));
     A(dalloc(&ctx->c_pop, Q));
     A(dalloc(&ctx->c_pos, Q));
+    A(dalloc(&ctx->tasks, Q));
     A(dalloc(&ctx->c_cost, Q));
     A(dalloc(&ctx->c_mask, Q * ctx->W));
     A(dalloc(&ctx->c_flag, Q));
@@ -483,23 +443,11 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
     ctx->eta = cfg.eta > 0.0f ? (double)cfg.eta : eta_rule(ctx->alpha);
     ctx->alpha_min = ctx->alpha / ctx->eta;
     ctx->alpha_max = ctx->eta * ctx->alpha;
-    // integer forms of the cp_hat tests (pop / N is exact for N a power of 2)
-    ctx->c_cut = (int)std::min<double>(ceil(ctx->alpha_max * N), (double)(N + 1));
-    ctx->c_min = (int)std::min<double>(ceil(ctx->alpha_min * N), (double)(N + 1));
+    cp_thresholds(ctx->alpha, ctx->eta, N, &ctx->c_cut, &ctx->c_min);
     ctx->h = (double)cfg.lambda * (double)cfg.r_conn;
     // tracking constants (eq. (2) for the double integrator; LQR)
-    lqr_axis(ctx->dt, (double)cfg.q_pos, (double)cfg.q_vel, (double)cfg.r_track, ctx->K);
-    const double dt = ctx->dt, s2 = (double)pr->sigma * (double)pr->sigma;
-    const double Bd[2] = {0.5 * dt * dt, dt};
-    ctx->Acl[0] = 1.0 - Bd[0] * ctx->K[0];
-    ctx->Acl[1] = dt - Bd[0] * ctx->K[1];
-    ctx->Acl[2] = -Bd[1] * ctx->K[0];
-    ctx->Acl[3] = 1.0 - Bd[1] * ctx->K[1];
-    const double V00 = s2 * (dt + dt * dt * dt / 3.0), V10 = s2 * (0.5 * dt * dt), V11 = s2 * dt;
-    ctx->L[0] = sqrt(V00);
-    ctx->L[1] = 0.0;
-    ctx->L[2] = ctx->L[0] > 0.0 ? V10 / ctx->L[0] : 0.0;
-    ctx->L[3] = sqrt(std::max(0.0, V11 - ctx->L[2] * ctx->L[2]));
+    tracking_constants(ctx->dt, (double)cfg.q_pos, (double)cfg.q_vel, (double)cfg.r_track,
+                       (double)pr->sigma, ctx->K, ctx->Acl, ctx->L);
 
     HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
     // uploads: x_init is node 0, sample i is node i + 1
@@ -551,7 +499,7 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
                           ctx->stream));
     tbeg(ctx, 2);
     launch_graph_fill(ctx->stream, ctx->X, ctx->n_nodes, (double)cfg.r_steer, ctx->ebits, ctx->row_ptr,
-                      ctx->col, ctx->etau, ctx->ecost, ctx->words_per_row);
+                      ctx->col, ctx->esrc, ctx->etau, ctx->ecost, ctx->words_per_row, ctx->n_edges);
     tend(ctx);
     HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev[1]));

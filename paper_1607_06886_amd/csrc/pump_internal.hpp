@@ -38,6 +38,8 @@ struct Ctl {
     int32_t n_surv;
     int32_t n_goal;
     int32_t n_front;
+    int32_t n_tasks;           // pairs queued for particle simulation this round
+    int32_t pad_;
     unsigned long long min_cost_bits;
     long long simulated;
     long long preprune;
@@ -96,7 +98,8 @@ struct RoundArgs {
     double* c_cost;
     uint32_t* c_mask;
     uint8_t* c_flag;
-    int32_t* c_pos;            // scan input/output over the pairs
+    int32_t* c_pos;            // scan input/output over the pairs (waypoint mask before)
+    int32_t* tasks;            // pairs queued for particle simulation
     Ctl* ctl;
 };
 
@@ -112,7 +115,7 @@ void launch_graph_mark(hipStream_t s, const float* X, const uint8_t* valid, int 
                        uint32_t* ebits, int32_t* deg, int words);
 void launch_graph_fill(hipStream_t s, const float* X, int n_nodes, double r_steer,
                        const uint32_t* ebits, const int32_t* row_ptr, int32_t* col,
-                       double* etau, double* ecost, int words);
+                       int32_t* esrc, double* etau, double* ecost, int words, int n_edges);
 
 void scan_exclusive(hipStream_t s, const int32_t* in, int32_t* out, const int32_t* n_dev,
                     int32_t n_upper, int32_t* total_dev, int32_t* blk_scratch);
@@ -152,6 +155,50 @@ struct SelectArgs {
     double L[4];
     Ctl* ctl;
 };
+
+// One query of the batched engine: its round and selection state plus the
+// graph-build buffers and inputs, all in device memory.
+struct BatchQuery {
+    RoundArgs a;
+    SelectArgs s;
+    const float* samples;      // [n][6] caller's device array
+    const float* obs_src;      // [n_obs][6] caller's device array
+    const float* noise;        // [S_max][6][N] caller's device array
+    float x_init[6];
+    float goal_box[6];
+    double Acl[4], L[4];
+    double alpha;
+    double r_steer, r_conn;
+    int32_t N, n_nodes, words;
+    int32_t cap_pairs, cap_edges;
+    int32_t bad;               // input / capacity errors (bit flags)
+    float* X;
+    float* obs;
+    uint8_t* valid;
+    uint8_t* goal;
+    uint32_t* ebits;
+    int32_t* deg;
+    int32_t* row_ptr;
+    int32_t* col;
+    int32_t* esrc;
+    double* etau;
+    double* ecost;
+    int32_t* b_deg;
+    int32_t* open_a;
+    int32_t* open_b;
+};
+
+// Per-query outcome written by the batched engine.
+struct BatchOut {
+    int32_t status, n_goal, n_front, best, best_plan, best_pop, best_mc, best_len;
+    double best_cost, best_cp_mc;
+    int32_t n_plans, n_edges, rounds, final_i, err, bad;
+    long long partial_plans;
+};
+
+void launch_batch(hipStream_t s, BatchQuery* qs_dev, int q, int N_max, int max_nodes, int S_max,
+                  int M, int words, int explore_blocks, int explore_threads, int* counters,
+                  BatchOut* out, const int* order);
 
 void launch_select_front(hipStream_t s, const SelectArgs& a);
 void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths);

@@ -1,0 +1,258 @@
+// Per-query setup operations: the particle deviation table and BuildGraph
+// (Alg. 3), shared by the single-query kernels and the batched engine.
+#pragma once
+
+#include "device_math.hpp"
+#include "pump_internal.hpp"
+
+namespace pump {
+
+
+// ---------------------------------------------------------------------------
+// Particle deviation table (Sec. III-B particles; eq. (2) closed loop).
+// One thread per (axis a, particle j) runs the recurrence
+//   dx_{s+1} = A_cl dx_s + L (xi[s][2a][j], xi[s][2a+1][j])^T,  dx_0 = 0
+// in FP64 and stores the position part D[s][a][j] in FP32.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void deviation_dev(const float* __restrict__ noise, float* __restrict__ D, int N,
+                            int S, double a00, double a01, double a10, double a11, double l00,
+                            double l10, double l11) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * N) return;
+    int a = t / N, j = t - a * N;
+    double p = 0.0, v = 0.0;
+    D[(size_t)a * N + j] = 0.0f;
+    constexpr int U = 8;   // noise loads issued a block of steps ahead
+    for (int s0 = 0; s0 < S; s0 += U) {
+        float w0[U], w1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int s = s0 + u < S ? s0 + u : S - 1;
+            w0[u] = noise[((size_t)s * 6 + 2 * a) * N + j];
+            w1[u] = noise[((size_t)s * 6 + 2 * a + 1) * N + j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (s0 + u >= S) break;
+            double pn = a00 * p + a01 * v + l00 * (double)w0[u];
+            double vn = a10 * p + a11 * v + (l10 * (double)w0[u] + l11 * (double)w1[u]);
+            p = pn;
+            v = vn;
+            D[((size_t)(s0 + u + 1) * 3 + a) * N + j] = (float)p;
+        }
+    }
+}
+
+// Bounding box of the particle cloud at each step: cloud[s] = (min_j D[s][a][j], max_j ...).
+__device__ __forceinline__ void cloud_dev(const float* __restrict__ D, float* __restrict__ cloud, int N) {
+    __shared__ float smin[3][256], smax[3][256];
+    int s = blockIdx.x, t = threadIdx.x;
+    for (int a = 0; a < 3; ++a) {
+        float mn = INFINITY, mx = -INFINITY;
+        for (int j = t; j < N; j += blockDim.x) {
+            float d = D[((size_t)s * 3 + a) * N + j];
+            mn = fminf(mn, d);
+            mx = fmaxf(mx, d);
+        }
+        smin[a][t] = mn;
+        smax[a][t] = mx;
+    }
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int a = 0; a < 3; ++a) {
+                smin[a][t] = fminf(smin[a][t], smin[a][t + w]);
+                smax[a][t] = fmaxf(smax[a][t], smax[a][t + w]);
+            }
+        __syncthreads();
+    }
+    if (t < 3) {
+        cloud[(size_t)s * 6 + t] = smin[t][0];
+        cloud[(size_t)s * 6 + 3 + t] = smax[t][0];
+    }
+}
+
+__device__ __forceinline__ void gcloud_dev(const float* __restrict__ cloud, float* __restrict__ g, int S1) {
+    __shared__ float sm[6][256];
+    const int t = threadIdx.x;
+    float v[6];
+    for (int k = 0; k < 6; ++k) v[k] = k < 3 ? INFINITY : -INFINITY;
+    for (int s = t; s < S1; s += blockDim.x)
+        for (int k = 0; k < 6; ++k) {
+            float c = cloud[(size_t)s * 6 + k];
+            v[k] = k < 3 ? fminf(v[k], c) : fmaxf(v[k], c);
+        }
+    for (int k = 0; k < 6; ++k) sm[k][t] = v[k];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < 6; ++k)
+                sm[k][t] = k < 3 ? fminf(sm[k][t], sm[k][t + w]) : fmaxf(sm[k][t], sm[k][t + w]);
+        __syncthreads();
+    }
+    if (t < 6) g[t] = sm[t][0];
+}
+
+// ---------------------------------------------------------------------------
+// Node validity (sample not in a closed obstacle box) and goal membership
+// (position in the closed goal box).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mark_valid_dev(const float* __restrict__ X, int n, const float* __restrict__ obs,
+                             int n_obs, float g0, float g1, float g2, float g3, float g4, float g5,
+                             uint8_t* __restrict__ valid, uint8_t* __restrict__ goal,
+                             int32_t* __restrict__ bad) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n_obs) {
+        // obstacle sanity: finite, ordered, inside [-16, 16]
+        const float* b = obs + (size_t)v * 6;
+        bool okb = true;
+        for (int k = 0; k < 3; ++k)
+            okb &= (b[k] <= b[3 + k]) & (fabsf(b[k]) <= 16.0f) & (fabsf(b[3 + k]) <= 16.0f);
+        if (!okb) atomicOr(bad, 1);
+    }
+    if (v >= n) return;
+    float p0 = X[(size_t)v * 6], p1 = X[(size_t)v * 6 + 1], p2 = X[(size_t)v * 6 + 2];
+    if (!(fabsf(p0) <= 16.0f && fabsf(p1) <= 16.0f && fabsf(p2) <= 16.0f)) atomicOr(bad, 1);
+    bool in = false;
+    for (int o = 0; o < n_obs; ++o) {
+        const float* b = obs + (size_t)o * 6;
+        in |= (p0 >= b[0]) & (p0 <= b[3]) & (p1 >= b[1]) & (p1 <= b[4]) & (p2 >= b[2]) & (p2 <= b[5]);
+    }
+    if (v == 0 && in) atomicOr(bad, 2);
+    valid[v] = in ? 0 : 1;
+    bool g = (p0 >= g0) & (p0 <= g3) & (p1 >= g1) & (p1 <= g4) & (p2 >= g2) & (p2 <= g5);
+    goal[v] = (!in && g) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// BuildGraph (Alg. 3).  Edge v -> u iff both nodes are valid, u != v,
+// c*(v,u) < r_n, tau* > 1e-6 and the nominal trajectory meets no obstacle
+// (continuous, exact; closed boxes).  Pass 1 evaluates every ordered pair and
+// records the result as a bit matrix and per-row counts; after a scan of the
+// counts, pass 2 writes each row's neighbours in ascending order with their
+// (tau*, c*).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool edge_free(const float* xv, const float* xu, double tau,
+                                          const float* s_obs, int n_obs) {
+    Cubic cs[3];
+    hermite(xv, xu, tau, cs);
+    double mn[3], mx[3];
+    for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
+    for (int o = 0; o < n_obs; ++o) {
+        const float* b = s_obs + o * 6;
+        bool disjoint = false;
+        for (int a = 0; a < 3; ++a)
+            disjoint |= (mx[a] < (double)b[a]) | (mn[a] > (double)b[3 + a]);
+        if (disjoint) continue;
+        if (trajectory_hits_box(cs, tau, b)) return false;
+    }
+    return true;
+}
+
+// One block per source row v.  The row is scanned in chunks of 4096 targets:
+// every thread applies the exact rejection test to 16 targets and appends the
+// survivors to a list in LDS; the block then steers the survivors densely (one
+// per thread) and sets their bits in the row's LDS bitmask, which is written
+// out with the row's degree at the end.
+constexpr int kMarkChunk = 4096;
+
+__device__ __forceinline__ void graph_mark_dev(const float* __restrict__ X,
+                                                    const uint8_t* __restrict__ valid, int n,
+                                                    const float* __restrict__ obs, int n_obs,
+                                                    double r_steer, double r_conn,
+                                                    uint32_t* __restrict__ ebits,
+                                                    int32_t* __restrict__ deg, int words) {
+    __shared__ float s_obs[kMaxObs * 6];
+    __shared__ int s_list[kMarkChunk];
+    __shared__ int s_cnt;
+    extern __shared__ uint32_t s_row[];          // words u32
+    for (int t = threadIdx.x; t < n_obs * 6; t += blockDim.x) s_obs[t] = obs[t];
+    for (int t = threadIdx.x; t < words; t += blockDim.x) s_row[t] = 0u;
+    const int v = blockIdx.x;
+    float xv[6];
+    for (int k = 0; k < 6; ++k) xv[k] = X[(size_t)v * 6 + k];
+    const bool vv = valid[v] != 0;
+    __syncthreads();
+    if (vv) {
+        for (int c0 = 0; c0 < n; c0 += kMarkChunk) {
+            if (threadIdx.x == 0) s_cnt = 0;
+            __syncthreads();
+            for (int u = c0 + threadIdx.x; u < c0 + kMarkChunk && u < n; u += blockDim.x) {
+                if (u == v || !valid[u]) continue;
+                float xu[6];
+                for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)u * 6 + k];
+                if (!surely_not_near(boundary_sums(xv, xu), r_steer, r_conn))
+                    s_list[atomicAdd(&s_cnt, 1)] = u;
+            }
+            __syncthreads();
+            const int cnt = s_cnt;
+            for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+                const int u = s_list[i];
+                float xu[6];
+                for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)u * 6 + k];
+                double tau, c;
+                steer64(xv, xu, r_steer, tau, c);
+                if (c < r_conn && tau > kTauMin && edge_free(xv, xu, tau, s_obs, n_obs))
+                    atomicOr(&s_row[u >> 5], 1u << (u & 31));
+            }
+            __syncthreads();
+        }
+    }
+    int d = 0;
+    for (int t = threadIdx.x; t < words; t += blockDim.x) {
+        const uint32_t w = s_row[t];
+        ebits[(size_t)v * words + t] = w;
+        d += __popc(w);
+    }
+    // block sum of the degree
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_down(d, o, 64);
+    __shared__ int s_deg[4];
+    if ((threadIdx.x & 63) == 0) s_deg[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) deg[v] = s_deg[0] + s_deg[1] + s_deg[2] + s_deg[3];
+}
+
+__device__ __forceinline__ void graph_fill_dev(int n, const uint32_t* __restrict__ ebits,
+                                                    const int32_t* __restrict__ row_ptr,
+                                                    int32_t* __restrict__ col,
+                                                    int32_t* __restrict__ esrc, int words) {
+    const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (v >= n) return;
+    int pos = row_ptr[v];
+    for (int base = 0; base < n; base += 64) {
+        uint32_t w = ebits[(size_t)v * words + base / 32 + (lane >> 5)];
+        bool e = (w >> (lane & 31)) & 1u;
+        unsigned long long b = __ballot(e);
+        if (e) {
+            unsigned long long below = lane ? (b & ((1ull << lane) - 1ull)) : 0ull;
+            int at = pos + (int)__popcll(below);
+            col[at] = base + lane;
+            esrc[at] = v;
+        }
+        pos += (int)__popcll(b);
+    }
+}
+
+// Edge controls, one lane per edge: the same FP64 steering as pass 1, so the
+// cached (tau*, c*) are bit-identical to the values that admitted the edge.
+__device__ __forceinline__ void edge_steer_dev(const float* __restrict__ X, int n,
+                                                    double r_steer,
+                                                    const int32_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const int32_t* __restrict__ esrc,
+                                                    double* __restrict__ etau,
+                                                    double* __restrict__ ecost) {
+    const int E = row_ptr[n];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x) {
+        const float* xv = X + (size_t)esrc[e] * 6;
+        const float* xu = X + (size_t)col[e] * 6;
+        double tau, c;
+        steer64(xv, xu, r_steer, tau, c);
+        etau[e] = tau;
+        ecost[e] = c;
+    }
+}
+
+
+}  // namespace pump

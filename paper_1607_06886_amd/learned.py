@@ -1,0 +1,238 @@
+"""Learned sampling proposal driver: data from plain PUMP, training on the
+device, and plain-vs-learned evaluation.
+
+Every numerical step runs in libpump kernels (planning, condition vectors,
+MLP forward/backward/Adam, mixture sampling); this module only moves arrays
+and keeps score.  A learned query draws half of its n samples from the
+network's mixture and half uniformly (with the usual goal-box share), then
+runs plain PUMP on them; the plan it returns is certified by MC(p) exactly as
+in the plain method (Alg. 5), so the CP guarantee is unchanged.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import _lib, scenes
+
+MAX_BOXES = 64
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def device_noise(S, N, M, seed):
+    """Standard normals for the exploration and certification particles."""
+    torch = _torch()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(seed))
+    noise = torch.randn((S, 6, N), generator=g, device="cuda", dtype=torch.float32)
+    noise_mc = torch.randn((S, 6, M), generator=g, device="cuda", dtype=torch.float32)
+    return noise, noise_mc
+
+
+class Runner:
+    """A planner context plus shared device noise for many queries."""
+
+    def __init__(self, n_max, N, S_max=256, M=2000, seed=0, n_obs_max=64):
+        self.N, self.S_max, self.M = N, S_max, M
+        self.pl = _lib.Planner(n_particles=N, max_nodes=n_max + 1, max_obstacles=n_obs_max,
+                               max_steps=S_max, mc_particles=M, cap_plans=1 << 21,
+                               cap_pairs=1 << 23, cap_edges=1 << 25)
+        self.noise, self.noise_mc = device_noise(S_max, N, M, seed)
+
+    def plan(self, x_init, goal, boxes, samples, alpha, sigma):
+        torch = _torch()
+        s = samples if not isinstance(samples, np.ndarray) else torch.from_numpy(samples).cuda()
+        b = torch.from_numpy(np.ascontiguousarray(boxes, np.float32)).cuda()
+        pr = self.pl.problem(s, b, x_init, goal, alpha, sigma, self.noise, self.noise_mc)
+        res = self.pl.plan(pr)
+        path = self.pl.path(res["best_plan"]) if res["status"] == 0 else None
+        return res, path
+
+    def close(self):
+        self.pl.close()
+
+
+def condition_batch(mlp, maps):
+    """Condition vectors [q, 396] (device) for a list of (x_init, goal, boxes)."""
+    torch = _torch()
+    q = len(maps)
+    x0 = np.stack([m[0] for m in maps]).astype(np.float32)
+    g = np.stack([m[1] for m in maps]).astype(np.float32)
+    bx = np.zeros((q, MAX_BOXES, 6), np.float32)
+    nb = np.zeros(q, np.int32)
+    for i, m in enumerate(maps):
+        k = min(MAX_BOXES, m[2].shape[0])
+        bx[i, :k] = m[2][:k]
+        nb[i] = k
+    t = lambda a: torch.from_numpy(a).cuda()
+    return mlp.condition(t(x0), t(g), t(bx), t(nb))
+
+
+def generate(n_queries, kinds, n_samples, N, alpha, sigma, seed0, log=None):
+    """Certified plans of plain PUMP on random maps: returns the maps, and per
+    certified plan its map index and node states (x_init excluded)."""
+    run = Runner(n_samples, N, seed=seed0)
+    maps, plans = [], []
+    t0 = time.time()
+    for q in range(n_queries):
+        kind = kinds[q % len(kinds)]
+        x0, g, b = scenes.random_map(kind, seed0 + q)
+        smp = scenes.uniform_samples(seed0 + q, n_samples, b, g)
+        res, path = run.plan(x0, g, b, smp, alpha, sigma)
+        maps.append((x0, g, b))
+        if path is not None and len(path) > 1:
+            plans.append((q, smp[np.asarray(path[1:]) - 1]))
+        if log and (q + 1) % 500 == 0:
+            log(f"generated {q + 1}/{n_queries} queries, {len(plans)} certified plans, "
+                f"{time.time() - t0:.0f} s")
+    run.close()
+    return maps, plans
+
+
+def train(mlp, maps, plans, steps, batch, lr, seed, log=None):
+    """Adam on the mean mixture NLL of certified-plan node states given their
+    map's condition vector."""
+    torch = _torch()
+    cond_all = condition_batch(mlp, maps)                    # [n_maps, 396] device
+    idx = np.concatenate([np.full(len(st), q, np.int64) for q, st in plans])
+    tgt = torch.from_numpy(np.concatenate([st for _, st in plans]).astype(np.float32)).cuda()
+    idx_t = torch.from_numpy(idx).cuda()
+    rng = np.random.default_rng(seed)
+    losses = []
+    for s in range(steps):
+        sel = torch.from_numpy(rng.integers(0, idx.shape[0], batch)).cuda()
+        c = cond_all.index_select(0, idx_t.index_select(0, sel)).contiguous()
+        z = tgt.index_select(0, sel).contiguous()
+        losses.append(mlp.train_step(c, z, lr))
+        if log and (s + 1) % 500 == 0:
+            log(f"step {s + 1}: loss {np.mean(losses[-100:]):.3f}")
+    return losses
+
+
+def learned_samples(mlp, x0, g, b, n, seed):
+    """n states: n // 2 from the mixture, the rest uniform (with the goal
+    share).  Returns a device tensor [n, 6] and the sampling time in ms."""
+    torch = _torch()
+    n_l = n // 2
+    uni = scenes.uniform_samples(seed, n - n_l, b, g)
+    rng = np.random.default_rng(seed + 17)
+    u = torch.from_numpy(rng.uniform(0, 1, (1, n_l)).astype(np.float32)).cuda()
+    eps = torch.from_numpy(rng.standard_normal((1, n_l, 6)).astype(np.float32)).cuda()
+    uni_t = torch.from_numpy(uni).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cond = condition_batch(mlp, [(x0, g, b)])
+    z = mlp.sample(cond, u, eps)[0]
+    out = torch.cat([z, uni_t], 0).contiguous()
+    torch.cuda.synchronize()
+    return out, 1e3 * (time.perf_counter() - t0)
+
+
+def evaluate(mlp, n_maps, kinds, sizes, N, alpha, sigma, seed0, log=None):
+    """Plain (n uniform) vs learned (n/2 mixture + n/2 uniform) on held-out maps."""
+    run = Runner(max(sizes), N, seed=seed0 + 99)
+    rows = []
+    for q in range(n_maps):
+        kind = kinds[q % len(kinds)]
+        x0, g, b = scenes.random_map(kind, seed0 + q)
+        for n in sizes:
+            smp = scenes.uniform_samples(seed0 + q, n, b, g)
+            rp, _ = run.plan(x0, g, b, smp, alpha, sigma)
+            ls, ms_s = learned_samples(mlp, x0, g, b, n, seed0 + q)
+            rl, _ = run.plan(x0, g, b, ls, alpha, sigma)
+            rows.append(dict(map=q, kind=kind, n=n,
+                             plain_status=rp["status"], plain_cost=rp["best_cost"],
+                             plain_cp=rp["best_cp_mc"], plain_ms=rp["ms_total"],
+                             learned_status=rl["status"], learned_cost=rl["best_cost"],
+                             learned_cp=rl["best_cp_mc"], learned_ms=rl["ms_total"] + ms_s))
+        if log and (q + 1) % 10 == 0:
+            log(f"evaluated {q + 1}/{n_maps} maps")
+    run.close()
+    return rows
+
+
+def summarise(rows, sizes):
+    out = {}
+    for n in sizes:
+        r = [x for x in rows if x["n"] == n]
+        ok_p = [x for x in r if x["plain_status"] == 0]
+        ok_l = [x for x in r if x["learned_status"] == 0]
+        both = [x for x in r if x["plain_status"] == 0 and x["learned_status"] == 0]
+        out[n] = dict(
+            maps=len(r), plain_certified=len(ok_p), learned_certified=len(ok_l),
+            mean_plain_cost=float(np.mean([x["plain_cost"] for x in both])) if both else None,
+            mean_learned_cost=float(np.mean([x["learned_cost"] for x in both])) if both else None,
+            learned_le_plain=float(np.mean([x["learned_cost"] <= x["plain_cost"] + 1e-12
+                                           for x in both])) if both else None,
+            max_cp_plain=max([x["plain_cp"] for x in ok_p], default=None),
+            max_cp_learned=max([x["learned_cp"] for x in ok_l], default=None),
+            median_plain_ms=float(np.median([x["plain_ms"] for x in r])),
+            median_learned_ms=float(np.median([x["learned_ms"] for x in r])),
+        )
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--queries", type=int, default=2000)
+    ap.add_argument("--n-train", type=int, default=4000)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=2048)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-maps", type=int, default=40)
+    ap.add_argument("--sizes", type=str, default="1000,2000,4000,8000")
+    ap.add_argument("--out", type=str, default="learned.json")
+    ap.add_argument("--weights", type=str, default="")
+    args = ap.parse_args()
+    torch = _torch()
+    torch.cuda.set_device(0)
+    log = lambda m: print(m, flush=True)
+    kinds = ["boxes", "indoor"]
+    t0 = time.time()
+    maps, plans = generate(args.queries, kinds, args.n_train, 128, 0.01, 0.02, 10_000, log)
+    log(f"data: {len(plans)} certified plans of {args.queries} queries in {time.time() - t0:.0f} s")
+    mlp = _lib.MLP(max(args.batch, 64))
+    mlp.set_params(init_params(7))
+    t1 = time.time()
+    losses = train(mlp, maps, plans, args.steps, args.batch, args.lr, 8, log)
+    log(f"trained {args.steps} steps in {time.time() - t1:.1f} s: "
+        f"loss {np.mean(losses[:50]):.3f} -> {np.mean(losses[-50:]):.3f}")
+    if args.weights:
+        mlp.get_params().tofile(args.weights)
+    sizes = [int(x) for x in args.sizes.split(",")]
+    rows = evaluate(mlp, args.eval_maps, kinds, sizes, 256, 0.01, 0.02, 900_000, log)
+    summary = dict(queries=args.queries, certified_plans=len(plans),
+                   targets=int(sum(len(st) for _, st in plans)), steps=args.steps,
+                   batch=args.batch, lr=args.lr, loss_first=float(np.mean(losses[:50])),
+                   loss_last=float(np.mean(losses[-50:])), eval=summarise(rows, sizes))
+    os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
+    with open(args.out, "w") as f:
+        json.dump(dict(summary=summary, rows=rows), f)
+    log(json.dumps(summary))
+    mlp.close()
+
+
+def init_params(seed):
+    """He-uniform weights and zero biases, flat in the library's layout."""
+    rng = np.random.default_rng(seed)
+    dims = [(396, 256), (256, 256), (256, 256), (256, 256), (256, 208)]
+    parts = []
+    for fi, fo in dims:
+        lim = math.sqrt(6.0 / fi)
+        parts.append(rng.uniform(-lim, lim, fo * fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+if __name__ == "__main__":
+    main()

@@ -193,18 +193,8 @@ def free_samples(rng, n: int, boxes: np.ndarray, goal, n_goal: int) -> np.ndarra
     return np.ascontiguousarray(np.concatenate([pos, vel], axis=1).astype(np.float32))
 
 
-def make_scene(spec, seed: int, *, M: int = 10_000, S_max: int = 512,
-               n: Optional[int] = None, N: Optional[int] = None,
-               n_obs: Optional[int] = None, alpha: Optional[float] = None,
-               sigma: Optional[float] = None) -> Scene:
-    """Build one seeded query.  `spec` is a WORKLOADS key or a dict of the same
-    fields; keyword arguments override individual fields."""
-    p = dict(WORKLOADS[spec]) if isinstance(spec, str) else dict(spec)
-    name = spec if isinstance(spec, str) else p.get("name", "custom")
-    for k, v in (("n", n), ("N", N), ("n_obs", n_obs), ("alpha", alpha),
-                 ("sigma", sigma)):
-        if v is not None:
-            p[k] = v
+def _map_of(p, seed: int):
+    """x_init, goal box, obstacle boxes and samples of one query (stream 0)."""
     rng = _rng(seed, 0)
     if p.get("indoor"):
         x_init = np.asarray(INDOOR_X_INIT, np.float32)
@@ -218,6 +208,22 @@ def make_scene(spec, seed: int, *, M: int = 10_000, S_max: int = 512,
     n_s = int(p["n"])
     n_goal = max(1, int(math.ceil(0.01 * n_s)))
     samples = free_samples(rng, n_s, boxes, goal, n_goal)
+    return x_init, goal, np.ascontiguousarray(boxes, np.float32), samples
+
+
+def make_scene(spec, seed: int, *, M: int = 10_000, S_max: int = 512,
+               n: Optional[int] = None, N: Optional[int] = None,
+               n_obs: Optional[int] = None, alpha: Optional[float] = None,
+               sigma: Optional[float] = None) -> Scene:
+    """Build one seeded query.  `spec` is a WORKLOADS key or a dict of the same
+    fields; keyword arguments override individual fields."""
+    p = dict(WORKLOADS[spec]) if isinstance(spec, str) else dict(spec)
+    name = spec if isinstance(spec, str) else p.get("name", "custom")
+    for k, v in (("n", n), ("N", N), ("n_obs", n_obs), ("alpha", alpha),
+                 ("sigma", sigma)):
+        if v is not None:
+            p[k] = v
+    x_init, goal, boxes, samples = _map_of(p, seed)
     Np = int(p["N"])
     noise = _rng(seed, 1).standard_normal((S_max, 6, Np), dtype=np.float32)
     noise_mc = _rng(seed, 2).standard_normal((S_max, 6, int(M)), dtype=np.float32)
@@ -226,3 +232,69 @@ def make_scene(spec, seed: int, *, M: int = 10_000, S_max: int = 512,
                  N=Np, sigma=float(np.float32(p["sigma"])),
                  noise=np.ascontiguousarray(noise), noise_mc=np.ascontiguousarray(noise_mc),
                  name=name, seed=int(seed))
+
+
+# ---------------------------------------------------------------------------
+# Maps for the learned-proposal workloads: random start and goal per map.
+# ---------------------------------------------------------------------------
+ROOM_CENTRES = [(0.125 + 0.25 * i, 0.125 + 0.25 * j) for i in range(4) for j in range(4)]
+
+
+def random_map(kind: str, seed: int):
+    """(x_init [6], goal [6], boxes [k, 6]) of one map.
+
+    'boxes': n_obs ~ U{5..60} boxes with sides U[0.05, 0.25], a start uniform in
+    [0.05, 0.95]^3 at rest and a 0.1-wide goal box at least 0.6 away.
+    'indoor': the 4x4 room grid with random doorways, start and goal at the
+    centres of two rooms at least two rooms apart (height 0.3), goal box 0.05."""
+    rng = _rng(seed, 3)
+    if kind == "indoor":
+        boxes = indoor_boxes(rng)
+        while True:
+            a, b = rng.choice(16, 2, replace=False)
+            (ax, ay), (bx, by) = ROOM_CENTRES[a], ROOM_CENTRES[b]
+            if abs(ax - bx) + abs(ay - by) >= 0.5 - 1e-9:
+                break
+        x_init = np.array([ax, ay, 0.3, 0, 0, 0], np.float32)
+        c = np.array([bx, by, 0.3])
+        goal = np.concatenate([c - INDOOR_GOAL_HALF, c + INDOOR_GOAL_HALF]).astype(np.float32)
+        return x_init, goal, boxes
+    while True:
+        s = rng.uniform(0.05, 0.95, 3)
+        c = rng.uniform(0.1, 0.9, 3)
+        if np.linalg.norm(c - s) >= 0.6:
+            break
+    x_init = np.concatenate([s, np.zeros(3)]).astype(np.float32)
+    goal = np.concatenate([c - 0.05, c + 0.05]).astype(np.float32)
+    boxes = random_boxes(rng, int(rng.integers(5, 61)), (0.05, 0.25), x_init, goal)
+    return x_init, goal, boxes
+
+
+def uniform_samples(seed: int, n: int, boxes, goal) -> np.ndarray:
+    """SampleFree(n): 1% (at least one) in the goal box, the rest uniform in the
+    unit cube, all outside the boxes; velocities uniform."""
+    rng = _rng(seed, 4)
+    return free_samples(rng, n, np.asarray(boxes, np.float32), goal, max(1, int(math.ceil(0.01 * n))))
+
+
+# ---------------------------------------------------------------------------
+# Batched workload: many independent queries of uneven size.
+# ---------------------------------------------------------------------------
+def batch_specs(seed: int, q: int = 256):
+    """Shapes of q batched queries: n ~ U{1000..8000} samples, N in
+    {64, 128, 256} particles, n_obs ~ U{5..60} random boxes with sides
+    U[0.05, 0.25], alpha in {0.01, 0.05}, sigma 0.02."""
+    rng = _rng(seed, 5)
+    out = []
+    for i in range(q):
+        out.append(dict(n=int(rng.integers(1000, 8001)), N=int(rng.choice([64, 128, 256])),
+                        n_obs=int(rng.integers(5, 61)), side=(0.05, 0.25), sigma=0.02,
+                        alpha=float(rng.choice([0.01, 0.05])), indoor=False,
+                        name=f"batch{i}"))
+    return out
+
+
+def batch_map(spec, seed: int):
+    """(x_init, goal, boxes, samples) of one batched query; its noise arrays
+    are drawn by the caller (on the device for large batches)."""
+    return _map_of(spec, seed)

@@ -2,9 +2,14 @@
 
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
+from oracle import pump as opump
 from paper_1607_06886_amd import _lib, scenes
+
+CFG = opump.Config()
 
 
 def small_spec(n=150, N=32, sigma=0.02, alpha=0.05, n_obs=3, side=(0.1, 0.3)):
@@ -45,3 +50,27 @@ def mask_words_from_bool(m):
 
 def print_case(name, **kw):
     print(f"[gpu case] {name} {kw}", flush=True)
+
+
+def scene(kind, seed):
+    """Parity scenes (M = 2000 certification particles, S_max = 256)."""
+    if kind == "cfg1":
+        return scenes.make_scene("cfg1", scenes.workload_seed(1, seed), M=2000, S_max=256)
+    if kind == "boxes20":
+        return scenes.make_scene(small_spec(n=400, N=128, sigma=0.02, alpha=0.01, n_obs=20,
+                                            side=(0.05, 0.25)), 500 + seed, M=2000, S_max=256)
+    if kind == "indoor":
+        return scenes.make_scene(dict(n=450, n_obs=60, side=None, N=128, sigma=0.02, alpha=0.05,
+                                      indoor=True), 700 + seed, M=2000, S_max=256)
+    if kind == "n64":
+        return scenes.make_scene(small_spec(n=250, N=64, sigma=0.03, alpha=0.05, n_obs=8),
+                                 900 + seed, M=2000, S_max=256)
+    if kind == "n256":
+        return scenes.make_scene(small_spec(n=300, N=256, sigma=0.02, alpha=0.02, n_obs=12,
+                                            side=(0.05, 0.25)), 950 + seed, M=2000, S_max=256)
+    raise ValueError(kind)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_run(kind, seed):
+    return opump.run(scene(kind, seed), CFG, record=True)

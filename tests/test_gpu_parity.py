@@ -8,15 +8,13 @@ ones).  Flagged decisions (a particle within 1e-5 of a face) are counted and
 printed; the tests require exact agreement regardless.
 """
 
-import functools
-
 import numpy as np
 import pytest
 
 from oracle import dynamics, graph as ogr, pump as opump, select as osel
 from paper_1607_06886_amd import _lib, scenes
-from tests._gpu import (gpu_plans, oracle_mask_bool, planner_for, print_case, small_spec,
-                        unpack_mask)
+from tests._gpu import (gpu_plans, oracle_mask_bool, oracle_run, planner_for, print_case, scene,
+                        small_spec, unpack_mask)
 
 pytestmark = pytest.mark.gpu
 
@@ -24,27 +22,8 @@ CFG = opump.Config()
 REL = 1e-12
 
 
-def _scene(kind, seed):
-    if kind == "cfg1":
-        return scenes.make_scene("cfg1", scenes.workload_seed(1, seed), M=2000, S_max=256)
-    if kind == "boxes20":
-        return scenes.make_scene(small_spec(n=400, N=128, sigma=0.02, alpha=0.01, n_obs=20,
-                                            side=(0.05, 0.25)), 500 + seed, M=2000, S_max=256)
-    if kind == "indoor":
-        return scenes.make_scene(dict(n=450, n_obs=60, side=None, N=128, sigma=0.02, alpha=0.05,
-                                      indoor=True), 700 + seed, M=2000, S_max=256)
-    if kind == "n64":
-        return scenes.make_scene(small_spec(n=250, N=64, sigma=0.03, alpha=0.05, n_obs=8),
-                                 900 + seed, M=2000, S_max=256)
-    if kind == "n256":
-        return scenes.make_scene(small_spec(n=300, N=256, sigma=0.02, alpha=0.02, n_obs=12,
-                                            side=(0.05, 0.25)), 950 + seed, M=2000, S_max=256)
-    raise ValueError(kind)
-
-
-@functools.lru_cache(maxsize=None)
-def _oracle(kind, seed):
-    return opump.run(_scene(kind, seed), CFG, record=True)
+_scene = scene
+_oracle = oracle_run
 
 
 @pytest.mark.parametrize("N", [32, 64, 128, 256])
