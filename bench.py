@@ -73,6 +73,10 @@ def kernel_models(sc, res, rounds_pairs, N):
         "expand": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
                        work=per_pair * (res["partial_plans"] / max(1, rounds_pairs)), scale=1e9,
                        per_pair_bytes=per_pair),
+        # Explore as one launch: every round's pairs in one kernel
+        "explore_single": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
+                               work=per_pair * res["partial_plans"], scale=1e9,
+                               per_pair_bytes=per_pair),
     }
 
 
@@ -235,8 +239,7 @@ def main():
     m = models[dom]
     ms_total, launches = kt[dom]
     avg_s = ms_total / 1e3 / max(1, launches)
-    per_launch = m["work"] if dom == "graph_mark" else m["work"]
-    achieved = per_launch / avg_s / m["scale"]
+    achieved = m["work"] / avg_s / m["scale"]
     roofline = {"bound": m["bound"], "kernel": dom, "achieved": achieved, "peak": m["peak"],
                 "unit": m["unit"], "frac": achieved / m["peak"], "traffic": None,
                 "avg_launch_us": avg_s * 1e6, "launches": launches}

@@ -211,13 +211,22 @@ int pump_mc_path(pump_ctx* ctx, const int32_t* nodes, int32_t len, int32_t* coun
  *   0 deviation table   1 graph pass 1 (all pairs)   2 graph pass 2 (fill)
  *   3 expand            4 prune (staircase update + mark)
  *   5 compact (scans + scatter)   6 next group (min, flags, scans)
- *   7 front selection   8 MC certification
+ *   7 front selection   8 MC certification   9 Explore as one launch
  * pump_set_timing(ctx, on) switches it and clears the totals;
  * pump_get_timing copies min(n, PUMP_TIMING_KINDS) totals (ms) and launch
  * counts (either pointer may be NULL). */
-#define PUMP_TIMING_KINDS 9
+#define PUMP_TIMING_KINDS 10
 int pump_set_timing(pump_ctx* ctx, int32_t on);
 int pump_get_timing(pump_ctx* ctx, double* ms, int64_t* launches, int32_t n);
+
+/* How pump_explore_run (and so pump_plan) runs Alg. 4's loop: mode 1 (the
+ * default where the device supports cooperative launches) runs all remaining
+ * rounds in one launch whose workgroups meet at grid-wide barriers; mode 0
+ * launches each phase of each round separately and reads the loop state back
+ * after every round (as pump_explore_round always does).  Both build the same
+ * plan store.  get reports the mode and the workgroups of the single launch. */
+int pump_set_explore_mode(pump_ctx* ctx, int32_t mode);
+int pump_get_explore_mode(pump_ctx* ctx, int32_t* mode, int32_t* blocks);
 
 /* ---------------------------------------------------------------------------
  * Learned sampling proposal.  The paper draws SampleFree(n) uniformly (Alg. 3;
@@ -227,7 +236,7 @@ int pump_get_timing(pump_ctx* ctx, double* ms, int64_t* launches, int32_t n);
  * centre 3 and half-size 3, then up to 64 obstacle boxes as lo xyz, hi xyz,
  * zero padded) -> 4 hidden layers of 256 with ReLU -> 208 outputs: 16 mixture
  * logits, then 16 x 6 means, then 16 x 6 log standard deviations (clamped to
- * [-7, 2]) of a diagonal Gaussian mixture over the 6-D state.  Weights are
+ * [-4, 2]) of a diagonal Gaussian mixture over the 6-D state.  Weights are
  * kept as FP32 masters with BF16 copies; matrix products take BF16 operands
  * with FP32 accumulation.  Parameters are one flat FP32 array: for each layer
  * W [out][in] row-major, then b [out].

@@ -9,7 +9,7 @@ the mixture, half stay uniform, and every plan is still certified by MC(p)
 
 Network: condition vector (start 6, goal centre 3, goal half-size 3, 64
 zero-padded boxes x (lo, hi) = 396) -> 4 hidden layers of 256 with ReLU ->
-16 x (1 logit + 6 means + 6 log-std) = 208; log-std clamped to [-7, 2].
+16 x (1 logit + 6 means + 6 log-std) = 208; log-std clamped to [-4, 2].
 Reading: weights are stored in BF16 and every matrix product takes BF16
 operands with FP32 accumulation; `bf16=True` rounds weights and layer inputs
 to BF16 (round to nearest even) exactly where the device does.
@@ -26,7 +26,7 @@ D_IN = 12 + 6 * MAX_BOXES          # 396
 HIDDEN = 256
 N_HIDDEN = 4
 D_OUT = K_COMP * (1 + 2 * D_STATE)  # 208
-LOGSTD_MIN, LOGSTD_MAX = -7.0, 2.0
+LOGSTD_MIN, LOGSTD_MAX = -4.0, 2.0
 LAYERS = [(D_IN, HIDDEN)] + [(HIDDEN, HIDDEN)] * (N_HIDDEN - 1) + [(HIDDEN, D_OUT)]
 # state box the samples live in (positions in the unit cube, velocities)
 STATE_LO = np.array([0.0, 0.0, 0.0, -0.5, -0.5, -0.5])

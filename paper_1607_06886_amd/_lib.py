@@ -84,7 +84,8 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
            "pump_explore_begin", "pump_explore_round", "pump_explore_run", "pump_select",
            "pump_get_deviation", "pump_get_graph", "pump_get_plans", "pump_get_candidates",
            "pump_get_front", "pump_get_path", "pump_mc_path", "pump_set_timing",
-           "pump_get_timing", "pump_status_str", "pump_last_error", "pump_mlp_create",
+           "pump_get_timing", "pump_set_explore_mode", "pump_get_explore_mode",
+           "pump_status_str", "pump_last_error", "pump_mlp_create",
            "pump_mlp_destroy", "pump_mlp_num_params", "pump_mlp_set_params",
            "pump_mlp_get_params", "pump_mlp_forward", "pump_mlp_loss_grad",
            "pump_mlp_train_step", "pump_mlp_condition", "pump_mlp_sample",
@@ -93,7 +94,7 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
            "pump_batch_last_error"]
 
 TIMING_KINDS = ["deviation", "graph_mark", "graph_fill", "expand", "prune", "compact",
-                "next_group", "select_front", "mc"]
+                "next_group", "select_front", "mc", "explore_single"]
 
 
 def load(path: Optional[str] = None):
@@ -132,6 +133,8 @@ def load(path: Optional[str] = None):
         "pump_mc_path": (_i32, [_p, _p, _i32, P(_i32)]),
         "pump_set_timing": (_i32, [_p, _i32]),
         "pump_get_timing": (_i32, [_p, _p, _p, _i32]),
+        "pump_set_explore_mode": (_i32, [_p, _i32]),
+        "pump_get_explore_mode": (_i32, [_p, P(_i32), P(_i32)]),
         "pump_status_str": (ctypes.c_char_p, [_i32]),
         "pump_last_error": (ctypes.c_char_p, [_p]),
         "pump_mlp_create": (_i32, [_i32, _p, P(_p)]),
@@ -350,6 +353,15 @@ class Planner:
         self._check(self.lib.pump_get_path(self.ctx, int(plan), buf.ctypes.data, cap,
                                            ctypes.byref(ln)))
         return tuple(int(v) for v in buf[:ln.value])
+
+    def set_explore_mode(self, mode: int):
+        """1: all rounds in one cooperative launch; 0: one launch per phase."""
+        self._check(self.lib.pump_set_explore_mode(self.ctx, int(mode)))
+
+    def explore_mode(self):
+        m, b = _i32(0), _i32(0)
+        self._check(self.lib.pump_get_explore_mode(self.ctx, ctypes.byref(m), ctypes.byref(b)))
+        return m.value, b.value
 
     def set_timing(self, on: bool):
         self._check(self.lib.pump_set_timing(self.ctx, 1 if on else 0))

@@ -43,27 +43,33 @@ struct Quartic {
 };
 
 // Root of a function monotone on [lo, hi] whose values at the ends have
-// opposite signs: Newton steps kept inside the shrinking bracket, bisection
-// when a step leaves it.  `which` selects f (0) or f' (1) of the quartic.
+// opposite signs: Halley steps (cubic convergence) from the end where
+// h * h'' > 0, kept inside the shrinking bracket (bisection when a step
+// leaves it); stops once a step moves t by at most 4 ulp.  `which` selects f
+// (0) or f' (1) of the quartic.
 __device__ __forceinline__ double bracket_root(const Quartic& q, int which, double lo, double hi) {
-    double flo = which ? q.g(lo) : q.f(lo);
-    double fhi = which ? q.g(hi) : q.f(hi);
+    auto h0 = [&](double t) { return which ? q.g(t) : q.f(t); };
+    auto h1 = [&](double t) { return which ? q.gp(t) : q.g(t); };
+    auto h2 = [&](double t) { return which ? 24.0 * t : q.gp(t); };
+    double flo = h0(lo);
+    double fhi = h0(hi);
     if (flo == 0.0) return lo;
     if (fhi == 0.0) return hi;
     if ((flo < 0.0) == (fhi < 0.0)) return fabs(flo) < fabs(fhi) ? lo : hi;
     const bool rising = flo < 0.0;
-    double t = 0.5 * (lo + hi);
+    double t = flo * h2(lo) > 0.0 ? lo : (fhi * h2(hi) > 0.0 ? hi : 0.5 * (lo + hi));
     for (int it = 0; it < 200; ++it) {
-        double v = which ? q.g(t) : q.f(t);
+        const double v = h0(t);
         if (v == 0.0) return t;
         if ((v < 0.0) == rising) lo = t; else hi = t;
-        double d = which ? q.gp(t) : q.g(t);
-        double tn = t - v / d;
-        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-        if (tn == t || !(hi > lo)) break;
+        const double d = h1(t);
+        const double tn = t - 2.0 * v * d / (2.0 * d * d - v * h2(t));
+        if (fabs(tn - t) <= 4.0 * 2.220446049250313e-16 * fabs(t)) return tn;
+        const double tb = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
+        if (tb == t || !(hi > lo)) break;
         // stop once the bracket is down to a few ulps
-        if (hi - lo <= 4.0 * 2.220446049250313e-16 * hi) { t = tn; break; }
-        t = tn;
+        if (hi - lo <= 4.0 * 2.220446049250313e-16 * hi) { t = tb; break; }
+        t = tb;
     }
     return t;
 }
@@ -189,16 +195,37 @@ __device__ __forceinline__ int stationary_points(const Cubic& c, double tau, dou
     return n;
 }
 
-// On a monotone piece [ta, tb] bracketing `level`: bisection for the crossing.
-// Returns the bracket (lo, hi) with p(lo) on the start side of the level.
+// On a monotone piece [ta, tb] bracketing `level`: the crossing, as a bracket
+// (lo, hi) of a few ulps with p(lo) on the start side of the level and p(hi)
+// on the other.  Newton steps inside the shrinking bracket (bisection when a
+// step leaves it); once a step is below 4 ulp, the points 2 ulp either side
+// of the estimate are tested, which closes the bracket.
 __device__ __forceinline__ void crossing(const Cubic& c, double ta, double tb, double level,
                                          bool rising, double& lo, double& hi) {
+    constexpr double eps = 2.220446049250313e-16;
     lo = ta; hi = tb;
-    for (int it = 0; it < 64; ++it) {
-        double mid = 0.5 * (lo + hi);
-        bool below = c.at(mid) < level;
-        bool right = rising ? below : !below;
-        if (right) lo = mid; else hi = mid;
+    auto put = [&](double t) {
+        if (!(t > lo && t < hi)) return;
+        const bool below = c.at(t) < level;
+        if (below == rising) lo = t; else hi = t;
+    };
+    const double pa = c.at(lo) - level, pb = c.at(hi) - level;
+    double t = (pb != pa) ? lo - pa / (pb - pa) * (hi - lo) : 0.5 * (lo + hi);
+    if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
+    for (int it = 0; it < 80; ++it) {
+        if (!(hi - lo > 8.0 * eps * fmax(fabs(lo), fabs(hi)))) return;
+        const double v = c.at(t) - level;
+        if ((v < 0.0) == rising) lo = t; else hi = t;
+        const double d = c.c1 + t * (2.0 * c.c2 + t * 3.0 * c.c3);
+        const double tn = t - v / d;
+        if (fabs(tn - t) <= 4.0 * eps * fabs(t)) {
+            const double w = 2.0 * eps * fmax(fabs(tn), 1e-300);
+            put(tn - w);
+            put(tn + w);
+            t = 0.5 * (lo + hi);
+            continue;
+        }
+        t = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
     }
 }
 
@@ -245,6 +272,16 @@ __device__ __forceinline__ void cubic_range(const Cubic& c, double tau, double& 
 // box? It is inside at time t iff all three coordinates are in their slabs,
 // so it meets the box iff the three per-axis in-slab sets intersect.
 __device__ __forceinline__ bool trajectory_hits_box(const Cubic* cs, double tau, const float* box) {
+    // a sampled point inside the closed box proves a hit (cheap, common case)
+    for (int k = 1; k < 8; ++k) {
+        const double t = tau * (0.125 * (double)k);
+        bool in = true;
+        for (int a = 0; a < 3; ++a) {
+            const double p = cs[a].at(t);
+            in &= (p >= (double)box[a]) & (p <= (double)box[3 + a]);
+        }
+        if (in) return true;
+    }
     double s[3][3], e[3][3];
     int n[3];
     for (int a = 0; a < 3; ++a) {

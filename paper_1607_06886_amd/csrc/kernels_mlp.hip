@@ -109,7 +109,7 @@ void launch_input_bf16(hipStream_t s, const float* X, int B, int Bp, int d_in, i
 // ---------------------------------------------------------------------------
 // Mixture NLL and its gradient with respect to the 208 outputs, one row per
 // thread.  Outputs: logits [16], means [16][6], log-std [16][6] clamped to
-// [-7, 2].  G rows beyond the batch are zero; loss partial sums per block.
+// [-4, 2].  G rows beyond the batch are zero; loss partial sums per block.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_mixture_nll(const float* __restrict__ Y, int ldy,
                                                      const float* __restrict__ Z, int B, int Bp,

@@ -15,7 +15,7 @@ constexpr int kHidden = 256;
 constexpr int kOut = kComp * (1 + 2 * kDState);  // 208 outputs
 constexpr int kOutPad = 224;
 constexpr int kLayers = 5;              // 4 hidden + output
-constexpr float kLogStdMin = -7.0f, kLogStdMax = 2.0f;
+constexpr float kLogStdMin = -4.0f, kLogStdMax = 2.0f;
 
 enum { kEpiHidden = 0, kEpiOutput = 1, kEpiWgrad = 2, kEpiDgrad = 3 };
 

@@ -57,6 +57,10 @@ struct pump_ctx {
     uint32_t* c_mask = nullptr;
     uint8_t* c_flag = nullptr;
     int32_t* blk = nullptr;
+    unsigned* coop_sync = nullptr;  // grid barrier: release word, failure flag, arrival words
+    int32_t* coop_tot = nullptr;    // [2][coop_blocks] chunk totals
+    int coop_blocks = 0;            // resident workgroups of the single-launch Explore
+    int explore_mode = 0;           // 0: one launch per phase, 1: single launch
     Ctl* ctl = nullptr;
     Ctl* ctl_h = nullptr;  // pinned mirror
     // selection
@@ -384,6 +388,23 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     A(dalloc(&ctx->c_mask, Q * ctx->W));
     A(dalloc(&ctx->c_flag, Q));
     A(dalloc(&ctx->blk, (size_t)2 * 65536));
+    {
+        int dev = 0, coop = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess &&
+            coop)
+            ctx->coop_blocks = coop_max_blocks(N);
+        // two workgroups per CU at most: enough waves to hide latency, and
+        // fewer arrivals to collect at each barrier
+        int n_cu = 0;
+        if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            n_cu > 0 && ctx->coop_blocks > 2 * n_cu)
+            ctx->coop_blocks = 2 * n_cu;
+        if (ctx->coop_blocks > 4096) ctx->coop_blocks = 4096;
+        ctx->explore_mode = ctx->coop_blocks > 0 ? 1 : 0;
+    }
+    A(dalloc(&ctx->coop_sync, 64 + 4096));
+    A(dalloc(&ctx->coop_tot, (size_t)2 * 4096));
     A(dalloc(&ctx->ctl, 1));
     A(dalloc(&ctx->goal_ids, (size_t)kMaxGoal));
     A(dalloc(&ctx->front_ids, (size_t)kMaxFront));
@@ -571,19 +592,74 @@ int pump_explore_round(pump_ctx* ctx, int32_t* done) {
     return PUMP_OK;
 }
 
+// Remaining rounds in one cooperative launch (see kernels_coop.hip).
+static int explore_single_launch(pump_ctx* ctx) {
+    RoundArgs a = round_args(ctx);
+    CoopArgs ca;
+    ca.sync.release = ctx->coop_sync;
+    ca.sync.fail = reinterpret_cast<int*>(ctx->coop_sync + 1);
+    ca.sync.arrive = ctx->coop_sync + 64;
+    ca.sync.n_blocks = (unsigned)ctx->coop_blocks;
+    ca.tot_a = ctx->coop_tot;
+    ca.tot_b = ctx->coop_tot + 4096;
+    ca.b_deg = ctx->b_deg;
+    ca.open_cur = ctx->open_cur;
+    ca.open_next = ctx->open_next;
+    ca.cap_pairs = ctx->cfg.cap_pairs;
+    HIPCHK(hipMemsetAsync(ctx->coop_sync, 0, (64 + (size_t)ctx->coop_blocks) * sizeof(unsigned),
+                          ctx->stream));
+    tbeg(ctx, 9);
+    HIPCHK(launch_explore_coop(ctx->stream, a, ca, ctx->N, ctx->coop_blocks));
+    tend(ctx);
+    int r = read_ctl(ctx);
+    if (r) return r;
+    const Ctl* c = ctx->ctl_h;
+    ctx->partial_plans += c->partial;
+    ctx->rounds += c->rounds;
+    if (c->open_final) std::swap(ctx->open_cur, ctx->open_next);
+    if (c->err == 4) return fail(ctx, PUMP_E_CAPACITY, "round pairs exceed cap_pairs");
+    if (c->err == 3) return fail(ctx, PUMP_E_STATE, "open plans without a finite cost");
+    if (c->err == 5) return fail(ctx, PUMP_E_STATE, "grid barrier timed out");
+    if (c->err == 6) return fail(ctx, PUMP_E_STATE, "Explore did not terminate");
+    if (c->err) return fail(ctx, PUMP_E_CAPACITY, "plan store exceeds cap_plans");
+    ctx->explore_done = true;
+    return PUMP_OK;
+}
+
 int pump_explore_run(pump_ctx* ctx) {
     if (!ctx) return PUMP_E_ARG;
+    if (!ctx->have_explore) return fail(ctx, PUMP_E_STATE, "pump_explore_begin first");
     HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
-    int32_t done = ctx->explore_done ? 1 : 0;
-    while (!done) {
-        int r = pump_explore_round(ctx, &done);
+    if (ctx->explore_mode == 1 && !ctx->explore_done) {
+        int r = explore_single_launch(ctx);
         if (r) return r;
+    } else {
+        int32_t done = ctx->explore_done ? 1 : 0;
+        while (!done) {
+            int r = pump_explore_round(ctx, &done);
+            if (r) return r;
+        }
     }
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev[2]));
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
     ctx->ms_explore = ms;
+    return PUMP_OK;
+}
+
+int pump_set_explore_mode(pump_ctx* ctx, int32_t mode) {
+    if (!ctx || (mode != 0 && mode != 1)) return PUMP_E_ARG;
+    if (mode == 1 && ctx->coop_blocks <= 0)
+        return fail(ctx, PUMP_E_ARG, "cooperative launches are not available on this device");
+    ctx->explore_mode = mode;
+    return PUMP_OK;
+}
+
+int pump_get_explore_mode(pump_ctx* ctx, int32_t* mode, int32_t* blocks) {
+    if (!ctx) return PUMP_E_ARG;
+    if (mode) *mode = ctx->explore_mode;
+    if (blocks) *blocks = ctx->coop_blocks;
     return PUMP_OK;
 }
 

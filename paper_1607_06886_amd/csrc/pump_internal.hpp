@@ -47,6 +47,9 @@ struct Ctl {
     long long dropped_steps;
     long long flagged;
     int32_t scan_total[8];
+    long long partial;         // pairs formed by the single-launch Explore
+    int32_t rounds;            // rounds run by the single-launch Explore
+    int32_t open_final;        // which open-list buffer it left current (0/1)
 };
 
 // Kernel arguments of one Explore round.
@@ -155,6 +158,29 @@ struct SelectArgs {
     double L[4];
     Ctl* ctl;
 };
+
+// Grid barrier state of the single-launch Explore (zeroed before launch).
+struct CoopSync {
+    unsigned* arrive;          // [n_blocks] last barrier each workgroup reached
+    unsigned* release;         // last barrier workgroup 0 released
+    int* fail;                 // set when a wait ran out of patience
+    unsigned n_blocks;
+};
+
+struct CoopArgs {
+    CoopSync sync;
+    int32_t* tot_a;            // [grid] chunk totals
+    int32_t* tot_b;            // [grid]
+    int32_t* b_deg;            // group degrees (scatter output)
+    int32_t* open_cur;         // open list read by the first round
+    int32_t* open_next;
+    int64_t cap_pairs;
+};
+
+// Single-launch Explore (cooperative; every workgroup resident).
+hipError_t launch_explore_coop(hipStream_t s, const RoundArgs& a, const CoopArgs& ca, int N,
+                               int blocks);
+int coop_max_blocks(int N);
 
 // One query of the batched engine: its round and selection state plus the
 // graph-build buffers and inputs, all in device memory.

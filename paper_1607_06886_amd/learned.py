@@ -42,11 +42,11 @@ def device_noise(S, N, M, seed):
 class Runner:
     """A planner context plus shared device noise for many queries."""
 
-    def __init__(self, n_max, N, S_max=256, M=2000, seed=0, n_obs_max=64):
+    def __init__(self, n_max, N, S_max=256, M=2000, seed=0, n_obs_max=64, cap_pairs=1 << 23):
         self.N, self.S_max, self.M = N, S_max, M
         self.pl = _lib.Planner(n_particles=N, max_nodes=n_max + 1, max_obstacles=n_obs_max,
                                max_steps=S_max, mc_particles=M, cap_plans=1 << 21,
-                               cap_pairs=1 << 23, cap_edges=1 << 25)
+                               cap_pairs=cap_pairs, cap_edges=1 << 25)
         self.noise, self.noise_mc = device_noise(S_max, N, M, seed)
 
     def plan(self, x_init, goal, boxes, samples, alpha, sigma):
@@ -54,7 +54,13 @@ class Runner:
         s = samples if not isinstance(samples, np.ndarray) else torch.from_numpy(samples).cuda()
         b = torch.from_numpy(np.ascontiguousarray(boxes, np.float32)).cuda()
         pr = self.pl.problem(s, b, x_init, goal, alpha, sigma, self.noise, self.noise_mc)
-        res = self.pl.plan(pr)
+        t0 = time.perf_counter()
+        try:
+            res = self.pl.plan(pr)
+        except _lib.PumpError as e:
+            # a workspace limit: the query counts as not certified
+            return dict(status=e.code, best_cost=math.inf, best_cp_mc=math.nan,
+                        ms_total=1e3 * (time.perf_counter() - t0), partial_plans=0), None
         path = self.pl.path(res["best_plan"]) if res["status"] == 0 else None
         return res, path
 
@@ -140,7 +146,7 @@ def learned_samples(mlp, x0, g, b, n, seed):
 
 def evaluate(mlp, n_maps, kinds, sizes, N, alpha, sigma, seed0, log=None):
     """Plain (n uniform) vs learned (n/2 mixture + n/2 uniform) on held-out maps."""
-    run = Runner(max(sizes), N, seed=seed0 + 99)
+    run = Runner(max(sizes), N, seed=seed0 + 99, cap_pairs=1 << 24)
     rows = []
     for q in range(n_maps):
         kind = kinds[q % len(kinds)]
@@ -153,8 +159,10 @@ def evaluate(mlp, n_maps, kinds, sizes, N, alpha, sigma, seed0, log=None):
             rows.append(dict(map=q, kind=kind, n=n,
                              plain_status=rp["status"], plain_cost=rp["best_cost"],
                              plain_cp=rp["best_cp_mc"], plain_ms=rp["ms_total"],
+                             plain_pairs=rp["partial_plans"],
                              learned_status=rl["status"], learned_cost=rl["best_cost"],
-                             learned_cp=rl["best_cp_mc"], learned_ms=rl["ms_total"] + ms_s))
+                             learned_cp=rl["best_cp_mc"], learned_ms=rl["ms_total"] + ms_s,
+                             learned_pairs=rl["partial_plans"]))
         if log and (q + 1) % 10 == 0:
             log(f"evaluated {q + 1}/{n_maps} maps")
     run.close()
@@ -162,6 +170,10 @@ def evaluate(mlp, n_maps, kinds, sizes, N, alpha, sigma, seed0, log=None):
 
 
 def summarise(rows, sizes):
+    """Per sample count: certification rates, costs where both certify, CP and
+    median times.  Across counts: for learned at n_l against plain at n_p, the
+    share of maps where learned certifies a plan at least as cheap as plain's
+    (plain uncertified counts as infinite cost) and the ratio of median times."""
     out = {}
     for n in sizes:
         r = [x for x in rows if x["n"] == n]
@@ -178,15 +190,38 @@ def summarise(rows, sizes):
             max_cp_learned=max([x["learned_cp"] for x in ok_l], default=None),
             median_plain_ms=float(np.median([x["plain_ms"] for x in r])),
             median_learned_ms=float(np.median([x["learned_ms"] for x in r])),
+            median_plain_pairs=float(np.median([x["plain_pairs"] for x in r])),
+            median_learned_pairs=float(np.median([x["learned_pairs"] for x in r])),
         )
-    return out
+    cross = {}
+    by = {(x["map"], x["n"]): x for x in rows}
+    maps = sorted({x["map"] for x in rows})
+    for nl in sizes:
+        for np_ in sizes:
+            wins, tl, tp = [], [], []
+            for m in maps:
+                a, b = by.get((m, nl)), by.get((m, np_))
+                if a is None or b is None:
+                    continue
+                cl = a["learned_cost"] if a["learned_status"] == 0 else math.inf
+                cp = b["plain_cost"] if b["plain_status"] == 0 else math.inf
+                if math.isinf(cl) and math.isinf(cp):
+                    continue
+                wins.append(cl <= cp + 1e-12)
+                tl.append(a["learned_ms"])
+                tp.append(b["plain_ms"])
+            if wins:
+                cross[f"learned@{nl} vs plain@{np_}"] = dict(
+                    maps=len(wins), learned_le_plain=float(np.mean(wins)),
+                    median_ms_ratio=float(np.median(tl) / max(1e-9, np.median(tp))))
+    return dict(per_n=out, cross=cross)
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--queries", type=int, default=2000)
+    ap.add_argument("--queries", type=int, default=6000)
     ap.add_argument("--n-train", type=int, default=4000)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval-maps", type=int, default=40)

@@ -224,3 +224,32 @@ def test_device_inputs_match_host_inputs():
     for k in sa:
         np.testing.assert_array_equal(sa[k], sb[k])
     pl.close()
+
+
+@pytest.mark.parametrize("kind,seed", [("cfg1", 0), ("boxes20", 1), ("n64", 4), ("n256", 5),
+                                       ("indoor", 2)])
+def test_single_launch_explore_equals_per_phase_launches(kind, seed):
+    """Explore as one cooperative launch and as one launch per phase build the
+    same plan store, counters and selection (and both equal the oracle's)."""
+    print_case("explore_modes", kind=kind, seed=seed)
+    sc = _scene(kind, seed)
+    ref = _oracle(kind, seed)
+    pl = planner_for(sc)
+    mode, blocks = pl.explore_mode()
+    print("  single-launch workgroups", blocks, flush=True)
+    assert mode == 1 and blocks > 0
+    pr = pl.scene_problem(sc, device=True)
+    a = pl.plan(pr)
+    sa = pl.plans()
+    pl.set_explore_mode(0)
+    b = pl.plan(pr)
+    sb = pl.plans()
+    for k in ("status", "partial_plans", "simulated", "preprune", "inserted", "survivors",
+              "dropped_steps", "flagged", "rounds", "final_i", "n_plans", "best_plan",
+              "best_cost", "best_mc_count", "n_front", "n_goal_plans"):
+        assert a[k] == b[k], k
+    for k in sa:
+        np.testing.assert_array_equal(sa[k], sb[k])
+    assert a["partial_plans"] == ref["stats"]["partial_plans"]
+    assert a["rounds"] == ref["stats"]["rounds"]
+    pl.close()
