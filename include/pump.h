@@ -212,10 +212,14 @@ int pump_mc_path(pump_ctx* ctx, const int32_t* nodes, int32_t len, int32_t* coun
  *   3 expand            4 prune (staircase update + mark)
  *   5 compact (scans + scatter)   6 next group (min, flags, scans)
  *   7 front selection   8 MC certification   9 Explore as one launch
+ *   10..16 phases of the single-launch Explore as seen by its first
+ *   workgroup (expand, simulate, staircase, marks, scans + compaction,
+ *   next group, group scatter + pair offsets; each includes its barrier;
+ *   "launches" counts rounds)   17 reserved
  * pump_set_timing(ctx, on) switches it and clears the totals;
  * pump_get_timing copies min(n, PUMP_TIMING_KINDS) totals (ms) and launch
  * counts (either pointer may be NULL). */
-#define PUMP_TIMING_KINDS 10
+#define PUMP_TIMING_KINDS 18
 int pump_set_timing(pump_ctx* ctx, int32_t on);
 int pump_get_timing(pump_ctx* ctx, double* ms, int64_t* launches, int32_t n);
 
@@ -282,20 +286,24 @@ const char* pump_mlp_last_error(const pump_mlp* m);
  * with no host round trip between them, captured in one HIP graph.  Setup
  * and selection run as batched kernels with the query index as a grid
  * dimension; Explore runs in one persistent kernel whose workgroups take
- * whole queries from a device queue and run all of a query's rounds with
- * workgroup barriers only.  Each query's results equal those of pump_plan on
+ * slots of a device queue; the workgroups holding a query's slots form a
+ * team that runs all of its rounds, meeting at barriers (one workgroup for a
+ * small query, several for a large one).  Each query's results equal those of pump_plan on
  * the same inputs (same per-element code, same orders).  Selection certifies
  * at most 32 Pareto-front plans per query (a larger front makes that query
  * report PUMP_E_CAPACITY).
  * ------------------------------------------------------------------------- */
 typedef struct pump_batch pump_batch;
 
-/* Shape of the persistent Explore kernel. */
+/* Shape of the persistent Explore kernel (every shape gives the same results). */
 typedef struct pump_batch_tuning {
-    int32_t explore_threads; /* 256 or 512 threads per workgroup */
+    int32_t explore_threads; /* threads per workgroup: 256 */
     int32_t blocks_per_cu;   /* 1..8 persistent workgroups per compute unit */
     int32_t order;           /* 0: queue in input order; 1: largest query first */
     int32_t use_graph;       /* 1: capture the launches in a HIP graph and launch it */
+    int32_t team_scale;      /* workgroups per query: 0 = one; k > 0 = k/4 times the
+                                query's share of the estimated work (samples^2 x
+                                sqrt(particles)) of all workgroups, at most 64 */
 } pump_batch_tuning;
 
 /* Allocate per-query workspaces for up to max_queries queries, each sized by
@@ -308,8 +316,8 @@ int pump_batch_destroy(pump_batch* b);
 /* Plan q queries.  probs[i] must have mem == PUMP_MEM_DEVICE (every array on
  * the device, read only, kept alive until the call returns); n_particles[i]
  * is that query's N (32/64/128/256, at most cfg.n_particles; noise arrays are
- * [S_max][6][N] for that N).  tune may be NULL (512 threads, 2 per CU,
- * largest first, graph on).  out[i] receives query i's result; the returned
+ * [S_max][6][N] for that N).  tune may be NULL (256 threads, 2 per CU,
+ * largest first, graph on, team_scale 4).  out[i] receives query i's result; the returned
  * code is PUMP_OK or the first negative per-query status.  ms_total holds the
  * wall time of the whole batch. */
 int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_particles,
@@ -319,7 +327,7 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
 int pump_batch_get_path(pump_batch* b, int32_t query, int32_t plan, int32_t* nodes, int32_t cap,
                         int32_t* len);
 /* Autotuner: time every persistent-kernel shape (threads x workgroups per CU x
- * order, graph on) on these queries, check that every shape returns the same
+ * team scale, largest first, graph on) on these queries, check that every shape returns the same
  * per-query results, write the timings as JSON to json_path (if not NULL)
  * and return the fastest shape and its time. */
 int pump_batch_tune(pump_batch* b, const pump_problem* probs, const int32_t* n_particles,

@@ -68,7 +68,7 @@ class Result(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("explore_threads", _i32), ("blocks_per_cu", _i32), ("order", _i32),
-                ("use_graph", _i32)]
+                ("use_graph", _i32), ("team_scale", _i32)]
 
 
 class PumpError(RuntimeError):
@@ -94,7 +94,9 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
            "pump_batch_last_error"]
 
 TIMING_KINDS = ["deviation", "graph_mark", "graph_fill", "expand", "prune", "compact",
-                "next_group", "select_front", "mc", "explore_single"]
+                "next_group", "select_front", "mc", "explore_single", "ph_expand",
+                "ph_simulate", "ph_stair", "ph_mark", "ph_compact", "ph_next_group",
+                "ph_group", "reserved"]
 
 
 def load(path: Optional[str] = None):
@@ -562,8 +564,9 @@ class Batch:
         out = (Result * q)()
         t = None
         if tuning is not None:
-            t = Tuning(*[int(tuning[k]) for k in ("explore_threads", "blocks_per_cu", "order",
-                                                  "use_graph")])
+            t = Tuning(*[int(tuning.get(k, d)) for k, d in (
+                ("explore_threads", 256), ("blocks_per_cu", 2), ("order", 1), ("use_graph", 1),
+                ("team_scale", 4))])
         rc = self.lib.pump_batch_plan(self.b, arr, ns, q, ctypes.byref(t) if t else None, out)
         if rc < 0 and raise_on_error:
             self._err(rc)
@@ -590,4 +593,5 @@ class Batch:
         if rc != 0:
             self._err(rc)
         return dict(explore_threads=best.explore_threads, blocks_per_cu=best.blocks_per_cu,
-                    order=best.order, use_graph=best.use_graph), ms.value
+                    order=best.order, use_graph=best.use_graph,
+                    team_scale=best.team_scale), ms.value

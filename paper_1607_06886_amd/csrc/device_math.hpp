@@ -195,37 +195,17 @@ __device__ __forceinline__ int stationary_points(const Cubic& c, double tau, dou
     return n;
 }
 
-// On a monotone piece [ta, tb] bracketing `level`: the crossing, as a bracket
-// (lo, hi) of a few ulps with p(lo) on the start side of the level and p(hi)
-// on the other.  Newton steps inside the shrinking bracket (bisection when a
-// step leaves it); once a step is below 4 ulp, the points 2 ulp either side
-// of the estimate are tested, which closes the bracket.
+// On a monotone piece [ta, tb] bracketing `level`: bisection for the crossing
+// (a fixed 64 halvings, so lanes stay in step).  Returns the bracket (lo, hi)
+// with p(lo) on the start side of the level.
 __device__ __forceinline__ void crossing(const Cubic& c, double ta, double tb, double level,
                                          bool rising, double& lo, double& hi) {
-    constexpr double eps = 2.220446049250313e-16;
     lo = ta; hi = tb;
-    auto put = [&](double t) {
-        if (!(t > lo && t < hi)) return;
-        const bool below = c.at(t) < level;
-        if (below == rising) lo = t; else hi = t;
-    };
-    const double pa = c.at(lo) - level, pb = c.at(hi) - level;
-    double t = (pb != pa) ? lo - pa / (pb - pa) * (hi - lo) : 0.5 * (lo + hi);
-    if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
-    for (int it = 0; it < 80; ++it) {
-        if (!(hi - lo > 8.0 * eps * fmax(fabs(lo), fabs(hi)))) return;
-        const double v = c.at(t) - level;
-        if ((v < 0.0) == rising) lo = t; else hi = t;
-        const double d = c.c1 + t * (2.0 * c.c2 + t * 3.0 * c.c3);
-        const double tn = t - v / d;
-        if (fabs(tn - t) <= 4.0 * eps * fabs(t)) {
-            const double w = 2.0 * eps * fmax(fabs(tn), 1e-300);
-            put(tn - w);
-            put(tn + w);
-            t = 0.5 * (lo + hi);
-            continue;
-        }
-        t = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
+    for (int it = 0; it < 64; ++it) {
+        double mid = 0.5 * (lo + hi);
+        bool below = c.at(mid) < level;
+        bool right = rising ? below : !below;
+        if (right) lo = mid; else hi = mid;
     }
 }
 

@@ -1,0 +1,454 @@
+// Explore (Alg. 4) of one query by a team of workgroups that meet at
+// barriers: all rounds run back to back without host round trips or
+// per-phase launches.  A team is the whole grid of a cooperative launch (one
+// query on the whole device) or a few workgroups of the batched engine's
+// persistent kernel.  The phases call the same per-element bodies as the
+// per-phase kernels (explore_ops.hpp) and keep their orders (scans over the
+// same index ranges), so the plan store is identical to the one the
+// per-round path builds, whatever the team size.
+//
+// Work split: expansion strides over pairs by wave, the particle queue by
+// wave, the staircase update by thread.  Marking, compaction and the next
+// group use contiguous chunks of the pair and open lists, one chunk per
+// member, so each scan needs one barrier: a member publishes its chunk
+// total, and after the barrier adds the totals of the members before it.
+#pragma once
+
+#include "explore_ops.hpp"
+
+namespace pump {
+
+
+constexpr long long kSpinLimit = 1ll << 25;   // about 1-2 s of polling per wait
+
+// Team of workgroups working on one query: its rank/size, barrier words,
+// per-workgroup scan totals and buffers.
+struct TeamCtx {
+    unsigned* arrive;          // [size] last barrier each member reached
+    unsigned* release;         // last barrier member 0 released
+    int* fail;                 // set when a wait ran out of patience
+    int rank, size;
+    int32_t* tot_a;            // [size] chunk totals
+    int32_t* tot_b;            // [size]
+    int32_t* b_deg;            // group degrees (scatter output)
+    int32_t* open_cur;         // open list read by the first round
+    int32_t* open_next;
+    int64_t cap_pairs;
+};
+
+// Team barrier without a contended counter: member r announces arrival at
+// barrier number `epoch` by storing it in its own word arrive[r]; the threads
+// of member 0 poll all arrival words, then store `epoch` in the release word
+// that every other member polls.  Each member releases its writes
+// (agent-scope release fence) before it arrives and acquires the others'
+// (agent-scope acquire fence) once released: one cache write-back and one
+// invalidation per member and barrier.  A team of one workgroup needs only
+// the workgroup barrier.  A wait that exceeds the spin limit records a
+// failure, so the kernel always ends.  Returns true (the same in every thread
+// of the workgroup) when the team has failed; the caller then leaves its loop.
+__device__ __forceinline__ bool team_barrier(const TeamCtx& g, unsigned& epoch, int* s_flag) {
+    __syncthreads();
+    if (g.size == 1) return false;
+    epoch += 1u;
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(g.arrive + g.rank, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (g.rank == 0) {
+        int ok = 1;
+        for (int k = threadIdx.x; k < g.size && ok; k += blockDim.x) {
+            long long spins = 0;
+            while (__hip_atomic_load(g.arrive + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit) {
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        if (!ok) atomicOr(g.fail, 1);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(g.release, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else if (threadIdx.x == 0) {
+        long long spins = 0;
+        while (__hip_atomic_load(g.release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                atomicOr(g.fail, 1);
+                break;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (g.rank != 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_flag = __hip_atomic_load(g.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
+
+// A value that is the same in every lane, declared so to the compiler.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Contiguous chunk [lo, hi) of n items owned by workgroup b of G.
+__device__ __forceinline__ void chunk_of(int n, int b, int G, int& lo, int& hi) {
+    const long long c = ((long long)n + G - 1) / G;
+    const long long l = (long long)b * c;
+    lo = (int)(l < n ? l : n);
+    hi = (int)(l + c < n ? l + c : n);
+}
+
+// Block sum of an int (all threads get the result).
+__device__ __forceinline__ int block_sum_int(int v, int* s_w) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_w[w];
+    __syncthreads();
+    return t;
+}
+
+// Sum of tot[0..b) and of tot[0..G) (all threads get both).
+__device__ __forceinline__ void prefix_of(const int* tot, int b, int G, int* s_w, int& before,
+                                          int& all) {
+    int x = 0, y = 0;
+    for (int k = threadIdx.x; k < G; k += blockDim.x) {
+        const int v = __hip_atomic_load(tot + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        y += v;
+        if (k < b) x += v;
+    }
+    before = uni(block_sum_int(x, s_w));
+    all = uni(block_sum_int(y, s_w));
+}
+
+// Exclusive scan of v over the block's threads in thread order, for one
+// tile of blockDim.x items; returns the tile total (all threads).
+__device__ __forceinline__ int block_excl(int v, int& excl, int* s_w) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) off += s_w[w];
+        tot += s_w[w];
+    }
+    excl = off + x - v;
+    return tot;
+}
+
+__device__ __forceinline__ unsigned long long block_min_u64(unsigned long long m,
+                                                            unsigned long long* s) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_down(m, o, 64);
+        m = y < m ? y : m;
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
+    __syncthreads();
+    unsigned long long r = s[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = s[w] < r ? s[w] : r;
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ long long block_sum_ll2(long long v, long long* s) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s[w];
+    __syncthreads();
+    return t;
+}
+
+// All rounds of Alg. 4 for one query by one team (see the file comment).
+// With `init`, the team first empties the staircases and creates the root
+// (otherwise the loop state is read from the control block as left by the
+// caller).  ra[0] and ra[1] are the round arguments with the open lists
+// (open_cur -> open_next) and (open_next -> open_cur); they are read through
+// the pointer, so they stay in memory rather than in registers.  The LDS
+// arrays are the caller's: obstacles raw/in/out
+// [kMaxObs * 6] each, and small reduction scratch.
+template <int N>
+__device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g, bool init,
+                             int n_nodes, float* s_raw,
+                             float* s_in, float* s_out, int* s_w, unsigned long long* s_m,
+                             long long* s_ll, int* s_fail_p) {
+    constexpr int W = N / 32;
+    unsigned epoch = 0;
+    const int G = g.size, b = g.rank, T = blockDim.x, tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int gwave = b * (T >> 6) + (tid >> 6), n_gwaves = G * (T >> 6);
+    Ctl* c = ra[0].ctl;
+    const bool leader = (b == 0 && tid == 0);
+    stage_obstacles_block(ra[0].obs, ra[0].n_obs, s_raw, s_in, s_out);
+    if (init) {
+        // the root goes to the list the first round reads (ra[1].open_out)
+        explore_init_fill(ra[1], n_nodes, (size_t)b * T + tid, (size_t)G * T);
+        if (team_barrier(g, epoch, s_fail_p)) return;
+        if (leader) explore_init_root(ra[1], N);
+        if (team_barrier(g, epoch, s_fail_p)) return;
+    }
+    float gl[3], gh[3];
+    for (int k = 0; k < 3; ++k) { gl[k] = ra[0].gcloud[k]; gh[k] = ra[0].gcloud[3 + k]; }
+    // loop state, identical in every workgroup
+    // (readfirstlane: the values are the same in every lane, so the loop
+    // state and the round arguments can live in scalar registers)
+    int n_pairs = uni(c->n_pairs), n_B = uni(c->n_B), n_open = uni(c->n_open);
+    int n_plans = uni(c->n_plans), i_cur = uni(c->i), done = uni(c->done);
+    int32_t* cur = g.open_cur;
+    int32_t* nxt = g.open_next;
+    int par = 0;
+    long long n_sim = 0, n_pre = 0, n_drop = 0, kept = 0;
+    long long w_pre = 0, w_flag = 0;     // wave-uniform
+    long long partial = 0;
+    int rounds = 0, err = 0;
+    // phase wall times seen by the leader (constant-rate real-time counter)
+    unsigned long long t_prev = 0, ticks[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    auto tick = [&](int k) {
+        const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+        ticks[k] += now - t_prev;
+        t_prev = now;
+    };
+    __syncthreads();
+    while (!done) {
+        if ((long long)n_pairs > g.cap_pairs) {
+            err = 4;
+            break;
+        }
+        if (rounds >= (1 << 22)) {   // the loop must have ended long before
+            err = 6;
+            break;
+        }
+        // the round's arguments: ra[par] reads cur and writes nxt
+        const RoundArgs& a = ra[par];
+        partial += n_pairs;
+        ++rounds;
+        if (leader) t_prev = __builtin_amdgcn_s_memrealtime();
+        // (1) expansion, one pair per lane; particle simulations queued
+        for (int tile = gwave * 64; tile < n_pairs; tile += n_gwaves * 64) {
+            const int q = tile + lane;
+            const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_out, gl, gh, n_sim, n_pre, n_drop) : 0;
+            queue_pairs(a, q, st);
+        }
+        if (team_barrier(g, epoch, s_fail_p)) break;
+        if (leader) tick(0);
+        // (2) particle simulation, one queued pair per wave
+        const int n_tasks = uni(__hip_atomic_load(&c->n_tasks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        for (int task = gwave; task < n_tasks; task += n_gwaves)
+            simulate_pair<N>(a, a.tasks[task], s_raw, s_in, s_out, w_pre, w_flag);
+        if (team_barrier(g, epoch, s_fail_p)) break;
+        if (leader) tick(1);
+        // (3) staircase update; the leader resets the per-round accumulators
+        //     (nothing reads them until after the next barrier)
+        for (int q = b * T + tid; q < n_pairs; q += G * T) stair_update_pair(a, q);
+        if (leader) {
+            c->n_tasks = 0;
+            c->min_cost_bits = 0x7FF0000000000000ull;
+            c->goal_stop = 0;
+        }
+        if (team_barrier(g, epoch, s_fail_p)) break;
+        if (leader) tick(2);
+        // (4) marks over contiguous chunks; chunk totals of the survivor and
+        //     kept-open flags
+        int p_lo, p_hi, o_lo, o_hi;
+        chunk_of(n_pairs, b, G, p_lo, p_hi);
+        chunk_of(n_open, b, G, o_lo, o_hi);
+        int my_s = 0, my_k = 0;
+        for (int t = p_lo + tid; t < p_hi; t += T) {
+            kept += mark_pair(a, t) ? 1 : 0;
+            my_s += a.c_pos[t];
+        }
+        for (int t = o_lo + tid; t < o_hi; t += T) {
+            mark_open(a, t);
+            my_k += a.o_keep[t];
+        }
+        my_s = block_sum_int(my_s, s_w);
+        my_k = block_sum_int(my_k, s_w);
+        if (tid == 0) {
+            g.tot_a[b] = my_s;
+            g.tot_b[b] = my_k;
+        }
+        if (team_barrier(g, epoch, s_fail_p)) break;
+        if (leader) tick(3);
+        // (5) scans of both flag arrays, compaction, cheapest new open plan
+        int s_before, n_surv, k_before, n_keep;
+        prefix_of(g.tot_a, b, G, s_w, s_before, n_surv);
+        prefix_of(g.tot_b, b, G, s_w, k_before, n_keep);
+        const bool fits = (long long)n_plans + n_surv <= a.cap_plans;
+        unsigned long long m = 0x7FF0000000000000ull;
+        {
+            int carry = s_before;
+            for (int t0 = p_lo; t0 < p_hi; t0 += T) {
+                const int t = t0 + tid;
+                const int v = t < p_hi ? a.c_pos[t] : 0;
+                int ex;
+                const int tot = block_excl(v, ex, s_w);
+                if (t < p_hi) a.c_pos[t] = carry + ex;
+                carry += tot;
+            }
+            carry = k_before;
+            for (int t0 = o_lo; t0 < o_hi; t0 += T) {
+                const int t = t0 + tid;
+                const int v = t < o_hi ? a.o_keep[t] : 0;
+                int ex;
+                const int tot = block_excl(v, ex, s_w);
+                if (t < o_hi) a.o_keep[t] = carry + ex;
+                carry += tot;
+            }
+        }
+        __syncthreads();
+        for (int t = p_lo + tid; t < p_hi; t += T) {
+            if (fits) {
+                compact_pair<W>(a, t, n_plans, n_keep, i_cur);
+                if (a.c_flag[t] == 1) {
+                    const unsigned long long bits =
+                        (unsigned long long)__double_as_longlong(a.c_cost[t]);
+                    m = bits < m ? bits : m;
+                }
+            }
+        }
+        for (int t = o_lo + tid; t < o_hi; t += T) {
+            compact_open(a, t);
+            const int p = a.open_in[t];
+            if (a.p_state[p] == kOpen) {
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(a.p_cost[p]);
+                m = bits < m ? bits : m;
+            }
+        }
+        m = block_min_u64(m, s_m);
+        if (tid == 0 && m != 0x7FF0000000000000ull) atomicMin(&c->min_cost_bits, m);
+        if (!fits) {
+            err = 1;
+            break;
+        }
+        n_plans += n_surv;
+        n_open = n_keep + n_surv;
+        {
+            // the list just written is current from here on (the phases
+            // below still address it as a.open_out)
+            int32_t* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+            par ^= 1;
+        }
+        if (team_barrier(g, epoch, s_fail_p)) break;
+        if (leader) tick(4);
+        // (6) next group index; flag the group and count it per chunk
+        if (n_open == 0) {
+            done = 1;
+            i_cur += 1;
+        } else {
+            const double mc = __longlong_as_double((long long)__hip_atomic_load(
+                &c->min_cost_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (!(mc >= 0.0 && mc < 1e300) || !(mc / a.h < 2.0e9)) {
+                err = 3;
+                break;
+            }
+            long long k = (long long)ceil(mc / a.h);
+            if (k < 0) k = 0;
+            while (k > 0 && mc <= (double)(k - 1) * a.h) --k;
+            while (!(mc <= (double)k * a.h)) ++k;
+            const long long inext = (long long)i_cur + 1;
+            i_cur = (int)(k > inext ? k : inext);
+        }
+        if (done) break;
+        const double thr = (double)i_cur * a.h;
+        int n_lo, n_hi;
+        chunk_of(n_open, b, G, n_lo, n_hi);
+        int stop = 0, my_b = 0, my_d = 0;
+        for (int t = n_lo + tid; t < n_hi; t += T) {
+            stop |= flag_group_one(a, t, thr) ? 1 : 0;
+            if (a.o_inB[t]) {
+                const int h = a.p_head[a.open_out[t]];
+                ++my_b;
+                my_d += a.row_ptr[h + 1] - a.row_ptr[h];
+            }
+        }
+        if (__any(stop) && lane == 0) atomicOr(&c->goal_stop, 1);
+        my_b = block_sum_int(my_b, s_w);
+        my_d = block_sum_int(my_d, s_w);
+        if (tid == 0) {
+            g.tot_a[b] = my_b;
+            g.tot_b[b] = my_d;
+        }
+        if (team_barrier(g, epoch, s_fail_p)) break;
+        if (leader) tick(5);
+        // (7) scans of the group flags and of the group's degrees in group
+        //     order (= open-list order), per chunk: scatter of the group and
+        //     its pair offsets
+        int b_before, nB, d_before, n_pairs_next;
+        prefix_of(g.tot_a, b, G, s_w, b_before, nB);
+        prefix_of(g.tot_b, b, G, s_w, d_before, n_pairs_next);
+        {
+            int carry = b_before, dcarry = d_before;
+            for (int t0 = n_lo; t0 < n_hi; t0 += T) {
+                const int t = t0 + tid;
+                const int v = t < n_hi ? a.o_keep[t] : 0;
+                int dv = 0;
+                if (v) {
+                    const int h = a.p_head[a.open_out[t]];
+                    dv = a.row_ptr[h + 1] - a.row_ptr[h];
+                }
+                int ex, dex;
+                const int tot = block_excl(v, ex, s_w);
+                const int dtot = block_excl(dv, dex, s_w);
+                if (t < n_hi) a.o_keep[t] = carry + ex;
+                if (v) a.b_off[carry + ex] = dcarry + dex;
+                carry += tot;
+                dcarry += dtot;
+            }
+        }
+        __syncthreads();
+        for (int t = n_lo + tid; t < n_hi; t += T) scatter_group_one(a, t, g.b_deg);
+        const int goal_stop = uni(__hip_atomic_load(&c->goal_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (leader) a.b_off[nB] = n_pairs_next;
+        n_B = nB;
+        n_pairs = n_pairs_next;
+        done = goal_stop ? 1 : 0;
+        if (team_barrier(g, epoch, s_fail_p)) break;
+        if (leader) tick(6);
+    }
+    // counters and the final loop state
+    const long long s_sim = block_sum_ll2(n_sim, s_ll);
+    const long long s_pre = block_sum_ll2(n_pre + (lane == 0 ? w_pre : 0), s_ll);
+    const long long s_drop = block_sum_ll2(n_drop, s_ll);
+    const long long s_flag = block_sum_ll2(lane == 0 ? w_flag : 0, s_ll);
+    const long long s_kept = block_sum_ll2(kept, s_ll);
+    if (tid == 0) {
+        if (s_sim) atomicAdd((unsigned long long*)&c->simulated, (unsigned long long)s_sim);
+        if (s_pre) atomicAdd((unsigned long long*)&c->preprune, (unsigned long long)s_pre);
+        if (s_drop) atomicAdd((unsigned long long*)&c->dropped_steps, (unsigned long long)s_drop);
+        if (s_flag) atomicAdd((unsigned long long*)&c->flagged, (unsigned long long)s_flag);
+        if (s_kept) atomicAdd((unsigned long long*)&c->inserted, (unsigned long long)s_kept);
+    }
+    if (leader) {
+        const bool failed =
+            __hip_atomic_load(g.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        c->n_plans = n_plans;
+        c->n_open = n_open;
+        c->n_B = done ? 0 : n_B;
+        c->n_pairs = done ? 0 : n_pairs;
+        c->i = i_cur;
+        c->err = failed ? 5 : err;
+        c->done = 1;
+        c->rounds = rounds;
+        c->partial = partial;
+        c->open_final = (cur == g.open_cur) ? 0 : 1;
+        for (int k = 0; k < 8; ++k) c->phase_ticks[k] += (long long)ticks[k];
+    }
+}
+
+}  // namespace pump

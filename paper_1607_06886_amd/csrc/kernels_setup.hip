@@ -4,10 +4,19 @@
 
 namespace pump {
 
-__global__ void k_deviation(const float* __restrict__ noise, float* __restrict__ D, int N,
-                            int S, double a00, double a01, double a10, double a11, double l00,
-                            double l10, double l11) {
-    deviation_dev(noise, D, N, S, a00, a01, a10, a11, l00, l10, l11);
+__global__ void k_dev_local(const float* __restrict__ noise, double* __restrict__ E, int N, int S,
+                            DevCoef m) {
+    dev_local_dev(noise, E, N, S, m);
+}
+
+__global__ void k_dev_carry(const double* __restrict__ E, double* __restrict__ X0, int N, int S,
+                            DevCoef m) {
+    dev_carry_dev(E, X0, N, S, m);
+}
+
+__global__ void k_dev_final(const float* __restrict__ noise, const double* __restrict__ X0,
+                            float* __restrict__ D, int N, int S, DevCoef m) {
+    dev_final_dev(noise, X0, D, N, S, m);
 }
 
 __global__ void k_cloud(const float* __restrict__ D, float* __restrict__ cloud, int N) {
@@ -19,11 +28,16 @@ __global__ void k_gcloud(const float* __restrict__ cloud, float* __restrict__ g,
 }
 
 void launch_deviation_table(hipStream_t s, const float* noise, float* D, float* cloud,
-                            float* gcloud, int N, int S_max, const double* Acl,
-                            const double* L) {
-    int threads = 3 * N;
-    k_deviation<<<(threads + 255) / 256, 256, 0, s>>>(noise, D, N, S_max, Acl[0], Acl[1],
-                                                      Acl[2], Acl[3], L[0], L[2], L[3]);
+                            float* gcloud, int N, int S_max, const double* Acl, const double* L,
+                            double* scratch) {
+    const DevCoef m{Acl[0], Acl[1], Acl[2], Acl[3], L[0], L[2], L[3]};
+    const int K = (S_max + kDevChunk - 1) / kDevChunk;
+    double* E = scratch;
+    double* X0 = scratch + (size_t)2 * K * 3 * N;
+    const int threads = K * 3 * N;
+    k_dev_local<<<(threads + 255) / 256, 256, 0, s>>>(noise, E, N, S_max, m);
+    k_dev_carry<<<(3 * N + 63) / 64, 64, 0, s>>>(E, X0, N, S_max, m);
+    k_dev_final<<<(threads + 255) / 256, 256, 0, s>>>(noise, X0, D, N, S_max, m);
     k_cloud<<<S_max + 1, 256, 0, s>>>(D, cloud, N);
     k_gcloud<<<1, 256, 0, s>>>(cloud, gcloud, S_max + 1);
 }

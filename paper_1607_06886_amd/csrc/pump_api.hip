@@ -2,6 +2,7 @@
 // PlanSelection (Alg. 2-5).  Host code only orchestrates; every step of the
 // planner runs in the kernels of kernels_*.hip.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -29,6 +30,7 @@ struct pump_ctx {
     const float* noise = nullptr;
     const float* noise_mc = nullptr;
     float* D = nullptr;
+    double* dev_scratch = nullptr;  // deviation-table chunk states
     float* cloud = nullptr;
     float* gcloud = nullptr;
     int32_t* dev_ints = nullptr;  // [0] n_nodes, [1] bad-input flag
@@ -61,6 +63,8 @@ struct pump_ctx {
     int32_t* coop_tot = nullptr;    // [2][coop_blocks] chunk totals
     int coop_blocks = 0;            // resident workgroups of the single-launch Explore
     int explore_mode = 0;           // 0: one launch per phase, 1: single launch
+    RoundArgs* ra_dev = nullptr;    // [2] round arguments of the single launch
+    RoundArgs* ra_h = nullptr;      // [2] pinned staging
     Ctl* ctl = nullptr;
     Ctl* ctl_h = nullptr;  // pinned mirror
     // selection
@@ -295,6 +299,7 @@ int pump_destroy(pump_ctx* ctx) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (ctx->ctl_h) (void)hipHostFree(ctx->ctl_h);
+    if (ctx->ra_h) (void)hipHostFree(ctx->ra_h);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& p : ctx->pending) ctx->pool.push_back({p.a, p.b});
@@ -350,6 +355,7 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     A(dalloc(&ctx->noise_buf, S * 6 * N));
     A(dalloc(&ctx->noise_mc_buf, S * 6 * M));
     A(dalloc(&ctx->D, (S + 1) * 3 * N));
+    A(dalloc(&ctx->dev_scratch, (size_t)4 * ((S + 15) / 16) * 3 * N));
     A(dalloc(&ctx->cloud, (S + 1) * 6));
     A(dalloc(&ctx->gcloud, 8));
     A(dalloc(&ctx->dev_ints, 8));
@@ -394,17 +400,22 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
             hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess &&
             coop)
             ctx->coop_blocks = coop_max_blocks(N);
-        // two workgroups per CU at most: enough waves to hide latency, and
-        // fewer arrivals to collect at each barrier
+        // one workgroup per CU (PUMP_SINGLE_LAUNCH_WG_PER_CU may raise it):
+        // each barrier costs a cache write-back and invalidation per
+        // workgroup, which outweighs the extra waves of a second workgroup
+        int per_cu = 1;
+        if (const char* e = getenv("PUMP_SINGLE_LAUNCH_WG_PER_CU")) per_cu = atoi(e) >= 1 ? atoi(e) : 1;
         int n_cu = 0;
         if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            n_cu > 0 && ctx->coop_blocks > 2 * n_cu)
-            ctx->coop_blocks = 2 * n_cu;
+            n_cu > 0 && ctx->coop_blocks > per_cu * n_cu)
+            ctx->coop_blocks = per_cu * n_cu;
         if (ctx->coop_blocks > 4096) ctx->coop_blocks = 4096;
         ctx->explore_mode = ctx->coop_blocks > 0 ? 1 : 0;
     }
     A(dalloc(&ctx->coop_sync, 64 + 4096));
     A(dalloc(&ctx->coop_tot, (size_t)2 * 4096));
+    A(dalloc(&ctx->ra_dev, 2));
+    A(hipHostMalloc((void**)&ctx->ra_h, 2 * sizeof(RoundArgs), hipHostMallocDefault));
     A(dalloc(&ctx->ctl, 1));
     A(dalloc(&ctx->goal_ids, (size_t)kMaxGoal));
     A(dalloc(&ctx->front_ids, (size_t)kMaxFront));
@@ -492,7 +503,7 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
                    pr->goal.hi[0], pr->goal.hi[1], pr->goal.hi[2]};
     tbeg(ctx, 0);
     launch_deviation_table(ctx->stream, ctx->noise, ctx->D, ctx->cloud, ctx->gcloud, N, ctx->S_max,
-                           ctx->Acl, ctx->L);
+                           ctx->Acl, ctx->L, ctx->dev_scratch);
     tend(ctx);
     HIPCHK(hipMemsetAsync(ctx->dev_ints, 0, 8 * sizeof(int32_t), ctx->stream));
     launch_mark_valid(ctx->stream, ctx->X, ctx->n_nodes, ctx->obs, ctx->n_obs, gb, ctx->valid, ctx->goal,
@@ -609,11 +620,26 @@ static int explore_single_launch(pump_ctx* ctx) {
     HIPCHK(hipMemsetAsync(ctx->coop_sync, 0, (64 + (size_t)ctx->coop_blocks) * sizeof(unsigned),
                           ctx->stream));
     tbeg(ctx, 9);
-    HIPCHK(launch_explore_coop(ctx->stream, a, ca, ctx->N, ctx->coop_blocks));
+    ctx->ra_h[0] = a;
+    ctx->ra_h[0].open_in = ctx->open_cur;
+    ctx->ra_h[0].open_out = ctx->open_next;
+    ctx->ra_h[1] = a;
+    ctx->ra_h[1].open_in = ctx->open_next;
+    ctx->ra_h[1].open_out = ctx->open_cur;
+    HIPCHK(hipMemcpyAsync(ctx->ra_dev, ctx->ra_h, 2 * sizeof(RoundArgs), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(launch_explore_coop(ctx->stream, ctx->ra_dev, ca, ctx->N, ctx->coop_blocks));
     tend(ctx);
     int r = read_ctl(ctx);
     if (r) return r;
     const Ctl* c = ctx->ctl_h;
+    if (ctx->timing) {
+        // the real-time counter runs at 100 MHz
+        for (int k = 0; k < 8; ++k) {
+            ctx->t_ms[10 + k] += 1e-5 * (double)c->phase_ticks[k];
+            ctx->t_n[10 + k] += c->rounds;
+        }
+    }
     ctx->partial_plans += c->partial;
     ctx->rounds += c->rounds;
     if (c->open_final) std::swap(ctx->open_cur, ctx->open_next);

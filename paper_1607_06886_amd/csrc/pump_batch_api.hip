@@ -29,7 +29,9 @@ struct Slot {
     int32_t *open_a, *open_b, *o_keep, *b_ids, *b_off, *b_deg;
     int32_t *c_head, *c_parent, *c_edge, *c_step, *c_pop, *c_pos, *tasks;
     int32_t *goal_ids, *front_ids, *paths, *path_len, *wp_len, *mc_counts;
-    double *etau, *ecost, *p_cost, *c_cost, *wp;
+    double *etau, *ecost, *p_cost, *c_cost, *wp, *dev_scratch;
+    unsigned* team_sync;
+    int32_t* team_tot;
     unsigned long long* stair;
     Ctl* ctl;
 };
@@ -46,7 +48,8 @@ struct pump_batch {
     std::vector<void*> allocs;
     BatchQuery* qs_dev = nullptr;
     BatchOut* out_dev = nullptr;
-    int* order_dev = nullptr;
+    int* order_dev = nullptr;      // query of each schedule entry
+    int* off_dev = nullptr;        // first slot of each entry (+ total)
     int* counter = nullptr;
     std::vector<BatchQuery> qs;
     std::vector<BatchOut> outs;
@@ -126,7 +129,8 @@ int pump_batch_create(const pump_config* cfg_in, int32_t max_queries, void* hip_
     };
     Slot lay{};
     take(&lay.X, nn * 6); take(&lay.obs, (size_t)kMaxObs * 6); take(&lay.D, (S + 1) * 3 * N);
-    take(&lay.cloud, (S + 1) * 6); take(&lay.gcloud, 8); take(&lay.valid, nn); take(&lay.goal, nn);
+    take(&lay.cloud, (S + 1) * 6);
+    take(&lay.dev_scratch, (size_t)4 * ((S + 15) / 16) * 3 * N); take(&lay.gcloud, 8); take(&lay.valid, nn); take(&lay.goal, nn);
     take(&lay.ebits, nn * b->words); take(&lay.deg, nn + 1); take(&lay.row_ptr, nn + 2);
     take(&lay.col, E); take(&lay.esrc, E); take(&lay.etau, E); take(&lay.ecost, E);
     take(&lay.p_head, P); take(&lay.p_parent, P); take(&lay.p_edge, P); take(&lay.p_step, P);
@@ -140,14 +144,17 @@ int pump_batch_create(const pump_config* cfg_in, int32_t max_queries, void* hip_
     take(&lay.paths, (size_t)kBatchFrontHost * (S + 1)); take(&lay.path_len, kBatchFrontHost);
     take(&lay.wp_len, kBatchFrontHost); take(&lay.mc_counts, kBatchFrontHost);
     take(&lay.wp, (size_t)kBatchFrontHost * (S + 1) * 3); take(&lay.ctl, 1);
+    take(&lay.team_sync, (size_t)64 + kMaxTeam); take(&lay.team_tot, (size_t)2 * kMaxTeam);
     const size_t slot_bytes = (off + 255) & ~(size_t)255;
     off = slot_bytes * (size_t)max_queries;
-    size_t o_qs, o_out, o_order, o_counter;
+    size_t o_qs, o_out, o_order, o_counter, o_off;
     {
         BatchQuery* t0; BatchOut* t1; int* t2; int* t3;
         take(&t0, (size_t)max_queries); o_qs = (size_t)t0;
         take(&t1, (size_t)max_queries); o_out = (size_t)t1;
         take(&t2, (size_t)max_queries); o_order = (size_t)t2;
+        int* t4;
+        take(&t4, (size_t)max_queries + 1); o_off = (size_t)t4;
         take(&t3, 1); o_counter = (size_t)t3;
     }
     b->arena_bytes = off;
@@ -171,6 +178,7 @@ int pump_batch_create(const pump_config* cfg_in, int32_t max_queries, void* hip_
     b->qs_dev = reinterpret_cast<BatchQuery*>(base + o_qs);
     b->out_dev = reinterpret_cast<BatchOut*>(base + o_out);
     b->order_dev = reinterpret_cast<int*>(base + o_order);
+    b->off_dev = reinterpret_cast<int*>(base + o_off);
     b->counter = reinterpret_cast<int*>(base + o_counter);
     *out = b;
     return PUMP_OK;
@@ -183,9 +191,9 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
     const pump_config& cfg = b->cfg;
     pump_batch_tuning t;
     if (tune) t = *tune;
-    else { t.explore_threads = 512; t.blocks_per_cu = 2; t.order = 1; t.use_graph = 1; }
-    if (!(t.explore_threads == 256 || t.explore_threads == 512) ||
-        t.blocks_per_cu < 1 || t.blocks_per_cu > 8)
+    else { t.explore_threads = 256; t.blocks_per_cu = 2; t.order = 1; t.use_graph = 1; t.team_scale = 4; }
+    if (t.explore_threads != 256 ||
+        t.blocks_per_cu < 1 || t.blocks_per_cu > 8 || t.team_scale < 0 || t.team_scale > 64)
         return bfail(b, PUMP_E_ARG, "bad tuning");
     b->qs.assign(q, BatchQuery());
     int N_max = 0, max_nodes = 0;
@@ -222,10 +230,13 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         Q.noise = pr.noise;
         for (int k = 0; k < 6; ++k) Q.x_init[k] = pr.x_init[k];
         for (int k = 0; k < 3; ++k) { Q.goal_box[k] = pr.goal.lo[k]; Q.goal_box[3 + k] = pr.goal.hi[k]; }
+        Q.dev_scratch = s.dev_scratch;
+        Q.team_sync = s.team_sync;
+        Q.team_tot = s.team_tot;
         Q.X = s.X; Q.obs = s.obs; Q.valid = s.valid; Q.goal = s.goal; Q.ebits = s.ebits;
         Q.deg = s.deg; Q.row_ptr = s.row_ptr; Q.col = s.col; Q.esrc = s.esrc; Q.etau = s.etau;
         Q.ecost = s.ecost; Q.b_deg = s.b_deg; Q.open_a = s.open_a; Q.open_b = s.open_b;
-        RoundArgs& a = Q.a;
+        RoundArgs& a = Q.ra[0];
         a.X = s.X; a.goal = s.goal; a.obs = s.obs; a.n_obs = pr.n_obs; a.D = s.D; a.cloud = s.cloud;
         a.gcloud = s.gcloud; a.S_max = cfg.max_steps; a.dt = (double)cfg.dt;
         cp_thresholds(alpha, eta, N, &a.c_cut, &a.c_min);
@@ -235,10 +246,13 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         a.p_head = s.p_head; a.p_parent = s.p_parent; a.p_edge = s.p_edge; a.p_step = s.p_step;
         a.p_pop = s.p_pop; a.p_round = s.p_round; a.p_cost = s.p_cost; a.p_mask = s.p_mask;
         a.p_state = s.p_state; a.cap_plans = cfg.cap_plans; a.stair = s.stair; a.stair_w = N + 1;
-        a.open_in = s.open_b; a.open_out = s.open_a; a.o_inB = s.o_inB; a.o_keep = s.o_keep;
+        a.open_in = s.open_a; a.open_out = s.open_b; a.o_inB = s.o_inB; a.o_keep = s.o_keep;
         a.b_ids = s.b_ids; a.b_off = s.b_off; a.c_head = s.c_head; a.c_parent = s.c_parent;
         a.c_edge = s.c_edge; a.c_step = s.c_step; a.c_pop = s.c_pop; a.c_cost = s.c_cost;
         a.c_mask = s.c_mask; a.c_flag = s.c_flag; a.c_pos = s.c_pos; a.tasks = s.tasks; a.ctl = s.ctl;
+        Q.ra[1] = Q.ra[0];
+        Q.ra[1].open_in = s.open_b;
+        Q.ra[1].open_out = s.open_a;
         SelectArgs& sa = Q.s;
         sa.X = s.X; sa.obs = s.obs; sa.n_obs = pr.n_obs; sa.goal = s.goal; sa.p_head = s.p_head;
         sa.p_parent = s.p_parent; sa.p_pop = s.p_pop; sa.p_cost = s.p_cost; sa.p_state = s.p_state;
@@ -250,26 +264,51 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         sa.ctl = s.ctl;
         N_max = std::max(N_max, N);
         max_nodes = std::max(max_nodes, Q.n_nodes);
-        work[i] = (double)Q.n_nodes * Q.n_nodes * (1.0 + N / 128.0);
+        work[i] = (double)Q.n_nodes * Q.n_nodes * sqrt((double)N);
     }
-    // query order for the persistent kernel: input order or largest first
-    std::vector<int> order(q);
+    // Schedule of the persistent Explore kernel: entries in input order or
+    // largest first; entry i gets a team of workgroups in proportion to its
+    // share of the estimated work (team_scale / 4 times the proportional
+    // share; 0 = one workgroup per query).  Teams need every workgroup of the
+    // launch resident at once, so the launch is capped by occupancy.
+    int per_cu = t.blocks_per_cu;
+    const int fit = batch_explore_per_cu(t.explore_threads);
+    if (fit > 0 && per_cu > fit) per_cu = fit;
+    const int grid = std::max(1, b->n_cu * per_cu);
+    std::vector<int> order(q), off(q + 1, 0);
     for (int i = 0; i < q; ++i) order[i] = i;
     if (t.order == 1)
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    double wsum = 0.0;
+    for (int i = 0; i < q; ++i) wsum += work[i];
+    const int team_cap = std::min(kMaxTeam, grid);
+    for (int e = 0; e < q; ++e) {
+        int size = 1;
+        if (t.team_scale > 0 && wsum > 0.0) {
+            const double share = 0.25 * t.team_scale * grid * work[order[e]] / wsum;
+            size = (int)std::min<double>(std::max(1.0, floor(share + 0.5)), (double)team_cap);
+        }
+        off[e + 1] = off[e] + size;
+    }
+    BatchSched sch;
+    sch.query = b->order_dev;
+    sch.off = b->off_dev;
+    sch.n_entries = q;
+    sch.total = off[q];
     b->outs.assign(q, BatchOut());
     memset(b->outs.data(), 0, sizeof(BatchOut) * q);
     BCHK(hipMemcpyAsync(b->qs_dev, b->qs.data(), sizeof(BatchQuery) * q, hipMemcpyHostToDevice, b->stream));
     BCHK(hipMemcpyAsync(b->out_dev, b->outs.data(), sizeof(BatchOut) * q, hipMemcpyHostToDevice, b->stream));
     BCHK(hipMemcpyAsync(b->order_dev, order.data(), sizeof(int) * q, hipMemcpyHostToDevice, b->stream));
-    const int blocks = std::max(1, std::min(q, b->n_cu * t.blocks_per_cu));
+    BCHK(hipMemcpyAsync(b->off_dev, off.data(), sizeof(int) * (q + 1), hipMemcpyHostToDevice, b->stream));
+    const int blocks = std::max(1, std::min(sch.total, grid));
     auto t0 = std::chrono::steady_clock::now();
     if (t.use_graph) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         launch_batch(b->stream, b->qs_dev, q, N_max, max_nodes, cfg.max_steps, cfg.mc_particles,
-                     b->words, blocks, t.explore_threads, b->counter, b->out_dev, b->order_dev);
+                     b->words, blocks, t.explore_threads, b->counter, b->out_dev, sch);
         BCHK(hipStreamEndCapture(b->stream, &graph));
         BCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         BCHK(hipGraphLaunch(exec, b->stream));
@@ -278,7 +317,7 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         (void)hipGraphDestroy(graph);
     } else {
         launch_batch(b->stream, b->qs_dev, q, N_max, max_nodes, cfg.max_steps, cfg.mc_particles,
-                     b->words, blocks, t.explore_threads, b->counter, b->out_dev, b->order_dev);
+                     b->words, blocks, t.explore_threads, b->counter, b->out_dev, sch);
     }
     BCHK(hipGetLastError());
     BCHK(hipMemcpyAsync(b->outs.data(), b->out_dev, sizeof(BatchOut) * q, hipMemcpyDeviceToHost, b->stream));
@@ -313,8 +352,8 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         r.final_i = ctls[i].i;
         r.n_plans = ctls[i].n_plans;
         r.n_edges = o.n_edges;
-        r.c_cut = b->qs[i].a.c_cut;
-        r.c_min = b->qs[i].a.c_min;
+        r.c_cut = b->qs[i].ra[0].c_cut;
+        r.c_min = b->qs[i].ra[0].c_min;
         r.ms_total = ms;
         if (out) out[i] = r;
         if (o.status < 0 && worst == PUMP_OK) {
@@ -349,18 +388,19 @@ int pump_batch_get_path(pump_batch* b, int32_t query, int32_t plan, int32_t* nod
 int pump_batch_tune(pump_batch* b, const pump_problem* probs, const int32_t* n_particles, int32_t q,
                     pump_batch_tuning* best, double* best_ms, const char* json_path) {
     if (!b || !probs || !n_particles || !best) return PUMP_E_ARG;
-    const int threads[2] = {256, 512};
+    const int threads[1] = {256};
     const int per_cu[3] = {1, 2, 4};
+    const int scales[3] = {0, 4, 8};
     std::vector<pump_result> ref(q), cur(q);
     double bms = 1e30;
-    pump_batch_tuning bt{512, 2, 1, 1};
+    pump_batch_tuning bt{256, 2, 1, 1, 4};
     std::string js = "{\"candidates\": [";
     bool first = true;
     bool have_ref = false;
     for (int th : threads)
         for (int pc : per_cu)
-            for (int ord = 0; ord < 2; ++ord) {
-                pump_batch_tuning t{th, pc, ord, 1};
+            for (int sc : scales) {
+                pump_batch_tuning t{th, pc, 1, 1, sc};
                 int r = pump_batch_plan(b, probs, n_particles, q, &t, cur.data());
                 if (r < 0) return r;
                 // timed run
@@ -372,23 +412,25 @@ int pump_batch_tune(pump_batch* b, const pump_problem* probs, const int32_t* n_p
                     ref = cur;
                     have_ref = true;
                 } else {
-                    // the choice of tiles must not change any result
+                    // the shape of the kernel must not change any result
                     for (int i = 0; i < q; ++i)
                         if (cur[i].status != ref[i].status || cur[i].best_plan != ref[i].best_plan ||
                             cur[i].best_cost != ref[i].best_cost ||
                             cur[i].partial_plans != ref[i].partial_plans)
                             return bfail(b, PUMP_E_STATE, "tuning changed a result");
                 }
-                char buf[160];
-                snprintf(buf, sizeof(buf), "%s{\"threads\": %d, \"blocks_per_cu\": %d, \"order\": %d, \"ms\": %.3f}",
-                         first ? "" : ", ", th, pc, ord, ms);
+                char buf[200];
+                snprintf(buf, sizeof(buf),
+                         "%s{\"threads\": %d, \"blocks_per_cu\": %d, \"team_scale\": %d, \"ms\": %.3f}",
+                         first ? "" : ", ", th, pc, sc, ms);
                 js += buf;
                 first = false;
                 if (ms < bms) { bms = ms; bt = t; }
             }
     char buf[200];
-    snprintf(buf, sizeof(buf), "], \"best\": {\"threads\": %d, \"blocks_per_cu\": %d, \"order\": %d, \"ms\": %.3f}}",
-             bt.explore_threads, bt.blocks_per_cu, bt.order, bms);
+    snprintf(buf, sizeof(buf),
+             "], \"best\": {\"threads\": %d, \"blocks_per_cu\": %d, \"team_scale\": %d, \"ms\": %.3f}}",
+             bt.explore_threads, bt.blocks_per_cu, bt.team_scale, bms);
     js += buf;
     if (json_path) {
         FILE* f = fopen(json_path, "w");

@@ -50,6 +50,7 @@ struct Ctl {
     long long partial;         // pairs formed by the single-launch Explore
     int32_t rounds;            // rounds run by the single-launch Explore
     int32_t open_final;        // which open-list buffer it left current (0/1)
+    long long phase_ticks[8];  // its phase wall times (real-time counter ticks)
 };
 
 // Kernel arguments of one Explore round.
@@ -107,9 +108,10 @@ struct RoundArgs {
 };
 
 // ---- launchers (kernels_*.hip) ----
+// scratch: 4 * ceil(S_max / 16) * 3 * N doubles
 void launch_deviation_table(hipStream_t s, const float* noise, float* D, float* cloud,
                             float* gcloud, int N, int S_max, const double* Acl,
-                            const double* L);
+                            const double* L, double* scratch);
 void launch_mark_valid(hipStream_t s, const float* X, int n_nodes, const float* obs,
                        int n_obs, const float* goal_box, uint8_t* valid, uint8_t* goal,
                        int32_t* bad);
@@ -178,14 +180,16 @@ struct CoopArgs {
 };
 
 // Single-launch Explore (cooperative; every workgroup resident).
-hipError_t launch_explore_coop(hipStream_t s, const RoundArgs& a, const CoopArgs& ca, int N,
+// ra_dev: two round-argument blocks in device memory, open lists
+// (open_cur -> open_next) and (open_next -> open_cur).
+hipError_t launch_explore_coop(hipStream_t s, const RoundArgs* ra_dev, const CoopArgs& ca, int N,
                                int blocks);
 int coop_max_blocks(int N);
 
 // One query of the batched engine: its round and selection state plus the
 // graph-build buffers and inputs, all in device memory.
 struct BatchQuery {
-    RoundArgs a;
+    RoundArgs ra[2];           // round arguments: open lists (a -> b) and (b -> a)
     SelectArgs s;
     const float* samples;      // [n][6] caller's device array
     const float* obs_src;      // [n_obs][6] caller's device array
@@ -212,6 +216,20 @@ struct BatchQuery {
     int32_t* b_deg;
     int32_t* open_a;
     int32_t* open_b;
+    double* dev_scratch;       // deviation-table chunk states
+    unsigned* team_sync;       // [64 + kMaxTeam] team barrier words (release, fail, arrivals)
+    int32_t* team_tot;         // [2 * kMaxTeam] team scan totals
+};
+
+constexpr int kMaxTeam = 64;   // workgroups planning one batched query
+
+// Schedule of the persistent Explore kernel: entry e plans query query[e]
+// with the workgroups holding slots off[e] .. off[e + 1] - 1.
+struct BatchSched {
+    const int32_t* query;      // [n_entries]
+    const int32_t* off;        // [n_entries + 1]
+    int32_t n_entries;
+    int32_t total;             // off[n_entries]
 };
 
 // Per-query outcome written by the batched engine.
@@ -224,7 +242,9 @@ struct BatchOut {
 
 void launch_batch(hipStream_t s, BatchQuery* qs_dev, int q, int N_max, int max_nodes, int S_max,
                   int M, int words, int explore_blocks, int explore_threads, int* counters,
-                  BatchOut* out, const int* order);
+                  BatchOut* out, const BatchSched& sch);
+// Workgroups of the batched Explore kernel that fit on one CU at once.
+int batch_explore_per_cu(int threads);
 
 void launch_select_front(hipStream_t s, const SelectArgs& a);
 void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths);

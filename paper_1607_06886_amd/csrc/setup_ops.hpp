@@ -10,37 +10,93 @@ namespace pump {
 
 // ---------------------------------------------------------------------------
 // Particle deviation table (Sec. III-B particles; eq. (2) closed loop).
-// One thread per (axis a, particle j) runs the recurrence
+// Per (axis a, particle j) the recurrence
 //   dx_{s+1} = A_cl dx_s + L (xi[s][2a][j], xi[s][2a+1][j])^T,  dx_0 = 0
-// in FP64 and stores the position part D[s][a][j] in FP32.
+// runs in FP64 and the position part D[s][a][j] is stored in FP32.  The
+// steps are cut into chunks of kDevChunk so that many lanes work at once:
+// (1) every (chunk, a, j) runs its chunk from a zero state, giving the
+// chunk's own response E_k; (2) every (a, j) chains the chunk start states,
+// X_{k+1} = A_cl^C X_k + E_k; (3) every (chunk, a, j) reruns its chunk from
+// X_k and stores D.  The state at a chunk start differs from the sequential
+// recurrence only by FP64 rounding.
+// Scratch: E and X0, each [K][3][N] double2 with K = ceil(S / kDevChunk).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void deviation_dev(const float* __restrict__ noise, float* __restrict__ D, int N,
-                            int S, double a00, double a01, double a10, double a11, double l00,
-                            double l10, double l11) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * N) return;
-    int a = t / N, j = t - a * N;
-    double p = 0.0, v = 0.0;
-    D[(size_t)a * N + j] = 0.0f;
-    constexpr int U = 8;   // noise loads issued a block of steps ahead
-    for (int s0 = 0; s0 < S; s0 += U) {
-        float w0[U], w1[U];
+constexpr int kDevChunk = 16;
+
+struct DevCoef {
+    double a00, a01, a10, a11, l00, l10, l11;
+};
+
+__device__ __forceinline__ void dev_run_chunk(const float* __restrict__ noise, int N, int S, int a,
+                                              int j, int k, const DevCoef& m, double& p,
+                                              double& v, float* __restrict__ D) {
+    const int s0 = k * kDevChunk;
+    float w0[kDevChunk], w1[kDevChunk];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int s = s0 + u < S ? s0 + u : S - 1;
-            w0[u] = noise[((size_t)s * 6 + 2 * a) * N + j];
-            w1[u] = noise[((size_t)s * 6 + 2 * a + 1) * N + j];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (s0 + u >= S) break;
-            double pn = a00 * p + a01 * v + l00 * (double)w0[u];
-            double vn = a10 * p + a11 * v + (l10 * (double)w0[u] + l11 * (double)w1[u]);
-            p = pn;
-            v = vn;
-            D[((size_t)(s0 + u + 1) * 3 + a) * N + j] = (float)p;
-        }
+    for (int u = 0; u < kDevChunk; ++u) {
+        const int s = s0 + u < S ? s0 + u : S - 1;
+        w0[u] = noise[((size_t)s * 6 + 2 * a) * N + j];
+        w1[u] = noise[((size_t)s * 6 + 2 * a + 1) * N + j];
     }
+#pragma unroll
+    for (int u = 0; u < kDevChunk; ++u) {
+        if (s0 + u >= S) break;
+        const double pn = m.a00 * p + m.a01 * v + m.l00 * (double)w0[u];
+        const double vn = m.a10 * p + m.a11 * v + (m.l10 * (double)w0[u] + m.l11 * (double)w1[u]);
+        p = pn;
+        v = vn;
+        if (D) D[((size_t)(s0 + u + 1) * 3 + a) * N + j] = (float)p;
+    }
+}
+
+// (1) chunk responses; thread t = (k * 3 + a) * N + j
+__device__ __forceinline__ void dev_local_dev(const float* __restrict__ noise, double* __restrict__ E,
+                                              int N, int S, const DevCoef& m) {
+    const int K = (S + kDevChunk - 1) / kDevChunk;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= K * 3 * N) return;
+    const int j = t % N, a = (t / N) % 3, k = t / (3 * N);
+    double p = 0.0, v = 0.0;
+    dev_run_chunk(noise, N, S, a, j, k, m, p, v, nullptr);
+    E[2 * (size_t)t] = p;
+    E[2 * (size_t)t + 1] = v;
+}
+
+// (2) chunk start states; thread col = a * N + j
+__device__ __forceinline__ void dev_carry_dev(const double* __restrict__ E, double* __restrict__ X0,
+                                              int N, int S, const DevCoef& m) {
+    const int K = (S + kDevChunk - 1) / kDevChunk;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= 3 * N) return;
+    // Phi = A_cl^C
+    double f00 = 1.0, f01 = 0.0, f10 = 0.0, f11 = 1.0;
+    for (int u = 0; u < kDevChunk; ++u) {
+        const double g00 = m.a00 * f00 + m.a01 * f10, g01 = m.a00 * f01 + m.a01 * f11;
+        const double g10 = m.a10 * f00 + m.a11 * f10, g11 = m.a10 * f01 + m.a11 * f11;
+        f00 = g00; f01 = g01; f10 = g10; f11 = g11;
+    }
+    double p = 0.0, v = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const size_t t = (size_t)k * 3 * N + col;
+        X0[2 * t] = p;
+        X0[2 * t + 1] = v;
+        const double pn = f00 * p + f01 * v + E[2 * t];
+        const double vn = f10 * p + f11 * v + E[2 * t + 1];
+        p = pn;
+        v = vn;
+    }
+}
+
+// (3) the table; thread t = (k * 3 + a) * N + j
+__device__ __forceinline__ void dev_final_dev(const float* __restrict__ noise, const double* __restrict__ X0,
+                                              float* __restrict__ D, int N, int S, const DevCoef& m) {
+    const int K = (S + kDevChunk - 1) / kDevChunk;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= K * 3 * N) return;
+    const int j = t % N, a = (t / N) % 3, k = t / (3 * N);
+    if (k == 0) D[(size_t)a * N + j] = 0.0f;
+    double p = X0[2 * (size_t)t], v = X0[2 * (size_t)t + 1];
+    dev_run_chunk(noise, N, S, a, j, k, m, p, v, D);
 }
 
 // Bounding box of the particle cloud at each step: cloud[s] = (min_j D[s][a][j], max_j ...).
@@ -132,29 +188,17 @@ __device__ __forceinline__ void mark_valid_dev(const float* __restrict__ X, int 
 // counts, pass 2 writes each row's neighbours in ascending order with their
 // (tau*, c*).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool edge_free(const float* xv, const float* xu, double tau,
-                                          const float* s_obs, int n_obs) {
-    Cubic cs[3];
-    hermite(xv, xu, tau, cs);
-    double mn[3], mx[3];
-    for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
-    for (int o = 0; o < n_obs; ++o) {
-        const float* b = s_obs + o * 6;
-        bool disjoint = false;
-        for (int a = 0; a < 3; ++a)
-            disjoint |= (mx[a] < (double)b[a]) | (mn[a] > (double)b[3 + a]);
-        if (disjoint) continue;
-        if (trajectory_hits_box(cs, tau, b)) return false;
-    }
-    return true;
-}
-
-// One block per source row v.  The row is scanned in chunks of 4096 targets:
-// every thread applies the exact rejection test to 16 targets and appends the
-// survivors to a list in LDS; the block then steers the survivors densely (one
-// per thread) and sets their bits in the row's LDS bitmask, which is written
-// out with the row's degree at the end.
+// One block (256 threads) per source row v.  The row is scanned in chunks of
+// 4096 targets: every thread applies the exact rejection test to 16 targets
+// and appends the survivors to a list in LDS.  The survivors are then steered
+// densely (one per thread); a near pair whose trajectory's bounding box meets
+// some obstacle boxes contributes one (pair, box) entry per such box to an
+// LDS queue, and the queue is processed densely too (one exact trajectory-box
+// test per thread), so lanes do not idle while a few pairs test many boxes.
+// Bits of edges are set in the row's LDS bitmask, which is written out with
+// the row's degree at the end.
 constexpr int kMarkChunk = 4096;
+constexpr int kMarkQueue = 2048;
 
 __device__ __forceinline__ void graph_mark_dev(const float* __restrict__ X,
                                                     const uint8_t* __restrict__ valid, int n,
@@ -164,10 +208,15 @@ __device__ __forceinline__ void graph_mark_dev(const float* __restrict__ X,
                                                     int32_t* __restrict__ deg, int words) {
     __shared__ float s_obs[kMaxObs * 6];
     __shared__ int s_list[kMarkChunk];
+    __shared__ double s_tau[256];
+    __shared__ int s_blk[256];
+    __shared__ uint32_t s_q[kMarkQueue];
+    __shared__ int s_w[4];
     __shared__ int s_cnt;
     extern __shared__ uint32_t s_row[];          // words u32
-    for (int t = threadIdx.x; t < n_obs * 6; t += blockDim.x) s_obs[t] = obs[t];
-    for (int t = threadIdx.x; t < words; t += blockDim.x) s_row[t] = 0u;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int t = tid; t < n_obs * 6; t += blockDim.x) s_obs[t] = obs[t];
+    for (int t = tid; t < words; t += blockDim.x) s_row[t] = 0u;
     const int v = blockIdx.x;
     float xv[6];
     for (int k = 0; k < 6; ++k) xv[k] = X[(size_t)v * 6 + k];
@@ -175,9 +224,9 @@ __device__ __forceinline__ void graph_mark_dev(const float* __restrict__ X,
     __syncthreads();
     if (vv) {
         for (int c0 = 0; c0 < n; c0 += kMarkChunk) {
-            if (threadIdx.x == 0) s_cnt = 0;
+            if (tid == 0) s_cnt = 0;
             __syncthreads();
-            for (int u = c0 + threadIdx.x; u < c0 + kMarkChunk && u < n; u += blockDim.x) {
+            for (int u = c0 + tid; u < c0 + kMarkChunk && u < n; u += blockDim.x) {
                 if (u == v || !valid[u]) continue;
                 float xu[6];
                 for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)u * 6 + k];
@@ -186,20 +235,89 @@ __device__ __forceinline__ void graph_mark_dev(const float* __restrict__ X,
             }
             __syncthreads();
             const int cnt = s_cnt;
-            for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-                const int u = s_list[i];
-                float xu[6];
-                for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)u * 6 + k];
-                double tau, c;
-                steer64(xv, xu, r_steer, tau, c);
-                if (c < r_conn && tau > kTauMin && edge_free(xv, xu, tau, s_obs, n_obs))
-                    atomicOr(&s_row[u >> 5], 1u << (u & 31));
+            for (int base = 0; base < cnt; base += 256) {
+                const int i = base + tid;
+                int u = -1;
+                bool near = false;
+                double tau = 0.0;
+                unsigned long long ov[kMaxObs / 64] = {0ull, 0ull, 0ull, 0ull};
+                int n_ov = 0;
+                if (i < cnt) {
+                    u = s_list[i];
+                    float xu[6];
+                    for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)u * 6 + k];
+                    double c;
+                    steer64(xv, xu, r_steer, tau, c);
+                    near = c < r_conn && tau > kTauMin;
+                    if (near && n_obs > 0) {
+                        Cubic cs[3];
+                        hermite(xv, xu, tau, cs);
+                        double mn[3], mx[3];
+                        for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
+                        for (int o = 0; o < n_obs; ++o) {
+                            const float* bx = s_obs + o * 6;
+                            bool disjoint = false;
+                            for (int a = 0; a < 3; ++a)
+                                disjoint |= (mx[a] < (double)bx[a]) | (mn[a] > (double)bx[3 + a]);
+                            if (!disjoint) {
+                                ov[o >> 6] |= 1ull << (o & 63);
+                                ++n_ov;
+                            }
+                        }
+                    }
+                }
+                s_tau[tid] = tau;
+                s_blk[tid] = 0;
+                // exclusive scan of the per-thread test counts
+                int x = n_ov;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(x, o, 64);
+                    if (lane >= o) x += y;
+                }
+                if (lane == 63) s_w[wave] = x;
+                __syncthreads();
+                int off = x - n_ov, total = 0;
+                for (int w = 0; w < 4; ++w) {
+                    if (w < wave) off += s_w[w];
+                    total += s_w[w];
+                }
+                for (int seg = 0; seg < total; seg += kMarkQueue) {
+                    if (n_ov > 0 && off < seg + kMarkQueue && off + n_ov > seg) {
+                        int k = off;
+                        for (int wd = 0; wd < kMaxObs / 64; ++wd) {
+                            unsigned long long m = ov[wd];
+                            while (m) {
+                                const int o = wd * 64 + __ffsll((long long)m) - 1;
+                                m &= m - 1ull;
+                                if (k >= seg && k < seg + kMarkQueue)
+                                    s_q[k - seg] = ((uint32_t)tid << 8) | (uint32_t)o;
+                                ++k;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    const int m = total - seg < kMarkQueue ? total - seg : kMarkQueue;
+                    for (int e = tid; e < m; e += blockDim.x) {
+                        const uint32_t ent = s_q[e];
+                        const int slot = (int)(ent >> 8), o = (int)(ent & 255u);
+                        if (s_blk[slot]) continue;   // already known to collide
+                        const int uu = s_list[base + slot];
+                        float xu[6];
+                        for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)uu * 6 + k];
+                        Cubic cs[3];
+                        const double tt = s_tau[slot];
+                        hermite(xv, xu, tt, cs);
+                        if (trajectory_hits_box(cs, tt, s_obs + o * 6)) s_blk[slot] = 1;
+                    }
+                    __syncthreads();
+                }
+                if (near && !s_blk[tid]) atomicOr(&s_row[u >> 5], 1u << (u & 31));
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
     int d = 0;
-    for (int t = threadIdx.x; t < words; t += blockDim.x) {
+    for (int t = tid; t < words; t += blockDim.x) {
         const uint32_t w = s_row[t];
         ebits[(size_t)v * words + t] = w;
         d += __popc(w);
@@ -207,9 +325,9 @@ __device__ __forceinline__ void graph_mark_dev(const float* __restrict__ X,
     // block sum of the degree
     for (int o = 32; o > 0; o >>= 1) d += __shfl_down(d, o, 64);
     __shared__ int s_deg[4];
-    if ((threadIdx.x & 63) == 0) s_deg[threadIdx.x >> 6] = d;
+    if ((tid & 63) == 0) s_deg[tid >> 6] = d;
     __syncthreads();
-    if (threadIdx.x == 0) deg[v] = s_deg[0] + s_deg[1] + s_deg[2] + s_deg[3];
+    if (tid == 0) deg[v] = s_deg[0] + s_deg[1] + s_deg[2] + s_deg[3];
 }
 
 __device__ __forceinline__ void graph_fill_dev(int n, const uint32_t* __restrict__ ebits,

@@ -88,9 +88,11 @@ def test_batch_matches_oracle():
     b.close()
 
 
-TUNINGS = [dict(explore_threads=t, blocks_per_cu=c, order=o, use_graph=g)
-           for t, c, o, g in [(512, 2, 1, 1), (256, 1, 0, 1), (256, 4, 1, 1), (512, 1, 0, 0),
-                              (512, 8, 1, 0)]]
+# shapes of the persistent kernel, including teams of several workgroups per
+# query (team_scale > 0) and scales that give even the small queries teams
+TUNINGS = [dict(explore_threads=t, blocks_per_cu=c, order=o, use_graph=g, team_scale=k)
+           for t, c, o, g, k in [(256, 2, 1, 1, 0), (256, 1, 0, 1, 0), (256, 4, 1, 1, 4),
+                                 (256, 1, 0, 0, 4), (256, 8, 1, 0, 8), (256, 2, 1, 1, 64)]]
 
 
 def test_batch_equals_single_query_path_under_every_shape():
@@ -188,7 +190,7 @@ def test_autotuner_picks_a_shape_and_writes_json(tmp_path):
     out = os.path.join(str(tmp_path), "tune.json")
     best, ms = b.tune([_dev(s) for s in scs], json_path=out)
     rec = json.load(open(out))
-    assert len(rec["candidates"]) == 12
-    assert best["explore_threads"] in (256, 512) and ms > 0
+    assert len(rec["candidates"]) == 9
+    assert best["explore_threads"] == 256 and ms > 0
     assert rec["best"]["threads"] == best["explore_threads"]
     b.close()
