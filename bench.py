@@ -49,6 +49,16 @@ def make_inputs(seed):
     return scenes.make_scene("cfg2", scenes.workload_seed(2, seed), M=10_000, S_max=512)
 
 
+VALU_PEAK_TLANEOPS = 39.3          # 256 CU x 64 lanes x 2.4 GHz (one lane-op per lane per clock)
+
+# Algorithmic lane-ops of Explore (per unit; the design doc gives the derivation):
+OPS_PAIR = 40          # locate the pair in the group, its edge, cost, steps, cutoff, pre-prune lookup
+OPS_GEOM = 150         # + Hermite coefficients, three cubic ranges, per-waypoint cloud boxes ...
+OPS_GEOM_PER_BOX = 12  # ... and one box-overlap test per obstacle (pairs past the pre-prune)
+OPS_PARTICLE_WP = 3    # particle position at a tested waypoint
+OPS_PARTICLE_BOX = 12  # inner and outer box test of a particle (6 compares each)
+
+
 def kernel_models(sc, res, rounds_pairs, N):
     """Algorithmic work per launch for the kernels the roofline may name.
 
@@ -57,26 +67,34 @@ def kernel_models(sc, res, rounds_pairs, N):
     FP64 arithmetic: the closed-form parts of the connection cost (boundary
     sums, quartic coefficients, two cost evaluations) plus the root solves
     modelled at 2 roots x 8 Newton steps x 9 flops: 230 FP64 flops per pair.
-    expand: one (plan, neighbour) pair per unit; algorithmic HBM bytes per pair
-    = edge record (col 4 + tau 8 + cost 8) + pair identity, flag and count
-    (4 + 4 + 1 + 4) + kept fraction x (edge 4 + step 4 + cost 8 + N/8 mask)
-    + parent record (head, cost, step, pop 20 + N/8) / mean degree.
+    expand (per-phase path): one (plan, neighbour) pair per unit; algorithmic
+    HBM bytes per pair = edge record (col 4 + tau 8 + cost 8) + pair identity,
+    flag and count (4 + 4 + 1 + 4) + kept fraction x (edge 4 + step 4 + cost 8
+    + N/8 mask) + parent record (head, cost, step, pop 20 + N/8) / mean degree.
+    explore_single (all rounds in one launch): lane-operations, counted from
+    the library's counters: every pair OPS_PAIR, every pair past the
+    pre-prune OPS_GEOM + OPS_GEOM_PER_BOX x n_obs, and per particle
+    OPS_PARTICLE_WP at each tested waypoint and OPS_PARTICLE_BOX per
+    waypoint-box test.
     """
     n1 = sc.n + 1
     pairs = n1 * (n1 - 1)
     kept = res["inserted"] / max(1, res["partial_plans"])
     deg = res["n_edges"] / max(1, res["n_valid_nodes"])
     per_pair = 20 + 13 + kept * (16 + N / 8) + (20 + N / 8) / max(1.0, deg)
+    lane_ops = (OPS_PAIR * res["partial_plans"]
+                + (OPS_GEOM + OPS_GEOM_PER_BOX * sc.n_obs) * res["simulated"]
+                + N * (OPS_PARTICLE_WP * res["sim_waypoints"]
+                       + OPS_PARTICLE_BOX * res["sim_box_tests"]))
     return {
         "graph_mark": dict(bound="alu", unit="TFLOP/s", peak=FP64_VALU_PEAK_TFLOPS,
                            work=230.0 * pairs, scale=1e12),
         "expand": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
                        work=per_pair * (res["partial_plans"] / max(1, rounds_pairs)), scale=1e9,
                        per_pair_bytes=per_pair),
-        # Explore as one launch: every round's pairs in one kernel
-        "explore_single": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
-                               work=per_pair * res["partial_plans"], scale=1e9,
-                               per_pair_bytes=per_pair),
+        "explore_single": dict(bound="alu", unit="T lane-ops/s", peak=VALU_PEAK_TLANEOPS,
+                               work=lane_ops, scale=1e12, lane_ops=lane_ops,
+                               hbm_bytes_model=per_pair * res["partial_plans"]),
     }
 
 
@@ -128,6 +146,38 @@ def cpu_baseline(seconds):
     }
 
 
+# HBM traffic of the dominant kernel, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE) recorded in profiles/ together with a hash of the sources
+# that define the kernel; it is reported only while those sources are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "explore_single_cfg2_traffic.txt")
+TRAFFIC_SOURCES = ["paper_1607_06886_amd/csrc/" + f for f in (
+    "kernels_coop.hip", "explore_team.hpp", "explore_ops.hpp", "device_math.hpp",
+    "pump_internal.hpp")]
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """Bytes per launch of `kernel` measured by the counters, or None."""
+    try:
+        rec = dict(line.strip().split("=", 1) for line in open(TRAFFIC_FILE)
+                   if "=" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if rec.get("bench_kernel") != kernel or rec.get("sources_sha256") != sources_digest():
+        return None
+    kib = (float(rec["fetch_kib"]) * float(rec["fetch_scale"])
+           + float(rec["write_kib"]) * float(rec["write_scale"]))
+    return kib * 1024.0
+
+
 def batched_inputs(q, seed, S_max=512, M=10_000):
     """q uneven queries (scenes.batch_specs) with device-resident inputs; the
     particle noise is drawn on the device from a per-query seed."""
@@ -164,12 +214,14 @@ def batched_leg(q, seed, steps, tune_q, S_max=512, M=10_000):
     best, tune_ms = b.tune(queries[:tune_q])
     t_tune = time.perf_counter() - t0
     best["use_graph"] = 1
-    res = b.plan(queries, tuning=best)          # warm-up (and the reference results)
+    # warm-up (and the reference results); a query that fails reports its
+    # status and the others complete
+    res = b.plan(queries, tuning=best, raise_on_error=False)
     times = []
     for _ in range(steps):
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        r = b.plan(queries, tuning=best)
+        r = b.plan(queries, tuning=best, raise_on_error=False)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - ta)
         assert [x["partial_plans"] for x in r] == [x["partial_plans"] for x in res]
@@ -241,8 +293,11 @@ def main():
     avg_s = ms_total / 1e3 / max(1, launches)
     achieved = m["work"] / avg_s / m["scale"]
     roofline = {"bound": m["bound"], "kernel": dom, "achieved": achieved, "peak": m["peak"],
-                "unit": m["unit"], "frac": achieved / m["peak"], "traffic": None,
+                "unit": m["unit"], "frac": achieved / m["peak"], "traffic": recorded_traffic(dom),
                 "avg_launch_us": avg_s * 1e6, "launches": launches}
+    if "hbm_bytes_model" in m:
+        roofline["algorithmic_hbm_bytes"] = m["hbm_bytes_model"]
+        roofline["algorithmic_hbm_gbs"] = m["hbm_bytes_model"] / avg_s / 1e9
     line = {
         "metric": "partial plans evaluated/s; ms to certified plan at CP<=alpha, plain vs learned",
         "value": pairs / total_s,
@@ -266,6 +321,8 @@ def main():
         "partial_plans_per_query": r0["partial_plans"],
         "simulated_per_query": r0["simulated"],
         "preprune_per_query": r0["preprune"],
+        "sim_waypoints_per_query": r0["sim_waypoints"],
+        "sim_box_tests_per_query": r0["sim_box_tests"],
         "rounds": r0["rounds"],
         "status": r0["status"],
         "best_cost": r0["best_cost"],

@@ -75,6 +75,14 @@ typedef struct pump_config {
     float eta;             /* CP approximation factor of Alg. 2; 0 = 2 above 1%,
                               10 at 0.1%, log-linear between                      */
     float lambda;          /* group cost factor of Alg. 4, default 0.5             */
+    int32_t cp_model;      /* exploration collision model of a particle at a
+                              waypoint: 0 (default) position inside a closed box;
+                              1 Half-Space Monte Carlo (Sec. III-B): deviation
+                              beyond a plane of the waypoint's local convex
+                              region, planes made perpendicular to the nominal
+                              velocity (eq. (7)).  Certification (MC(p)) is the
+                              same for both.                                   */
+    int32_t reserved_;     /* zero                                               */
     int64_t cap_edges;     /* capacity: graph edges                                 */
     int64_t cap_plans;     /* capacity: plan records over a whole query             */
     int64_t cap_pairs;     /* capacity: (plan, neighbour) pairs in one round        */
@@ -136,6 +144,9 @@ typedef struct pump_result {
     float ms_explore;        /* Alg. 4                                          */
     float ms_select;         /* Alg. 5                                          */
     float ms_total;          /* whole pump_plan call                            */
+    int64_t sim_waypoints;   /* (pair, waypoint) particle tests: each covers the N
+                                particles at a waypoint whose cloud meets a box */
+    int64_t sim_box_tests;   /* (pair, waypoint, box) tests, each over N particles */
 } pump_result;
 
 typedef struct pump_ctx pump_ctx;
@@ -224,8 +235,8 @@ int pump_set_timing(pump_ctx* ctx, int32_t on);
 int pump_get_timing(pump_ctx* ctx, double* ms, int64_t* launches, int32_t n);
 
 /* How pump_explore_run (and so pump_plan) runs Alg. 4's loop: mode 1 (the
- * default where the device supports cooperative launches) runs all remaining
- * rounds in one launch whose workgroups meet at grid-wide barriers; mode 0
+ * default) runs all remaining rounds in one launch whose workgroups (all
+ * resident at once) meet at grid-wide barriers; mode 0
  * launches each phase of each round separately and reads the loop state back
  * after every round (as pump_explore_round always does).  Both build the same
  * plan store.  get reports the mode and the workgroups of the single launch. */

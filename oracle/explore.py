@@ -51,11 +51,19 @@ class Plan:
 
 
 def extend_batch(V, graph, D, boxes, dt, S_max, parents: List[Plan], edges: np.ndarray,
-                 chunk=256):
+                 chunk=256, cp_model="box", hs_cache=None):
     """q = (x, p.path + p.head, p.cost + Cost(p.head, x), CP_hat(x, p)) for many
     (p, edge) pairs (Alg. 4, the line that forms q).
 
+    cp_model "box": a particle collides at a waypoint when its position lies in
+    a closed box; "hsmc": when its deviation violates one of the waypoint's
+    half-spaces (hsmc.py).  hs_cache (dict) keeps the half-spaces of each
+    (edge, waypoint).
+
     Returns (x, cost, step, mask [m, N], over_steps [m], flagged [m])."""
+    if cp_model == "hsmc":
+        return _extend_hsmc(V, graph, D, boxes, dt, S_max, parents, edges,
+                            {} if hs_cache is None else hs_cache)
     V = np.asarray(V, np.float64)
     b = np.asarray(boxes, np.float64)
     m = len(parents)
@@ -106,8 +114,60 @@ def extend_batch(V, graph, D, boxes, dt, S_max, parents: List[Plan], edges: np.n
     return x, cost, step, mask, over, flagged
 
 
+def _extend_hsmc(V, graph, D, boxes, dt, S_max, parents, edges, cache):
+    """extend_batch with the HSMC predicate (one pair at a time)."""
+    from . import hsmc
+    V = np.asarray(V, np.float64)
+    m = len(parents)
+    N = D.shape[2]
+    x = graph["col"][edges]
+    tau = graph["tau"][edges]
+    cst = graph["cost"][edges]
+    K = st.waypoint_count(tau, dt)
+    s_p = np.array([p.step for p in parents], np.int64)
+    heads = np.array([p.head for p in parents], np.int64)
+    cost = np.array([p.cost for p in parents]) + cst
+    step = s_p + K
+    over = step > S_max
+    mask = np.stack([p.mask for p in parents]) if m else np.zeros((0, N), bool)
+    mask = mask.copy()
+    flagged = np.zeros(m, np.int64)
+    Dd = D.astype(np.float64)
+    for q in range(m):
+        if over[q]:
+            continue
+        e = int(edges[q])
+        regions = cache.get(e)
+        if regions is None:
+            coef = st.hermite(V[heads[q]][None], V[x[q]][None], tau[q:q + 1])[0]   # [3, 4]
+            regions = []
+            for k in range(1, int(K[q]) + 1):
+                t = k * tau[q] / K[q]
+                pos = coef[:, 0] + t * (coef[:, 1] + t * (coef[:, 2] + t * coef[:, 3]))
+                vel = coef[:, 1] + t * (2.0 * coef[:, 2] + t * 3.0 * coef[:, 3])
+                regions.append(hsmc.halfspaces(pos, vel, boxes))
+            cache[e] = regions
+        hit = np.zeros(N, bool)
+        best = np.full(N, -np.inf)
+        near = np.zeros(N, bool)
+        for k, (a, b) in enumerate(regions, start=1):
+            if a.shape[0] == 0:
+                continue
+            dy = Dd[min(int(s_p[q]) + k, S_max)]                       # [3, N]
+            hit |= hsmc.violations(a, b, dy)
+            na = np.sqrt(b)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                mg = np.where(na[:, None] > 0, ((a @ dy) - b[:, None]) / na[:, None], -np.inf)
+            best = np.maximum(best, mg.max(axis=0))
+            near |= (np.abs(mg) < EPS_FLAG).any(axis=0)
+        par = mask[q]
+        flagged[q] = int(((~par) & near & (best < EPS_FLAG)).sum())
+        mask[q] = par | hit
+    return x, cost, step, mask, over, flagged
+
+
 def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
-            S_max, record=False):
+            S_max, record=False, cp_model="box"):
     """Alg. 4.  Returns (plans, P, stats, rounds) where P maps head -> plan ids
     still in P(head) at exit and `rounds` holds per-round snapshots if `record`."""
     N = D.shape[2]
@@ -122,6 +182,7 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
     goal[np.asarray(goal_nodes, np.int64)] = True
     stats = dict(partial_plans=0, inserted=0, rounds=0, iterations=0,
                  dropped_steps=0, flagged_particles=0)
+    hs_cache = {}
     rounds = []
 
     def stop_now():
@@ -141,7 +202,8 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
         if B:
             stats["rounds"] += 1
         x, cost, step, mask, over, flagged = extend_batch(
-            V, graph, D, boxes, dt, S_max, parents, edges)
+            V, graph, D, boxes, dt, S_max, parents, edges, cp_model=cp_model,
+            hs_cache=hs_cache)
         stats["partial_plans"] += len(parents)
         stats["dropped_steps"] += int(over.sum())
         stats["flagged_particles"] += int(flagged.sum())

@@ -36,6 +36,7 @@ class Config:
     r_conn: float = f32(1.0)
     eta: float = 0.0          # 0: the rule above
     lam: float = f32(0.5)
+    cp_model: str = "box"     # exploration collision model: "box" or "hsmc"
 
 
 def eta_rule(alpha: float) -> float:
@@ -71,7 +72,7 @@ def run(scene, cfg: Config = Config(), record=False, with_selection=True):
     goal_nodes = np.nonzero(in_goal)[0]
     plans, P, stats, rounds = ex.explore(V, g, D, scene.obstacles, goal_nodes, alpha_min,
                                          alpha_max, cfg.lam, cfg.r_conn, cfg.dt, S_max,
-                                         record=record)
+                                         record=record, cp_model=cfg.cp_model)
     t2 = time.perf_counter()
     Pg = ex.goal_plans(plans, P, goal_nodes)
     out = dict(V=V, graph=g, D=D, A_cl=A_cl, L=L, K=K, eta=eta, alpha_min=alpha_min,

@@ -37,8 +37,9 @@ class Config(ctypes.Structure):
     _fields_ = [("n_particles", _i32), ("max_nodes", _i32), ("max_obstacles", _i32),
                 ("max_steps", _i32), ("mc_particles", _i32), ("preprune", _i32),
                 ("dt", _f), ("q_pos", _f), ("q_vel", _f), ("r_track", _f), ("r_steer", _f),
-                ("r_conn", _f), ("eta", _f), ("lambda_", _f),
-                ("cap_edges", _i64), ("cap_plans", _i64), ("cap_pairs", _i64)]
+                ("r_conn", _f), ("eta", _f), ("lambda_", _f), ("cp_model", _i32),
+                ("reserved_", _i32), ("cap_edges", _i64), ("cap_plans", _i64),
+                ("cap_pairs", _i64)]
 
 
 class AABB(ctypes.Structure):
@@ -60,7 +61,7 @@ class Result(ctypes.Structure):
                 ("flagged", _i64), ("rounds", _i32), ("final_i", _i32), ("n_plans", _i32),
                 ("n_edges", _i32), ("n_valid_nodes", _i32), ("c_cut", _i32), ("c_min", _i32),
                 ("pad", _i32), ("ms_setup", _f), ("ms_explore", _f), ("ms_select", _f),
-                ("ms_total", _f)]
+                ("ms_total", _f), ("sim_waypoints", _i64), ("sim_box_tests", _i64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}

@@ -7,6 +7,8 @@
 
 namespace pump {
 
+constexpr int kMaxObsWords = 4;   // 64-bit words of a box bit set (256 boxes)
+
 // Boundary sums of a connection x0 -> x1:
 //   S_PP = sum P_a^2, S_Pv = sum P_a (v0_a + v1_a), S_vv = sum v0^2 + v0 v1 + v1^2
 // with P = p1 - p0.  The minimum-effort cost of duration tau is
@@ -276,6 +278,77 @@ __device__ __forceinline__ bool trajectory_hits_box(const Cubic* cs, double tau,
                 if (st <= en) return true;
             }
     return false;
+}
+
+// ---------------------------------------------------------------------------
+// Half-Space Monte Carlo (Sec. III-B): the local convex region around a
+// workspace point y is built one plane at a time.  Each step takes the
+// closest point of the remaining boxes (ties: lowest box index), d = that
+// point - y, and drops every remaining box that lies in the closed
+// half-space d.(z - y) >= d.d (always the box that gave d).  `rem` holds the
+// remaining boxes as bits; returns false when none remains.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool hs_next(const double* y, const float* boxes, int n_obs,
+                                        unsigned long long* rem, double* d) {
+#pragma clang fp contract(off)
+    int best = -1;
+    double best_d2 = INFINITY;
+    double bd[3] = {0.0, 0.0, 0.0};
+    for (int w = 0; w * 64 < n_obs; ++w) {
+        unsigned long long m = rem[w];
+        while (m) {
+            const int o = w * 64 + __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const float* b = boxes + o * 6;
+            double dv[3];
+            for (int a = 0; a < 3; ++a)
+                dv[a] = fmin(fmax(y[a], (double)b[a]), (double)b[3 + a]) - y[a];
+            const double d2 = (dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2];
+            if (d2 < best_d2) {
+                best_d2 = d2;
+                best = o;
+                bd[0] = dv[0]; bd[1] = dv[1]; bd[2] = dv[2];
+            }
+        }
+    }
+    if (best < 0) return false;
+    d[0] = bd[0]; d[1] = bd[1]; d[2] = bd[2];
+    const double dd = (bd[0] * bd[0] + bd[1] * bd[1]) + bd[2] * bd[2];
+    const double dy = (bd[0] * y[0] + bd[1] * y[1]) + bd[2] * y[2];
+    for (int w = 0; w * 64 < n_obs; ++w) {
+        unsigned long long m = rem[w];
+        while (m) {
+            const int o = w * 64 + __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const float* b = boxes + o * 6;
+            double lo_part = 0.0;
+            for (int a = 0; a < 3; ++a)
+                lo_part += fmin(bd[a] * (double)b[a], bd[a] * (double)b[3 + a]);
+            if (o == best || lo_part - dy >= dd) rem[w] &= ~(1ull << (o & 63));
+        }
+    }
+    return true;
+}
+
+// eq. (7): the plane normal made perpendicular to the nominal velocity v
+// (unchanged at rest); b = a.a.
+__device__ __forceinline__ void hs_project(const double* d, const double* v, double* a, double& b) {
+#pragma clang fp contract(off)
+    const double vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+    if (vv > 0.0) {
+        const double f = ((d[0] * v[0] + d[1] * v[1]) + d[2] * v[2]) / vv;
+        for (int k = 0; k < 3; ++k) a[k] = d[k] - f * v[k];
+    } else {
+        for (int k = 0; k < 3; ++k) a[k] = d[k];
+    }
+    b = (a[0] * a[0] + a[1] * a[1]) + a[2] * a[2];
+}
+
+__device__ __forceinline__ void all_boxes(int n_obs, unsigned long long* rem) {
+    for (int w = 0; w < kMaxObsWords; ++w) {
+        const int lo = w * 64;
+        rem[w] = n_obs >= lo + 64 ? ~0ull : (n_obs > lo ? ((1ull << (n_obs - lo)) - 1ull) : 0ull);
+    }
 }
 
 }  // namespace pump

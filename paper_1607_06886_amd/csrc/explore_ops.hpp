@@ -71,6 +71,7 @@ __device__ __forceinline__ void explore_init_root(const RoundArgs& a, int N) {
     c->err = 0;
     c->n_tasks = 0;
     c->simulated = c->preprune = c->inserted = c->dropped_steps = c->flagged = 0;
+    c->sim_waypoints = c->sim_box_tests = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -83,9 +84,9 @@ __device__ __forceinline__ void explore_init_root(const RoundArgs& a, int N) {
 // bits (written here), 2 if its particles must be simulated, 0 if resolved.
 // ---------------------------------------------------------------------------
 template <int N>
-__device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int n_B, const float* s_out,
-                                           const float* gl, const float* gh, long long& n_sim,
-                                           long long& n_pre, long long& n_drop) {
+__device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int n_B, const float* s_raw,
+                                           const float* s_out, const float* gl, const float* gh,
+                                           long long& n_sim, long long& n_pre, long long& n_drop) {
     constexpr int W = N / 32;
     const int n_obs = a.n_obs;
     int lo = 0, hi = n_B;  // b_off[lo] <= q < b_off[hi]
@@ -119,6 +120,45 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int n_B, c
     ++n_sim;
     Cubic cs[3];
     hermite(a.X + (size_t)head * 6, a.X + (size_t)x * 6, tau, cs);
+    if (a.cp_model == 1) {
+        // HSMC: mark the waypoints where some particle of the cloud box can
+        // reach a plane of the local region, or come within the flag distance
+        unsigned near = 0u;
+        for (int k = 1; k <= K; ++k) {
+            const double t = ((double)k * tau) / (double)K;
+            double y[3], v[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                y[ax] = cs[ax].at(t);
+                v[ax] = cs[ax].c1 + t * (2.0 * cs[ax].c2 + t * 3.0 * cs[ax].c3);
+            }
+            const float* cl = a.cloud + (size_t)(s_p + k) * 6;
+            unsigned long long rem[kMaxObsWords];
+            all_boxes(n_obs, rem);
+            double dd[3];
+            while (hs_next(y, s_raw, n_obs, rem, dd)) {
+                double av[3], b;
+                hs_project(dd, v, av, b);
+                double reach = 0.0;
+                for (int ax = 0; ax < 3; ++ax)
+                    reach += fmax(av[ax] * (double)cl[ax], av[ax] * (double)cl[3 + ax]);
+                if (reach > b - kFlagEps * sqrt(b) - 1e-12 * (b + 1.0)) {
+                    near |= 1u << (k - 1);
+                    break;
+                }
+            }
+        }
+        a.c_edge[q] = e;
+        a.c_cost[q] = cost;
+        a.c_step[q] = s_p + K;
+        if (near == 0u) {
+            a.c_flag[q] = 1;
+            a.c_pop[q] = pop_p;
+            for (int w = 0; w < W; ++w) a.c_mask[(size_t)q * W + w] = a.p_mask[(size_t)p * W + w];
+            return 1;
+        }
+        a.c_pos[q] = (int)near;
+        return 2;
+    }
     // obstacles the cloud can reach anywhere along the edge
     float elo[3], ehi[3];
     for (int k = 0; k < 3; ++k) {
@@ -188,12 +228,14 @@ __device__ __forceinline__ void queue_pairs(const RoundArgs& a, int q, int st) {
 // at each marked waypoint, lanes test their particles against the obstacles
 // the cloud touches (FP32 with an FP64 re-test inside the guard band); hits
 // are gathered with ballots into the N-bit mask, ORed with the parent's bits
-// and counted; the pair is cut if pop >= c_cut.  Counters are wave-uniform.
+// and counted; the pair is cut if pop >= c_cut.  Counters are wave-uniform
+// (n_wp: waypoints tested, n_bt: waypoint-box tests, each over all particles).
 // ---------------------------------------------------------------------------
 template <int N>
 __device__ __forceinline__ void simulate_pair(const RoundArgs& a, int qj, const float* s_raw,
                                               const float* s_in, const float* s_out,
-                                              long long& n_pre, long long& n_flag) {
+                                              long long& n_pre, long long& n_flag, long long& n_wp,
+                                              long long& n_bt) {
     constexpr int W = N / 32;                      // u32 mask words
     constexpr int PPL = N >= 64 ? N / 64 : 1;      // particles per lane
     const int n_obs = a.n_obs;
@@ -210,6 +252,45 @@ __device__ __forceinline__ void simulate_pair(const RoundArgs& a, int qj, const 
     bool hit[PPL], deep[PPL], nearp[PPL];
     for (int r = 0; r < PPL; ++r) { hit[r] = false; deep[r] = false; nearp[r] = false; }
     unsigned wm = nj;
+    n_wp += __popc(wm);   // waypoints whose cloud box meets an obstacle (or a plane)
+    if (a.cp_model == 1) {
+        // HSMC: at each marked waypoint, every plane of the local region
+        // against every particle's deviation, in FP64
+        while (wm) {
+            const int k = __ffs((int)wm);
+            wm &= wm - 1u;
+            const int s = spj + k;
+            const double t = ((double)k * tj) / (double)Kj;
+            double y[3], v[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                y[ax] = cs[ax].at(t);
+                v[ax] = cs[ax].c1 + t * (2.0 * cs[ax].c2 + t * 3.0 * cs[ax].c3);
+            }
+            double dy[PPL][3];
+            for (int r = 0; r < PPL; ++r) {
+                const int jj = valid_lane ? r * 64 + lane : 0;
+                for (int ax = 0; ax < 3; ++ax) dy[r][ax] = (double)a.D[((size_t)s * 3 + ax) * N + jj];
+            }
+            unsigned long long rem[kMaxObsWords];
+            all_boxes(n_obs, rem);
+            double dd[3];
+            while (hs_next(y, s_raw, n_obs, rem, dd)) {
+                double av[3], b;
+                hs_project(dd, v, av, b);
+                ++n_bt;
+                const double na = sqrt(b);
+                if (!(na > 0.0)) continue;
+                for (int r = 0; r < PPL; ++r) {
+                    const double g = (av[0] * dy[r][0] + av[1] * dy[r][1]) + av[2] * dy[r][2];
+                    const double mg = (g - b) / na;
+                    if (g > b) hit[r] = true;
+                    if (mg >= kFlagEps) deep[r] = true;
+                    if (fabs(mg) < kFlagEps) nearp[r] = true;
+                }
+            }
+        }
+        wm = 0u;
+    }
     while (wm) {
         const int k = __ffs((int)wm);
         wm &= wm - 1u;
@@ -230,6 +311,7 @@ __device__ __forceinline__ void simulate_pair(const RoundArgs& a, int qj, const 
             const int o = c0 + lane;
             const bool ov = o < n_obs && boxes_overlap(lo3, hi3, s_out + o * 6);
             unsigned long long om = __ballot(ov);
+            n_bt += __popcll(om);   // boxes tested against every particle
             if (om && !loaded) {
                 for (int r = 0; r < PPL; ++r) {
                     const int jj = valid_lane ? r * 64 + lane : 0;

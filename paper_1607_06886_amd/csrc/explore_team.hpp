@@ -1,6 +1,6 @@
 // Explore (Alg. 4) of one query by a team of workgroups that meet at
 // barriers: all rounds run back to back without host round trips or
-// per-phase launches.  A team is the whole grid of a cooperative launch (one
+// per-phase launches.  A team is the whole grid of the single launch (one
 // query on the whole device) or a few workgroups of the batched engine's
 // persistent kernel.  The phases call the same per-element bodies as the
 // per-phase kernels (explore_ops.hpp) and keep their orders (scans over the
@@ -212,7 +212,7 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
     int32_t* nxt = g.open_next;
     int par = 0;
     long long n_sim = 0, n_pre = 0, n_drop = 0, kept = 0;
-    long long w_pre = 0, w_flag = 0;     // wave-uniform
+    long long w_pre = 0, w_flag = 0, w_wp = 0, w_bt = 0;     // wave-uniform
     long long partial = 0;
     int rounds = 0, err = 0;
     // phase wall times seen by the leader (constant-rate real-time counter)
@@ -240,7 +240,7 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         // (1) expansion, one pair per lane; particle simulations queued
         for (int tile = gwave * 64; tile < n_pairs; tile += n_gwaves * 64) {
             const int q = tile + lane;
-            const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_out, gl, gh, n_sim, n_pre, n_drop) : 0;
+            const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_raw, s_out, gl, gh, n_sim, n_pre, n_drop) : 0;
             queue_pairs(a, q, st);
         }
         if (team_barrier(g, epoch, s_fail_p)) break;
@@ -248,7 +248,7 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         // (2) particle simulation, one queued pair per wave
         const int n_tasks = uni(__hip_atomic_load(&c->n_tasks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         for (int task = gwave; task < n_tasks; task += n_gwaves)
-            simulate_pair<N>(a, a.tasks[task], s_raw, s_in, s_out, w_pre, w_flag);
+            simulate_pair<N>(a, a.tasks[task], s_raw, s_in, s_out, w_pre, w_flag, w_wp, w_bt);
         if (team_barrier(g, epoch, s_fail_p)) break;
         if (leader) tick(1);
         // (3) staircase update; the leader resets the per-round accumulators
@@ -426,12 +426,16 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
     const long long s_pre = block_sum_ll2(n_pre + (lane == 0 ? w_pre : 0), s_ll);
     const long long s_drop = block_sum_ll2(n_drop, s_ll);
     const long long s_flag = block_sum_ll2(lane == 0 ? w_flag : 0, s_ll);
+    const long long s_wp = block_sum_ll2(lane == 0 ? w_wp : 0, s_ll);
+    const long long s_bt = block_sum_ll2(lane == 0 ? w_bt : 0, s_ll);
     const long long s_kept = block_sum_ll2(kept, s_ll);
     if (tid == 0) {
         if (s_sim) atomicAdd((unsigned long long*)&c->simulated, (unsigned long long)s_sim);
         if (s_pre) atomicAdd((unsigned long long*)&c->preprune, (unsigned long long)s_pre);
         if (s_drop) atomicAdd((unsigned long long*)&c->dropped_steps, (unsigned long long)s_drop);
         if (s_flag) atomicAdd((unsigned long long*)&c->flagged, (unsigned long long)s_flag);
+        if (s_wp) atomicAdd((unsigned long long*)&c->sim_waypoints, (unsigned long long)s_wp);
+        if (s_bt) atomicAdd((unsigned long long*)&c->sim_box_tests, (unsigned long long)s_bt);
         if (s_kept) atomicAdd((unsigned long long*)&c->inserted, (unsigned long long)s_kept);
     }
     if (leader) {

@@ -1,6 +1,6 @@
-// Explore (Alg. 4) of one query as a single cooperative launch: the whole
-// grid is one team (explore_team.hpp), so every round runs inside the kernel
-// with grid-wide barriers between its phases and no host round trip.
+// Explore (Alg. 4) of one query as a single launch: the whole grid is one
+// team (explore_team.hpp), so every round runs inside the kernel with
+// grid-wide barriers between its phases and no host round trip.
 #include "explore_team.hpp"
 
 namespace pump {
@@ -45,7 +45,11 @@ hipError_t launch_explore_coop(hipStream_t s, const RoundArgs* ra_dev, const Coo
         case 128: fn = (const void*)k_explore_coop<128>; break;
         default: fn = (const void*)k_explore_coop<256>; break;
     }
-    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kCoopThreads), args, 0, s);
+    // An ordinary launch: `blocks` never exceeds what the occupancy query
+    // says fits on the device at once, so on an otherwise idle stream every
+    // workgroup is resident and the barriers complete (a wait that runs out
+    // of patience still ends the kernel with an error).
+    return hipLaunchKernel(fn, dim3(blocks), dim3(kCoopThreads), args, 0, s);
 }
 
 int coop_max_blocks(int N) {

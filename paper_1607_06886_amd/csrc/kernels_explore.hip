@@ -123,8 +123,9 @@ void launch_explore_init(hipStream_t s, const RoundArgs& a, int n_nodes, int N) 
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
+    __shared__ float s_raw[kMaxObs * 6];
     __shared__ float s_out[kMaxObs * 6];
-    stage_obstacles_block(a.obs, a.n_obs, nullptr, nullptr, s_out);
+    stage_obstacles_block(a.obs, a.n_obs, s_raw, nullptr, s_out);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int n_pairs = a.ctl->n_pairs;
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
     const int wave_stride = gridDim.x * 4;
     for (int tile = wave_global * 64; tile < n_pairs; tile += wave_stride * 64) {
         const int q = tile + lane;
-        const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_out, gl, gh, n_sim, n_pre, n_drop) : 0;
+        const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_raw, s_out, gl, gh, n_sim, n_pre, n_drop) : 0;
         queue_pairs(a, q, st);
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -160,13 +161,15 @@ __global__ __launch_bounds__(256) void k_expand_sim(RoundArgs a) {
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int n_tasks = a.ctl->n_tasks;
-    long long n_pre = 0, n_flag = 0;
+    long long n_pre = 0, n_flag = 0, n_wp = 0, n_bt = 0;
     for (int task = blockIdx.x * 4 + (threadIdx.x >> 6); task < n_tasks; task += gridDim.x * 4)
-        simulate_pair<N>(a, a.tasks[task], s_raw, s_in, s_out, n_pre, n_flag);
+        simulate_pair<N>(a, a.tasks[task], s_raw, s_in, s_out, n_pre, n_flag, n_wp, n_bt);
     // counts are wave-uniform
     if (lane == 0) {
         if (n_pre) atomicAdd((unsigned long long*)&a.ctl->preprune, (unsigned long long)n_pre);
         if (n_flag) atomicAdd((unsigned long long*)&a.ctl->flagged, (unsigned long long)n_flag);
+        if (n_wp) atomicAdd((unsigned long long*)&a.ctl->sim_waypoints, (unsigned long long)n_wp);
+        if (n_bt) atomicAdd((unsigned long long*)&a.ctl->sim_box_tests, (unsigned long long)n_bt);
     }
 }
 

@@ -131,6 +131,7 @@ RoundArgs round_args(pump_ctx* c) {
     a.c_min = c->c_min;
     a.h = c->h;
     a.preprune = c->cfg.preprune;
+    a.cp_model = c->cfg.cp_model;
     a.row_ptr = c->row_ptr;
     a.col = c->col;
     a.etau = c->etau;
@@ -264,6 +265,7 @@ void pump_config_default(pump_config* c) {
     c->r_conn = 1.0f;
     c->eta = 0.0f;
     c->lambda = 0.5f;
+    c->cp_model = 0;
     c->cap_edges = 4 << 20;
     c->cap_plans = 1 << 20;
     c->cap_pairs = 4 << 20;
@@ -320,6 +322,7 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     const int N = cfg.n_particles;
     if (!(N == 32 || N == 64 || N == 128 || N == 256)) return PUMP_E_ARG;
     if (cfg.max_nodes < 2 || cfg.max_nodes > 65535) return PUMP_E_ARG;
+    if (cfg.cp_model != 0 && cfg.cp_model != 1) return PUMP_E_ARG;
     if (cfg.max_obstacles < 0 || cfg.max_obstacles > kMaxObs) return PUMP_E_ARG;
     if (cfg.max_steps < 1 || cfg.max_steps > 4096 || cfg.mc_particles < 1) return PUMP_E_ARG;
     if (!(cfg.dt > 0) || !(cfg.r_conn > 0) || !(cfg.lambda > 0) || !(cfg.r_steer > 0) ||
@@ -395,11 +398,8 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     A(dalloc(&ctx->c_flag, Q));
     A(dalloc(&ctx->blk, (size_t)2 * 65536));
     {
-        int dev = 0, coop = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess &&
-            coop)
-            ctx->coop_blocks = coop_max_blocks(N);
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) ctx->coop_blocks = coop_max_blocks(N);
         // one workgroup per CU (PUMP_SINGLE_LAUNCH_WG_PER_CU may raise it):
         // each barrier costs a cache write-back and invalidation per
         // workgroup, which outweighs the extra waves of a second workgroup
@@ -603,7 +603,7 @@ int pump_explore_round(pump_ctx* ctx, int32_t* done) {
     return PUMP_OK;
 }
 
-// Remaining rounds in one cooperative launch (see kernels_coop.hip).
+// Remaining rounds in one launch (see kernels_coop.hip).
 static int explore_single_launch(pump_ctx* ctx) {
     RoundArgs a = round_args(ctx);
     CoopArgs ca;
@@ -677,7 +677,7 @@ int pump_explore_run(pump_ctx* ctx) {
 int pump_set_explore_mode(pump_ctx* ctx, int32_t mode) {
     if (!ctx || (mode != 0 && mode != 1)) return PUMP_E_ARG;
     if (mode == 1 && ctx->coop_blocks <= 0)
-        return fail(ctx, PUMP_E_ARG, "cooperative launches are not available on this device");
+        return fail(ctx, PUMP_E_ARG, "the single-launch Explore does not fit on this device");
     ctx->explore_mode = mode;
     return PUMP_OK;
 }
@@ -698,6 +698,8 @@ static void fill_counters(pump_ctx* ctx, pump_result* o) {
     o->survivors = c->n_plans - 1;
     o->dropped_steps = c->dropped_steps;
     o->flagged = c->flagged;
+    o->sim_waypoints = c->sim_waypoints;
+    o->sim_box_tests = c->sim_box_tests;
     o->rounds = ctx->rounds;
     o->final_i = c->i;
     o->n_plans = c->n_plans;

@@ -91,6 +91,7 @@ int pump_batch_create(const pump_config* cfg_in, int32_t max_queries, void* hip_
     const pump_config& cfg = *cfg_in;
     const int N = cfg.n_particles;
     if (!(N == 32 || N == 64 || N == 128 || N == 256)) return PUMP_E_ARG;
+    if (cfg.cp_model != 0 && cfg.cp_model != 1) return PUMP_E_ARG;
     if (cfg.max_nodes < 2 || cfg.max_nodes > 65535 || cfg.max_obstacles > kMaxObs ||
         cfg.max_steps < 1 || cfg.max_steps > 4096 || cfg.mc_particles < 1)
         return PUMP_E_ARG;
@@ -242,6 +243,7 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         cp_thresholds(alpha, eta, N, &a.c_cut, &a.c_min);
         a.h = (double)cfg.lambda * (double)cfg.r_conn;
         a.preprune = cfg.preprune;
+        a.cp_model = cfg.cp_model;
         a.row_ptr = s.row_ptr; a.col = s.col; a.etau = s.etau; a.ecost = s.ecost;
         a.p_head = s.p_head; a.p_parent = s.p_parent; a.p_edge = s.p_edge; a.p_step = s.p_step;
         a.p_pop = s.p_pop; a.p_round = s.p_round; a.p_cost = s.p_cost; a.p_mask = s.p_mask;
@@ -348,6 +350,8 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         r.survivors = ctls[i].n_plans - 1;
         r.dropped_steps = ctls[i].dropped_steps;
         r.flagged = ctls[i].flagged;
+        r.sim_waypoints = ctls[i].sim_waypoints;
+        r.sim_box_tests = ctls[i].sim_box_tests;
         r.rounds = o.rounds;
         r.final_i = ctls[i].i;
         r.n_plans = ctls[i].n_plans;

@@ -51,6 +51,8 @@ struct Ctl {
     int32_t rounds;            // rounds run by the single-launch Explore
     int32_t open_final;        // which open-list buffer it left current (0/1)
     long long phase_ticks[8];  // its phase wall times (real-time counter ticks)
+    long long sim_waypoints;   // simulated (pair, waypoint) tests, each over N particles
+    long long sim_box_tests;   // simulated (pair, waypoint, box) tests, each over N particles
 };
 
 // Kernel arguments of one Explore round.
@@ -68,6 +70,7 @@ struct RoundArgs {
     int32_t c_cut, c_min;
     double h;                  // lambda * r_n
     int32_t preprune;
+    int32_t cp_model;          // exploration collision model: 0 box, 1 half-space (HSMC)
     // graph
     const int32_t* row_ptr;
     const int32_t* col;
@@ -179,7 +182,8 @@ struct CoopArgs {
     int64_t cap_pairs;
 };
 
-// Single-launch Explore (cooperative; every workgroup resident).
+// Single-launch Explore (every workgroup resident: the grid is sized by the
+// occupancy query).
 // ra_dev: two round-argument blocks in device memory, open lists
 // (open_cur -> open_next) and (open_next -> open_cur).
 hipError_t launch_explore_coop(hipStream_t s, const RoundArgs* ra_dev, const CoopArgs& ca, int N,

@@ -8,6 +8,8 @@ ones).  Flagged decisions (a particle within 1e-5 of a face) are counted and
 printed; the tests require exact agreement regardless.
 """
 
+import functools
+
 import numpy as np
 import pytest
 
@@ -246,10 +248,52 @@ def test_single_launch_explore_equals_per_phase_launches(kind, seed):
     sb = pl.plans()
     for k in ("status", "partial_plans", "simulated", "preprune", "inserted", "survivors",
               "dropped_steps", "flagged", "rounds", "final_i", "n_plans", "best_plan",
-              "best_cost", "best_mc_count", "n_front", "n_goal_plans"):
+              "best_cost", "best_mc_count", "n_front", "n_goal_plans", "sim_waypoints",
+              "sim_box_tests"):
         assert a[k] == b[k], k
     for k in sa:
         np.testing.assert_array_equal(sa[k], sb[k])
     assert a["partial_plans"] == ref["stats"]["partial_plans"]
     assert a["rounds"] == ref["stats"]["rounds"]
+    pl.close()
+
+
+HSMC_SCENES = [("cfg1", 0), ("n64", 4)]
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_hsmc(kind, seed):
+    import dataclasses
+    return opump.run(_scene(kind, seed), dataclasses.replace(CFG, cp_model="hsmc"), record=True)
+
+
+@pytest.mark.parametrize("mode,preprune", [(1, 0), (0, 1)])
+@pytest.mark.parametrize("kind,seed", HSMC_SCENES)
+def test_hsmc_plan_end_to_end(kind, seed, mode, preprune):
+    """Half-space exploration model: plan sets, counters, the front and p*
+    equal the oracle's, in both Explore modes (flag counts with pre-pruning
+    off, since pre-pruned pairs are never simulated)."""
+    print_case("hsmc_plan", kind=kind, seed=seed, mode=mode, preprune=preprune)
+    sc = _scene(kind, seed)
+    ref = _oracle_hsmc(kind, seed)
+    pl = planner_for(sc, cp_model=1, preprune=preprune)
+    pl.set_explore_mode(mode)
+    res = pl.plan(pl.scene_problem(sc))
+    print("  gpu", {k: res[k] for k in ("status", "partial_plans", "simulated", "rounds",
+                                        "flagged", "sim_box_tests")},
+          "oracle flagged", ref["stats"]["flagged_particles"], flush=True)
+    assert res["partial_plans"] == ref["stats"]["partial_plans"]
+    assert res["rounds"] == ref["stats"]["rounds"]
+    assert res["final_i"] == ref["stats"]["final_i"]
+    if preprune == 0:
+        assert res["flagged"] == ref["stats"]["flagged_particles"]
+        assert res["inserted"] == ref["stats"]["inserted"]
+    _compare_end_state(pl, ref, sc)
+    assert res["status"] == ref["status"]
+    assert res["n_goal_plans"] == len(ref["goal_plans"])
+    if ref["status"] == 0:
+        assert pl.path(res["best_plan"]) == ref["best"].nodes
+        assert res["best_pop"] == ref["best"].pop
+        k = ref["front"].index(ref["best"]) + 1
+        assert res["best_mc_count"] == ref["evals"][k][0]
     pl.close()

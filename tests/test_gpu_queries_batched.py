@@ -20,7 +20,7 @@ KINDS = [("cfg1", 0), ("cfg1", 3), ("boxes20", 1), ("n64", 4), ("n256", 5), ("in
 SAME = ("status", "n_goal_plans", "n_front", "best", "best_plan", "best_pop", "best_mc_count",
         "best_len", "best_cost", "best_cp_mc", "partial_plans", "simulated", "preprune",
         "inserted", "survivors", "dropped_steps", "flagged", "rounds", "final_i", "n_plans",
-        "n_edges", "c_cut", "c_min")
+        "n_edges", "c_cut", "c_min", "sim_waypoints", "sim_box_tests")
 
 
 def _dev(sc):
@@ -193,4 +193,21 @@ def test_autotuner_picks_a_shape_and_writes_json(tmp_path):
     assert len(rec["candidates"]) == 9
     assert best["explore_threads"] == 256 and ms > 0
     assert rec["best"]["threads"] == best["explore_threads"]
+    b.close()
+
+
+def test_batch_hsmc_equals_single_query_path():
+    """The half-space exploration model in the batched engine (teams and one
+    workgroup per query) equals the single-query path."""
+    kinds = [("cfg1", 0), ("n64", 4), ("cfg1", 3)]
+    print_case("batch_hsmc", kinds=kinds)
+    scs = [scene(k, s) for k, s in kinds]
+    single = [_single(s, cp_model=1) for s in scs]
+    b = _batch_for(scs, cp_model=1)
+    qs = [_dev(s) for s in scs]
+    for t in (TUNINGS[0], TUNINGS[2]):
+        res = b.plan(qs, tuning=t)
+        for i in range(len(scs)):
+            for k in SAME:
+                assert res[i][k] == single[i][0][k], (t, i, k)
     b.close()
