@@ -19,6 +19,8 @@ the one place the oracle rounds.
 
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -97,3 +99,75 @@ def deviation_table(A_cl, L, noise, steps):
     """Position part of the deviations, D[s][a][j], rounded to FP32 storage."""
     dev = deviation_states(A_cl, L, noise, steps)
     return dev[:, :, 0, :].astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# LQG tracking (eq. (2) with the measurement y = C x + w and a Kalman
+# estimate; the controller acts on the estimate).  Readings: C = [1, 0] per
+# axis (the workspace output is the position); W = W_c / dt with
+# W_c = sigma_meas^2 per axis; steady-state LQR gain on the estimate
+# (certainty equivalence) and steady-state Kalman gain; the start state is
+# known exactly (dx_0 = 0, estimate 0); the measurement taken after step s
+# uses the s-th row of the measurement noise.
+# ---------------------------------------------------------------------------
+def kalman_gain(A, C, V, W, tol=1e-14, max_iter=1_000_000):
+    """Steady-state Kalman gain G (update x_hat += G (y - C x_hat_pred)).
+
+    Iterates the predicted covariance P <- A (P - P C^T S^-1 C P) A^T + V,
+    S = C P C^T + W, from P = V to a relative change below `tol`;
+    G = P C^T S^-1 with the converged predicted covariance P."""
+    A = np.asarray(A, float)
+    C = np.atleast_2d(np.asarray(C, float))
+    V = np.asarray(V, float)
+    W = np.atleast_2d(np.asarray(W, float))
+    P = V.copy()
+    for _ in range(max_iter):
+        S = C @ P @ C.T + W
+        Pu = P - P @ C.T @ np.linalg.solve(S, C @ P)
+        Pn = A @ Pu @ A.T + V
+        delta = np.max(np.abs(Pn - P)) / max(np.max(np.abs(Pn)), 1e-300)
+        P = Pn
+        if delta < tol:
+            break
+    G = P @ C.T @ np.linalg.inv(C @ P @ C.T + W)
+    return G, P
+
+
+def lqg_closed_loop(dt, sigma, sigma_meas, q_pos, q_vel, r_track):
+    """Joint closed loop of (dx, x_hat) for one axis: z_{t+1} = M z_t + E xi_t
+    with xi_t = (process normal 1, process normal 2, measurement normal).
+
+        dx'    = A dx - B K x_hat + L xi_p
+        x_hat' = G C A dx + ((I - G C) A - B K) x_hat + G C L xi_p + G sqrt(W) xi_m
+
+    (predict with the applied control, then correct with the measurement of
+    the new state).  Returns M [4, 4], E [4, 3], K [1, 2], G [2, 1]."""
+    A, B, V = discretize(dt, sigma)
+    K, _ = lqr_gain(A, B, np.diag([q_pos, q_vel]), [[r_track]])
+    C = np.array([[1.0, 0.0]])
+    W = np.array([[float(sigma_meas) ** 2 / float(dt)]])
+    G, _ = kalman_gain(A, C, V, W)
+    L = np.linalg.cholesky(V)
+    I2 = np.eye(2)
+    M = np.block([[A, -B @ K], [G @ C @ A, (I2 - G @ C) @ A - B @ K]])
+    E = np.block([[L, np.zeros((2, 1))], [G @ C @ L, G * math.sqrt(W[0, 0])]])
+    return M, E, K, G
+
+
+def lqg_deviation_states(M, E, noise, noise_meas, steps):
+    """Joint states z_s (s = 0..steps) [steps+1, 3, 4, P]; noise [>= steps, 6, P]
+    (process, two per axis), noise_meas [>= steps, 3, P] (one per axis)."""
+    noise = np.asarray(noise, np.float64)
+    meas = np.asarray(noise_meas, np.float64)
+    P = noise.shape[2]
+    out = np.zeros((steps + 1, 3, 4, P))
+    for s in range(steps):
+        for a in range(3):
+            xi = np.concatenate([noise[s, 2 * a:2 * a + 2, :], meas[s, a:a + 1, :]], axis=0)
+            out[s + 1, a] = M @ out[s, a] + E @ xi
+    return out
+
+
+def lqg_deviation_table(M, E, noise, noise_meas, steps):
+    """Position part of the true deviation, D[s][a][j], rounded to FP32."""
+    return lqg_deviation_states(M, E, noise, noise_meas, steps)[:, :, 0, :].astype(np.float32)

@@ -37,6 +37,7 @@ class Config:
     eta: float = 0.0          # 0: the rule above
     lam: float = f32(0.5)
     cp_model: str = "box"     # exploration collision model: "box" or "hsmc"
+    estimator: str = "lqr"    # tracking: "lqr" (full state) or "lqg" (Kalman estimate)
 
 
 def eta_rule(alpha: float) -> float:
@@ -64,7 +65,12 @@ def run(scene, cfg: Config = Config(), record=False, with_selection=True):
     alpha_min, alpha_max = thresholds(alpha, eta)
     A_cl, L, K = dynamics.closed_loop(cfg.dt, scene.sigma, cfg.q_pos, cfg.q_vel, cfg.r_track)
     S_max = scene.S_max
-    D = dynamics.deviation_table(A_cl, L, scene.noise, S_max)
+    if cfg.estimator == "lqg":
+        M_cl, E_cl, _, _ = dynamics.lqg_closed_loop(cfg.dt, scene.sigma, scene.sigma_meas,
+                                                    cfg.q_pos, cfg.q_vel, cfg.r_track)
+        D = dynamics.lqg_deviation_table(M_cl, E_cl, scene.noise, scene.noise_meas, S_max)
+    else:
+        D = dynamics.deviation_table(A_cl, L, scene.noise, S_max)
     g = gr.build_graph(V, scene.obstacles, cfg.r_conn, cfg.r_steer)
     t1 = time.perf_counter()
     gl = scene.goal.astype(np.float64)
@@ -84,8 +90,12 @@ def run(scene, cfg: Config = Config(), record=False, with_selection=True):
     M = scene.M
 
     def mc(plan):
-        c = sel.mc_count(V, plan.nodes, scene.obstacles, A_cl, L, scene.noise_mc,
-                         cfg.r_steer, cfg.dt)
+        if cfg.estimator == "lqg":
+            c = sel.mc_count_lqg(V, plan.nodes, scene.obstacles, M_cl, E_cl, scene.noise_mc,
+                                 scene.noise_mc_meas, cfg.r_steer, cfg.dt)
+        else:
+            c = sel.mc_count(V, plan.nodes, scene.obstacles, A_cl, L, scene.noise_mc,
+                             cfg.r_steer, cfg.dt)
         return c, c / M
 
     best, front, evals = sel.plan_selection(Pg, alpha, mc)

@@ -81,6 +81,32 @@ def mc_count(V, nodes, boxes, A_cl, L, noise_mc, r_u, dt):
     return int(hit.sum())
 
 
+def mc_count_lqg(V, nodes, boxes, M_cl, E, noise_mc, noise_mc_meas, r_u, dt):
+    """mc_count with LQG tracking (dynamics.lqg_closed_loop): each
+    certification particle carries (dx, x_hat) per axis, driven by its process
+    and measurement noise; its position is the waypoint plus dx's position."""
+    W = plan_waypoints(V, nodes, r_u, dt)
+    S = W.shape[0] - 1
+    xi = np.asarray(noise_mc, np.float64)
+    xm = np.asarray(noise_mc_meas, np.float64)
+    M = xi.shape[2]
+    if S > xi.shape[0]:
+        raise ValueError("plan longer than the certification noise")
+    b = np.asarray(boxes, np.float64)
+    z = np.zeros((3, 4, M))
+    prev = np.broadcast_to(W[0][:, None], (3, M)).T.copy()
+    hit = np.zeros(M, bool)
+    for s in range(S):
+        for a in range(3):
+            nz = np.concatenate([xi[s, 2 * a:2 * a + 2, :], xm[s, a:a + 1, :]], axis=0)
+            z[a] = M_cl @ z[a] + E @ nz
+        cur = (W[s + 1][:, None] + z[:, 0, :]).T
+        for j in range(b.shape[0]):
+            hit |= segments_hit_box(prev, cur, b[j, :3], b[j, 3:])
+        prev = cur
+    return int(hit.sum())
+
+
 def pareto_front(plans):
     """Plans of the list not dominated by another of the list:
     d dominates p iff p.cost > d.cost and p.pop >= d.pop."""

@@ -67,6 +67,10 @@ class Scene:
     noise_mc: np.ndarray     # [S_max, 6, M] standard normals (certification)
     name: str = ""
     seed: int = 0
+    # measurement noise of LQG tracking (only with sigma_meas > 0)
+    sigma_meas: float = 0.0
+    noise_meas: Optional[np.ndarray] = None     # [S_max, 3, N] standard normals
+    noise_mc_meas: Optional[np.ndarray] = None  # [S_max, 3, M] standard normals
 
     @property
     def n(self) -> int:
@@ -214,7 +218,7 @@ def _map_of(p, seed: int):
 def make_scene(spec, seed: int, *, M: int = 10_000, S_max: int = 512,
                n: Optional[int] = None, N: Optional[int] = None,
                n_obs: Optional[int] = None, alpha: Optional[float] = None,
-               sigma: Optional[float] = None) -> Scene:
+               sigma: Optional[float] = None, sigma_meas: float = 0.0) -> Scene:
     """Build one seeded query.  `spec` is a WORKLOADS key or a dict of the same
     fields; keyword arguments override individual fields."""
     p = dict(WORKLOADS[spec]) if isinstance(spec, str) else dict(spec)
@@ -227,11 +231,18 @@ def make_scene(spec, seed: int, *, M: int = 10_000, S_max: int = 512,
     Np = int(p["N"])
     noise = _rng(seed, 1).standard_normal((S_max, 6, Np), dtype=np.float32)
     noise_mc = _rng(seed, 2).standard_normal((S_max, 6, int(M)), dtype=np.float32)
-    return Scene(samples=samples, obstacles=np.ascontiguousarray(boxes, np.float32),
-                 x_init=x_init, goal=goal, alpha=float(np.float32(p["alpha"])),
-                 N=Np, sigma=float(np.float32(p["sigma"])),
-                 noise=np.ascontiguousarray(noise), noise_mc=np.ascontiguousarray(noise_mc),
-                 name=name, seed=int(seed))
+    sc = Scene(samples=samples, obstacles=np.ascontiguousarray(boxes, np.float32),
+               x_init=x_init, goal=goal, alpha=float(np.float32(p["alpha"])),
+               N=Np, sigma=float(np.float32(p["sigma"])),
+               noise=np.ascontiguousarray(noise), noise_mc=np.ascontiguousarray(noise_mc),
+               name=name, seed=int(seed))
+    if sigma_meas > 0.0:
+        sc.sigma_meas = float(np.float32(sigma_meas))
+        sc.noise_meas = np.ascontiguousarray(
+            _rng(seed, 6).standard_normal((S_max, 3, Np), dtype=np.float32))
+        sc.noise_mc_meas = np.ascontiguousarray(
+            _rng(seed, 7).standard_normal((S_max, 3, int(M)), dtype=np.float32))
+    return sc
 
 
 # ---------------------------------------------------------------------------
