@@ -19,7 +19,7 @@ import time
 
 import numpy as np
 
-from . import dynamics, explore as ex, graph as gr, select as sel
+from . import dynamics, explore as ex, graph as gr, select as sel, smooth as sm
 
 
 def f32(x) -> float:
@@ -38,6 +38,7 @@ class Config:
     lam: float = f32(0.5)
     cp_model: str = "box"     # exploration collision model: "box" or "hsmc"
     estimator: str = "lqr"    # tracking: "lqr" (full state) or "lqg" (Kalman estimate)
+    smooth: bool = False      # Smooth(p*, alpha) after selection (smooth.py); off: identity
 
 
 def eta_rule(alpha: float) -> float:
@@ -108,4 +109,13 @@ def run(scene, cfg: Config = Config(), record=False, with_selection=True):
         status = 0
     out.update(best=best, front=front, evals=evals, status=status,
                ms_select=1e3 * (t3 - t2))
+    if cfg.smooth and best is not None:
+        def count_w(W):
+            if cfg.estimator == "lqg":
+                return sel.mc_count_lqg_waypoints(W, scene.obstacles, M_cl, E_cl, scene.noise_mc,
+                                                  scene.noise_mc_meas)
+            return sel.mc_count_waypoints(W, scene.obstacles, A_cl, L, scene.noise_mc)
+        k = front.index(best) + 1
+        out["smooth"] = sm.smooth(V, best.nodes, best.cost, best.step, evals[k][0], alpha, M,
+                                  S_max, count_w, cfg.r_steer, cfg.dt)
     return out

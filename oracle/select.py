@@ -11,7 +11,7 @@ its waypoint positions, and it collides iff some segment meets a closed box;
 MC(p) = colliding / M (no variance reduction).  Before sorting, P_goal is
 reduced to its Pareto front across goal nodes (same dominance as
 RemoveDominated); ties in cp_hat are broken by cost descending, then by node
-sequence.  Smooth is the identity.
+sequence.  Smooth(p, alpha) is in smooth.py.
 """
 
 from __future__ import annotations
@@ -61,7 +61,11 @@ def segments_hit_box(a, b, lo, hi):
 
 def mc_count(V, nodes, boxes, A_cl, L, noise_mc, r_u, dt):
     """Number of the M certification particles whose path meets an obstacle."""
-    W = plan_waypoints(V, nodes, r_u, dt)
+    return mc_count_waypoints(plan_waypoints(V, nodes, r_u, dt), boxes, A_cl, L, noise_mc)
+
+
+def mc_count_waypoints(W, boxes, A_cl, L, noise_mc):
+    """MC count over given nominal waypoints W [S+1, 3] (step 0 = start)."""
     S = W.shape[0] - 1
     xi = np.asarray(noise_mc, np.float64)
     M = xi.shape[2]
@@ -85,7 +89,12 @@ def mc_count_lqg(V, nodes, boxes, M_cl, E, noise_mc, noise_mc_meas, r_u, dt):
     """mc_count with LQG tracking (dynamics.lqg_closed_loop): each
     certification particle carries (dx, x_hat) per axis, driven by its process
     and measurement noise; its position is the waypoint plus dx's position."""
-    W = plan_waypoints(V, nodes, r_u, dt)
+    return mc_count_lqg_waypoints(plan_waypoints(V, nodes, r_u, dt), boxes, M_cl, E, noise_mc,
+                                  noise_mc_meas)
+
+
+def mc_count_lqg_waypoints(W, boxes, M_cl, E, noise_mc, noise_mc_meas):
+    """mc_count_lqg over given nominal waypoints W [S+1, 3]."""
     S = W.shape[0] - 1
     xi = np.asarray(noise_mc, np.float64)
     xm = np.asarray(noise_mc_meas, np.float64)
