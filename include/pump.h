@@ -6,7 +6,8 @@
  * The planning problem is the stochastic kinodynamic motion planning problem
  * of Sec. II, eq. (3): find the lowest-cost nominal trajectory from x_init to a
  * goal region whose collision probability (CP) under an LQ tracking controller
- * and Gaussian process noise is at most alpha.  The robot is the 6-D double
+ * (full-state LQR, or LQG with a Kalman estimate) and Gaussian process (and
+ * measurement) noise is at most alpha.  The robot is the 6-D double
  * integrator of Sec. V-A; obstacles are unions of axis-aligned boxes (Sec. V-C).
  * pump_plan() runs Alg. 2: BuildGraph (Alg. 3), Explore (Alg. 4), PlanSelection
  * (Alg. 5).
@@ -82,7 +83,13 @@ typedef struct pump_config {
                               region, planes made perpendicular to the nominal
                               velocity (eq. (7)).  Certification (MC(p)) is the
                               same for both.                                   */
-    int32_t reserved_;     /* zero                                               */
+    int32_t estimator;     /* tracking controller of eq. (2): 0 (default) LQR on
+                              the true deviation (no measurement noise); 1 LQG:
+                              the LQR gain acts on a steady-state Kalman
+                              estimate built from a position measurement
+                              dy = C dx + w, C = [I 0], W = sigma_meas^2 / dt
+                              per axis.  Exploration particles and MC(p) both
+                              follow the chosen controller.                   */
     int64_t cap_edges;     /* capacity: graph edges                                 */
     int64_t cap_plans;     /* capacity: plan records over a whole query             */
     int64_t cap_pairs;     /* capacity: (plan, neighbour) pairs in one round        */
@@ -98,7 +105,15 @@ typedef struct pump_config {
  *                             component 2a and 2a+1 drive axis a at step s
  *   noise_mc  [S_max][6][M]   standard normals for certification
  * alpha in (0, 1) is the CP bound of eq. (3); sigma is the process-noise
- * intensity (V_c = sigma^2 I in eq. (1)). */
+ * intensity (V_c = sigma^2 I in eq. (1)).
+ * With cfg.estimator = 1 (LQG) three more fields are read (ignored otherwise):
+ *   sigma_meas > 0            measurement-noise intensity (W_c = sigma_meas^2 I
+ *                             in eq. (1))
+ *   noise_meas    [S_max][3][N]  standard normals of the exploration
+ *                             particles' measurements; row s, component a is
+ *                             the axis-a measurement taken after step s
+ *   noise_mc_meas [S_max][3][M]  the same for certification
+ * in the memory space `mem` names, like the other arrays. */
 typedef struct pump_problem {
     const float* samples;
     int32_t n;
@@ -111,6 +126,9 @@ typedef struct pump_problem {
     const float* noise;
     const float* noise_mc;
     int32_t mem;             /* PUMP_MEM_HOST or PUMP_MEM_DEVICE */
+    float sigma_meas;
+    const float* noise_meas;
+    const float* noise_mc_meas;
 } pump_problem;
 
 /* Outcome of a query (Alg. 2 output plus counters). */

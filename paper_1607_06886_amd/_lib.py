@@ -38,7 +38,7 @@ class Config(ctypes.Structure):
                 ("max_steps", _i32), ("mc_particles", _i32), ("preprune", _i32),
                 ("dt", _f), ("q_pos", _f), ("q_vel", _f), ("r_track", _f), ("r_steer", _f),
                 ("r_conn", _f), ("eta", _f), ("lambda_", _f), ("cp_model", _i32),
-                ("reserved_", _i32), ("cap_edges", _i64), ("cap_plans", _i64),
+                ("estimator", _i32), ("cap_edges", _i64), ("cap_plans", _i64),
                 ("cap_pairs", _i64)]
 
 
@@ -49,7 +49,8 @@ class AABB(ctypes.Structure):
 class Problem(ctypes.Structure):
     _fields_ = [("samples", _p), ("n", _i32), ("obstacles", _p), ("n_obs", _i32),
                 ("x_init", _f * 6), ("goal", AABB), ("alpha", _f), ("sigma", _f),
-                ("noise", _p), ("noise_mc", _p), ("mem", _i32)]
+                ("noise", _p), ("noise_mc", _p), ("mem", _i32), ("sigma_meas", _f),
+                ("noise_meas", _p), ("noise_mc_meas", _p)]
 
 
 class Result(ctypes.Structure):
@@ -224,16 +225,22 @@ class Planner:
         return rc
 
     # -- problem -------------------------------------------------------------
-    def problem(self, samples, obstacles, x_init, goal, alpha, sigma, noise, noise_mc):
+    def problem(self, samples, obstacles, x_init, goal, alpha, sigma, noise, noise_mc,
+                sigma_meas=0.0, noise_meas=None, noise_mc_meas=None):
         """Build the C problem struct.  Array arguments are numpy (host) or
-        torch CUDA tensors (device), all of the same kind."""
+        torch CUDA tensors (device), all of the same kind.  The measurement
+        noise is read only with estimator = 1 (LQG)."""
         dev = not isinstance(samples, np.ndarray)
         if not dev:
             samples = _np(samples, np.float32)
             obstacles = _np(obstacles, np.float32).reshape(-1, 6)
             noise = _np(noise, np.float32)
             noise_mc = _np(noise_mc, np.float32)
-        self._keep = [samples, obstacles, noise, noise_mc]
+            if noise_meas is not None:
+                noise_meas = _np(noise_meas, np.float32)
+            if noise_mc_meas is not None:
+                noise_mc_meas = _np(noise_mc_meas, np.float32)
+        self._keep = [samples, obstacles, noise, noise_mc, noise_meas, noise_mc_meas]
         pr = Problem()
         pr.samples = _ptr(samples)
         pr.n = int(samples.shape[0])
@@ -251,16 +258,22 @@ class Planner:
         pr.noise = _ptr(noise)
         pr.noise_mc = _ptr(noise_mc)
         pr.mem = MEM_DEVICE if dev else MEM_HOST
+        pr.sigma_meas = float(sigma_meas)
+        pr.noise_meas = _ptr(noise_meas)
+        pr.noise_mc_meas = _ptr(noise_mc_meas)
         return pr
 
     def scene_problem(self, sc, device=False):
         if device:
             import torch
             t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+            tm = lambda a: None if a is None else t(a)
             return self.problem(t(sc.samples), t(sc.obstacles), sc.x_init, sc.goal, sc.alpha,
-                                sc.sigma, t(sc.noise), t(sc.noise_mc))
+                                sc.sigma, t(sc.noise), t(sc.noise_mc), sc.sigma_meas,
+                                tm(sc.noise_meas), tm(sc.noise_mc_meas))
         return self.problem(sc.samples, sc.obstacles, sc.x_init, sc.goal, sc.alpha, sc.sigma,
-                            sc.noise, sc.noise_mc)
+                            sc.noise, sc.noise_mc, sc.sigma_meas, sc.noise_meas,
+                            sc.noise_mc_meas)
 
     # -- whole query and stages ----------------------------------------------
     def plan(self, pr) -> dict:
@@ -494,7 +507,8 @@ class MLP:
 class Batch:
     """The batched engine: many device-resident queries in one graph launch.
     Queries are (samples, obstacles, x_init, goal, alpha, sigma, noise,
-    noise_mc) with torch CUDA tensors for the arrays; N is taken from
+    noise_mc) with torch CUDA tensors for the arrays, optionally followed by
+    (sigma_meas, noise_meas, noise_mc_meas) for LQG tracking; N is taken from
     noise.shape[2]."""
 
     def __init__(self, max_queries, stream=None, **cfg):
@@ -528,8 +542,10 @@ class Batch:
         arr = (Problem * q)()
         ns = (_i32 * q)()
         keep = []
-        for i, (smp, obs, x0, goal, alpha, sigma, noise, noise_mc) in enumerate(queries):
-            keep += [smp, obs, noise, noise_mc]
+        for i, qu in enumerate(queries):
+            smp, obs, x0, goal, alpha, sigma, noise, noise_mc = qu[:8]
+            sm, nm, nmc = (tuple(qu[8:11]) + (0.0, None, None)[len(qu[8:11]):])
+            keep += [smp, obs, noise, noise_mc, nm, nmc]
             pr = arr[i]
             pr.samples = _ptr(smp)
             pr.n = int(smp.shape[0])
@@ -547,6 +563,9 @@ class Batch:
             pr.noise = _ptr(noise)
             pr.noise_mc = _ptr(noise_mc)
             pr.mem = MEM_DEVICE
+            pr.sigma_meas = float(sm)
+            pr.noise_meas = _ptr(nm)
+            pr.noise_mc_meas = _ptr(nmc)
             ns[i] = int(noise.shape[2])
         self._keep = keep
         return arr, ns

@@ -28,22 +28,37 @@ __device__ __forceinline__ DevCoef dev_coef(const BatchQuery& Q) {
     return DevCoef{Q.Acl[0], Q.Acl[1], Q.Acl[2], Q.Acl[3], Q.L[0], Q.L[2], Q.L[3]};
 }
 
+// Deviation table per query (LQR or LQG tracking; the scratch holds the chunk
+// responses, then the chunk start states: 2 or 4 doubles per column each).
 __global__ void k_b_dev_local(BatchQuery* qs, int S) {
     const BatchQuery& Q = qs[blockIdx.y];
-    dev_local_dev(Q.noise, Q.dev_scratch, Q.N, S, dev_coef(Q));
+    if (Q.estimator)
+        lqg_local_dev(Q.noise, Q.noise_meas, Q.dev_scratch, Q.N, S, Q.lqg);
+    else
+        dev_local_dev(Q.noise, Q.dev_scratch, Q.N, S, dev_coef(Q));
 }
 
 __global__ void k_b_dev_carry(BatchQuery* qs, int S) {
     const BatchQuery& Q = qs[blockIdx.y];
     const int K = (S + kDevChunk - 1) / kDevChunk;
-    dev_carry_dev(Q.dev_scratch, Q.dev_scratch + (size_t)2 * K * 3 * Q.N, Q.N, S, dev_coef(Q));
+    const int per = Q.estimator ? 4 : 2;
+    double* X0 = Q.dev_scratch + (size_t)per * K * 3 * Q.N;
+    if (Q.estimator)
+        lqg_carry_dev(Q.dev_scratch, X0, Q.N, S, Q.lqg);
+    else
+        dev_carry_dev(Q.dev_scratch, X0, Q.N, S, dev_coef(Q));
 }
 
 __global__ void k_b_dev_final(BatchQuery* qs, int S) {
     const BatchQuery& Q = qs[blockIdx.y];
     const int K = (S + kDevChunk - 1) / kDevChunk;
-    dev_final_dev(Q.noise, Q.dev_scratch + (size_t)2 * K * 3 * Q.N, const_cast<float*>(Q.ra[0].D),
-                  Q.N, S, dev_coef(Q));
+    const int per = Q.estimator ? 4 : 2;
+    const double* X0 = Q.dev_scratch + (size_t)per * K * 3 * Q.N;
+    float* D = const_cast<float*>(Q.ra[0].D);
+    if (Q.estimator)
+        lqg_final_dev(Q.noise, Q.noise_meas, X0, D, Q.N, S, Q.lqg);
+    else
+        dev_final_dev(Q.noise, X0, D, Q.N, S, dev_coef(Q));
 }
 
 __global__ void k_b_cloud(BatchQuery* qs) {

@@ -19,6 +19,22 @@ __global__ void k_dev_final(const float* __restrict__ noise, const double* __res
     dev_final_dev(noise, X0, D, N, S, m);
 }
 
+__global__ void k_lqg_local(const float* __restrict__ noise, const float* __restrict__ meas,
+                            double* __restrict__ E, int N, int S, LqgCoef q) {
+    lqg_local_dev(noise, meas, E, N, S, q);
+}
+
+__global__ void k_lqg_carry(const double* __restrict__ E, double* __restrict__ X0, int N, int S,
+                            LqgCoef q) {
+    lqg_carry_dev(E, X0, N, S, q);
+}
+
+__global__ void k_lqg_final(const float* __restrict__ noise, const float* __restrict__ meas,
+                            const double* __restrict__ X0, float* __restrict__ D, int N, int S,
+                            LqgCoef q) {
+    lqg_final_dev(noise, meas, X0, D, N, S, q);
+}
+
 __global__ void k_cloud(const float* __restrict__ D, float* __restrict__ cloud, int N) {
     cloud_dev(D, cloud, N);
 }
@@ -38,6 +54,20 @@ void launch_deviation_table(hipStream_t s, const float* noise, float* D, float* 
     k_dev_local<<<(threads + 255) / 256, 256, 0, s>>>(noise, E, N, S_max, m);
     k_dev_carry<<<(3 * N + 63) / 64, 64, 0, s>>>(E, X0, N, S_max, m);
     k_dev_final<<<(threads + 255) / 256, 256, 0, s>>>(noise, X0, D, N, S_max, m);
+    k_cloud<<<S_max + 1, 256, 0, s>>>(D, cloud, N);
+    k_gcloud<<<1, 256, 0, s>>>(cloud, gcloud, S_max + 1);
+}
+
+void launch_deviation_table_lqg(hipStream_t s, const float* noise, const float* noise_meas,
+                                float* D, float* cloud, float* gcloud, int N, int S_max,
+                                const LqgCoef& q, double* scratch) {
+    const int K = (S_max + kDevChunk - 1) / kDevChunk;
+    double* E = scratch;
+    double* X0 = scratch + (size_t)4 * K * 3 * N;
+    const int threads = K * 3 * N;
+    k_lqg_local<<<(threads + 255) / 256, 256, 0, s>>>(noise, noise_meas, E, N, S_max, q);
+    k_lqg_carry<<<(3 * N + 63) / 64, 64, 0, s>>>(E, X0, N, S_max, q);
+    k_lqg_final<<<(threads + 255) / 256, 256, 0, s>>>(noise, noise_meas, X0, D, N, S_max, q);
     k_cloud<<<S_max + 1, 256, 0, s>>>(D, cloud, N);
     k_gcloud<<<1, 256, 0, s>>>(cloud, gcloud, S_max + 1);
 }

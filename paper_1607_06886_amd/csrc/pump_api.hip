@@ -29,6 +29,11 @@ struct pump_ctx {
     float* noise_mc_buf = nullptr;
     const float* noise = nullptr;
     const float* noise_mc = nullptr;
+    float* noise_meas_buf = nullptr;     // LQG only
+    float* noise_mc_meas_buf = nullptr;  // LQG only
+    const float* noise_meas = nullptr;
+    const float* noise_mc_meas = nullptr;
+    LqgCoef lqg;
     float* D = nullptr;
     double* dev_scratch = nullptr;  // deviation-table chunk states
     float* cloud = nullptr;
@@ -194,6 +199,9 @@ SelectArgs select_args(pump_ctx* c) {
     a.dt = c->dt;
     a.r_steer = (double)c->cfg.r_steer;
     for (int k = 0; k < 4; ++k) { a.Acl[k] = c->Acl[k]; a.L[k] = c->L[k]; }
+    a.estimator = c->cfg.estimator;
+    a.noise_mc_meas = c->noise_mc_meas;
+    a.lqg = c->lqg;
     a.ctl = c->ctl;
     return a;
 }
@@ -266,6 +274,7 @@ void pump_config_default(pump_config* c) {
     c->eta = 0.0f;
     c->lambda = 0.5f;
     c->cp_model = 0;
+    c->estimator = 0;
     c->cap_edges = 4 << 20;
     c->cap_plans = 1 << 20;
     c->cap_pairs = 4 << 20;
@@ -290,6 +299,7 @@ int pump_destroy(pump_ctx* ctx) {
     if (!ctx) return PUMP_OK;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     void* ptrs[] = {ctx->X, ctx->valid, ctx->goal, ctx->obs, ctx->noise_buf, ctx->noise_mc_buf,
+                    ctx->noise_meas_buf, ctx->noise_mc_meas_buf,
                     ctx->D, ctx->cloud, ctx->gcloud, ctx->dev_ints, ctx->ebits, ctx->deg,
                     ctx->row_ptr, ctx->col, ctx->esrc, ctx->etau, ctx->ecost, ctx->p_head, ctx->p_parent,
                     ctx->p_edge, ctx->p_step, ctx->p_pop, ctx->p_round, ctx->p_cost, ctx->p_mask,
@@ -323,6 +333,7 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     if (!(N == 32 || N == 64 || N == 128 || N == 256)) return PUMP_E_ARG;
     if (cfg.max_nodes < 2 || cfg.max_nodes > 65535) return PUMP_E_ARG;
     if (cfg.cp_model != 0 && cfg.cp_model != 1) return PUMP_E_ARG;
+    if (cfg.estimator != 0 && cfg.estimator != 1) return PUMP_E_ARG;
     if (cfg.max_obstacles < 0 || cfg.max_obstacles > kMaxObs) return PUMP_E_ARG;
     if (cfg.max_steps < 1 || cfg.max_steps > 4096 || cfg.mc_particles < 1) return PUMP_E_ARG;
     if (!(cfg.dt > 0) || !(cfg.r_conn > 0) || !(cfg.lambda > 0) || !(cfg.r_steer > 0) ||
@@ -358,7 +369,11 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     A(dalloc(&ctx->noise_buf, S * 6 * N));
     A(dalloc(&ctx->noise_mc_buf, S * 6 * M));
     A(dalloc(&ctx->D, (S + 1) * 3 * N));
-    A(dalloc(&ctx->dev_scratch, (size_t)4 * ((S + 15) / 16) * 3 * N));
+    if (cfg.estimator == 1) {
+        A(dalloc(&ctx->noise_meas_buf, S * 3 * N));
+        A(dalloc(&ctx->noise_mc_meas_buf, S * 3 * M));
+    }
+    A(dalloc(&ctx->dev_scratch, (size_t)kDevScratchPer * ((S + 15) / 16) * 3 * N));
     A(dalloc(&ctx->cloud, (S + 1) * 6));
     A(dalloc(&ctx->gcloud, 8));
     A(dalloc(&ctx->dev_ints, 8));
@@ -445,6 +460,12 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
         return fail(ctx, PUMP_E_ARG, "null input pointer");
     if (!(pr->alpha > 0.0f && pr->alpha < 1.0f)) return fail(ctx, PUMP_E_ARG, "alpha must lie in (0, 1)");
     if (!(pr->sigma >= 0.0f) || !std::isfinite(pr->sigma)) return fail(ctx, PUMP_E_ARG, "sigma must be finite and >= 0");
+    if (cfg.estimator == 1) {
+        if (!(pr->sigma_meas > 0.0f) || !std::isfinite(pr->sigma_meas))
+            return fail(ctx, PUMP_E_ARG, "LQG needs a finite sigma_meas > 0");
+        if (!pr->noise_meas || !pr->noise_mc_meas)
+            return fail(ctx, PUMP_E_ARG, "LQG needs noise_meas and noise_mc_meas");
+    }
     if (!finite6(pr->x_init)) return fail(ctx, PUMP_E_ARG, "x_init not finite");
     for (int k = 0; k < 3; ++k) {
         if (fabsf(pr->x_init[k]) > 16.0f) return fail(ctx, PUMP_E_ARG, "x_init outside [-16, 16]");
@@ -480,6 +501,10 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
     // tracking constants (eq. (2) for the double integrator; LQR)
     tracking_constants(ctx->dt, (double)cfg.q_pos, (double)cfg.q_vel, (double)cfg.r_track,
                        (double)pr->sigma, ctx->K, ctx->Acl, ctx->L);
+    memset(&ctx->lqg, 0, sizeof(ctx->lqg));
+    if (cfg.estimator == 1)
+        lqg_constants(ctx->dt, (double)cfg.q_pos, (double)cfg.q_vel, (double)cfg.r_track,
+                      (double)pr->sigma, (double)pr->sigma_meas, ctx->lqg.m, ctx->lqg.e);
 
     HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
     // uploads: x_init is node 0, sample i is node i + 1
@@ -495,15 +520,33 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
                               ctx->stream));
         ctx->noise = ctx->noise_buf;
         ctx->noise_mc = ctx->noise_mc_buf;
+        if (cfg.estimator == 1) {
+            HIPCHK(hipMemcpyAsync(ctx->noise_meas_buf, pr->noise_meas,
+                                  (size_t)ctx->S_max * 3 * N * sizeof(float),
+                                  hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync(ctx->noise_mc_meas_buf, pr->noise_mc_meas,
+                                  (size_t)ctx->S_max * 3 * ctx->M * sizeof(float),
+                                  hipMemcpyHostToDevice, ctx->stream));
+            ctx->noise_meas = ctx->noise_meas_buf;
+            ctx->noise_mc_meas = ctx->noise_mc_meas_buf;
+        }
     } else {
         ctx->noise = pr->noise;
         ctx->noise_mc = pr->noise_mc;
+        if (cfg.estimator == 1) {
+            ctx->noise_meas = pr->noise_meas;
+            ctx->noise_mc_meas = pr->noise_mc_meas;
+        }
     }
     float gb[6] = {pr->goal.lo[0], pr->goal.lo[1], pr->goal.lo[2],
                    pr->goal.hi[0], pr->goal.hi[1], pr->goal.hi[2]};
     tbeg(ctx, 0);
-    launch_deviation_table(ctx->stream, ctx->noise, ctx->D, ctx->cloud, ctx->gcloud, N, ctx->S_max,
-                           ctx->Acl, ctx->L, ctx->dev_scratch);
+    if (cfg.estimator == 1)
+        launch_deviation_table_lqg(ctx->stream, ctx->noise, ctx->noise_meas, ctx->D, ctx->cloud,
+                                   ctx->gcloud, N, ctx->S_max, ctx->lqg, ctx->dev_scratch);
+    else
+        launch_deviation_table(ctx->stream, ctx->noise, ctx->D, ctx->cloud, ctx->gcloud, N,
+                               ctx->S_max, ctx->Acl, ctx->L, ctx->dev_scratch);
     tend(ctx);
     HIPCHK(hipMemsetAsync(ctx->dev_ints, 0, 8 * sizeof(int32_t), ctx->stream));
     launch_mark_valid(ctx->stream, ctx->X, ctx->n_nodes, ctx->obs, ctx->n_obs, gb, ctx->valid, ctx->goal,

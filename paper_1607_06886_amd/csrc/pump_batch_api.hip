@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <string>
 #include <type_traits>
@@ -92,6 +93,7 @@ int pump_batch_create(const pump_config* cfg_in, int32_t max_queries, void* hip_
     const int N = cfg.n_particles;
     if (!(N == 32 || N == 64 || N == 128 || N == 256)) return PUMP_E_ARG;
     if (cfg.cp_model != 0 && cfg.cp_model != 1) return PUMP_E_ARG;
+    if (cfg.estimator != 0 && cfg.estimator != 1) return PUMP_E_ARG;
     if (cfg.max_nodes < 2 || cfg.max_nodes > 65535 || cfg.max_obstacles > kMaxObs ||
         cfg.max_steps < 1 || cfg.max_steps > 4096 || cfg.mc_particles < 1)
         return PUMP_E_ARG;
@@ -131,7 +133,7 @@ int pump_batch_create(const pump_config* cfg_in, int32_t max_queries, void* hip_
     Slot lay{};
     take(&lay.X, nn * 6); take(&lay.obs, (size_t)kMaxObs * 6); take(&lay.D, (S + 1) * 3 * N);
     take(&lay.cloud, (S + 1) * 6);
-    take(&lay.dev_scratch, (size_t)4 * ((S + 15) / 16) * 3 * N); take(&lay.gcloud, 8); take(&lay.valid, nn); take(&lay.goal, nn);
+    take(&lay.dev_scratch, (size_t)kDevScratchPer * ((S + 15) / 16) * 3 * N); take(&lay.gcloud, 8); take(&lay.valid, nn); take(&lay.goal, nn);
     take(&lay.ebits, nn * b->words); take(&lay.deg, nn + 1); take(&lay.row_ptr, nn + 2);
     take(&lay.col, E); take(&lay.esrc, E); take(&lay.etau, E); take(&lay.ecost, E);
     take(&lay.p_head, P); take(&lay.p_parent, P); take(&lay.p_edge, P); take(&lay.p_step, P);
@@ -210,6 +212,10 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         if (!(pr.alpha > 0.0f && pr.alpha < 1.0f) || !(pr.sigma >= 0.0f) || !pr.samples ||
             !pr.noise || !pr.noise_mc || (pr.n_obs > 0 && !pr.obstacles))
             return bfail(b, PUMP_E_ARG, "query " + std::to_string(i) + ": arguments");
+        if (cfg.estimator == 1 && (!(pr.sigma_meas > 0.0f) || !std::isfinite(pr.sigma_meas) ||
+                                   !pr.noise_meas || !pr.noise_mc_meas))
+            return bfail(b, PUMP_E_ARG, "query " + std::to_string(i) +
+                                            ": LQG needs sigma_meas > 0, noise_meas and noise_mc_meas");
         const Slot& s = b->slots[i];
         BatchQuery& Q = b->qs[i];
         memset(&Q, 0, sizeof(Q));
@@ -229,6 +235,13 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         Q.samples = pr.samples;
         Q.obs_src = reinterpret_cast<const float*>(pr.obstacles);
         Q.noise = pr.noise;
+        Q.estimator = cfg.estimator;
+        if (cfg.estimator == 1) {
+            Q.noise_meas = pr.noise_meas;
+            lqg_constants((double)cfg.dt, (double)cfg.q_pos, (double)cfg.q_vel,
+                          (double)cfg.r_track, (double)pr.sigma, (double)pr.sigma_meas, Q.lqg.m,
+                          Q.lqg.e);
+        }
         for (int k = 0; k < 6; ++k) Q.x_init[k] = pr.x_init[k];
         for (int k = 0; k < 3; ++k) { Q.goal_box[k] = pr.goal.lo[k]; Q.goal_box[3 + k] = pr.goal.hi[k]; }
         Q.dev_scratch = s.dev_scratch;
@@ -263,6 +276,9 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         sa.noise_mc = pr.noise_mc; sa.M = cfg.mc_particles; sa.S_max = cfg.max_steps; sa.dt = (double)cfg.dt;
         sa.r_steer = (double)cfg.r_steer;
         for (int k = 0; k < 4; ++k) { sa.Acl[k] = Q.Acl[k]; sa.L[k] = Q.L[k]; }
+        sa.estimator = Q.estimator;
+        sa.noise_mc_meas = cfg.estimator == 1 ? pr.noise_mc_meas : nullptr;
+        sa.lqg = Q.lqg;
         sa.ctl = s.ctl;
         N_max = std::max(N_max, N);
         max_nodes = std::max(max_nodes, Q.n_nodes);

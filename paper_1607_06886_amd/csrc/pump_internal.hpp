@@ -24,6 +24,26 @@ constexpr double kTauMin = 1e-6;      // connections shorter than this are skipp
 
 enum PlanState : uint8_t { kOpen = 0, kClosed = 1, kRemoved = 2 };
 
+// LQG tracking of one axis (eq. (2) with a Kalman estimate): the state
+// z = (dp, dv, p_hat, v_hat) follows z' = m z + e (xi_p0, xi_p1, xi_m),
+// m row-major 4x4 and e row-major 4x3.
+struct LqgCoef {
+    double m[16];
+    double e[12];
+};
+
+// One step of that recurrence in FP64.
+__device__ __forceinline__ void lqg_step(const LqgCoef& q, double z[4], double w0, double w1,
+                                         double w2) {
+    double zn[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        zn[i] = q.m[4 * i] * z[0] + q.m[4 * i + 1] * z[1] + q.m[4 * i + 2] * z[2] +
+                q.m[4 * i + 3] * z[3] + (q.e[3 * i] * w0 + q.e[3 * i + 1] * w1 + q.e[3 * i + 2] * w2);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z[i] = zn[i];
+}
+
 // Device-resident control block of the Explore loop.
 struct Ctl {
     int32_t n_plans;
@@ -111,10 +131,15 @@ struct RoundArgs {
 };
 
 // ---- launchers (kernels_*.hip) ----
-// scratch: 4 * ceil(S_max / 16) * 3 * N doubles
+// scratch: kDevScratchPer * ceil(S_max / 16) * 3 * N doubles
+constexpr int kDevScratchPer = 8;
 void launch_deviation_table(hipStream_t s, const float* noise, float* D, float* cloud,
                             float* gcloud, int N, int S_max, const double* Acl,
                             const double* L, double* scratch);
+// The same table under LQG tracking: noise_meas [S_max][3][N].
+void launch_deviation_table_lqg(hipStream_t s, const float* noise, const float* noise_meas,
+                                float* D, float* cloud, float* gcloud, int N, int S_max,
+                                const LqgCoef& q, double* scratch);
 void launch_mark_valid(hipStream_t s, const float* X, int n_nodes, const float* obs,
                        int n_obs, const float* goal_box, uint8_t* valid, uint8_t* goal,
                        int32_t* bad);
@@ -161,6 +186,9 @@ struct SelectArgs {
     double r_steer;
     double Acl[4];
     double L[4];
+    int32_t estimator;           // 0 LQR, 1 LQG (then noise_mc_meas and lqg are used)
+    const float* noise_mc_meas;  // [S_max][3][M]
+    LqgCoef lqg;
     Ctl* ctl;
 };
 
@@ -198,6 +226,9 @@ struct BatchQuery {
     const float* samples;      // [n][6] caller's device array
     const float* obs_src;      // [n_obs][6] caller's device array
     const float* noise;        // [S_max][6][N] caller's device array
+    const float* noise_meas;   // [S_max][3][N] caller's device array (LQG only)
+    int32_t estimator;         // 0 LQR, 1 LQG
+    LqgCoef lqg;
     float x_init[6];
     float goal_box[6];
     double Acl[4], L[4];

@@ -142,13 +142,47 @@ __device__ __forceinline__ void waypoints_one(const SelectArgs& a, int f) {
     a.wp_len[f] = ok ? s : -1;
 }
 
+// Does the segment prev -> cur meet a closed obstacle box?  Slab clipping in
+// FP64 after a bounding-box reject.
+__device__ __forceinline__ bool segment_hits_boxes(const double prev[3], const double cur[3],
+                                                   const float* s_obs, int n_obs) {
+    double smin[3], smax[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        smin[ax] = fmin(prev[ax], cur[ax]);
+        smax[ax] = fmax(prev[ax], cur[ax]);
+    }
+    bool hit = false;
+    for (int o = 0; o < n_obs && !hit; ++o) {
+        const float* b = s_obs + o * 6;
+        // a segment whose bounding box misses the box misses the box
+        if ((smax[0] < (double)b[0]) | (smin[0] > (double)b[3]) | (smax[1] < (double)b[1]) |
+            (smin[1] > (double)b[4]) | (smax[2] < (double)b[2]) | (smin[2] > (double)b[5]))
+            continue;
+        double t0 = 0.0, t1 = 1.0;
+        bool miss = false;
+        for (int ax = 0; ax < 3; ++ax) {
+            const double d = cur[ax] - prev[ax];
+            const double lo = (double)b[ax], hi = (double)b[3 + ax];
+            if (d == 0.0) {
+                miss |= (prev[ax] < lo) | (prev[ax] > hi);
+            } else {
+                const double ta = (lo - prev[ax]) / d, tb = (hi - prev[ax]) / d;
+                t0 = fmax(t0, fmin(ta, tb));
+                t1 = fmin(t1, fmax(ta, tb));
+            }
+        }
+        hit = !miss && (t0 <= t1);
+    }
+    return hit;
+}
+
 // MC(p) for one certification particle m of path f: its deviation follows
 // the closed-loop recurrence from zero with its own noise; its workspace path
 // is the polyline through the waypoint positions; it collides iff a segment
 // meets a closed obstacle box (slab clipping, FP64).
-__device__ __forceinline__ bool mc_particle(const SelectArgs& a, int f, int m, const float* s_obs) {
+__device__ __forceinline__ bool mc_particle_lqr(const SelectArgs& a, int f, int m,
+                                                const float* s_obs) {
     const int S = a.wp_len[f];
-    if (m >= a.M || S < 0) return false;
     const int stride = a.S_max + 1;
     const double* wp = a.wp + (size_t)f * stride * 3;
     double dp[3] = {0.0, 0.0, 0.0}, dv[3] = {0.0, 0.0, 0.0};
@@ -167,35 +201,40 @@ __device__ __forceinline__ bool mc_particle(const SelectArgs& a, int f, int m, c
             dv[ax] = vn;
             cur[ax] = wp[(size_t)(s + 1) * 3 + ax] + pn;
         }
-        double smin[3], smax[3];
-        for (int ax = 0; ax < 3; ++ax) {
-            smin[ax] = fmin(prev[ax], cur[ax]);
-            smax[ax] = fmax(prev[ax], cur[ax]);
-        }
-        for (int o = 0; o < a.n_obs && !hit; ++o) {
-            const float* b = s_obs + o * 6;
-            // a segment whose bounding box misses the box misses the box
-            if ((smax[0] < (double)b[0]) | (smin[0] > (double)b[3]) | (smax[1] < (double)b[1]) |
-                (smin[1] > (double)b[4]) | (smax[2] < (double)b[2]) | (smin[2] > (double)b[5]))
-                continue;
-            double t0 = 0.0, t1 = 1.0;
-            bool miss = false;
-            for (int ax = 0; ax < 3; ++ax) {
-                const double d = cur[ax] - prev[ax];
-                const double lo = (double)b[ax], hi = (double)b[3 + ax];
-                if (d == 0.0) {
-                    miss |= (prev[ax] < lo) | (prev[ax] > hi);
-                } else {
-                    const double ta = (lo - prev[ax]) / d, tb = (hi - prev[ax]) / d;
-                    t0 = fmax(t0, fmin(ta, tb));
-                    t1 = fmin(t1, fmax(ta, tb));
-                }
-            }
-            hit = !miss && (t0 <= t1);
-        }
+        hit = segment_hits_boxes(prev, cur, s_obs, a.n_obs);
         prev[0] = cur[0]; prev[1] = cur[1]; prev[2] = cur[2];
     }
     return hit;
+}
+
+// The same under LQG tracking: per axis the particle carries (dp, dv, p_hat,
+// v_hat), driven by its two process normals and its measurement normal.
+__device__ __forceinline__ bool mc_particle_lqg(const SelectArgs& a, int f, int m,
+                                                const float* s_obs) {
+    const int S = a.wp_len[f];
+    const int stride = a.S_max + 1;
+    const double* wp = a.wp + (size_t)f * stride * 3;
+    double z[3][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    double prev[3] = {wp[0], wp[1], wp[2]};
+    bool hit = false;
+    for (int s = 0; s < S && !hit; ++s) {
+        double cur[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            const double w0 = (double)a.noise_mc[((size_t)s * 6 + 2 * ax) * a.M + m];
+            const double w1 = (double)a.noise_mc[((size_t)s * 6 + 2 * ax + 1) * a.M + m];
+            const double w2 = (double)a.noise_mc_meas[((size_t)s * 3 + ax) * a.M + m];
+            lqg_step(a.lqg, z[ax], w0, w1, w2);
+            cur[ax] = wp[(size_t)(s + 1) * 3 + ax] + z[ax][0];
+        }
+        hit = segment_hits_boxes(prev, cur, s_obs, a.n_obs);
+        prev[0] = cur[0]; prev[1] = cur[1]; prev[2] = cur[2];
+    }
+    return hit;
+}
+
+__device__ __forceinline__ bool mc_particle(const SelectArgs& a, int f, int m, const float* s_obs) {
+    if (m >= a.M || a.wp_len[f] < 0) return false;
+    return a.estimator ? mc_particle_lqg(a, f, m, s_obs) : mc_particle_lqr(a, f, m, s_obs);
 }
 
 }  // namespace pump

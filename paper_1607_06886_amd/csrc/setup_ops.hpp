@@ -99,6 +99,102 @@ __device__ __forceinline__ void dev_final_dev(const float* __restrict__ noise, c
     dev_run_chunk(noise, N, S, a, j, k, m, p, v, D);
 }
 
+// ---------------------------------------------------------------------------
+// The deviation table under LQG tracking.  Per (axis a, particle j) the
+// joint state z = (dp, dv, p_hat, v_hat) follows z' = m z + e xi with
+// xi = (noise[s][2a][j], noise[s][2a+1][j], noise_meas[s][a][j]), z_0 = 0;
+// D stores dp.  Same three chunked passes as above with a 4-state carry
+// (Phi = m^C).  Scratch: E and X0, each [K][3][N] of 4 doubles.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lqg_run_chunk(const float* __restrict__ noise,
+                                              const float* __restrict__ meas, int N, int S, int a,
+                                              int j, int k, const LqgCoef& q, double z[4],
+                                              float* __restrict__ D) {
+    const int s0 = k * kDevChunk;
+    float w0[kDevChunk], w1[kDevChunk], w2[kDevChunk];
+#pragma unroll
+    for (int u = 0; u < kDevChunk; ++u) {
+        const int s = s0 + u < S ? s0 + u : S - 1;
+        w0[u] = noise[((size_t)s * 6 + 2 * a) * N + j];
+        w1[u] = noise[((size_t)s * 6 + 2 * a + 1) * N + j];
+        w2[u] = meas[((size_t)s * 3 + a) * N + j];
+    }
+#pragma unroll
+    for (int u = 0; u < kDevChunk; ++u) {
+        if (s0 + u >= S) break;
+        lqg_step(q, z, (double)w0[u], (double)w1[u], (double)w2[u]);
+        if (D) D[((size_t)(s0 + u + 1) * 3 + a) * N + j] = (float)z[0];
+    }
+}
+
+// (1) chunk responses; thread t = (k * 3 + a) * N + j
+__device__ __forceinline__ void lqg_local_dev(const float* __restrict__ noise,
+                                              const float* __restrict__ meas,
+                                              double* __restrict__ E, int N, int S,
+                                              const LqgCoef& q) {
+    const int K = (S + kDevChunk - 1) / kDevChunk;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= K * 3 * N) return;
+    const int j = t % N, a = (t / N) % 3, k = t / (3 * N);
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    lqg_run_chunk(noise, meas, N, S, a, j, k, q, z, nullptr);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) E[4 * (size_t)t + i] = z[i];
+}
+
+// (2) chunk start states; thread col = a * N + j
+__device__ __forceinline__ void lqg_carry_dev(const double* __restrict__ E,
+                                              double* __restrict__ X0, int N, int S,
+                                              const LqgCoef& q) {
+    const int K = (S + kDevChunk - 1) / kDevChunk;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= 3 * N) return;
+    double f[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) f[i] = (i % 5 == 0) ? 1.0 : 0.0;
+    for (int u = 0; u < kDevChunk; ++u) {
+        double g[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                g[4 * i + c] = q.m[4 * i] * f[c] + q.m[4 * i + 1] * f[4 + c] +
+                               q.m[4 * i + 2] * f[8 + c] + q.m[4 * i + 3] * f[12 + c];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) f[i] = g[i];
+    }
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < K; ++k) {
+        const size_t t = (size_t)k * 3 * N + col;
+        double zn[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            X0[4 * t + i] = z[i];
+            zn[i] = f[4 * i] * z[0] + f[4 * i + 1] * z[1] + f[4 * i + 2] * z[2] +
+                    f[4 * i + 3] * z[3] + E[4 * t + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) z[i] = zn[i];
+    }
+}
+
+// (3) the table; thread t = (k * 3 + a) * N + j
+__device__ __forceinline__ void lqg_final_dev(const float* __restrict__ noise,
+                                              const float* __restrict__ meas,
+                                              const double* __restrict__ X0,
+                                              float* __restrict__ D, int N, int S,
+                                              const LqgCoef& q) {
+    const int K = (S + kDevChunk - 1) / kDevChunk;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= K * 3 * N) return;
+    const int j = t % N, a = (t / N) % 3, k = t / (3 * N);
+    if (k == 0) D[(size_t)a * N + j] = 0.0f;
+    double z[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z[i] = X0[4 * (size_t)t + i];
+    lqg_run_chunk(noise, meas, N, S, a, j, k, q, z, D);
+}
+
 // Bounding box of the particle cloud at each step: cloud[s] = (min_j D[s][a][j], max_j ...).
 __device__ __forceinline__ void cloud_dev(const float* __restrict__ D, float* __restrict__ cloud, int N) {
     __shared__ float smin[3][256], smax[3][256];

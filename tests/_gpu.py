@@ -52,25 +52,37 @@ def print_case(name, **kw):
     print(f"[gpu case] {name} {kw}", flush=True)
 
 
-def scene(kind, seed):
-    """Parity scenes (M = 2000 certification particles, S_max = 256)."""
+def scene(kind, seed, sigma_meas=0.0):
+    """Parity scenes (M = 2000 certification particles, S_max = 256);
+    sigma_meas > 0 adds the measurement noise of LQG tracking."""
+    kw = dict(M=2000, S_max=256, sigma_meas=sigma_meas)
     if kind == "cfg1":
-        return scenes.make_scene("cfg1", scenes.workload_seed(1, seed), M=2000, S_max=256)
+        return scenes.make_scene("cfg1", scenes.workload_seed(1, seed), **kw)
     if kind == "boxes20":
         return scenes.make_scene(small_spec(n=400, N=128, sigma=0.02, alpha=0.01, n_obs=20,
-                                            side=(0.05, 0.25)), 500 + seed, M=2000, S_max=256)
+                                            side=(0.05, 0.25)), 500 + seed, **kw)
     if kind == "indoor":
         return scenes.make_scene(dict(n=450, n_obs=60, side=None, N=128, sigma=0.02, alpha=0.05,
-                                      indoor=True), 700 + seed, M=2000, S_max=256)
+                                      indoor=True), 700 + seed, **kw)
     if kind == "n64":
         return scenes.make_scene(small_spec(n=250, N=64, sigma=0.03, alpha=0.05, n_obs=8),
-                                 900 + seed, M=2000, S_max=256)
+                                 900 + seed, **kw)
     if kind == "n256":
         return scenes.make_scene(small_spec(n=300, N=256, sigma=0.02, alpha=0.02, n_obs=12,
-                                            side=(0.05, 0.25)), 950 + seed, M=2000, S_max=256)
+                                            side=(0.05, 0.25)), 950 + seed, **kw)
     raise ValueError(kind)
 
 
 @functools.lru_cache(maxsize=None)
 def oracle_run(kind, seed):
     return opump.run(scene(kind, seed), CFG, record=True)
+
+
+# measurement-noise intensity of the LQG parity scenes (half the process
+# noise of the cfg1 workload)
+SIGMA_MEAS = 0.01
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_run_lqg(kind, seed):
+    return opump.run(scene(kind, seed, SIGMA_MEAS), opump.Config(estimator="lqg"), record=True)

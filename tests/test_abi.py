@@ -55,3 +55,42 @@ def test_struct_layouts_match_the_header():
     assert off["samples"] == 0 and off["n"] == 8 and off["obstacles"] == 16
     assert off["x_init"] == 28 and off["goal"] == 52 and off["alpha"] == 76
     assert off["noise"] == 88 and off["noise_mc"] == 96 and off["mem"] == 104
+    assert off["sigma_meas"] == 108 and off["noise_meas"] == 112 and off["noise_mc_meas"] == 120
+    assert ctypes.sizeof(_lib.Problem) == 128
+    assert _lib.Config.estimator.offset == 60
+
+
+def test_struct_offsets_agree_with_the_c_compiler(tmp_path):
+    """offsetof/sizeof of every field as the host C compiler lays out
+    include/pump.h, against the ctypes mirrors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    structs = {"pump_config": _lib.Config, "pump_problem": _lib.Problem,
+               "pump_result": _lib.Result, "pump_batch_tuning": _lib.Tuning}
+    rename = {"lambda_": "lambda"}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pump.h"', 'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            if f == "pad":
+                continue
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {rename.get(f, f)}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for ln in out.splitlines():
+        cname, f, v = ln.split()
+        got[(cname, f)] = int(v)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            if f != "pad":
+                assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
