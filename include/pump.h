@@ -90,6 +90,15 @@ typedef struct pump_config {
                               dy = C dx + w, C = [I 0], W = sigma_meas^2 / dt
                               per axis.  Exploration particles and MC(p) both
                               follow the chosen controller.                   */
+    int32_t smooth;        /* Alg. 5's final Smooth(p*, alpha): 0 (default) the
+                              identity; 1 blend p* with the optimal connection
+                              x_init -> p*.head (weight beta, normalised time,
+                              both boundary states kept), beta = 1 tried first,
+                              then 9 bisection steps re-certified by MC over
+                              the blend's tracking grid; the cheaper certified
+                              blend replaces p* (pump_result.smooth_*,
+                              pump_get_smooth_path).                           */
+    int32_t reserved_;     /* zero                                               */
     int64_t cap_edges;     /* capacity: graph edges                                 */
     int64_t cap_plans;     /* capacity: plan records over a whole query             */
     int64_t cap_pairs;     /* capacity: (plan, neighbour) pairs in one round        */
@@ -165,6 +174,11 @@ typedef struct pump_result {
     int64_t sim_waypoints;   /* (pair, waypoint) particle tests: each covers the N
                                 particles at a waypoint whose cloud meets a box */
     int64_t sim_box_tests;   /* (pair, waypoint, box) tests, each over N particles */
+    /* Smooth(p*, alpha) with cfg.smooth = 1 (else beta 0 and p*'s figures):  */
+    double smooth_beta;      /* blend weight returned (0: p* kept)            */
+    double smooth_cost;      /* cost of the returned trajectory               */
+    int32_t smooth_mc_count; /* its certification count (of M)                */
+    int32_t smooth_steps;    /* its tracking steps                            */
 } pump_result;
 
 typedef struct pump_ctx pump_ctx;
@@ -233,6 +247,26 @@ int pump_get_path(pump_ctx* ctx, int32_t plan, int32_t* nodes, int32_t cap, int3
 /* MC(p) (Sec. IV) for an arbitrary node sequence (nodes[0] must be 0):
  * number of the M certification particles whose path meets an obstacle. */
 int pump_mc_path(pump_ctx* ctx, const int32_t* nodes, int32_t len, int32_t* count);
+/* Nominal tracking waypoints of the trajectory pump_select returned last:
+ * the Smooth(p*, alpha) blend (cfg.smooth = 1, smooth_beta > 0) or p* itself;
+ * (*steps + 1) positions [*steps + 1][3] (FP64, host memory) go to `wp`,
+ * which holds cap_steps + 1 of them.  PUMP_E_STATE if the last selection
+ * certified no plan, PUMP_E_CAPACITY if cap_steps < *steps. */
+int pump_get_smooth_path(pump_ctx* ctx, double* wp, int32_t cap_steps, int32_t* steps);
+
+/* SampleFree(n) (Alg. 3) with the Halton sequence the paper samples with
+ * (Sec. V-A).  Writes n states [n][6] (FP32) to device memory `out` on
+ * `hip_stream` (NULL: the null stream) and returns once they are written.
+ * Point i of the sequence has coordinate d = lo + (hi - lo) * phi_b(i) with
+ * phi_b the radical inverse in base b = 2, 3, 5, 7, 11, 13 for
+ * (px, py, pz, vx, vy, vz).  The first n - n_goal states are points
+ * start .. over the box [lo, hi]; the last n_goal continue the sequence with
+ * positions over `goal` and velocities over [lo, hi] (Alg. 3 asks for at least
+ * one sample from X_goal; `goal` may be NULL when n_goal = 0).  Samples that
+ * fall in obstacles are dropped by pump_setup as usual.  PUMP_E_ARG for n < 1,
+ * n_goal outside [0, n], an empty or non-finite box, or start + n >= 2^31. */
+int pump_sample_halton(int32_t n, int32_t n_goal, const float* lo, const float* hi,
+                       const pump_aabb* goal, int64_t start, float* out, void* hip_stream);
 
 /* Per-kernel timing.  When on, every launch of the kernels below is
  * bracketed by HIP events on the context's stream and the elapsed times are
@@ -244,7 +278,7 @@ int pump_mc_path(pump_ctx* ctx, const int32_t* nodes, int32_t len, int32_t* coun
  *   10..16 phases of the single-launch Explore as seen by its first
  *   workgroup (expand, simulate, staircase, marks, scans + compaction,
  *   next group, group scatter + pair offsets; each includes its barrier;
- *   "launches" counts rounds)   17 reserved
+ *   "launches" counts rounds)   17 Smooth (all of its launches)
  * pump_set_timing(ctx, on) switches it and clears the totals;
  * pump_get_timing copies min(n, PUMP_TIMING_KINDS) totals (ms) and launch
  * counts (either pointer may be NULL). */

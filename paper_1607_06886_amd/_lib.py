@@ -38,7 +38,7 @@ class Config(ctypes.Structure):
                 ("max_steps", _i32), ("mc_particles", _i32), ("preprune", _i32),
                 ("dt", _f), ("q_pos", _f), ("q_vel", _f), ("r_track", _f), ("r_steer", _f),
                 ("r_conn", _f), ("eta", _f), ("lambda_", _f), ("cp_model", _i32),
-                ("estimator", _i32), ("cap_edges", _i64), ("cap_plans", _i64),
+                ("estimator", _i32), ("smooth", _i32), ("reserved_", _i32), ("cap_edges", _i64), ("cap_plans", _i64),
                 ("cap_pairs", _i64)]
 
 
@@ -62,7 +62,9 @@ class Result(ctypes.Structure):
                 ("flagged", _i64), ("rounds", _i32), ("final_i", _i32), ("n_plans", _i32),
                 ("n_edges", _i32), ("n_valid_nodes", _i32), ("c_cut", _i32), ("c_min", _i32),
                 ("pad", _i32), ("ms_setup", _f), ("ms_explore", _f), ("ms_select", _f),
-                ("ms_total", _f), ("sim_waypoints", _i64), ("sim_box_tests", _i64)]
+                ("ms_total", _f), ("sim_waypoints", _i64), ("sim_box_tests", _i64),
+                ("smooth_beta", _d), ("smooth_cost", _d), ("smooth_mc_count", _i32),
+                ("smooth_steps", _i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -85,7 +87,8 @@ _LIB = None
 EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "pump_setup",
            "pump_explore_begin", "pump_explore_round", "pump_explore_run", "pump_select",
            "pump_get_deviation", "pump_get_graph", "pump_get_plans", "pump_get_candidates",
-           "pump_get_front", "pump_get_path", "pump_mc_path", "pump_set_timing",
+           "pump_get_front", "pump_get_path", "pump_mc_path", "pump_get_smooth_path",
+           "pump_sample_halton", "pump_set_timing",
            "pump_get_timing", "pump_set_explore_mode", "pump_get_explore_mode",
            "pump_status_str", "pump_last_error", "pump_mlp_create",
            "pump_mlp_destroy", "pump_mlp_num_params", "pump_mlp_set_params",
@@ -98,7 +101,7 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
 TIMING_KINDS = ["deviation", "graph_mark", "graph_fill", "expand", "prune", "compact",
                 "next_group", "select_front", "mc", "explore_single", "ph_expand",
                 "ph_simulate", "ph_stair", "ph_mark", "ph_compact", "ph_next_group",
-                "ph_group", "reserved"]
+                "ph_group", "smooth"]
 
 
 def load(path: Optional[str] = None):
@@ -135,6 +138,8 @@ def load(path: Optional[str] = None):
         "pump_get_front": (_i32, [_p, _p, _p, _i32, P(_i32)]),
         "pump_get_path": (_i32, [_p, _i32, _p, _i32, P(_i32)]),
         "pump_mc_path": (_i32, [_p, _p, _i32, P(_i32)]),
+        "pump_get_smooth_path": (_i32, [_p, _p, _i32, P(_i32)]),
+        "pump_sample_halton": (_i32, [_i32, _i32, P(_f), P(_f), P(AABB), _i64, _p, _p]),
         "pump_set_timing": (_i32, [_p, _i32]),
         "pump_get_timing": (_i32, [_p, _p, _p, _i32]),
         "pump_set_explore_mode": (_i32, [_p, _i32]),
@@ -176,6 +181,31 @@ def default_config(**over) -> Config:
     for k, v in over.items():
         setattr(c, "lambda_" if k == "lam" else k, v)
     return c
+
+
+def sample_halton(n, lo, hi, goal=None, n_goal=None, start=1, stream=None):
+    """SampleFree(n) with the Halton sequence on the device (pump_sample_halton):
+    a torch CUDA float32 tensor [n, 6].  n_goal defaults to max(1, n // 100)
+    with a goal box (6 floats, lo xyz then hi xyz), else 0."""
+    import torch
+    lib = load()
+    if n_goal is None:
+        n_goal = max(1, n // 100) if goal is not None else 0
+    out = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+    lo_a = (_f * 6)(*[float(v) for v in lo])
+    hi_a = (_f * 6)(*[float(v) for v in hi])
+    g = None
+    if goal is not None:
+        gb = np.asarray(goal, np.float32)
+        g = AABB((_f * 3)(*gb[:3]), (_f * 3)(*gb[3:]))
+    s = getattr(stream, "cuda_stream", stream) if stream is not None else \
+        torch.cuda.current_stream().cuda_stream
+    rc = lib.pump_sample_halton(int(n), int(n_goal), lo_a, hi_a,
+                                ctypes.byref(g) if g is not None else None, int(start),
+                                out.data_ptr(), s)
+    if rc != 0:
+        raise PumpError(rc, "pump_sample_halton failed")
+    return out
 
 
 def _ptr(a):
@@ -388,6 +418,15 @@ class Planner:
         cnt = np.zeros(n, np.int64)
         self._check(self.lib.pump_get_timing(self.ctx, ms.ctypes.data, cnt.ctypes.data, n))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(TIMING_KINDS)}
+
+    def smooth_path(self):
+        """Waypoints [steps + 1, 3] of the trajectory the last selection
+        returned (the Smooth blend, or p* itself)."""
+        cap = int(self.cfg.max_steps)
+        buf = np.zeros((cap + 1, 3), np.float64)
+        n = _i32(0)
+        self._check(self.lib.pump_get_smooth_path(self.ctx, buf.ctypes.data, cap, ctypes.byref(n)))
+        return buf[:n.value + 1].copy()
 
     def mc_path(self, nodes):
         nd = np.ascontiguousarray(np.asarray(nodes, np.int32))

@@ -9,6 +9,7 @@
 #include "explore_team.hpp"
 #include "select_ops.hpp"
 #include "setup_ops.hpp"
+#include "smooth_ops.hpp"
 
 namespace pump {
 
@@ -293,6 +294,56 @@ __global__ void k_b_finalize(BatchQuery* qs, int q, BatchOut* outs) {
     o.best_len = Q.s.path_len[m - 1];
     o.best_cost = Q.ra[0].p_cost[p];
     o.best_cp_mc = (double)o.best_mc / (double)M;
+    // the identity Smooth (replaced when smoothing runs)
+    o.smooth_beta = 0.0;
+    o.smooth_cost = o.best_cost;
+    o.smooth_count = o.best_mc;
+    o.smooth_steps = Q.s.wp_len[m - 1];
+}
+
+// Smooth(p*, alpha) per query (smooth_ops.hpp), after the outcome records:
+// queries without a certified plan keep beta = 0.
+__global__ __launch_bounds__(256) void k_b_smooth_prep(BatchQuery* qs, const BatchOut* outs) {
+    const BatchQuery& Q = qs[blockIdx.x];
+    const BatchOut& o = outs[blockIdx.x];
+    const int f = o.status == PUMP_OK ? o.best : -1;
+    smooth_prep_block(Q.s, f, f >= 0 ? o.best_cost : 0.0, Q.sm);
+}
+
+__global__ __launch_bounds__(256) void k_b_smooth_wp(BatchQuery* qs, int r) {
+    const BatchQuery& Q = qs[blockIdx.z];
+    smooth_wp_one(Q.s, Q.sm, r, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_b_smooth_mc(BatchQuery* qs, int r) {
+    __shared__ float s_obs[kMaxObs * 6];
+    const BatchQuery& Q = qs[blockIdx.z];
+    const int c = blockIdx.y;
+    if (smooth_beta(*Q.sm.st, r, c) < 0.0) return;   // uniform per block
+    for (int t = threadIdx.x; t < Q.s.n_obs * 6; t += blockDim.x) s_obs[t] = Q.s.obs[t];
+    __syncthreads();
+    const bool hit = smooth_mc_one(Q.s, Q.sm, r, c, blockIdx.x * blockDim.x + threadIdx.x, s_obs);
+    const unsigned long long m = __ballot(hit);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&Q.sm.st->cnt[c], (int)__popcll(m));
+}
+
+__global__ void k_b_smooth_resolve(BatchQuery* qs, int q, int r) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < q) smooth_resolve_one(qs[i].s, qs[i].alpha, qs[i].sm, r);
+}
+
+__global__ __launch_bounds__(256) void k_b_smooth_final(BatchQuery* qs, BatchOut* outs) {
+    const BatchQuery& Q = qs[blockIdx.x];
+    BatchOut& o = outs[blockIdx.x];
+    const bool ok = o.status == PUMP_OK;
+    smooth_final_block(Q.s, Q.sm, Q.r_steer, ok ? o.best_mc : 0, ok ? Q.s.wp_len[o.best] : -1);
+    __syncthreads();
+    if (threadIdx.x == 0 && ok) {
+        o.smooth_beta = Q.sm.st->beta;
+        o.smooth_cost = Q.sm.st->cost;
+        o.smooth_count = Q.sm.st->count;
+        o.smooth_steps = Q.sm.st->steps;
+    }
 }
 
 // Queue counter and every query's team barrier words and totals to zero.
@@ -305,7 +356,7 @@ __global__ void k_b_reset(BatchQuery* qs, int* counter) {
 
 void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes, int S_max, int M,
                   int words, int explore_blocks, int explore_threads, int* counter, BatchOut* out,
-                  const BatchSched& sch) {
+                  const BatchSched& sch, bool smooth) {
     const int max_elems = std::max(max_nodes * 6, kMaxObs * 6);
     k_b_load<<<dim3((max_elems + 255) / 256, q), 256, 0, s>>>(qs);
     {
@@ -330,6 +381,15 @@ void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes
     k_b_waypoints<<<q, 64, 0, s>>>(qs);
     k_b_mc<<<dim3((M + 255) / 256, kBatchFront, q), 256, 0, s>>>(qs);
     k_b_finalize<<<(q + 63) / 64, 64, 0, s>>>(qs, q, out);
+    if (smooth) {
+        k_b_smooth_prep<<<q, 256, 0, s>>>(qs, out);
+        for (int r = 0; r < kSmoothRounds; ++r) {
+            k_b_smooth_wp<<<dim3((S_max + 1 + 255) / 256, kSmoothCands, q), 256, 0, s>>>(qs, r);
+            k_b_smooth_mc<<<dim3((M + 255) / 256, kSmoothCands, q), 256, 0, s>>>(qs, r);
+            k_b_smooth_resolve<<<(q + 63) / 64, 64, 0, s>>>(qs, q, r);
+        }
+        k_b_smooth_final<<<q, 256, 0, s>>>(qs, out);
+    }
 }
 
 int batch_explore_per_cu(int threads) {

@@ -2,6 +2,7 @@
 // by cp_hat, and certify with Monte Carlo (MC(p), Sec. IV).  The bodies live
 // in select_ops.hpp.
 #include "select_ops.hpp"
+#include "smooth_ops.hpp"
 
 namespace pump {
 
@@ -37,6 +38,46 @@ void launch_mc(hipStream_t s, const SelectArgs& a, int32_t n_paths) {
     if (n_paths <= 0) return;
     dim3 grid((a.M + 255) / 256, n_paths);
     k_mc<<<grid, 256, 0, s>>>(a);
+}
+
+// ---- Smooth(p*, alpha) ----
+__global__ __launch_bounds__(256) void k_smooth_prep(SelectArgs a, SmoothBuf b, int f_best,
+                                                     const double* plan_cost) {
+    smooth_prep_block(a, f_best, f_best >= 0 ? *plan_cost : 0.0, b);
+}
+
+__global__ __launch_bounds__(256) void k_smooth_wp(SelectArgs a, SmoothBuf b, int r) {
+    smooth_wp_one(a, b, r, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_smooth_mc(SelectArgs a, SmoothBuf b, int r) {
+    __shared__ float s_obs[kMaxObs * 6];
+    for (int t = threadIdx.x; t < a.n_obs * 6; t += blockDim.x) s_obs[t] = a.obs[t];
+    __syncthreads();
+    const int c = blockIdx.y;
+    const bool hit = smooth_mc_one(a, b, r, c, blockIdx.x * blockDim.x + threadIdx.x, s_obs);
+    const unsigned long long m = __ballot(hit);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&b.st->cnt[c], (int)__popcll(m));
+}
+
+__global__ void k_smooth_resolve(SelectArgs a, SmoothBuf b, double alpha, int r) {
+    if (threadIdx.x == 0) smooth_resolve_one(a, alpha, b, r);
+}
+
+__global__ __launch_bounds__(256) void k_smooth_final(SelectArgs a, SmoothBuf b, int plan_count,
+                                                      int plan_steps) {
+    smooth_final_block(a, b, a.r_steer, plan_count, plan_steps);
+}
+
+void launch_smooth(hipStream_t s, const SelectArgs& a, const SmoothBuf& b, int f_best,
+                   const double* plan_cost, double alpha, int plan_count, int plan_steps) {
+    k_smooth_prep<<<1, 256, 0, s>>>(a, b, f_best, plan_cost);
+    for (int r = 0; r < kSmoothRounds; ++r) {
+        k_smooth_wp<<<dim3((a.S_max + 1 + 255) / 256, kSmoothCands), 256, 0, s>>>(a, b, r);
+        k_smooth_mc<<<dim3((a.M + 255) / 256, kSmoothCands), 256, 0, s>>>(a, b, r);
+        k_smooth_resolve<<<1, 64, 0, s>>>(a, b, alpha, r);
+    }
+    k_smooth_final<<<1, 256, 0, s>>>(a, b, plan_count, plan_steps);
 }
 
 }  // namespace pump

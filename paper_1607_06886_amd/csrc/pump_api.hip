@@ -76,6 +76,11 @@ struct pump_ctx {
     int32_t *goal_ids = nullptr, *front_ids = nullptr, *paths = nullptr, *path_len = nullptr,
             *wp_len = nullptr, *mc_counts = nullptr;
     double* wp = nullptr;
+    // Smooth(p*, alpha)
+    SmoothBuf sm{nullptr, nullptr, nullptr, nullptr, nullptr};
+    int last_best = -1;        // front index of the last p* (-1: none)
+    int last_steps = 0;        // tracking steps of the trajectory returned last
+    bool last_smoothed = false;
     // query state
     int n_nodes = 0, n_obs = 0, M = 0, S_max = 0;
     double alpha = 0, eta = 0, alpha_min = 0, alpha_max = 0, h = 0, dt = 0;
@@ -275,6 +280,8 @@ void pump_config_default(pump_config* c) {
     c->lambda = 0.5f;
     c->cp_model = 0;
     c->estimator = 0;
+    c->smooth = 0;
+    c->reserved_ = 0;
     c->cap_edges = 4 << 20;
     c->cap_plans = 1 << 20;
     c->cap_pairs = 4 << 20;
@@ -307,7 +314,8 @@ int pump_destroy(pump_ctx* ctx) {
                     ctx->b_ids, ctx->b_off, ctx->b_deg, ctx->c_head, ctx->c_parent, ctx->c_edge,
                     ctx->c_step, ctx->c_pop, ctx->c_pos, ctx->tasks, ctx->c_cost, ctx->c_mask, ctx->c_flag,
                     ctx->blk, ctx->ctl, ctx->goal_ids, ctx->front_ids, ctx->paths,
-                    ctx->path_len, ctx->wp_len, ctx->mc_counts, ctx->wp};
+                    ctx->path_len, ctx->wp_len, ctx->mc_counts, ctx->wp, ctx->sm.st,
+                    ctx->sm.e_coef, ctx->sm.e_t0, ctx->sm.wp, ctx->sm.out_wp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (ctx->ctl_h) (void)hipHostFree(ctx->ctl_h);
@@ -334,6 +342,7 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     if (cfg.max_nodes < 2 || cfg.max_nodes > 65535) return PUMP_E_ARG;
     if (cfg.cp_model != 0 && cfg.cp_model != 1) return PUMP_E_ARG;
     if (cfg.estimator != 0 && cfg.estimator != 1) return PUMP_E_ARG;
+    if (cfg.smooth != 0 && cfg.smooth != 1) return PUMP_E_ARG;
     if (cfg.max_obstacles < 0 || cfg.max_obstacles > kMaxObs) return PUMP_E_ARG;
     if (cfg.max_steps < 1 || cfg.max_steps > 4096 || cfg.mc_particles < 1) return PUMP_E_ARG;
     if (!(cfg.dt > 0) || !(cfg.r_conn > 0) || !(cfg.lambda > 0) || !(cfg.r_steer > 0) ||
@@ -438,6 +447,11 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     A(dalloc(&ctx->path_len, (size_t)kMaxFront));
     A(dalloc(&ctx->wp_len, (size_t)kMaxFront));
     A(dalloc(&ctx->mc_counts, (size_t)kMaxFront));
+    A(dalloc(&ctx->sm.st, 1));
+    A(dalloc(&ctx->sm.e_coef, S * 12));
+    A(dalloc(&ctx->sm.e_t0, S + 1));
+    A(dalloc(&ctx->sm.wp, (size_t)kSmoothCands * (S + 1) * 3));
+    A(dalloc(&ctx->sm.out_wp, (S + 1) * 3));
     A(dalloc(&ctx->wp, (size_t)kMaxFront * (S + 1) * 3));
     A(hipHostMalloc((void**)&ctx->ctl_h, sizeof(Ctl), hipHostMallocDefault));
     for (auto& e : ctx->ev) A(hipEventCreate(&e));
@@ -761,6 +775,8 @@ int pump_select(pump_ctx* ctx, pump_result* out) {
     memset(&res, 0, sizeof(res));
     res.best = -1;
     res.best_plan = -1;
+    ctx->last_best = -1;
+    ctx->last_smoothed = false;
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
     SelectArgs a = select_args(ctx);
     HIPCHK(hipMemsetAsync(ctx->mc_counts, 0, kMaxFront * sizeof(int32_t), ctx->stream));
@@ -809,6 +825,28 @@ int pump_select(pump_ctx* ctx, pump_result* out) {
             res.best_len = plen[m - 1];
             HIPCHK(hipMemcpy(&res.best_cost, ctx->p_cost + ids[m - 1], sizeof(double), hipMemcpyDeviceToHost));
             HIPCHK(hipMemcpy(&res.best_pop, ctx->p_pop + ids[m - 1], sizeof(int32_t), hipMemcpyDeviceToHost));
+            ctx->last_best = m - 1;
+            res.smooth_beta = 0.0;
+            res.smooth_cost = res.best_cost;
+            res.smooth_mc_count = res.best_mc_count;
+            res.smooth_steps = wl[m - 1];
+            ctx->last_steps = wl[m - 1];
+            if (ctx->cfg.smooth) {
+                tbeg(ctx, 17);
+                launch_smooth(ctx->stream, a, ctx->sm, m - 1, ctx->p_cost + ids[m - 1], ctx->alpha,
+                              mc[m - 1], wl[m - 1]);
+                tend(ctx);
+                HIPCHK(hipGetLastError());
+                SmoothState st;
+                HIPCHK(hipMemcpyAsync(&st, ctx->sm.st, sizeof(st), hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHK(hipStreamSynchronize(ctx->stream));
+                res.smooth_beta = st.beta;
+                res.smooth_cost = st.cost;
+                res.smooth_mc_count = st.count;
+                res.smooth_steps = st.steps;
+                ctx->last_steps = st.steps;
+                ctx->last_smoothed = true;
+            }
         }
     }
     HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
@@ -847,6 +885,40 @@ int pump_plan(pump_ctx* ctx, const pump_problem* pr, pump_result* out) {
     res.ms_total = ms;
     if (out) *out = res;
     return r;
+}
+
+int pump_sample_halton(int32_t n, int32_t n_goal, const float* lo, const float* hi,
+                       const pump_aabb* goal, int64_t start, float* out, void* hip_stream) {
+    if (n < 1 || n_goal < 0 || n_goal > n || !lo || !hi || !out || (n_goal > 0 && !goal))
+        return PUMP_E_ARG;
+    if (start < 0 || start + (int64_t)n >= (1ll << 31)) return PUMP_E_ARG;
+    for (int d = 0; d < 6; ++d)
+        if (!std::isfinite(lo[d]) || !std::isfinite(hi[d]) || !(lo[d] <= hi[d])) return PUMP_E_ARG;
+    float glo[6], ghi[6];
+    for (int d = 0; d < 6; ++d) {
+        glo[d] = d < 3 && goal ? goal->lo[d] : lo[d];
+        ghi[d] = d < 3 && goal ? goal->hi[d] : hi[d];
+    }
+    if (goal)
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(glo[d]) || !std::isfinite(ghi[d]) || !(glo[d] <= ghi[d])) return PUMP_E_ARG;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int32_t n_box = n - n_goal;
+    if (launch_halton(s, start, n_box, lo, hi, out) != hipSuccess) return PUMP_E_HIP;
+    if (launch_halton(s, start + n_box, n_goal, glo, ghi, out + (size_t)n_box * 6) != hipSuccess)
+        return PUMP_E_HIP;
+    return hipStreamSynchronize(s) == hipSuccess ? PUMP_OK : PUMP_E_HIP;
+}
+
+int pump_get_smooth_path(pump_ctx* ctx, double* wp, int32_t cap_steps, int32_t* steps) {
+    if (!ctx || !wp) return PUMP_E_ARG;
+    if (ctx->last_best < 0) return fail(ctx, PUMP_E_STATE, "no certified plan from the last selection");
+    if (steps) *steps = ctx->last_steps;
+    if (cap_steps < ctx->last_steps) return fail(ctx, PUMP_E_CAPACITY, "cap_steps below the trajectory's steps");
+    const double* src = ctx->last_smoothed ? ctx->sm.out_wp
+                                           : ctx->wp + (size_t)ctx->last_best * (ctx->S_max + 1) * 3;
+    HIPCHK(hipMemcpy(wp, src, (size_t)(ctx->last_steps + 1) * 3 * sizeof(double), hipMemcpyDeviceToHost));
+    return PUMP_OK;
 }
 
 int pump_set_timing(pump_ctx* ctx, int32_t on) {

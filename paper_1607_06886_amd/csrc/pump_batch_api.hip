@@ -34,6 +34,8 @@ struct Slot {
     unsigned* team_sync;
     int32_t* team_tot;
     unsigned long long* stair;
+    SmoothState* sm_st;
+    double *sm_coef, *sm_t0, *sm_wp, *sm_out;
     Ctl* ctl;
 };
 
@@ -94,6 +96,7 @@ int pump_batch_create(const pump_config* cfg_in, int32_t max_queries, void* hip_
     if (!(N == 32 || N == 64 || N == 128 || N == 256)) return PUMP_E_ARG;
     if (cfg.cp_model != 0 && cfg.cp_model != 1) return PUMP_E_ARG;
     if (cfg.estimator != 0 && cfg.estimator != 1) return PUMP_E_ARG;
+    if (cfg.smooth != 0 && cfg.smooth != 1) return PUMP_E_ARG;
     if (cfg.max_nodes < 2 || cfg.max_nodes > 65535 || cfg.max_obstacles > kMaxObs ||
         cfg.max_steps < 1 || cfg.max_steps > 4096 || cfg.mc_particles < 1)
         return PUMP_E_ARG;
@@ -148,6 +151,8 @@ int pump_batch_create(const pump_config* cfg_in, int32_t max_queries, void* hip_
     take(&lay.wp_len, kBatchFrontHost); take(&lay.mc_counts, kBatchFrontHost);
     take(&lay.wp, (size_t)kBatchFrontHost * (S + 1) * 3); take(&lay.ctl, 1);
     take(&lay.team_sync, (size_t)64 + kMaxTeam); take(&lay.team_tot, (size_t)2 * kMaxTeam);
+    take(&lay.sm_st, 1); take(&lay.sm_coef, S * 12); take(&lay.sm_t0, S + 1);
+    take(&lay.sm_wp, (size_t)kSmoothCands * (S + 1) * 3); take(&lay.sm_out, (S + 1) * 3);
     const size_t slot_bytes = (off + 255) & ~(size_t)255;
     off = slot_bytes * (size_t)max_queries;
     size_t o_qs, o_out, o_order, o_counter, o_off;
@@ -247,6 +252,7 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         Q.dev_scratch = s.dev_scratch;
         Q.team_sync = s.team_sync;
         Q.team_tot = s.team_tot;
+        Q.sm = SmoothBuf{s.sm_st, s.sm_coef, s.sm_t0, s.sm_wp, s.sm_out};
         Q.X = s.X; Q.obs = s.obs; Q.valid = s.valid; Q.goal = s.goal; Q.ebits = s.ebits;
         Q.deg = s.deg; Q.row_ptr = s.row_ptr; Q.col = s.col; Q.esrc = s.esrc; Q.etau = s.etau;
         Q.ecost = s.ecost; Q.b_deg = s.b_deg; Q.open_a = s.open_a; Q.open_b = s.open_b;
@@ -326,7 +332,8 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         hipGraphExec_t exec = nullptr;
         BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         launch_batch(b->stream, b->qs_dev, q, N_max, max_nodes, cfg.max_steps, cfg.mc_particles,
-                     b->words, blocks, t.explore_threads, b->counter, b->out_dev, sch);
+                     b->words, blocks, t.explore_threads, b->counter, b->out_dev, sch,
+                     cfg.smooth != 0);
         BCHK(hipStreamEndCapture(b->stream, &graph));
         BCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         BCHK(hipGraphLaunch(exec, b->stream));
@@ -335,7 +342,8 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         (void)hipGraphDestroy(graph);
     } else {
         launch_batch(b->stream, b->qs_dev, q, N_max, max_nodes, cfg.max_steps, cfg.mc_particles,
-                     b->words, blocks, t.explore_threads, b->counter, b->out_dev, sch);
+                     b->words, blocks, t.explore_threads, b->counter, b->out_dev, sch,
+                     cfg.smooth != 0);
     }
     BCHK(hipGetLastError());
     BCHK(hipMemcpyAsync(b->outs.data(), b->out_dev, sizeof(BatchOut) * q, hipMemcpyDeviceToHost, b->stream));
@@ -374,6 +382,10 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         r.n_edges = o.n_edges;
         r.c_cut = b->qs[i].ra[0].c_cut;
         r.c_min = b->qs[i].ra[0].c_min;
+        r.smooth_beta = o.smooth_beta;
+        r.smooth_cost = o.smooth_cost;
+        r.smooth_mc_count = o.smooth_count;
+        r.smooth_steps = o.smooth_steps;
         r.ms_total = ms;
         if (out) out[i] = r;
         if (o.status < 0 && worst == PUMP_OK) {

@@ -140,6 +140,10 @@ void launch_deviation_table(hipStream_t s, const float* noise, float* D, float* 
 void launch_deviation_table_lqg(hipStream_t s, const float* noise, const float* noise_meas,
                                 float* D, float* cloud, float* gcloud, int N, int S_max,
                                 const LqgCoef& q, double* scratch);
+// Halton points start .. start + n - 1 over the box [lo, hi] (6 floats each)
+// into out [n][6] (kernels_sample.hip).
+hipError_t launch_halton(hipStream_t s, int64_t start, int32_t n, const float* lo, const float* hi,
+                         float* out);
 void launch_mark_valid(hipStream_t s, const float* X, int n_nodes, const float* obs,
                        int n_obs, const float* goal_box, uint8_t* valid, uint8_t* goal,
                        int32_t* bad);
@@ -191,6 +195,37 @@ struct SelectArgs {
     LqgCoef lqg;
     Ctl* ctl;
 };
+
+// ---- Smooth(p*, alpha) (smooth_ops.hpp) ----
+constexpr int kSmoothLevels = 9;           // bisection steps
+constexpr int kSmoothRounds = kSmoothLevels / 3;
+constexpr int kSmoothCands = 8;            // candidate weights per round
+
+// Device state of one query's Smooth.
+struct SmoothState {
+    double lo, hi;            // bisection interval (lo: certified side)
+    double T_p, tau_q;        // plan and optimal-connection durations
+    double plan_cost;         // cost of p*
+    double qc[12];            // optimal connection cubic, per axis (c0, c1, c2, c3)
+    double beta, cost;        // result
+    int32_t E;                // edges of p* (0: nothing to smooth)
+    int32_t f_best;           // front index of p* (-1: none)
+    int32_t done;             // search finished
+    int32_t lo_cnt, lo_K;     // MC count and steps of the blend at lo
+    int32_t count, steps;     // result
+    int32_t cnt[kSmoothCands], K[kSmoothCands];
+};
+
+struct SmoothBuf {
+    SmoothState* st;
+    double* e_coef;           // [S_max][3][4] edge cubics of p*
+    double* e_t0;             // [S_max + 1] edge start times, e_t0[E] = T_p
+    double* wp;               // [kSmoothCands][S_max + 1][3] candidate waypoints
+    double* out_wp;           // [S_max + 1][3] waypoints of the result
+};
+
+void launch_smooth(hipStream_t s, const SelectArgs& a, const SmoothBuf& b, int f_best,
+                   const double* plan_cost, double alpha, int plan_count, int plan_steps);
 
 // Grid barrier state of the single-launch Explore (zeroed before launch).
 struct CoopSync {
@@ -252,6 +287,7 @@ struct BatchQuery {
     int32_t* open_a;
     int32_t* open_b;
     double* dev_scratch;       // deviation-table chunk states
+    SmoothBuf sm;              // Smooth(p*, alpha) state and buffers
     unsigned* team_sync;       // [64 + kMaxTeam] team barrier words (release, fail, arrivals)
     int32_t* team_tot;         // [2 * kMaxTeam] team scan totals
 };
@@ -273,11 +309,13 @@ struct BatchOut {
     double best_cost, best_cp_mc;
     int32_t n_plans, n_edges, rounds, final_i, err, bad;
     long long partial_plans;
+    double smooth_beta, smooth_cost;
+    int32_t smooth_count, smooth_steps;
 };
 
 void launch_batch(hipStream_t s, BatchQuery* qs_dev, int q, int N_max, int max_nodes, int S_max,
                   int M, int words, int explore_blocks, int explore_threads, int* counters,
-                  BatchOut* out, const BatchSched& sch);
+                  BatchOut* out, const BatchSched& sch, bool smooth);
 // Workgroups of the batched Explore kernel that fit on one CU at once.
 int batch_explore_per_cu(int threads);
 

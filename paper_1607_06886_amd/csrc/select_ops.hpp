@@ -176,15 +176,13 @@ __device__ __forceinline__ bool segment_hits_boxes(const double prev[3], const d
     return hit;
 }
 
-// MC(p) for one certification particle m of path f: its deviation follows
-// the closed-loop recurrence from zero with its own noise; its workspace path
-// is the polyline through the waypoint positions; it collides iff a segment
-// meets a closed obstacle box (slab clipping, FP64).
-__device__ __forceinline__ bool mc_particle_lqr(const SelectArgs& a, int f, int m,
-                                                const float* s_obs) {
-    const int S = a.wp_len[f];
-    const int stride = a.S_max + 1;
-    const double* wp = a.wp + (size_t)f * stride * 3;
+// MC(p) for one certification particle m over nominal waypoints wp[0..S]
+// (step 0 = the start): its deviation follows the closed-loop recurrence from
+// zero with its own noise; its workspace path is the polyline through the
+// waypoint positions plus deviations; it collides iff a segment meets a
+// closed obstacle box (slab clipping, FP64).
+__device__ __forceinline__ bool mc_particle_lqr(const SelectArgs& a, const double* wp, int S,
+                                                int m, const float* s_obs) {
     double dp[3] = {0.0, 0.0, 0.0}, dv[3] = {0.0, 0.0, 0.0};
     double prev[3] = {wp[0], wp[1], wp[2]};
     const double a00 = a.Acl[0], a01 = a.Acl[1], a10 = a.Acl[2], a11 = a.Acl[3];
@@ -209,11 +207,8 @@ __device__ __forceinline__ bool mc_particle_lqr(const SelectArgs& a, int f, int 
 
 // The same under LQG tracking: per axis the particle carries (dp, dv, p_hat,
 // v_hat), driven by its two process normals and its measurement normal.
-__device__ __forceinline__ bool mc_particle_lqg(const SelectArgs& a, int f, int m,
-                                                const float* s_obs) {
-    const int S = a.wp_len[f];
-    const int stride = a.S_max + 1;
-    const double* wp = a.wp + (size_t)f * stride * 3;
+__device__ __forceinline__ bool mc_particle_lqg(const SelectArgs& a, const double* wp, int S,
+                                                int m, const float* s_obs) {
     double z[3][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     double prev[3] = {wp[0], wp[1], wp[2]};
     bool hit = false;
@@ -232,9 +227,15 @@ __device__ __forceinline__ bool mc_particle_lqg(const SelectArgs& a, int f, int 
     return hit;
 }
 
+__device__ __forceinline__ bool mc_particle_wp(const SelectArgs& a, const double* wp, int S, int m,
+                                               const float* s_obs) {
+    if (m >= a.M || S < 0) return false;
+    return a.estimator ? mc_particle_lqg(a, wp, S, m, s_obs) : mc_particle_lqr(a, wp, S, m, s_obs);
+}
+
+// MC(p) for particle m of front path f.
 __device__ __forceinline__ bool mc_particle(const SelectArgs& a, int f, int m, const float* s_obs) {
-    if (m >= a.M || a.wp_len[f] < 0) return false;
-    return a.estimator ? mc_particle_lqg(a, f, m, s_obs) : mc_particle_lqr(a, f, m, s_obs);
+    return mc_particle_wp(a, a.wp + (size_t)f * (a.S_max + 1) * 3, a.wp_len[f], m, s_obs);
 }
 
 }  // namespace pump

@@ -50,7 +50,7 @@ def test_struct_layouts_match_the_header():
     """Field order and sizes of the ctypes mirrors (a mismatch would shift
     every later field)."""
     assert ctypes.sizeof(_lib.AABB) == 24
-    assert ctypes.sizeof(_lib.Config) == 88  # 16 four-byte fields, then 3 x int64
+    assert ctypes.sizeof(_lib.Config) == 96  # 18 four-byte fields, then 3 x int64
     off = {name: getattr(_lib.Problem, name).offset for name, _ in _lib.Problem._fields_}
     assert off["samples"] == 0 and off["n"] == 8 and off["obstacles"] == 16
     assert off["x_init"] == 28 and off["goal"] == 52 and off["alpha"] == 76
