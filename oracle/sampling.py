@@ -16,9 +16,10 @@ Readings (the paper fixes none of them):
     k the digit count) rounded once to FP64; lo + (hi - lo) * phi is rounded
     after each operation in FP64 and stored in FP32;
   * SampleFree(n) with a goal region ("including at least one from X_goal"):
-    the first n - n_goal points cover the state box, the next n_goal =
-    max(1, round(goal_share * n)) points of the sequence cover the goal
-    box's positions (velocities over the state box's velocity range);
+    the first n - n_goal points cover the state box, the next n_goal
+    points of the sequence (default max(1, n // 100), the 1% goal share of
+    the uniform inputs) cover the goal box's positions (velocities over the
+    state box's velocity range);
     samples that land in obstacles are kept as nodes without edges, as for
     uniform samples.
 """
@@ -61,9 +62,10 @@ def halton(start: int, n: int, lo, hi) -> np.ndarray:
     return out
 
 
-def sample_free_halton(n: int, lo, hi, goal_lo, goal_hi, goal_share=0.01, start=1):
+def sample_free_halton(n: int, lo, hi, goal_lo, goal_hi, n_goal=None, start=1):
     """SampleFree(n) as in the module header: [n, 6] FP32."""
-    n_goal = max(1, int(round(goal_share * n)))
+    if n_goal is None:
+        n_goal = max(1, n // 100)
     n_box = n - n_goal
     a = halton(start, n_box, lo, hi)
     glo = np.array([*np.asarray(goal_lo, np.float32)[:3], *np.asarray(lo, np.float32)[3:]])
