@@ -247,6 +247,50 @@ def batched_leg(q, seed, steps, tune_q, S_max=512, M=10_000):
     }
 
 
+def roadmap_leg(pl, samples, pr, r0, steps):
+    """The same query with the graph built over a cached roadmap (Near and the
+    optimal connections of the samples computed once, as the paper caches them
+    offline): build time, then per-query times with the cache."""
+    import torch
+
+    from paper_1607_06886_amd import _lib
+    cfg = pl.cfg
+    rm = _lib.Roadmap(samples, max_nodes=cfg.max_nodes, cap_edges=cfg.cap_edges,
+                      r_steer=cfg.r_steer, r_conn=cfg.r_conn)
+    pl.set_roadmap(rm)
+    pl.plan(pr)
+    torch.cuda.synchronize()
+    res = [pl.plan(pr) for _ in range(steps)]
+    pl.set_roadmap(None)
+    info = rm.info()
+    rm.close()
+    same = all(r["partial_plans"] == r0["partial_plans"] and r["best_plan"] == r0["best_plan"]
+               and r["best_cost"] == r0["best_cost"] for r in res)
+    return {"ms_build": info["ms_build"], "cached_connections": info["n_edges"],
+            "ms_to_certified_plan": statistics.median(r["ms_total"] for r in res),
+            "setup_ms": statistics.median(r["ms_setup"] for r in res),
+            "partial_plans_per_s": r0["partial_plans"] / (statistics.median(
+                r["ms_total"] for r in res) / 1e3),
+            "same_result_as_scratch_graph": same}
+
+
+def smooth_leg(sc, stream, samples, obstacles, noise, noise_mc):
+    """Smooth(p*, alpha) on the same query: the blend weight, cost and time."""
+    from paper_1607_06886_amd import _lib
+    pl = _lib.Planner(stream=stream, n_particles=sc.N, max_nodes=sc.n + 1,
+                      max_obstacles=max(1, sc.n_obs), max_steps=sc.S_max, mc_particles=sc.M,
+                      cap_plans=1 << 21, cap_pairs=1 << 23, cap_edges=1 << 24, smooth=1)
+    pr = pl.problem(samples, obstacles, sc.x_init, sc.goal, sc.alpha, sc.sigma, noise, noise_mc)
+    pl.plan(pr)
+    pl.set_timing(True)
+    r = pl.plan(pr)
+    kt = pl.timing()
+    pl.close()
+    return {"beta": r["smooth_beta"], "cost": r["smooth_cost"], "plan_cost": r["best_cost"],
+            "mc_count": r["smooth_mc_count"], "steps": r["smooth_steps"],
+            "ms": kt["smooth"][0], "ms_to_certified_smoothed_plan": r["ms_total"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -333,6 +377,8 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
         "roofline": roofline,
     }
+    line["roadmap"] = roadmap_leg(pl, samples, pr, r0, args.steps)
+    line["smooth"] = smooth_leg(sc, stream, samples, obstacles, noise, noise_mc)
     pl.close()
     if args.batch_queries > 0:
         line["batched"] = batched_leg(args.batch_queries, args.seed, args.batch_steps,

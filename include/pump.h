@@ -254,6 +254,31 @@ int pump_mc_path(pump_ctx* ctx, const int32_t* nodes, int32_t len, int32_t* coun
  * certified no plan, PUMP_E_CAPACITY if cap_steps < *steps. */
 int pump_get_smooth_path(pump_ctx* ctx, double* wp, int32_t cap_steps, int32_t* steps);
 
+/* Cached roadmap (Alg. 3's obstacle-independent part; the paper caches
+ * neighbours and edge controls offline, Sec. V-A).  pump_roadmap_create runs
+ * Near and the optimal connections (tau*, c*) over every ordered pair of the
+ * n samples, with no obstacles, and keeps each connection with its nominal
+ * position range.  A context given the roadmap (pump_set_roadmap) builds a
+ * query's graph by testing only the cached connections against the query's
+ * obstacles, plus the connections to and from its x_init; the graph equals
+ * the one pump_setup builds from scratch.  `samples` [n][6] is host or device
+ * memory as `mem` says; cfg supplies r_steer, r_conn, max_nodes (n + 1 at
+ * most) and cap_edges.  The roadmap owns its device memory; it is used on
+ * the context's stream and must outlive its use.  Errors: PUMP_E_ARG (sizes,
+ * non-finite samples or outside [-16, 16]), PUMP_E_CAPACITY (more than
+ * cap_edges connections), PUMP_E_HIP. */
+typedef struct pump_roadmap pump_roadmap;
+int pump_roadmap_create(const pump_config* cfg, const float* samples, int32_t n, int32_t mem,
+                        void* hip_stream, pump_roadmap** out);
+int pump_roadmap_destroy(pump_roadmap* rm);
+/* Sample count, cached connections and build time (ms) of a roadmap. */
+int pump_roadmap_info(const pump_roadmap* rm, int32_t* n, int64_t* n_edges, float* ms_build);
+/* Use `rm` (NULL: none) for the graph of later pump_setup / pump_plan calls
+ * on ctx.  PUMP_E_ARG if its radii differ from the context's or it holds
+ * more samples than max_nodes - 1.  pump_setup then fails with PUMP_E_ARG if
+ * the problem's samples differ from the roadmap's (compared bit for bit). */
+int pump_set_roadmap(pump_ctx* ctx, const pump_roadmap* rm);
+
 /* SampleFree(n) (Alg. 3) with the Halton sequence the paper samples with
  * (Sec. V-A).  Writes n states [n][6] (FP32) to device memory `out` on
  * `hip_stream` (NULL: the null stream) and returns once they are written.

@@ -88,7 +88,8 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
            "pump_explore_begin", "pump_explore_round", "pump_explore_run", "pump_select",
            "pump_get_deviation", "pump_get_graph", "pump_get_plans", "pump_get_candidates",
            "pump_get_front", "pump_get_path", "pump_mc_path", "pump_get_smooth_path",
-           "pump_sample_halton", "pump_set_timing",
+           "pump_sample_halton", "pump_roadmap_create", "pump_roadmap_destroy",
+           "pump_roadmap_info", "pump_set_roadmap", "pump_set_timing",
            "pump_get_timing", "pump_set_explore_mode", "pump_get_explore_mode",
            "pump_status_str", "pump_last_error", "pump_mlp_create",
            "pump_mlp_destroy", "pump_mlp_num_params", "pump_mlp_set_params",
@@ -140,6 +141,10 @@ def load(path: Optional[str] = None):
         "pump_mc_path": (_i32, [_p, _p, _i32, P(_i32)]),
         "pump_get_smooth_path": (_i32, [_p, _p, _i32, P(_i32)]),
         "pump_sample_halton": (_i32, [_i32, _i32, P(_f), P(_f), P(AABB), _i64, _p, _p]),
+        "pump_roadmap_create": (_i32, [P(Config), _p, _i32, _i32, _p, P(_p)]),
+        "pump_roadmap_destroy": (_i32, [_p]),
+        "pump_roadmap_info": (_i32, [_p, P(_i32), P(_i64), P(_f)]),
+        "pump_set_roadmap": (_i32, [_p, _p]),
         "pump_set_timing": (_i32, [_p, _i32]),
         "pump_get_timing": (_i32, [_p, _p, _p, _i32]),
         "pump_set_explore_mode": (_i32, [_p, _i32]),
@@ -419,6 +424,12 @@ class Planner:
         self._check(self.lib.pump_get_timing(self.ctx, ms.ctypes.data, cnt.ctypes.data, n))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(TIMING_KINDS)}
 
+    def set_roadmap(self, rm):
+        """Build later queries' graphs from a cached Roadmap (None: from
+        scratch)."""
+        self._check(self.lib.pump_set_roadmap(self.ctx, rm.rm if rm is not None else None))
+        self._rm = rm
+
     def smooth_path(self):
         """Waypoints [steps + 1, 3] of the trajectory the last selection
         returned (the Smooth blend, or p* itself)."""
@@ -541,6 +552,43 @@ class MLP:
         self._check(self.lib.pump_mlp_sample(self.m, _ptr(cond), q, _ptr(u), _ptr(eps), n,
                                              _ptr(out), self._mem(cond)))
         return out
+
+
+class Roadmap:
+    """BuildGraph's obstacle-independent part over a fixed sample set
+    (pump_roadmap_create).  `samples` is a numpy array (host) or a torch CUDA
+    tensor (device); cfg keywords as for Planner (r_steer, r_conn, max_nodes,
+    cap_edges matter)."""
+
+    def __init__(self, samples, stream=None, **cfg):
+        self.lib = load()
+        self.cfg = default_config(**cfg)
+        dev = not isinstance(samples, np.ndarray)
+        if not dev:
+            samples = _np(samples, np.float32)
+        s = getattr(stream, "cuda_stream", stream) if stream is not None else None
+        self.rm = _p()
+        rc = self.lib.pump_roadmap_create(ctypes.byref(self.cfg), _ptr(samples),
+                                          int(samples.shape[0]), MEM_DEVICE if dev else MEM_HOST,
+                                          s, ctypes.byref(self.rm))
+        if rc != 0:
+            raise PumpError(rc, "pump_roadmap_create failed")
+
+    def info(self):
+        n, e, ms = _i32(0), _i64(0), _f(0.0)
+        self.lib.pump_roadmap_info(self.rm, ctypes.byref(n), ctypes.byref(e), ctypes.byref(ms))
+        return dict(n=n.value, n_edges=e.value, ms_build=ms.value)
+
+    def close(self):
+        if self.rm:
+            self.lib.pump_roadmap_destroy(self.rm)
+            self.rm = _p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

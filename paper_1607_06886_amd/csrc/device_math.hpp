@@ -252,18 +252,53 @@ __device__ __forceinline__ void cubic_range(const Cubic& c, double tau, double& 
 
 // Does the nominal trajectory (three axis cubics on [0, tau]) meet the closed
 // box? It is inside at time t iff all three coordinates are in their slabs,
-// so it meets the box iff the three per-axis in-slab sets intersect.
-__device__ __forceinline__ bool trajectory_hits_box(const Cubic* cs, double tau, const float* box) {
-    // a sampled point inside the closed box proves a hit (cheap, common case)
-    for (int k = 1; k < 8; ++k) {
-        const double t = tau * (0.125 * (double)k);
-        bool in = true;
-        for (int a = 0; a < 3; ++a) {
-            const double p = cs[a].at(t);
-            in &= (p >= (double)box[a]) & (p <= (double)box[3 + a]);
-        }
-        if (in) return true;
+// so it meets the box iff the three per-axis in-slab sets intersect
+// (trajectory_hits_box_exact).
+//
+// Two cheap tests settle most cases first (trajectory_box_quick).  The
+// trajectory is swept over 8 equal pieces: a sample point (interior piece
+// ends) inside the box proves a hit; and on each piece a cubic lies in the
+// hull of its Bernstein coefficients p(ta), p(ta) + h p'(ta)/3,
+// p(tb) - h p'(tb)/3, p(tb), so when every piece's hull (widened by
+// kHullMargin, far above the rounding of these values) misses the box on some
+// axis, the trajectory misses it.  Both only settle cases the exact test
+// decides the same way.
+constexpr double kHullMargin = 1e-9;
+enum BoxTest : int { kBoxMiss = 0, kBoxHit = 1, kBoxUnsure = 2 };
+
+__device__ __forceinline__ int trajectory_box_quick(const Cubic* cs, double tau, const float* box) {
+    const double h = 0.125 * tau;
+    double pa[3], da[3];
+    for (int a = 0; a < 3; ++a) {
+        pa[a] = cs[a].c0;
+        da[a] = cs[a].c1;
     }
+    bool ambiguous = false;
+    for (int k = 1; k <= 8; ++k) {
+        const double t = k == 8 ? tau : tau * (0.125 * (double)k);
+        double pb[3], db[3];
+        bool in = true, sep = false;
+        for (int a = 0; a < 3; ++a) {
+            pb[a] = cs[a].at(t);
+            db[a] = cs[a].c1 + t * (2.0 * cs[a].c2 + t * 3.0 * cs[a].c3);
+            in &= (pb[a] >= (double)box[a]) & (pb[a] <= (double)box[3 + a]);
+            const double b1 = pa[a] + h * da[a] / 3.0, b2 = pb[a] - h * db[a] / 3.0;
+            const double lo = fmin(fmin(pa[a], pb[a]), fmin(b1, b2)) - kHullMargin;
+            const double hi = fmax(fmax(pa[a], pb[a]), fmax(b1, b2)) + kHullMargin;
+            sep |= (hi < (double)box[a]) | (lo > (double)box[3 + a]);
+        }
+        if (k < 8 && in) return kBoxHit;
+        ambiguous |= !sep;
+        for (int a = 0; a < 3; ++a) {
+            pa[a] = pb[a];
+            da[a] = db[a];
+        }
+    }
+    return ambiguous ? kBoxUnsure : kBoxMiss;
+}
+
+__device__ __forceinline__ bool trajectory_hits_box_exact(const Cubic* cs, double tau,
+                                                          const float* box) {
     double s[3][3], e[3][3];
     int n[3];
     for (int a = 0; a < 3; ++a) {
@@ -278,6 +313,12 @@ __device__ __forceinline__ bool trajectory_hits_box(const Cubic* cs, double tau,
                 if (st <= en) return true;
             }
     return false;
+}
+
+__device__ __forceinline__ bool trajectory_hits_box(const Cubic* cs, double tau, const float* box) {
+    const int q = trajectory_box_quick(cs, tau, box);
+    if (q != kBoxUnsure) return q == kBoxHit;
+    return trajectory_hits_box_exact(cs, tau, box);
 }
 
 // ---------------------------------------------------------------------------

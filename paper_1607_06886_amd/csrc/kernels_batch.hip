@@ -79,11 +79,52 @@ __global__ void k_b_valid(BatchQuery* qs) {
                    Q.goal, &Q.bad);
 }
 
-__global__ __launch_bounds__(256) void k_b_graph_mark(BatchQuery* qs) {
+// BuildGraph pass 1 stages per query (setup_ops.hpp); the work lists live in
+// the query's Explore candidate arrays, the counters in its descriptor.
+__device__ __forceinline__ GraphWork graph_work(BatchQuery& Q) {
+    const RoundArgs& a = Q.ra[0];
+    return GraphWork{Q.esrc, Q.col, Q.etau, a.c_pop, a.c_pos, Q.gcount, Q.cap_edges, Q.cap_pairs};
+}
+
+__global__ __launch_bounds__(256) void k_b_zero_ebits(BatchQuery* qs) {
     const BatchQuery& Q = qs[blockIdx.y];
+    const size_t n = (size_t)Q.n_nodes * Q.words;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x)
+        Q.ebits[t] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_b_gw_near_rows(BatchQuery* qs) {
+    __shared__ int s_list[kNearChunk];
+    __shared__ int s_cnt;
+    BatchQuery& Q = qs[blockIdx.y];
     if ((int)blockIdx.x >= Q.n_nodes) return;
-    graph_mark_dev(Q.X, Q.valid, Q.n_nodes, Q.obs, Q.ra[0].n_obs, Q.r_steer, Q.r_conn, Q.ebits, Q.deg,
-                   Q.words);
+    gw_near_row(Q.X, Q.valid, Q.n_nodes, blockIdx.x, Q.r_steer, Q.r_conn, graph_work(Q), s_list,
+                &s_cnt);
+}
+
+__global__ __launch_bounds__(256) void k_b_gw_boxes(BatchQuery* qs) {
+    __shared__ float s_obs[kMaxObs * 6];
+    BatchQuery& Q = qs[blockIdx.y];
+    const int n_obs = Q.ra[0].n_obs;
+    for (int t = threadIdx.x; t < n_obs * 6; t += blockDim.x) s_obs[t] = Q.obs[t];
+    __syncthreads();
+    const GraphWork gw = graph_work(Q);
+    gw_boxes(Q.X, Q.valid, gw.near_src, gw.near_dst, gw.near_tau, nullptr,
+             min(gw.counts[0], gw.near_cap), true, false, s_obs, n_obs, gw, Q.ebits, Q.words,
+             blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_b_gw_exact(BatchQuery* qs) {
+    BatchQuery& Q = qs[blockIdx.y];
+    gw_exact(Q.X, Q.obs, graph_work(Q), nullptr, nullptr, nullptr, Q.ebits, Q.words,
+             blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_b_row_deg(BatchQuery* qs) {
+    const BatchQuery& Q = qs[blockIdx.y];
+    row_deg_dev(Q.ebits, Q.n_nodes, Q.words, Q.deg,
+                blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
 // exclusive scan of arr_in[0..n) into arr_out (may alias), whole block;
@@ -120,6 +161,7 @@ __global__ __launch_bounds__(1024) void k_b_row_scan(BatchQuery* qs) {
     if (threadIdx.x == 0) {
         Q.row_ptr[Q.n_nodes] = total;
         if (total > Q.cap_edges) atomicOr(&Q.bad, 4);
+        if (Q.gcount[0] > Q.cap_edges || Q.gcount[1] > Q.cap_pairs) atomicOr(&Q.bad, 4);
     }
 }
 
@@ -370,7 +412,11 @@ void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes
     k_b_gcloud<<<dim3(1, q), 256, 0, s>>>(qs, S_max + 1);
     const int vmax = std::max(max_nodes, kMaxObs);
     k_b_valid<<<dim3((vmax + 255) / 256, q), 256, 0, s>>>(qs);
-    k_b_graph_mark<<<dim3(max_nodes, q), 256, (size_t)words * sizeof(uint32_t), s>>>(qs);
+    k_b_zero_ebits<<<dim3(256, q), 256, 0, s>>>(qs);
+    k_b_gw_near_rows<<<dim3(max_nodes, q), 256, 0, s>>>(qs);
+    k_b_gw_boxes<<<dim3(256, q), 256, 0, s>>>(qs);
+    k_b_gw_exact<<<dim3(64, q), 256, 0, s>>>(qs);
+    k_b_row_deg<<<dim3((max_nodes + 3) / 4, q), 256, 0, s>>>(qs);
     k_b_row_scan<<<q, 1024, 0, s>>>(qs);
     k_b_graph_fill<<<dim3((max_nodes + 3) / 4, q), 256, 0, s>>>(qs);
     k_b_edge_steer<<<dim3(256, q), 256, 0, s>>>(qs);

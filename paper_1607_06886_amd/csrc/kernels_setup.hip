@@ -86,13 +86,54 @@ void launch_mark_valid(hipStream_t s, const float* X, int n_nodes, const float* 
                                                  gb[3], gb[4], gb[5], valid, goal, bad);
 }
 
-__global__ __launch_bounds__(256) void k_graph_mark(const float* __restrict__ X,
-                                                    const uint8_t* __restrict__ valid, int n,
-                                                    const float* __restrict__ obs, int n_obs,
-                                                    double r_steer, double r_conn,
-                                                    uint32_t* __restrict__ ebits,
-                                                    int32_t* __restrict__ deg, int words) {
-    graph_mark_dev(X, valid, n, obs, n_obs, r_steer, r_conn, ebits, deg, words);
+// ---- BuildGraph pass 1 stages (setup_ops.hpp) ----
+__global__ __launch_bounds__(256) void k_gw_near_rows(const float* __restrict__ X,
+                                                      const uint8_t* __restrict__ valid, int n,
+                                                      int row0, double r_steer, double r_conn,
+                                                      GraphWork gw) {
+    __shared__ int s_list[kNearChunk];
+    __shared__ int s_cnt;
+    gw_near_row(X, valid, n, row0 + blockIdx.x, r_steer, r_conn, gw, s_list, &s_cnt);
+}
+
+__global__ __launch_bounds__(256) void k_gw_near_col0(const float* __restrict__ X,
+                                                      const uint8_t* __restrict__ valid, int n,
+                                                      double r_steer, double r_conn,
+                                                      GraphWork gw) {
+    gw_near_col0(X, valid, n, blockIdx.x * blockDim.x + threadIdx.x, r_steer, r_conn, gw);
+}
+
+// boxes over the near list (count on the device) or a cached list (count given)
+__global__ __launch_bounds__(256) void k_gw_boxes(const float* __restrict__ X,
+                                                  const uint8_t* __restrict__ valid,
+                                                  const int32_t* __restrict__ src,
+                                                  const int32_t* __restrict__ dst,
+                                                  const double* __restrict__ tau,
+                                                  const double* __restrict__ bbox, int count,
+                                                  int near_list, const float* __restrict__ obs,
+                                                  int n_obs, GraphWork gw,
+                                                  uint32_t* __restrict__ ebits, int words) {
+    __shared__ float s_obs[kMaxObs * 6];
+    for (int t = threadIdx.x; t < n_obs * 6; t += blockDim.x) s_obs[t] = obs[t];
+    __syncthreads();
+    const int N = near_list ? min(gw.counts[0], gw.near_cap) : count;
+    gw_boxes(X, valid, src, dst, tau, bbox, N, near_list != 0, near_list == 0, s_obs, n_obs, gw,
+             ebits, words, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_gw_exact(const float* __restrict__ X,
+                                                  const float* __restrict__ obs, GraphWork gw,
+                                                  const int32_t* __restrict__ rm_src,
+                                                  const int32_t* __restrict__ rm_dst,
+                                                  const double* __restrict__ rm_tau,
+                                                  uint32_t* __restrict__ ebits, int words) {
+    gw_exact(X, obs, gw, rm_src, rm_dst, rm_tau, ebits, words, blockIdx.x * blockDim.x + threadIdx.x,
+             gridDim.x * blockDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_row_deg(const uint32_t* __restrict__ ebits, int n_nodes,
+                                                 int words, int32_t* __restrict__ deg) {
+    row_deg_dev(ebits, n_nodes, words, deg, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
 __global__ __launch_bounds__(256) void k_graph_fill(int n, const uint32_t* __restrict__ ebits,
@@ -112,11 +153,46 @@ __global__ __launch_bounds__(256) void k_edge_steer(const float* __restrict__ X,
     edge_steer_dev(X, n, r_steer, row_ptr, col, esrc, etau, ecost);
 }
 
+namespace {
+constexpr int kStageBlocks = 2048;   // grid of the grid-stride stages
+}
+
 void launch_graph_mark(hipStream_t s, const float* X, const uint8_t* valid, int n_nodes,
                        const float* obs, int n_obs, double r_steer, double r_conn,
-                       uint32_t* ebits, int32_t* deg, int words) {
-    k_graph_mark<<<n_nodes, 256, (size_t)words * sizeof(uint32_t), s>>>(
-        X, valid, n_nodes, obs, n_obs, r_steer, r_conn, ebits, deg, words);
+                       uint32_t* ebits, int32_t* deg, int words, const GraphWork& gw) {
+    (void)hipMemsetAsync(ebits, 0, (size_t)n_nodes * words * sizeof(uint32_t), s);
+    k_gw_near_rows<<<n_nodes, 256, 0, s>>>(X, valid, n_nodes, 0, r_steer, r_conn, gw);
+    k_gw_boxes<<<kStageBlocks, 256, 0, s>>>(X, valid, gw.near_src, gw.near_dst, gw.near_tau,
+                                            nullptr, 0, 1, obs, n_obs, gw, ebits, words);
+    k_gw_exact<<<kStageBlocks, 256, 0, s>>>(X, obs, gw, nullptr, nullptr, nullptr, ebits, words);
+    k_row_deg<<<(n_nodes + 3) / 4, 256, 0, s>>>(ebits, n_nodes, words, deg);
+}
+
+void launch_graph_pass1_roadmap(hipStream_t s, const float* X, const uint8_t* valid, int n_nodes,
+                                const float* obs, int n_obs, double r_steer, double r_conn,
+                                const int32_t* rm_src, const int32_t* rm_dst,
+                                const double* rm_tau, const double* rm_bbox, int rm_edges,
+                                uint32_t* ebits, int32_t* deg, int words, const GraphWork& gw) {
+    (void)hipMemsetAsync(ebits, 0, (size_t)n_nodes * words * sizeof(uint32_t), s);
+    // the pairs at node 0: its row, then its column
+    k_gw_near_rows<<<1, 256, 0, s>>>(X, valid, n_nodes, 0, r_steer, r_conn, gw);
+    const int col = n_nodes - 1;
+    k_gw_near_col0<<<(col + 255) / 256 > 0 ? (col + 255) / 256 : 1, 256, 0, s>>>(
+        X, valid, n_nodes, r_steer, r_conn, gw);
+    k_gw_boxes<<<64, 256, 0, s>>>(X, valid, gw.near_src, gw.near_dst, gw.near_tau, nullptr, 0, 1, obs,
+                                  n_obs, gw, ebits, words);
+    int blocks = (rm_edges + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > kStageBlocks) blocks = kStageBlocks;
+    k_gw_boxes<<<blocks, 256, 0, s>>>(X, valid, rm_src, rm_dst, rm_tau, rm_bbox, rm_edges, 0, obs,
+                                      n_obs, gw, ebits, words);
+    k_gw_exact<<<kStageBlocks, 256, 0, s>>>(X, obs, gw, rm_src, rm_dst, rm_tau, ebits, words);
+    k_row_deg<<<(n_nodes + 3) / 4, 256, 0, s>>>(ebits, n_nodes, words, deg);
+}
+
+void launch_graph_cols(hipStream_t s, int n_nodes, const uint32_t* ebits, const int32_t* row_ptr,
+                       int32_t* col, int32_t* esrc, int words) {
+    k_graph_fill<<<(n_nodes + 3) / 4, 256, 0, s>>>(n_nodes, ebits, row_ptr, col, esrc, words);
 }
 
 void launch_graph_fill(hipStream_t s, const float* X, int n_nodes, double r_steer,

@@ -81,6 +81,7 @@ struct pump_ctx {
     int last_best = -1;        // front index of the last p* (-1: none)
     int last_steps = 0;        // tracking steps of the trajectory returned last
     bool last_smoothed = false;
+    const pump_roadmap* rm = nullptr;  // cached Near connections (pump_set_roadmap)
     // query state
     int n_nodes = 0, n_obs = 0, M = 0, S_max = 0;
     double alpha = 0, eta = 0, alpha_min = 0, alpha_max = 0, h = 0, dt = 0;
@@ -469,6 +470,9 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
     ctx->have_setup = ctx->have_explore = ctx->explore_done = false;
     const pump_config& cfg = ctx->cfg;
     if (pr->n < 1 || pr->n + 1 > cfg.max_nodes) return fail(ctx, PUMP_E_ARG, "n out of range for max_nodes");
+    if (ctx->rm && pr->n != ctx->rm->n)
+        return fail(ctx, PUMP_E_ARG, "the problem has " + std::to_string(pr->n) + " samples, the roadmap " +
+                                         std::to_string(ctx->rm->n));
     if (pr->n_obs < 0 || pr->n_obs > cfg.max_obstacles) return fail(ctx, PUMP_E_ARG, "n_obs exceeds max_obstacles");
     if (!pr->samples || (pr->n_obs > 0 && !pr->obstacles) || !pr->noise || !pr->noise_mc)
         return fail(ctx, PUMP_E_ARG, "null input pointer");
@@ -566,20 +570,38 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
     launch_mark_valid(ctx->stream, ctx->X, ctx->n_nodes, ctx->obs, ctx->n_obs, gb, ctx->valid, ctx->goal,
                       ctx->dev_ints + 1);
     HIPCHK(hipMemsetAsync(ctx->deg, 0, (size_t)(ctx->n_nodes + 1) * sizeof(int32_t), ctx->stream));
+    // pass-1 work lists: the near list in the edge arrays (free until pass 2),
+    // the exact queue in two Explore candidate arrays (free until Explore)
+    const GraphWork gw{ctx->esrc, ctx->col, ctx->etau, ctx->c_pop, ctx->c_pos, ctx->dev_ints + 2,
+                       (int32_t)std::min<int64_t>(cfg.cap_edges, (1ll << 31) - 1),
+                       (int32_t)cfg.cap_pairs};
     tbeg(ctx, 1);
-    launch_graph_mark(ctx->stream, ctx->X, ctx->valid, ctx->n_nodes, ctx->obs, ctx->n_obs,
-                      (double)cfg.r_steer, (double)cfg.r_conn, ctx->ebits, ctx->deg, ctx->words_per_row);
+    if (ctx->rm)
+        launch_rm_query(ctx->stream, ctx->X, ctx->valid, ctx->n_nodes, ctx->obs, ctx->n_obs,
+                        (double)cfg.r_steer, (double)cfg.r_conn, ctx->rm->d, ctx->ebits,
+                        ctx->words_per_row, ctx->deg, ctx->dev_ints + 1, gw);
+    else
+        launch_graph_mark(ctx->stream, ctx->X, ctx->valid, ctx->n_nodes, ctx->obs, ctx->n_obs,
+                          (double)cfg.r_steer, (double)cfg.r_conn, ctx->ebits, ctx->deg,
+                          ctx->words_per_row, gw);
     tend(ctx);
     int32_t nn = ctx->n_nodes;
     HIPCHK(hipMemcpyAsync(ctx->dev_ints, &nn, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
     scan_exclusive(ctx->stream, ctx->deg, ctx->row_ptr, ctx->dev_ints, nn, &ctx->ctl->scan_total[4],
                    ctx->blk);
     HIPCHK(hipMemcpyAsync(ctx->ctl_h, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
-    int32_t flags[2];
-    HIPCHK(hipMemcpyAsync(flags, ctx->dev_ints, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    int32_t flags[4];
+    HIPCHK(hipMemcpyAsync(flags, ctx->dev_ints, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (flags[1] & 1) return fail(ctx, PUMP_E_ARG, "a sample or obstacle is not finite or lies outside [-16, 16]");
     if (flags[1] & 2) return fail(ctx, PUMP_E_ARG, "x_init lies in an obstacle");
+    if (flags[1] & 4) return fail(ctx, PUMP_E_ARG, "the samples differ from the roadmap's");
+    if ((long long)flags[2] > cfg.cap_edges)
+        return fail(ctx, PUMP_E_CAPACITY, "near connections " + std::to_string(flags[2]) +
+                                              " exceed cap_edges");
+    if ((long long)flags[3] > cfg.cap_pairs)
+        return fail(ctx, PUMP_E_CAPACITY, "exact box tests " + std::to_string(flags[3]) +
+                                              " exceed cap_pairs");
     ctx->n_edges = ctx->ctl_h->scan_total[4];
     if ((long long)ctx->n_edges > cfg.cap_edges)
         return fail(ctx, PUMP_E_CAPACITY, "graph edges " + std::to_string(ctx->n_edges) +
@@ -587,8 +609,16 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
     HIPCHK(hipMemcpyAsync(ctx->row_ptr + nn, &ctx->n_edges, sizeof(int32_t), hipMemcpyHostToDevice,
                           ctx->stream));
     tbeg(ctx, 2);
-    launch_graph_fill(ctx->stream, ctx->X, ctx->n_nodes, (double)cfg.r_steer, ctx->ebits, ctx->row_ptr,
-                      ctx->col, ctx->esrc, ctx->etau, ctx->ecost, ctx->words_per_row, ctx->n_edges);
+    if (ctx->rm) {
+        launch_graph_cols(ctx->stream, ctx->n_nodes, ctx->ebits, ctx->row_ptr, ctx->col, ctx->esrc,
+                          ctx->words_per_row);
+        launch_rm_fill(ctx->stream, ctx->X, ctx->n_nodes, (double)cfg.r_steer, ctx->row_ptr, ctx->col,
+                       ctx->esrc, ctx->rm->d, ctx->etau, ctx->ecost, ctx->n_edges);
+    } else {
+        launch_graph_fill(ctx->stream, ctx->X, ctx->n_nodes, (double)cfg.r_steer, ctx->ebits,
+                          ctx->row_ptr, ctx->col, ctx->esrc, ctx->etau, ctx->ecost,
+                          ctx->words_per_row, ctx->n_edges);
+    }
     tend(ctx);
     HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev[1]));
@@ -885,6 +915,17 @@ int pump_plan(pump_ctx* ctx, const pump_problem* pr, pump_result* out) {
     res.ms_total = ms;
     if (out) *out = res;
     return r;
+}
+
+int pump_set_roadmap(pump_ctx* ctx, const pump_roadmap* rm) {
+    if (!ctx) return PUMP_E_ARG;
+    if (rm && (rm->r_steer != ctx->cfg.r_steer || rm->r_conn != ctx->cfg.r_conn))
+        return fail(ctx, PUMP_E_ARG, "roadmap radii differ from the context's");
+    if (rm && rm->n + 1 > ctx->cfg.max_nodes)
+        return fail(ctx, PUMP_E_ARG, "roadmap holds more samples than max_nodes - 1");
+    ctx->rm = rm;
+    ctx->have_setup = ctx->have_explore = ctx->explore_done = false;
+    return PUMP_OK;
 }
 
 int pump_sample_halton(int32_t n, int32_t n_goal, const float* lo, const float* hi,

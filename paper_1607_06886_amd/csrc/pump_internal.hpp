@@ -130,6 +130,19 @@ struct RoundArgs {
     Ctl* ctl;
 };
 
+// Work lists of BuildGraph's pass 1 (setup_ops.hpp): the near list lives in
+// the final edge arrays (free until pass 2), the exact queue in two Explore
+// candidate arrays (free until Explore).
+struct GraphWork {
+    int32_t* near_src;         // near connections [near_cap]
+    int32_t* near_dst;
+    double* near_tau;
+    int32_t* xq_edge;          // (connection, box) pairs for the exact test [xq_cap]
+    int32_t* xq_box;
+    int32_t* counts;           // [0] near, [1] exact queue (device)
+    int32_t near_cap, xq_cap;
+};
+
 // ---- launchers (kernels_*.hip) ----
 // scratch: kDevScratchPer * ceil(S_max / 16) * 3 * N doubles
 constexpr int kDevScratchPer = 8;
@@ -140,6 +153,43 @@ void launch_deviation_table(hipStream_t s, const float* noise, float* D, float* 
 void launch_deviation_table_lqg(hipStream_t s, const float* noise, const float* noise_meas,
                                 float* D, float* cloud, float* gcloud, int N, int S_max,
                                 const LqgCoef& q, double* scratch);
+// The obstacle-independent part of BuildGraph over a fixed sample set
+// (roadmap_ops.hpp): every Near connection between samples with its tau*,
+// c* and nominal position range.  Node numbering as in a query (samples are
+// nodes 1..n; row 0 is empty).
+struct RoadmapDev {
+    const float* X;            // [n + 1][6] (row 0 unused)
+    const int32_t* row_ptr;    // [n + 2]
+    const int32_t* col;        // [E], ascending within a row
+    const int32_t* esrc;       // [E]
+    const double* tau;         // [E]
+    const double* cost;        // [E]
+    const double* bbox;        // [E][6] nominal position range (lo xyz, hi xyz)
+    int32_t n_nodes;           // n + 1
+    int32_t n_edges;
+};
+void launch_rm_bbox(hipStream_t s, const float* X, const int32_t* esrc, const int32_t* col,
+                    const double* tau, double* bbox, int E);
+// Pass 1 from a roadmap (ebits cleared here), then the row degrees; bit 4 of
+// *bad when the query's samples differ from it.  gw.counts must be zero.
+void launch_rm_query(hipStream_t s, const float* X, const uint8_t* valid, int n_nodes,
+                     const float* obs, int n_obs, double r_steer, double r_conn,
+                     const RoadmapDev& rm, uint32_t* ebits, int words, int32_t* deg, int32_t* bad,
+                     const GraphWork& gw);
+// Pass 1 over cached connections (src, dst, tau, nominal range) plus the
+// pairs at node 0 (kernels_setup.hip).
+void launch_graph_pass1_roadmap(hipStream_t s, const float* X, const uint8_t* valid, int n_nodes,
+                                const float* obs, int n_obs, double r_steer, double r_conn,
+                                const int32_t* rm_src, const int32_t* rm_dst,
+                                const double* rm_tau, const double* rm_bbox, int rm_edges,
+                                uint32_t* ebits, int32_t* deg, int words, const GraphWork& gw);
+void launch_rm_fill(hipStream_t s, const float* X, int n_nodes, double r_steer,
+                    const int32_t* row_ptr, const int32_t* col, const int32_t* esrc,
+                    const RoadmapDev& rm, double* etau, double* ecost, int n_edges);
+// Pass 2 of BuildGraph without the edge controls (col and esrc only).
+void launch_graph_cols(hipStream_t s, int n_nodes, const uint32_t* ebits, const int32_t* row_ptr,
+                       int32_t* col, int32_t* esrc, int words);
+
 // Halton points start .. start + n - 1 over the box [lo, hi] (6 floats each)
 // into out [n][6] (kernels_sample.hip).
 hipError_t launch_halton(hipStream_t s, int64_t start, int32_t n, const float* lo, const float* hi,
@@ -147,9 +197,11 @@ hipError_t launch_halton(hipStream_t s, int64_t start, int32_t n, const float* l
 void launch_mark_valid(hipStream_t s, const float* X, int n_nodes, const float* obs,
                        int n_obs, const float* goal_box, uint8_t* valid, uint8_t* goal,
                        int32_t* bad);
+// BuildGraph pass 1 from scratch: the edge bit matrix (cleared here) and the
+// row degrees.  gw.counts must be zero.
 void launch_graph_mark(hipStream_t s, const float* X, const uint8_t* valid, int n_nodes,
                        const float* obs, int n_obs, double r_steer, double r_conn,
-                       uint32_t* ebits, int32_t* deg, int words);
+                       uint32_t* ebits, int32_t* deg, int words, const GraphWork& gw);
 void launch_graph_fill(hipStream_t s, const float* X, int n_nodes, double r_steer,
                        const uint32_t* ebits, const int32_t* row_ptr, int32_t* col,
                        int32_t* esrc, double* etau, double* ecost, int words, int n_edges);
@@ -272,6 +324,7 @@ struct BatchQuery {
     int32_t N, n_nodes, words;
     int32_t cap_pairs, cap_edges;
     int32_t bad;               // input / capacity errors (bit flags)
+    int32_t gcount[4];         // graph-build work-list counters (zero on upload)
     float* X;
     float* obs;
     uint8_t* valid;
@@ -324,3 +377,15 @@ void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths);
 void launch_mc(hipStream_t s, const SelectArgs& a, int32_t n_paths);
 
 }  // namespace pump
+
+// A roadmap owned by the caller (pump_roadmap_create): device arrays, the
+// radii it was built with and its sample count.
+struct pump_roadmap {
+    pump::RoadmapDev d;
+    float* X = nullptr;
+    int32_t *row_ptr = nullptr, *col = nullptr, *esrc = nullptr;
+    double *tau = nullptr, *cost = nullptr, *bbox = nullptr;
+    float r_steer = 0.0f, r_conn = 0.0f;
+    int32_t n = 0;
+    float ms_build = 0.0f;
+};

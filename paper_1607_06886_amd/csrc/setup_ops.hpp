@@ -279,151 +279,198 @@ __device__ __forceinline__ void mark_valid_dev(const float* __restrict__ X, int 
 // ---------------------------------------------------------------------------
 // BuildGraph (Alg. 3).  Edge v -> u iff both nodes are valid, u != v,
 // c*(v,u) < r_n, tau* > 1e-6 and the nominal trajectory meets no obstacle
-// (continuous, exact; closed boxes).  Pass 1 evaluates every ordered pair and
-// records the result as a bit matrix and per-row counts; after a scan of the
-// counts, pass 2 writes each row's neighbours in ascending order with their
-// (tau*, c*).
+// (continuous, exact; closed boxes).  The result is a bit matrix (row v,
+// bit u) and per-row counts; after a scan of the counts, pass 2 writes each
+// row's neighbours in ascending order with their (tau*, c*).
+//
+// Pass 1 runs as stages, each its own kernel so that the register-heavy
+// exact box test does not hold down the occupancy of the others:
+//   near    one workgroup per row: every target through the exact Near
+//           rejection test into an LDS list, then the survivors steered
+//           densely (tau*, c*); near connections -> the near list;
+//   boxes   per near connection, its nominal position range against every
+//           box and, where they meet, the quick trajectory-box test; a hit
+//           blocks it, an unsure case goes to the exact queue; connections
+//           not blocked set their bit;
+//   exact   the exact trajectory-box test per queued (connection, box); a
+//           hit clears the bit;
+//   degree  popcount of each row.
+// A connection's bit ends set iff no box blocks it, the decision of the exact
+// test on every box its range meets.
 // ---------------------------------------------------------------------------
-// One block (256 threads) per source row v.  The row is scanned in chunks of
-// 4096 targets: every thread applies the exact rejection test to 16 targets
-// and appends the survivors to a list in LDS.  The survivors are then steered
-// densely (one per thread); a near pair whose trajectory's bounding box meets
-// some obstacle boxes contributes one (pair, box) entry per such box to an
-// LDS queue, and the queue is processed densely too (one exact trajectory-box
-// test per thread), so lanes do not idle while a few pairs test many boxes.
-// Bits of edges are set in the row's LDS bitmask, which is written out with
-// the row's degree at the end.
-constexpr int kMarkChunk = 4096;
-constexpr int kMarkQueue = 2048;
+constexpr int kNearChunk = 4096;   // targets per LDS survivor list
 
-__device__ __forceinline__ void graph_mark_dev(const float* __restrict__ X,
-                                                    const uint8_t* __restrict__ valid, int n,
-                                                    const float* __restrict__ obs, int n_obs,
-                                                    double r_steer, double r_conn,
-                                                    uint32_t* __restrict__ ebits,
-                                                    int32_t* __restrict__ deg, int words) {
-    __shared__ float s_obs[kMaxObs * 6];
-    __shared__ int s_list[kMarkChunk];
-    __shared__ double s_tau[256];
-    __shared__ int s_blk[256];
-    __shared__ uint32_t s_q[kMarkQueue];
-    __shared__ int s_w[4];
-    __shared__ int s_cnt;
-    extern __shared__ uint32_t s_row[];          // words u32
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int t = tid; t < n_obs * 6; t += blockDim.x) s_obs[t] = obs[t];
-    for (int t = tid; t < words; t += blockDim.x) s_row[t] = 0u;
-    const int v = blockIdx.x;
+// Append `ok` items of a wave to a list: one atomic per wave (all 64 lanes
+// call it).  Returns the slot of this lane's item.
+__device__ __forceinline__ int wave_append(bool ok, int32_t* counter) {
+    const unsigned long long m = __ballot(ok);
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0 && m) base = atomicAdd(counter, (int)__popcll(m));
+    base = __shfl(base, 0, 64);
+    return base + (int)__popcll(m & (lane ? ((1ull << lane) - 1ull) : 0ull));
+}
+
+__device__ __forceinline__ void gw_push_near(const GraphWork& gw, bool ok, int src, int dst,
+                                             double tau) {
+    const int slot = wave_append(ok, gw.counts + 0);
+    if (ok && slot < gw.near_cap) {
+        gw.near_src[slot] = src;
+        gw.near_dst[slot] = dst;
+        gw.near_tau[slot] = tau;
+    }
+}
+
+// near: row v (whole workgroup of 256 threads; s_list holds kNearChunk ints)
+__device__ __forceinline__ void gw_near_row(const float* __restrict__ X,
+                                            const uint8_t* __restrict__ valid, int n, int v,
+                                            double r_steer, double r_conn, const GraphWork& gw,
+                                            int* s_list, int* s_cnt) {
+    if (!valid[v]) return;
     float xv[6];
     for (int k = 0; k < 6; ++k) xv[k] = X[(size_t)v * 6 + k];
-    const bool vv = valid[v] != 0;
-    __syncthreads();
-    if (vv) {
-        for (int c0 = 0; c0 < n; c0 += kMarkChunk) {
-            if (tid == 0) s_cnt = 0;
-            __syncthreads();
-            for (int u = c0 + tid; u < c0 + kMarkChunk && u < n; u += blockDim.x) {
-                if (u == v || !valid[u]) continue;
-                float xu[6];
-                for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)u * 6 + k];
-                if (!surely_not_near(boundary_sums(xv, xu), r_steer, r_conn))
-                    s_list[atomicAdd(&s_cnt, 1)] = u;
+    for (int c0 = 0; c0 < n; c0 += kNearChunk) {
+        if (threadIdx.x == 0) *s_cnt = 0;
+        __syncthreads();
+        for (int u = c0 + threadIdx.x; u < c0 + kNearChunk && u < n; u += blockDim.x) {
+            if (u == v || !valid[u]) continue;
+            float xu[6];
+            for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)u * 6 + k];
+            if (!surely_not_near(boundary_sums(xv, xu), r_steer, r_conn))
+                s_list[atomicAdd(s_cnt, 1)] = u;
+        }
+        __syncthreads();
+        const int cnt = *s_cnt;
+        for (int base = 0; base < cnt; base += blockDim.x) {
+            const int i = base + threadIdx.x;
+            bool ok = false;
+            int u = 0;
+            double tau = 0.0;
+            if (i < cnt) {
+                u = s_list[i];
+                double c;
+                steer64(xv, X + (size_t)u * 6, r_steer, tau, c);
+                ok = c < r_conn && tau > kTauMin;
             }
-            __syncthreads();
-            const int cnt = s_cnt;
-            for (int base = 0; base < cnt; base += 256) {
-                const int i = base + tid;
-                int u = -1;
-                bool near = false;
-                double tau = 0.0;
-                unsigned long long ov[kMaxObs / 64] = {0ull, 0ull, 0ull, 0ull};
-                int n_ov = 0;
-                if (i < cnt) {
-                    u = s_list[i];
-                    float xu[6];
-                    for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)u * 6 + k];
-                    double c;
-                    steer64(xv, xu, r_steer, tau, c);
-                    near = c < r_conn && tau > kTauMin;
-                    if (near && n_obs > 0) {
-                        Cubic cs[3];
-                        hermite(xv, xu, tau, cs);
-                        double mn[3], mx[3];
-                        for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
-                        for (int o = 0; o < n_obs; ++o) {
-                            const float* bx = s_obs + o * 6;
-                            bool disjoint = false;
-                            for (int a = 0; a < 3; ++a)
-                                disjoint |= (mx[a] < (double)bx[a]) | (mn[a] > (double)bx[3 + a]);
-                            if (!disjoint) {
-                                ov[o >> 6] |= 1ull << (o & 63);
-                                ++n_ov;
-                            }
+            gw_push_near(gw, ok, v, u, tau);
+        }
+        __syncthreads();
+    }
+}
+
+// near for the column of node 0: thread p is the pair (p + 1) -> 0 (all
+// lanes of a wave call it)
+__device__ __forceinline__ void gw_near_col0(const float* __restrict__ X,
+                                             const uint8_t* __restrict__ valid, int n, int p,
+                                             double r_steer, double r_conn, const GraphWork& gw) {
+    const int src = p + 1;
+    bool ok = false;
+    double tau = 0.0;
+    if (src < n && valid[0] && valid[src] &&
+        !surely_not_near(boundary_sums(X + (size_t)src * 6, X), r_steer, r_conn)) {
+        double c;
+        steer64(X + (size_t)src * 6, X, r_steer, tau, c);
+        ok = c < r_conn && tau > kTauMin;
+    }
+    gw_push_near(gw, ok, src, 0, tau);
+}
+
+// boxes over one list of connections (src, dst, tau, optional cached range).
+// Exact-queue entries name the connection by `tag` (>= 0: index into the
+// roadmap list, < 0: -1 - index into the near list).  check_valid: skip
+// connections with an invalid end (the cached roadmap list).
+__device__ __forceinline__ void gw_boxes(const float* __restrict__ X,
+                                         const uint8_t* __restrict__ valid,
+                                         const int32_t* __restrict__ src_a,
+                                         const int32_t* __restrict__ dst_a,
+                                         const double* __restrict__ tau_a,
+                                         const double* __restrict__ bbox, int count, bool near_list,
+                                         bool check_valid, const float* s_obs, int n_obs,
+                                         const GraphWork& gw, uint32_t* __restrict__ ebits,
+                                         int words, int gid, int stride) {
+    for (int i = gid; i < count; i += stride) {
+        const int src = src_a[i], dst = dst_a[i];
+        if (check_valid && !(valid[src] && valid[dst])) continue;
+        bool blocked = false;
+        if (n_obs > 0) {
+            const double tau = tau_a[i];
+            const float* xs = X + (size_t)src * 6;
+            const float* xd = X + (size_t)dst * 6;
+            Cubic cs[3];
+            hermite(xs, xd, tau, cs);
+            double mn[3], mx[3];
+            if (bbox) {
+                for (int a = 0; a < 3; ++a) {
+                    mn[a] = bbox[(size_t)i * 6 + a];
+                    mx[a] = bbox[(size_t)i * 6 + 3 + a];
+                }
+            } else {
+                for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
+            }
+            unsigned long long unsure[kMaxObs / 64] = {0ull, 0ull, 0ull, 0ull};
+            for (int o = 0; o < n_obs && !blocked; ++o) {
+                const float* bx = s_obs + o * 6;
+                bool disjoint = false;
+                for (int a = 0; a < 3; ++a)
+                    disjoint |= (mx[a] < (double)bx[a]) | (mn[a] > (double)bx[3 + a]);
+                if (disjoint) continue;
+                const int q = trajectory_box_quick(cs, tau, bx);
+                if (q == kBoxHit) blocked = true;
+                else if (q == kBoxUnsure) unsure[o >> 6] |= 1ull << (o & 63);
+            }
+            if (!blocked) {
+                const int tag = near_list ? -1 - i : i;
+                for (int w = 0; w < kMaxObs / 64; ++w) {
+                    unsigned long long m = unsure[w];
+                    while (m) {
+                        const int o = w * 64 + __ffsll((long long)m) - 1;
+                        m &= m - 1ull;
+                        const int slot = atomicAdd(gw.counts + 1, 1);
+                        if (slot < gw.xq_cap) {
+                            gw.xq_edge[slot] = tag;
+                            gw.xq_box[slot] = o;
                         }
                     }
                 }
-                s_tau[tid] = tau;
-                s_blk[tid] = 0;
-                // exclusive scan of the per-thread test counts
-                int x = n_ov;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(x, o, 64);
-                    if (lane >= o) x += y;
-                }
-                if (lane == 63) s_w[wave] = x;
-                __syncthreads();
-                int off = x - n_ov, total = 0;
-                for (int w = 0; w < 4; ++w) {
-                    if (w < wave) off += s_w[w];
-                    total += s_w[w];
-                }
-                for (int seg = 0; seg < total; seg += kMarkQueue) {
-                    if (n_ov > 0 && off < seg + kMarkQueue && off + n_ov > seg) {
-                        int k = off;
-                        for (int wd = 0; wd < kMaxObs / 64; ++wd) {
-                            unsigned long long m = ov[wd];
-                            while (m) {
-                                const int o = wd * 64 + __ffsll((long long)m) - 1;
-                                m &= m - 1ull;
-                                if (k >= seg && k < seg + kMarkQueue)
-                                    s_q[k - seg] = ((uint32_t)tid << 8) | (uint32_t)o;
-                                ++k;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                    const int m = total - seg < kMarkQueue ? total - seg : kMarkQueue;
-                    for (int e = tid; e < m; e += blockDim.x) {
-                        const uint32_t ent = s_q[e];
-                        const int slot = (int)(ent >> 8), o = (int)(ent & 255u);
-                        if (s_blk[slot]) continue;   // already known to collide
-                        const int uu = s_list[base + slot];
-                        float xu[6];
-                        for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)uu * 6 + k];
-                        Cubic cs[3];
-                        const double tt = s_tau[slot];
-                        hermite(xv, xu, tt, cs);
-                        if (trajectory_hits_box(cs, tt, s_obs + o * 6)) s_blk[slot] = 1;
-                    }
-                    __syncthreads();
-                }
-                if (near && !s_blk[tid]) atomicOr(&s_row[u >> 5], 1u << (u & 31));
-                __syncthreads();
             }
         }
+        if (!blocked) atomicOr(&ebits[(size_t)src * words + (dst >> 5)], 1u << (dst & 31));
     }
+}
+
+// exact: queued (connection, box) pairs; a hit clears the connection's bit
+__device__ __forceinline__ void gw_exact(const float* __restrict__ X, const float* __restrict__ obs,
+                                         const GraphWork& gw, const int32_t* __restrict__ rm_src,
+                                         const int32_t* __restrict__ rm_dst,
+                                         const double* __restrict__ rm_tau,
+                                         uint32_t* __restrict__ ebits, int words, int gid,
+                                         int stride) {
+    const int N = min(gw.counts[1], gw.xq_cap);
+    for (int i = gid; i < N; i += stride) {
+        const int tag = gw.xq_edge[i];
+        int src, dst;
+        double tau;
+        if (tag >= 0) {
+            src = rm_src[tag]; dst = rm_dst[tag]; tau = rm_tau[tag];
+        } else {
+            src = gw.near_src[-1 - tag]; dst = gw.near_dst[-1 - tag]; tau = gw.near_tau[-1 - tag];
+        }
+        Cubic cs[3];
+        hermite(X + (size_t)src * 6, X + (size_t)dst * 6, tau, cs);
+        if (trajectory_hits_box_exact(cs, tau, obs + (size_t)gw.xq_box[i] * 6))
+            atomicAnd(&ebits[(size_t)src * words + (dst >> 5)], ~(1u << (dst & 31)));
+    }
+}
+
+// degree: out-degree of each row of the bit matrix (one wave per row)
+__device__ __forceinline__ void row_deg_dev(const uint32_t* __restrict__ ebits, int n_nodes, int words,
+                                            int32_t* __restrict__ deg, int v) {
+    const int lane = threadIdx.x & 63;
+    if (v >= n_nodes) return;
     int d = 0;
-    for (int t = tid; t < words; t += blockDim.x) {
-        const uint32_t w = s_row[t];
-        ebits[(size_t)v * words + t] = w;
-        d += __popc(w);
-    }
-    // block sum of the degree
+    for (int w = lane; w < words; w += 64) d += __popc(ebits[(size_t)v * words + w]);
     for (int o = 32; o > 0; o >>= 1) d += __shfl_down(d, o, 64);
-    __shared__ int s_deg[4];
-    if ((tid & 63) == 0) s_deg[tid >> 6] = d;
-    __syncthreads();
-    if (tid == 0) deg[v] = s_deg[0] + s_deg[1] + s_deg[2] + s_deg[3];
+    if (lane == 0) deg[v] = d;
 }
 
 __device__ __forceinline__ void graph_fill_dev(int n, const uint32_t* __restrict__ ebits,
