@@ -51,7 +51,7 @@ def make_inputs(seed):
 
 VALU_PEAK_TLANEOPS = 39.3          # 256 CU x 64 lanes x 2.4 GHz (one lane-op per lane per clock)
 
-# Algorithmic lane-ops of Explore (per unit; the design doc gives the derivation):
+# Algorithmic lane-ops of Explore, per unit of work:
 OPS_PAIR = 40          # locate the pair in the group, its edge, cost, steps, cutoff, pre-prune lookup
 OPS_GEOM = 150         # + Hermite coefficients, three cubic ranges, per-waypoint cloud boxes ...
 OPS_GEOM_PER_BOX = 12  # ... and one box-overlap test per obstacle (pairs past the pre-prune)

@@ -410,6 +410,14 @@ int pump_batch_destroy(pump_batch* b);
  * wall time of the whole batch. */
 int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_particles,
                     int32_t q, const pump_batch_tuning* tune, pump_result* out);
+/* Cached roadmaps for the queries of later pump_batch_plan calls: query i
+ * (i < n) builds its graph from rms[i] (NULL: from scratch), as
+ * pump_set_roadmap does for a context; n = 0 clears them.  PUMP_E_ARG if a
+ * roadmap's radii differ from the batch configuration's or it holds more
+ * than max_nodes - 1 samples; at plan time a query whose sample count
+ * differs from its roadmap's fails the call, one whose samples differ gets
+ * PUMP_E_ARG as its own status.  The roadmaps must outlive their use. */
+int pump_batch_set_roadmaps(pump_batch* b, const pump_roadmap* const* rms, int32_t n);
 /* Node ids (x_init = 0, sample k = k + 1) of plan `plan` of query `query`
  * from the last pump_batch_plan call, root first. */
 int pump_batch_get_path(pump_batch* b, int32_t query, int32_t plan, int32_t* nodes, int32_t cap,

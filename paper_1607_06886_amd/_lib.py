@@ -89,7 +89,8 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
            "pump_get_deviation", "pump_get_graph", "pump_get_plans", "pump_get_candidates",
            "pump_get_front", "pump_get_path", "pump_mc_path", "pump_get_smooth_path",
            "pump_sample_halton", "pump_roadmap_create", "pump_roadmap_destroy",
-           "pump_roadmap_info", "pump_set_roadmap", "pump_set_timing",
+           "pump_roadmap_info", "pump_set_roadmap", "pump_batch_set_roadmaps",
+           "pump_set_timing",
            "pump_get_timing", "pump_set_explore_mode", "pump_get_explore_mode",
            "pump_status_str", "pump_last_error", "pump_mlp_create",
            "pump_mlp_destroy", "pump_mlp_num_params", "pump_mlp_set_params",
@@ -145,6 +146,7 @@ def load(path: Optional[str] = None):
         "pump_roadmap_destroy": (_i32, [_p]),
         "pump_roadmap_info": (_i32, [_p, P(_i32), P(_i64), P(_f)]),
         "pump_set_roadmap": (_i32, [_p, _p]),
+        "pump_batch_set_roadmaps": (_i32, [_p, P(_p), _i32]),
         "pump_set_timing": (_i32, [_p, _i32]),
         "pump_get_timing": (_i32, [_p, _p, _p, _i32]),
         "pump_set_explore_mode": (_i32, [_p, _i32]),
@@ -678,6 +680,14 @@ class Batch:
         if rc < 0 and raise_on_error:
             self._err(rc)
         return [r.as_dict() for r in out]
+
+    def set_roadmaps(self, rms):
+        """Per-query cached roadmaps (Roadmap or None each) for later plans."""
+        arr = (_p * max(1, len(rms)))(*[r.rm if r is not None else None for r in rms])
+        rc = self.lib.pump_batch_set_roadmaps(self.b, arr, len(rms))
+        if rc != 0:
+            self._err(rc)
+        self._rms = list(rms)
 
     def path(self, query, plan):
         cap = self.cfg.max_steps + 1

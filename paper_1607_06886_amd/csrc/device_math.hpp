@@ -141,7 +141,7 @@ __device__ __forceinline__ bool surely_not_near(const BSums& s, double r, double
     const double a0 = 12.0 * r * s.pp, a1 = -12.0 * r * s.pv * R, a2 = 4.0 * r * s.vv * R2;
     const double a3 = -R4, a4 = R4;
     const double m = 1e-9 * (fabs(a0) + fabs(a1) + fabs(a2) + fabs(a3) + fabs(a4));
-    double b[5] = {a0, a0 + 0.25 * a1, a0 + 0.5 * a1 + a2 / 6.0,
+    double b[5] = {a0, a0 + 0.25 * a1, a0 + 0.5 * a1 + a2 * (1.0 / 6.0),
                    a0 + 0.75 * a1 + 0.5 * a2 + 0.25 * a3, a0 + a1 + a2 + a3 + a4};
     if (bern_pos(b, m)) return true;
     double h[2][5];
@@ -197,17 +197,49 @@ __device__ __forceinline__ int stationary_points(const Cubic& c, double tau, dou
     return n;
 }
 
-// On a monotone piece [ta, tb] bracketing `level`: bisection for the crossing
-// (a fixed 64 halvings, so lanes stay in step).  Returns the bracket (lo, hi)
-// with p(lo) on the start side of the level.
+// On a monotone piece [ta, tb] bracketing `level`: the crossing as a bracket
+// (lo, hi) with p(lo) on the start side of the level and p(hi) past it.
+// Up to 8 Newton steps kept inside the shrinking bracket (bisection when a
+// step leaves it); once a step moves t by at most 4 ulp the bracket is
+// closed by testing t -/+ 8 ulp.  Otherwise (slow convergence, e.g. a level
+// grazing a stationary point) the bracket is bisected until it is a few ulp
+// wide (at most 64 halvings).
 __device__ __forceinline__ void crossing(const Cubic& c, double ta, double tb, double level,
                                          bool rising, double& lo, double& hi) {
+    constexpr double kEps = 2.220446049250313e-16;
     lo = ta; hi = tb;
-    for (int it = 0; it < 64; ++it) {
-        double mid = 0.5 * (lo + hi);
-        bool below = c.at(mid) < level;
-        bool right = rising ? below : !below;
-        if (right) lo = mid; else hi = mid;
+    auto on_start = [&](double t) {
+        const bool below = c.at(t) < level;
+        return rising ? below : !below;
+    };
+    double t = 0.5 * (lo + hi);
+    bool conv = false;
+    for (int it = 0; it < 8; ++it) {
+        const double p = c.at(t);
+        const bool below = p < level;
+        if (rising ? below : !below) lo = t; else hi = t;
+        const double d = c.c1 + t * (2.0 * c.c2 + 3.0 * c.c3 * t);
+        double tn = t - (p - level) / d;
+        if (!(tn >= lo && tn <= hi)) tn = 0.5 * (lo + hi);
+        if (fabs(tn - t) <= 4.0 * kEps * fabs(t)) {
+            t = tn;
+            conv = true;
+            break;
+        }
+        t = tn;
+    }
+    if (conv) {
+        const double dl = 8.0 * kEps * fmax(fabs(t), 1e-300);
+        const double a = fmax(t - dl, ta), b = fmin(t + dl, tb);
+        if (on_start(a) && !on_start(b)) {
+            lo = fmax(lo, a);
+            hi = fmin(hi, b);
+            return;
+        }
+    }
+    for (int it = 0; it < 64 && hi - lo > 2.0 * kEps * fabs(hi); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (on_start(mid)) lo = mid; else hi = mid;
     }
 }
 
@@ -259,15 +291,46 @@ __device__ __forceinline__ void cubic_range(const Cubic& c, double tau, double& 
 // trajectory is swept over 8 equal pieces: a sample point (interior piece
 // ends) inside the box proves a hit; and on each piece a cubic lies in the
 // hull of its Bernstein coefficients p(ta), p(ta) + h p'(ta)/3,
-// p(tb) - h p'(tb)/3, p(tb), so when every piece's hull (widened by
-// kHullMargin, far above the rounding of these values) misses the box on some
-// axis, the trajectory misses it.  Both only settle cases the exact test
-// decides the same way.
+// p(tb) - h p'(tb)/3, p(tb), so a piece whose hull (widened by kHullMargin,
+// far above the rounding of these values) misses the box on some axis
+// cannot meet it.  A piece whose hull does meet the box is split once more
+// into 4 (more sample points, tighter hulls).  When every piece is cleared
+// the trajectory misses the box.  Both tests only settle cases the exact
+// test decides the same way.
 constexpr double kHullMargin = 1e-9;
 enum BoxTest : int { kBoxMiss = 0, kBoxHit = 1, kBoxUnsure = 2 };
 
+// Does the hull of the piece with end values (pa, da), (pb, db) and length
+// 3 * h3 miss the box on some axis?
+__device__ __forceinline__ bool piece_clear(const double* pa, const double* da, const double* pb,
+                                            const double* db, double h3, const float* box) {
+    bool sep = false;
+    for (int a = 0; a < 3; ++a) {
+        const double b1 = pa[a] + h3 * da[a], b2 = pb[a] - h3 * db[a];
+        const double lo = fmin(fmin(pa[a], pb[a]), fmin(b1, b2)) - kHullMargin;
+        const double hi = fmax(fmax(pa[a], pb[a]), fmax(b1, b2)) + kHullMargin;
+        sep |= (hi < (double)box[a]) | (lo > (double)box[3 + a]);
+    }
+    return sep;
+}
+
+__device__ __forceinline__ bool point_in_box(const double* p, const float* box) {
+    bool in = true;
+    for (int a = 0; a < 3; ++a) in &= (p[a] >= (double)box[a]) & (p[a] <= (double)box[3 + a]);
+    return in;
+}
+
+__device__ __forceinline__ void eval_pd(const Cubic* cs, double t, double* p, double* d) {
+    for (int a = 0; a < 3; ++a) {
+        p[a] = cs[a].at(t);
+        d[a] = cs[a].c1 + t * (2.0 * cs[a].c2 + t * 3.0 * cs[a].c3);
+    }
+}
+
 __device__ __forceinline__ int trajectory_box_quick(const Cubic* cs, double tau, const float* box) {
     const double h = 0.125 * tau;
+    const double h3 = h * (1.0 / 3.0);          // piece length / 3 (within the margin)
+    const double q3 = 0.25 * h3;                // the same for a quarter piece
     double pa[3], da[3];
     for (int a = 0; a < 3; ++a) {
         pa[a] = cs[a].c0;
@@ -275,20 +338,26 @@ __device__ __forceinline__ int trajectory_box_quick(const Cubic* cs, double tau,
     }
     bool ambiguous = false;
     for (int k = 1; k <= 8; ++k) {
+        const double ta = tau * (0.125 * (double)(k - 1));
         const double t = k == 8 ? tau : tau * (0.125 * (double)k);
         double pb[3], db[3];
-        bool in = true, sep = false;
-        for (int a = 0; a < 3; ++a) {
-            pb[a] = cs[a].at(t);
-            db[a] = cs[a].c1 + t * (2.0 * cs[a].c2 + t * 3.0 * cs[a].c3);
-            in &= (pb[a] >= (double)box[a]) & (pb[a] <= (double)box[3 + a]);
-            const double b1 = pa[a] + h * da[a] / 3.0, b2 = pb[a] - h * db[a] / 3.0;
-            const double lo = fmin(fmin(pa[a], pb[a]), fmin(b1, b2)) - kHullMargin;
-            const double hi = fmax(fmax(pa[a], pb[a]), fmax(b1, b2)) + kHullMargin;
-            sep |= (hi < (double)box[a]) | (lo > (double)box[3 + a]);
+        eval_pd(cs, t, pb, db);
+        if (k < 8 && point_in_box(pb, box)) return kBoxHit;
+        if (!piece_clear(pa, da, pb, db, h3, box)) {
+            // split the piece into 4
+            double qa[3] = {pa[0], pa[1], pa[2]}, qd[3] = {da[0], da[1], da[2]};
+            for (int j = 1; j <= 4; ++j) {
+                double qb[3], qe[3];
+                if (j == 4) {
+                    for (int a = 0; a < 3; ++a) { qb[a] = pb[a]; qe[a] = db[a]; }
+                } else {
+                    eval_pd(cs, ta + 0.25 * (double)j * h, qb, qe);
+                    if (point_in_box(qb, box)) return kBoxHit;
+                }
+                ambiguous |= !piece_clear(qa, qd, qb, qe, q3, box);
+                for (int a = 0; a < 3; ++a) { qa[a] = qb[a]; qd[a] = qe[a]; }
+            }
         }
-        if (k < 8 && in) return kBoxHit;
-        ambiguous |= !sep;
         for (int a = 0; a < 3; ++a) {
             pa[a] = pb[a];
             da[a] = db[a];

@@ -9,6 +9,7 @@
 #include "explore_team.hpp"
 #include "select_ops.hpp"
 #include "setup_ops.hpp"
+#include "roadmap_ops.hpp"
 #include "smooth_ops.hpp"
 
 namespace pump {
@@ -94,11 +95,37 @@ __global__ __launch_bounds__(256) void k_b_zero_ebits(BatchQuery* qs) {
         Q.ebits[t] = 0u;
 }
 
+// With a cached roadmap only row 0 and column 0 (the pairs at x_init) are
+// steered here; the cached connections go through k_b_gw_boxes_rm.
+__global__ __launch_bounds__(256) void k_b_rm_check(BatchQuery* qs) {
+    BatchQuery& Q = qs[blockIdx.y];
+    if (Q.use_rm) rm_check_dev(Q.X, Q.rm.X, Q.n_nodes, &Q.bad, 1);
+}
+
+__global__ __launch_bounds__(256) void k_b_gw_near_col0(BatchQuery* qs) {
+    BatchQuery& Q = qs[blockIdx.y];
+    if (!Q.use_rm) return;
+    gw_near_col0(Q.X, Q.valid, Q.n_nodes, blockIdx.x * blockDim.x + threadIdx.x, Q.r_steer, Q.r_conn,
+                 graph_work(Q));
+}
+
+__global__ __launch_bounds__(256) void k_b_gw_boxes_rm(BatchQuery* qs) {
+    __shared__ float s_obs[kMaxObs * 6];
+    BatchQuery& Q = qs[blockIdx.y];
+    if (!Q.use_rm) return;
+    const int n_obs = Q.ra[0].n_obs;
+    for (int t = threadIdx.x; t < n_obs * 6; t += blockDim.x) s_obs[t] = Q.obs[t];
+    __syncthreads();
+    gw_boxes(Q.X, Q.valid, Q.rm.esrc, Q.rm.col, Q.rm.tau, Q.rm.bbox, Q.rm.n_edges, false, true,
+             s_obs, n_obs, graph_work(Q), Q.ebits, Q.words, blockIdx.x * blockDim.x + threadIdx.x,
+             gridDim.x * blockDim.x);
+}
+
 __global__ __launch_bounds__(256) void k_b_gw_near_rows(BatchQuery* qs) {
     __shared__ int s_list[kNearChunk];
     __shared__ int s_cnt;
     BatchQuery& Q = qs[blockIdx.y];
-    if ((int)blockIdx.x >= Q.n_nodes) return;
+    if ((int)blockIdx.x >= Q.n_nodes || (Q.use_rm && blockIdx.x > 0)) return;
     gw_near_row(Q.X, Q.valid, Q.n_nodes, blockIdx.x, Q.r_steer, Q.r_conn, graph_work(Q), s_list,
                 &s_cnt);
 }
@@ -117,7 +144,7 @@ __global__ __launch_bounds__(256) void k_b_gw_boxes(BatchQuery* qs) {
 
 __global__ __launch_bounds__(256) void k_b_gw_exact(BatchQuery* qs) {
     BatchQuery& Q = qs[blockIdx.y];
-    gw_exact(Q.X, Q.obs, graph_work(Q), nullptr, nullptr, nullptr, Q.ebits, Q.words,
+    gw_exact(Q.X, Q.obs, graph_work(Q), Q.rm.esrc, Q.rm.col, Q.rm.tau, Q.ebits, Q.words,
              blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
@@ -174,7 +201,10 @@ __global__ __launch_bounds__(256) void k_b_graph_fill(BatchQuery* qs) {
 __global__ __launch_bounds__(256) void k_b_edge_steer(BatchQuery* qs) {
     const BatchQuery& Q = qs[blockIdx.y];
     if (Q.bad) return;
-    edge_steer_dev(Q.X, Q.n_nodes, Q.r_steer, Q.row_ptr, Q.col, Q.esrc, Q.etau, Q.ecost);
+    if (Q.use_rm)
+        rm_fill_dev(Q.X, Q.n_nodes, Q.r_steer, Q.row_ptr, Q.col, Q.esrc, Q.rm, Q.etau, Q.ecost);
+    else
+        edge_steer_dev(Q.X, Q.n_nodes, Q.r_steer, Q.row_ptr, Q.col, Q.esrc, Q.etau, Q.ecost);
 }
 
 // ----------------------------- explore --------------------------------------
@@ -269,16 +299,16 @@ __global__ void k_b_waypoints(BatchQuery* qs) {
     if (f < Q.ra[0].ctl->n_front) waypoints_one(Q.s, f);
 }
 
-__global__ __launch_bounds__(256) void k_b_mc(BatchQuery* qs) {
+__global__ __launch_bounds__(kMcThreads) void k_b_mc(BatchQuery* qs) {
     __shared__ float s_obs[kMaxObs * 6];
+    __shared__ int s_hit[kMcParticles];
     const BatchQuery& Q = qs[blockIdx.z];
     const int f = blockIdx.y;
     if (Q.bad || Q.ra[0].ctl->err || f >= Q.ra[0].ctl->n_front) return;   // uniform per block
     for (int t = threadIdx.x; t < Q.s.n_obs * 6; t += blockDim.x) s_obs[t] = Q.s.obs[t];
     __syncthreads();
-    const bool hit = mc_particle(Q.s, f, blockIdx.x * blockDim.x + threadIdx.x, s_obs);
-    const unsigned long long b = __ballot(hit);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&Q.s.mc_counts[f], (int)__popcll(b));
+    mc_block_count(Q.s, Q.s.wp + (size_t)f * (Q.s.S_max + 1) * 3, Q.s.wp_len[f],
+                   blockIdx.x * kMcParticles, s_obs, s_hit, &Q.s.mc_counts[f]);
 }
 
 // Alg. 5 bisection on the certified counts, and the per-query outcome.
@@ -357,16 +387,16 @@ __global__ __launch_bounds__(256) void k_b_smooth_wp(BatchQuery* qs, int r) {
     smooth_wp_one(Q.s, Q.sm, r, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_b_smooth_mc(BatchQuery* qs, int r) {
+__global__ __launch_bounds__(kMcThreads) void k_b_smooth_mc(BatchQuery* qs, int r) {
     __shared__ float s_obs[kMaxObs * 6];
+    __shared__ int s_hit[kMcParticles];
     const BatchQuery& Q = qs[blockIdx.z];
     const int c = blockIdx.y;
-    if (smooth_beta(*Q.sm.st, r, c) < 0.0) return;   // uniform per block
+    if (smooth_beta(*Q.sm.st, r, c) < 0.0 || Q.sm.st->K[c] < 0) return;   // uniform per block
     for (int t = threadIdx.x; t < Q.s.n_obs * 6; t += blockDim.x) s_obs[t] = Q.s.obs[t];
     __syncthreads();
-    const bool hit = smooth_mc_one(Q.s, Q.sm, r, c, blockIdx.x * blockDim.x + threadIdx.x, s_obs);
-    const unsigned long long m = __ballot(hit);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&Q.sm.st->cnt[c], (int)__popcll(m));
+    mc_block_count(Q.s, Q.sm.wp + (size_t)c * (Q.s.S_max + 1) * 3, Q.sm.st->K[c],
+                   blockIdx.x * kMcParticles, s_obs, s_hit, &Q.sm.st->cnt[c]);
 }
 
 __global__ void k_b_smooth_resolve(BatchQuery* qs, int q, int r) {
@@ -413,8 +443,11 @@ void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes
     const int vmax = std::max(max_nodes, kMaxObs);
     k_b_valid<<<dim3((vmax + 255) / 256, q), 256, 0, s>>>(qs);
     k_b_zero_ebits<<<dim3(256, q), 256, 0, s>>>(qs);
+    k_b_rm_check<<<dim3((max_nodes * 6 + 255) / 256, q), 256, 0, s>>>(qs);
     k_b_gw_near_rows<<<dim3(max_nodes, q), 256, 0, s>>>(qs);
+    k_b_gw_near_col0<<<dim3((max_nodes + 255) / 256, q), 256, 0, s>>>(qs);
     k_b_gw_boxes<<<dim3(256, q), 256, 0, s>>>(qs);
+    k_b_gw_boxes_rm<<<dim3(256, q), 256, 0, s>>>(qs);
     k_b_gw_exact<<<dim3(64, q), 256, 0, s>>>(qs);
     k_b_row_deg<<<dim3((max_nodes + 3) / 4, q), 256, 0, s>>>(qs);
     k_b_row_scan<<<q, 1024, 0, s>>>(qs);
@@ -425,13 +458,14 @@ void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes
     k_b_goal_collect<<<q, 1024, 0, s>>>(qs);
     k_b_front<<<q, 256, 0, s>>>(qs);
     k_b_waypoints<<<q, 64, 0, s>>>(qs);
-    k_b_mc<<<dim3((M + 255) / 256, kBatchFront, q), 256, 0, s>>>(qs);
+    k_b_mc<<<dim3((M + kMcParticles - 1) / kMcParticles, kBatchFront, q), kMcThreads, 0, s>>>(qs);
     k_b_finalize<<<(q + 63) / 64, 64, 0, s>>>(qs, q, out);
     if (smooth) {
         k_b_smooth_prep<<<q, 256, 0, s>>>(qs, out);
         for (int r = 0; r < kSmoothRounds; ++r) {
             k_b_smooth_wp<<<dim3((S_max + 1 + 255) / 256, kSmoothCands, q), 256, 0, s>>>(qs, r);
-            k_b_smooth_mc<<<dim3((M + 255) / 256, kSmoothCands, q), 256, 0, s>>>(qs, r);
+            k_b_smooth_mc<<<dim3((M + kMcParticles - 1) / kMcParticles, kSmoothCands, q), kMcThreads,
+                            0, s>>>(qs, r);
             k_b_smooth_resolve<<<(q + 63) / 64, 64, 0, s>>>(qs, q, r);
         }
         k_b_smooth_final<<<q, 256, 0, s>>>(qs, out);

@@ -5,13 +5,16 @@
 
 namespace pump {
 
-namespace {
-constexpr int kCoopThreads = 256;
-}
+// Workgroup size: 512 threads (two waves per SIMD with one workgroup per CU)
+// where the kernel's registers allow it, 256 for N = 256.  More waves per
+// workgroup hide the latency of the wave-per-pair phases without adding
+// workgroups to the grid barriers.
+template <int N>
+constexpr int coop_threads() { return N == 256 ? 256 : 512; }
 
 template <int N>
-__global__ __launch_bounds__(kCoopThreads) void k_explore_coop(const RoundArgs* __restrict__ ra,
-                                                              CoopArgs ca) {
+__global__ __launch_bounds__(coop_threads<N>()) void k_explore_coop(const RoundArgs* __restrict__ ra,
+                                                                   CoopArgs ca) {
     __shared__ float s_raw[kMaxObs * 6];
     __shared__ float s_in[kMaxObs * 6];
     __shared__ float s_out[kMaxObs * 6];
@@ -34,22 +37,31 @@ __global__ __launch_bounds__(kCoopThreads) void k_explore_coop(const RoundArgs* 
     explore_team<N>(ra, t, false, 0, s_raw, s_in, s_out, s_w, s_m, s_ll, &s_fail);
 }
 
+namespace {
+struct CoopFn {
+    const void* fn;
+    int threads;
+};
+CoopFn coop_fn(int N) {
+    switch (N) {
+        case 32: return {(const void*)k_explore_coop<32>, coop_threads<32>()};
+        case 64: return {(const void*)k_explore_coop<64>, coop_threads<64>()};
+        case 128: return {(const void*)k_explore_coop<128>, coop_threads<128>()};
+        default: return {(const void*)k_explore_coop<256>, coop_threads<256>()};
+    }
+}
+}  // namespace
+
 hipError_t launch_explore_coop(hipStream_t s, const RoundArgs* ra_dev, const CoopArgs& ca, int N,
                                int blocks) {
     const RoundArgs* ra = ra_dev;
     void* args[2] = {(void*)&ra, (void*)&ca};
-    const void* fn;
-    switch (N) {
-        case 32: fn = (const void*)k_explore_coop<32>; break;
-        case 64: fn = (const void*)k_explore_coop<64>; break;
-        case 128: fn = (const void*)k_explore_coop<128>; break;
-        default: fn = (const void*)k_explore_coop<256>; break;
-    }
+    const CoopFn f = coop_fn(N);
     // An ordinary launch: `blocks` never exceeds what the occupancy query
     // says fits on the device at once, so on an otherwise idle stream every
     // workgroup is resident and the barriers complete (a wait that runs out
     // of patience still ends the kernel with an error).
-    return hipLaunchKernel(fn, dim3(blocks), dim3(kCoopThreads), args, 0, s);
+    return hipLaunchKernel(f.fn, dim3(blocks), dim3(f.threads), args, 0, s);
 }
 
 int coop_max_blocks(int N) {
@@ -57,14 +69,8 @@ int coop_max_blocks(int N) {
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
         return 0;
-    const void* fn;
-    switch (N) {
-        case 32: fn = (const void*)k_explore_coop<32>; break;
-        case 64: fn = (const void*)k_explore_coop<64>; break;
-        case 128: fn = (const void*)k_explore_coop<128>; break;
-        default: fn = (const void*)k_explore_coop<256>; break;
-    }
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kCoopThreads, 0) != hipSuccess)
+    const CoopFn f = coop_fn(N);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f.fn, f.threads, 0) != hipSuccess)
         return 0;
     return per_cu * prop.multiProcessorCount;
 }

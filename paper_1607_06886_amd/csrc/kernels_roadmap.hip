@@ -15,7 +15,7 @@ __global__ __launch_bounds__(256) void k_rm_bbox(const float* __restrict__ X,
 __global__ __launch_bounds__(256) void k_rm_check(const float* __restrict__ X,
                                                   const float* __restrict__ Xr, int n_nodes,
                                                   int32_t* __restrict__ bad) {
-    rm_check_dev(X, Xr, n_nodes, bad);
+    rm_check_dev(X, Xr, n_nodes, bad, 4);
 }
 
 __global__ __launch_bounds__(256) void k_rm_fill(const float* __restrict__ X, int n_nodes,

@@ -24,20 +24,20 @@ void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths) {
     k_waypoints<<<(n_paths + 63) / 64, 64, 0, s>>>(a, n_paths);
 }
 
-__global__ __launch_bounds__(256) void k_mc(SelectArgs a) {
+__global__ __launch_bounds__(kMcThreads) void k_mc(SelectArgs a) {
     __shared__ float s_obs[kMaxObs * 6];
+    __shared__ int s_hit[kMcParticles];
     for (int t = threadIdx.x; t < a.n_obs * 6; t += blockDim.x) s_obs[t] = a.obs[t];
     __syncthreads();
     const int f = blockIdx.y;
-    const bool hit = mc_particle(a, f, blockIdx.x * blockDim.x + threadIdx.x, s_obs);
-    const unsigned long long b = __ballot(hit);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&a.mc_counts[f], (int)__popcll(b));
+    mc_block_count(a, a.wp + (size_t)f * (a.S_max + 1) * 3, a.wp_len[f], blockIdx.x * kMcParticles,
+                   s_obs, s_hit, &a.mc_counts[f]);
 }
 
 void launch_mc(hipStream_t s, const SelectArgs& a, int32_t n_paths) {
     if (n_paths <= 0) return;
-    dim3 grid((a.M + 255) / 256, n_paths);
-    k_mc<<<grid, 256, 0, s>>>(a);
+    dim3 grid((a.M + kMcParticles - 1) / kMcParticles, n_paths);
+    k_mc<<<grid, kMcThreads, 0, s>>>(a);
 }
 
 // ---- Smooth(p*, alpha) ----
@@ -50,14 +50,15 @@ __global__ __launch_bounds__(256) void k_smooth_wp(SelectArgs a, SmoothBuf b, in
     smooth_wp_one(a, b, r, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_smooth_mc(SelectArgs a, SmoothBuf b, int r) {
+__global__ __launch_bounds__(kMcThreads) void k_smooth_mc(SelectArgs a, SmoothBuf b, int r) {
     __shared__ float s_obs[kMaxObs * 6];
+    __shared__ int s_hit[kMcParticles];
+    const int c = blockIdx.y;
+    if (smooth_beta(*b.st, r, c) < 0.0 || b.st->K[c] < 0) return;   // uniform per block
     for (int t = threadIdx.x; t < a.n_obs * 6; t += blockDim.x) s_obs[t] = a.obs[t];
     __syncthreads();
-    const int c = blockIdx.y;
-    const bool hit = smooth_mc_one(a, b, r, c, blockIdx.x * blockDim.x + threadIdx.x, s_obs);
-    const unsigned long long m = __ballot(hit);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&b.st->cnt[c], (int)__popcll(m));
+    mc_block_count(a, b.wp + (size_t)c * (a.S_max + 1) * 3, b.st->K[c], blockIdx.x * kMcParticles,
+                   s_obs, s_hit, &b.st->cnt[c]);
 }
 
 __global__ void k_smooth_resolve(SelectArgs a, SmoothBuf b, double alpha, int r) {
@@ -74,7 +75,8 @@ void launch_smooth(hipStream_t s, const SelectArgs& a, const SmoothBuf& b, int f
     k_smooth_prep<<<1, 256, 0, s>>>(a, b, f_best, plan_cost);
     for (int r = 0; r < kSmoothRounds; ++r) {
         k_smooth_wp<<<dim3((a.S_max + 1 + 255) / 256, kSmoothCands), 256, 0, s>>>(a, b, r);
-        k_smooth_mc<<<dim3((a.M + 255) / 256, kSmoothCands), 256, 0, s>>>(a, b, r);
+        k_smooth_mc<<<dim3((a.M + kMcParticles - 1) / kMcParticles, kSmoothCands), kMcThreads, 0,
+                      s>>>(a, b, r);
         k_smooth_resolve<<<1, 64, 0, s>>>(a, b, alpha, r);
     }
     k_smooth_final<<<1, 256, 0, s>>>(a, b, plan_count, plan_steps);

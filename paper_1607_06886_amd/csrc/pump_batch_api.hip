@@ -56,6 +56,7 @@ struct pump_batch {
     int* counter = nullptr;
     std::vector<BatchQuery> qs;
     std::vector<BatchOut> outs;
+    std::vector<const pump_roadmap*> rms;   // per query (pump_batch_set_roadmaps)
     std::string err;
 };
 
@@ -253,6 +254,14 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         Q.team_sync = s.team_sync;
         Q.team_tot = s.team_tot;
         Q.sm = SmoothBuf{s.sm_st, s.sm_coef, s.sm_t0, s.sm_wp, s.sm_out};
+        const pump_roadmap* rm = i < (int)b->rms.size() ? b->rms[i] : nullptr;
+        if (rm) {
+            if (rm->n != pr.n)
+                return bfail(b, PUMP_E_ARG, "query " + std::to_string(i) + ": roadmap has " +
+                                                std::to_string(rm->n) + " samples");
+            Q.use_rm = 1;
+            Q.rm = rm->d;
+        }
         Q.X = s.X; Q.obs = s.obs; Q.valid = s.valid; Q.goal = s.goal; Q.ebits = s.ebits;
         Q.deg = s.deg; Q.row_ptr = s.row_ptr; Q.col = s.col; Q.esrc = s.esrc; Q.etau = s.etau;
         Q.ecost = s.ecost; Q.b_deg = s.b_deg; Q.open_a = s.open_a; Q.open_b = s.open_b;
@@ -476,3 +485,18 @@ int pump_batch_tune(pump_batch* b, const pump_problem* probs, const int32_t* n_p
 const char* pump_batch_last_error(const pump_batch* b) { return b ? b->err.c_str() : ""; }
 
 }  // extern "C"
+
+int pump_batch_set_roadmaps(pump_batch* b, const pump_roadmap* const* rms, int32_t n) {
+    if (!b || n < 0 || (n > 0 && !rms)) return PUMP_E_ARG;
+    std::vector<const pump_roadmap*> v(rms, rms + n);
+    for (int i = 0; i < n; ++i) {
+        const pump_roadmap* rm = v[i];
+        if (!rm) continue;
+        if (rm->r_steer != b->cfg.r_steer || rm->r_conn != b->cfg.r_conn)
+            return bfail(b, PUMP_E_ARG, "roadmap " + std::to_string(i) + ": radii differ from the batch's");
+        if (rm->n + 1 > b->cfg.max_nodes)
+            return bfail(b, PUMP_E_ARG, "roadmap " + std::to_string(i) + ": more samples than max_nodes - 1");
+    }
+    b->rms = std::move(v);
+    return PUMP_OK;
+}

@@ -325,6 +325,8 @@ struct BatchQuery {
     int32_t cap_pairs, cap_edges;
     int32_t bad;               // input / capacity errors (bit flags)
     int32_t gcount[4];         // graph-build work-list counters (zero on upload)
+    int32_t use_rm;            // 1: the graph comes from `rm` (cached roadmap)
+    RoadmapDev rm;
     float* X;
     float* obs;
     uint8_t* valid;

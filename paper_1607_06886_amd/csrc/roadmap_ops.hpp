@@ -27,13 +27,13 @@ __device__ __forceinline__ void rm_bbox_dev(const float* __restrict__ X, const i
     }
 }
 
-// Samples of the query (nodes 1..n of X) equal to the roadmap's?  Sets bit 4
-// of *bad otherwise.
+// Samples of the query (nodes 1..n of X) equal to the roadmap's?  Sets
+// `bit` in *bad otherwise.
 __device__ __forceinline__ void rm_check_dev(const float* __restrict__ X, const float* __restrict__ Xr,
-                                             int n_nodes, int32_t* __restrict__ bad) {
+                                             int n_nodes, int32_t* __restrict__ bad, int bit) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 6 || t >= n_nodes * 6) return;
-    if (__float_as_uint(X[t]) != __float_as_uint(Xr[t])) atomicOr(bad, 4);
+    if (__float_as_uint(X[t]) != __float_as_uint(Xr[t])) atomicOr(bad, bit);
 }
 
 // tau* and c* of each final edge: cached for sample-to-sample edges (binary

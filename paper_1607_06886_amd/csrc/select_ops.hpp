@@ -142,17 +142,18 @@ __device__ __forceinline__ void waypoints_one(const SelectArgs& a, int f) {
     a.wp_len[f] = ok ? s : -1;
 }
 
-// Does the segment prev -> cur meet a closed obstacle box?  Slab clipping in
-// FP64 after a bounding-box reject.
+// Does the segment prev -> cur meet one of the closed obstacle boxes
+// o0, o0 + ostep, ...?  Slab clipping in FP64 after a bounding-box reject.
 __device__ __forceinline__ bool segment_hits_boxes(const double prev[3], const double cur[3],
-                                                   const float* s_obs, int n_obs) {
+                                                   const float* s_obs, int n_obs, int o0,
+                                                   int ostep) {
     double smin[3], smax[3];
     for (int ax = 0; ax < 3; ++ax) {
         smin[ax] = fmin(prev[ax], cur[ax]);
         smax[ax] = fmax(prev[ax], cur[ax]);
     }
     bool hit = false;
-    for (int o = 0; o < n_obs && !hit; ++o) {
+    for (int o = o0; o < n_obs && !hit; o += ostep) {
         const float* b = s_obs + o * 6;
         // a segment whose bounding box misses the box misses the box
         if ((smax[0] < (double)b[0]) | (smin[0] > (double)b[3]) | (smax[1] < (double)b[1]) |
@@ -182,7 +183,7 @@ __device__ __forceinline__ bool segment_hits_boxes(const double prev[3], const d
 // waypoint positions plus deviations; it collides iff a segment meets a
 // closed obstacle box (slab clipping, FP64).
 __device__ __forceinline__ bool mc_particle_lqr(const SelectArgs& a, const double* wp, int S,
-                                                int m, const float* s_obs) {
+                                                int m, const float* s_obs, int o0, int ostep) {
     double dp[3] = {0.0, 0.0, 0.0}, dv[3] = {0.0, 0.0, 0.0};
     double prev[3] = {wp[0], wp[1], wp[2]};
     const double a00 = a.Acl[0], a01 = a.Acl[1], a10 = a.Acl[2], a11 = a.Acl[3];
@@ -199,7 +200,7 @@ __device__ __forceinline__ bool mc_particle_lqr(const SelectArgs& a, const doubl
             dv[ax] = vn;
             cur[ax] = wp[(size_t)(s + 1) * 3 + ax] + pn;
         }
-        hit = segment_hits_boxes(prev, cur, s_obs, a.n_obs);
+        hit = segment_hits_boxes(prev, cur, s_obs, a.n_obs, o0, ostep);
         prev[0] = cur[0]; prev[1] = cur[1]; prev[2] = cur[2];
     }
     return hit;
@@ -208,7 +209,7 @@ __device__ __forceinline__ bool mc_particle_lqr(const SelectArgs& a, const doubl
 // The same under LQG tracking: per axis the particle carries (dp, dv, p_hat,
 // v_hat), driven by its two process normals and its measurement normal.
 __device__ __forceinline__ bool mc_particle_lqg(const SelectArgs& a, const double* wp, int S,
-                                                int m, const float* s_obs) {
+                                                int m, const float* s_obs, int o0, int ostep) {
     double z[3][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     double prev[3] = {wp[0], wp[1], wp[2]};
     bool hit = false;
@@ -221,21 +222,39 @@ __device__ __forceinline__ bool mc_particle_lqg(const SelectArgs& a, const doubl
             lqg_step(a.lqg, z[ax], w0, w1, w2);
             cur[ax] = wp[(size_t)(s + 1) * 3 + ax] + z[ax][0];
         }
-        hit = segment_hits_boxes(prev, cur, s_obs, a.n_obs);
+        hit = segment_hits_boxes(prev, cur, s_obs, a.n_obs, o0, ostep);
         prev[0] = cur[0]; prev[1] = cur[1]; prev[2] = cur[2];
     }
     return hit;
 }
 
 __device__ __forceinline__ bool mc_particle_wp(const SelectArgs& a, const double* wp, int S, int m,
-                                               const float* s_obs) {
+                                               const float* s_obs, int o0, int ostep) {
     if (m >= a.M || S < 0) return false;
-    return a.estimator ? mc_particle_lqg(a, wp, S, m, s_obs) : mc_particle_lqr(a, wp, S, m, s_obs);
+    return a.estimator ? mc_particle_lqg(a, wp, S, m, s_obs, o0, ostep)
+                       : mc_particle_lqr(a, wp, S, m, s_obs, o0, ostep);
 }
 
-// MC(p) for particle m of front path f.
-__device__ __forceinline__ bool mc_particle(const SelectArgs& a, int f, int m, const float* s_obs) {
-    return mc_particle_wp(a, a.wp + (size_t)f * (a.S_max + 1) * 3, a.wp_len[f], m, s_obs);
+// MC(p) over waypoints wp[0..S] for the 64 particles m_base .. m_base + 63,
+// one workgroup of kMcThreads: wave w tests the boxes w, w + 4, ... (each
+// wave follows all 64 particles through the same recurrence), the per-wave
+// hits are ORed in LDS and their count added to *count.  s_obs holds the
+// boxes, s_hit 64 flags.
+constexpr int kMcThreads = 256;
+constexpr int kMcParticles = 64;
+
+__device__ __forceinline__ void mc_block_count(const SelectArgs& a, const double* wp, int S,
+                                               int m_base, const float* s_obs, int* s_hit,
+                                               int* count) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x < kMcParticles) s_hit[threadIdx.x] = 0;
+    __syncthreads();
+    if (mc_particle_wp(a, wp, S, m_base + lane, s_obs, w, kMcThreads / 64)) s_hit[lane] = 1;
+    __syncthreads();
+    if (w == 0) {
+        const unsigned long long b = __ballot(s_hit[lane] != 0);
+        if (lane == 0 && b) atomicAdd(count, (int)__popcll(b));
+    }
 }
 
 }  // namespace pump

@@ -136,14 +136,6 @@ __device__ __forceinline__ void smooth_wp_one(const SelectArgs& a, const SmoothB
     o[0] = p[0]; o[1] = p[1]; o[2] = p[2];
 }
 
-// One certification particle of candidate c (uniform per block).
-__device__ __forceinline__ bool smooth_mc_one(const SelectArgs& a, const SmoothBuf& b, int r, int c,
-                                              int m, const float* s_obs) {
-    const SmoothState& st = *b.st;
-    if (smooth_beta(st, r, c) < 0.0 || st.K[c] < 0) return false;
-    return mc_particle_wp(a, b.wp + (size_t)c * (a.S_max + 1) * 3, st.K[c], m, s_obs);
-}
-
 // Replay of round r's three bisection levels (one thread).
 __device__ __forceinline__ void smooth_resolve_one(const SelectArgs& a, double alpha,
                                                    const SmoothBuf& b, int r) {

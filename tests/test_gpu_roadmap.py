@@ -97,3 +97,48 @@ def test_roadmap_mismatches_are_rejected():
         pl2.set_roadmap(rm)
     pl2.close()
     rm.close()
+
+
+def test_batched_queries_with_roadmaps():
+    """The batched engine with per-query roadmaps (two queries share one,
+    one has none, one has samples that differ from its roadmap's) equals the
+    scratch build query by query."""
+    import torch
+    print_case("roadmap_batch")
+    base = scene("n64", 4)
+    other = scene("cfg1", 0)
+    rng = np.random.default_rng(9)
+    lo = rng.uniform(0.2, 0.7, (6, 3))
+    boxes2 = np.concatenate([lo, lo + 0.1], 1).astype(np.float32)
+    scs = [base, dataclasses.replace(base, obstacles=boxes2), other, base]
+    rm_a = _lib.Roadmap(base.samples, max_nodes=base.n + 1, cap_edges=1 << 24)
+    rm_b = _lib.Roadmap(other.samples, max_nodes=other.n + 1, cap_edges=1 << 24)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    qs = [(t(s.samples), t(np.asarray(s.obstacles, np.float32).reshape(-1, 6)), s.x_init, s.goal,
+           s.alpha, s.sigma, t(s.noise), t(s.noise_mc)) for s in scs]
+    bad = list(qs[3])
+    smp = base.samples.copy()
+    smp[3, 0] += np.float32(1e-3)
+    bad[0] = t(smp)
+    qs[3] = tuple(bad)
+    b = _lib.Batch(len(scs), n_particles=max(s.N for s in scs),
+                   max_nodes=max(s.n for s in scs) + 1,
+                   max_obstacles=max(s.n_obs for s in scs), max_steps=base.S_max,
+                   mc_particles=base.M, cap_plans=1 << 20, cap_pairs=1 << 22, cap_edges=1 << 24)
+    b.set_roadmaps([rm_a, rm_a, None, rm_a])
+    res = b.plan(qs, raise_on_error=False)
+    for i in range(3):
+        _, ref, path = _graph_and_result(scs[i])
+        for k in SAME:
+            assert res[i][k] == ref[k], (i, k)
+        if path is not None:
+            assert b.path(i, res[i]["best_plan"]) == path
+    assert res[3]["status"] == _lib.PUMP_E_ARG
+    b.set_roadmaps([None, None, rm_b])
+    res2 = b.plan(qs[:3])
+    for i in range(3):
+        for k in SAME:
+            assert res2[i][k] == res[i][k], (i, k)
+    b.close()
+    rm_a.close()
+    rm_b.close()
