@@ -243,21 +243,25 @@ __device__ __forceinline__ void crossing(const Cubic& c, double ta, double tb, d
     }
 }
 
-// The set {t in [0, tau] : lo <= p(t) <= hi} as <= 3 closed intervals.
-__device__ __forceinline__ int slab_set(const Cubic& c, double tau, double lo, double hi,
-                                        double* s, double* e) {
+// The set {t in [0, tau] : lo <= p(t) <= hi} as up to 3 closed intervals,
+// one per monotone piece between the stationary points: interval k is
+// [s[k], e[k]] when ok[k].  Fixed slots (no dynamic indexing), so the
+// intervals stay in registers.
+__device__ __forceinline__ void slab_set(const Cubic& c, double tau, double lo, double hi,
+                                         double* s, double* e, bool* ok) {
     double br[2];
-    int nb = stationary_points(c, tau, br);
-    double edges[4];
-    edges[0] = 0.0;
-    for (int k = 0; k < nb; ++k) edges[1 + k] = br[k];
-    edges[1 + nb] = tau;
-    int n = 0;
-    for (int k = 0; k <= nb; ++k) {
-        double ta = edges[k], tb = edges[k + 1];
-        double pa = c.at(ta), pb = c.at(tb);
-        bool rising = pb >= pa;
-        double pmin = fmin(pa, pb), pmax = fmax(pa, pb);
+    const int nb = stationary_points(c, tau, br);
+    const double edge[4] = {0.0, nb > 0 ? br[0] : tau, nb > 1 ? br[1] : tau, tau};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        ok[k] = false;
+        s[k] = 0.0;
+        e[k] = 0.0;
+        if (k > nb) continue;
+        const double ta = k == 0 ? 0.0 : edge[k], tb = k == nb ? tau : edge[k + 1];
+        const double pa = c.at(ta), pb = c.at(tb);
+        const bool rising = pb >= pa;
+        const double pmin = fmin(pa, pb), pmax = fmax(pa, pb);
         if (!(pmax >= lo && pmin <= hi)) continue;
         double l0, l1, h0, h1;
         double st, en;
@@ -268,9 +272,10 @@ __device__ __forceinline__ int slab_set(const Cubic& c, double tau, double lo, d
             if (pmax <= hi) st = ta; else { crossing(c, ta, tb, hi, false, h0, h1); st = h1; }
             if (pmin >= lo) en = tb; else { crossing(c, ta, tb, lo, false, l0, l1); en = l0; }
         }
-        s[n] = st; e[n] = en; ++n;
+        s[k] = st;
+        e[k] = en;
+        ok[k] = true;
     }
-    return n;
 }
 
 // Range of a cubic over [0, tau] (endpoints and stationary points).
@@ -369,19 +374,24 @@ __device__ __forceinline__ int trajectory_box_quick(const Cubic* cs, double tau,
 __device__ __forceinline__ bool trajectory_hits_box_exact(const Cubic* cs, double tau,
                                                           const float* box) {
     double s[3][3], e[3][3];
-    int n[3];
+    bool ok[3][3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        n[a] = slab_set(cs[a], tau, (double)box[a], (double)box[3 + a], s[a], e[a]);
-        if (n[a] == 0) return false;
+        slab_set(cs[a], tau, (double)box[a], (double)box[3 + a], s[a], e[a], ok[a]);
+        if (!(ok[a][0] || ok[a][1] || ok[a][2])) return false;
     }
-    for (int i = 0; i < n[0]; ++i)
-        for (int j = 0; j < n[1]; ++j)
-            for (int k = 0; k < n[2]; ++k) {
-                double st = fmax(fmax(s[0][i], s[1][j]), s[2][k]);
-                double en = fmin(fmin(e[0][i], e[1][j]), e[2][k]);
-                if (st <= en) return true;
+    bool hit = false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double st = fmax(fmax(s[0][i], s[1][j]), s[2][k]);
+                const double en = fmin(fmin(e[0][i], e[1][j]), e[2][k]);
+                hit |= ok[0][i] && ok[1][j] && ok[2][k] && st <= en;
             }
-    return false;
+    return hit;
 }
 
 __device__ __forceinline__ bool trajectory_hits_box(const Cubic* cs, double tau, const float* box) {
