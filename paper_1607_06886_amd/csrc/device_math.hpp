@@ -332,8 +332,13 @@ __device__ __forceinline__ void eval_pd(const Cubic* cs, double t, double* p, do
     }
 }
 
-__device__ __forceinline__ int trajectory_box_quick(const Cubic* cs, double tau, const float* box) {
-    const double h = 0.125 * tau;
+// The piecewise test with `pieces` equal pieces (each split into 4 when its
+// hull meets the box).  The quick test uses 8 pieces; the exact stage first
+// tries 64 before solving for the slab crossings.
+__device__ __forceinline__ int trajectory_box_pieces(const Cubic* cs, double tau, const float* box,
+                                                     int pieces) {
+    const double inv = 1.0 / (double)pieces;
+    const double h = inv * tau;
     const double h3 = h * (1.0 / 3.0);          // piece length / 3 (within the margin)
     const double q3 = 0.25 * h3;                // the same for a quarter piece
     double pa[3], da[3];
@@ -342,12 +347,12 @@ __device__ __forceinline__ int trajectory_box_quick(const Cubic* cs, double tau,
         da[a] = cs[a].c1;
     }
     bool ambiguous = false;
-    for (int k = 1; k <= 8; ++k) {
-        const double ta = tau * (0.125 * (double)(k - 1));
-        const double t = k == 8 ? tau : tau * (0.125 * (double)k);
+    for (int k = 1; k <= pieces; ++k) {
+        const double ta = tau * (inv * (double)(k - 1));
+        const double t = k == pieces ? tau : tau * (inv * (double)k);
         double pb[3], db[3];
         eval_pd(cs, t, pb, db);
-        if (k < 8 && point_in_box(pb, box)) return kBoxHit;
+        if (k < pieces && point_in_box(pb, box)) return kBoxHit;
         if (!piece_clear(pa, da, pb, db, h3, box)) {
             // split the piece into 4
             double qa[3] = {pa[0], pa[1], pa[2]}, qd[3] = {da[0], da[1], da[2]};
@@ -369,6 +374,10 @@ __device__ __forceinline__ int trajectory_box_quick(const Cubic* cs, double tau,
         }
     }
     return ambiguous ? kBoxUnsure : kBoxMiss;
+}
+
+__device__ __forceinline__ int trajectory_box_quick(const Cubic* cs, double tau, const float* box) {
+    return trajectory_box_pieces(cs, tau, box, 8);
 }
 
 __device__ __forceinline__ bool trajectory_hits_box_exact(const Cubic* cs, double tau,

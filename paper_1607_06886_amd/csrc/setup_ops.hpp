@@ -292,8 +292,9 @@ __device__ __forceinline__ void mark_valid_dev(const float* __restrict__ X, int 
 //           box and, where they meet, the quick trajectory-box test; a hit
 //           blocks it, an unsure case goes to the exact queue; connections
 //           not blocked set their bit;
-//   exact   the exact trajectory-box test per queued (connection, box); a
-//           hit clears the bit;
+//   exact   per queued (connection, box) the piecewise test with 64 pieces
+//           and, if still unsure, the exact trajectory-box test; a hit
+//           clears the bit;
 //   degree  popcount of each row.
 // A connection's bit ends set iff no box blocks it, the decision of the exact
 // test on every box its range meets.
@@ -457,7 +458,10 @@ __device__ __forceinline__ void gw_exact(const float* __restrict__ X, const floa
         }
         Cubic cs[3];
         hermite(X + (size_t)src * 6, X + (size_t)dst * 6, tau, cs);
-        if (trajectory_hits_box_exact(cs, tau, obs + (size_t)gw.xq_box[i] * 6))
+        // 64 pieces settle most of the queued cases without solving for crossings
+        const float* box = obs + (size_t)gw.xq_box[i] * 6;
+        const int q = trajectory_box_pieces(cs, tau, box, 64);
+        if (q == kBoxHit || (q == kBoxUnsure && trajectory_hits_box_exact(cs, tau, box)))
             atomicAnd(&ebits[(size_t)src * words + (dst >> 5)], ~(1u << (dst & 31)));
     }
 }
