@@ -389,11 +389,21 @@ __device__ __forceinline__ void gw_boxes(const float* __restrict__ X,
                                          bool check_valid, const float* s_obs, int n_obs,
                                          const GraphWork& gw, uint32_t* __restrict__ ebits,
                                          int words, int gid, int stride) {
-    for (int i = gid; i < count; i += stride) {
-        const int src = src_a[i], dst = dst_a[i];
-        if (check_valid && !(valid[src] && valid[dst])) continue;
-        bool blocked = false;
-        if (n_obs > 0) {
+    // all lanes of a wave iterate together (stride is a multiple of 64), so the
+    // exact-queue slots are claimed with one atomic per wave
+    const int lane = threadIdx.x & 63;
+    for (int base = gid - lane; base < count; base += stride) {
+        const int i = base + lane;
+        bool keep = i < count;
+        int src = 0, dst = 0;
+        if (keep) {
+            src = src_a[i];
+            dst = dst_a[i];
+            keep = !check_valid || (valid[src] && valid[dst]);
+        }
+        unsigned long long unsure[kMaxObs / 64] = {0ull, 0ull, 0ull, 0ull};
+        int n_uns = 0;
+        if (keep && n_obs > 0) {
             const double tau = tau_a[i];
             const float* xs = X + (size_t)src * 6;
             const float* xd = X + (size_t)dst * 6;
@@ -408,34 +418,49 @@ __device__ __forceinline__ void gw_boxes(const float* __restrict__ X,
             } else {
                 for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
             }
-            unsigned long long unsure[kMaxObs / 64] = {0ull, 0ull, 0ull, 0ull};
-            for (int o = 0; o < n_obs && !blocked; ++o) {
+            for (int o = 0; o < n_obs && keep; ++o) {
                 const float* bx = s_obs + o * 6;
                 bool disjoint = false;
                 for (int a = 0; a < 3; ++a)
                     disjoint |= (mx[a] < (double)bx[a]) | (mn[a] > (double)bx[3 + a]);
                 if (disjoint) continue;
                 const int q = trajectory_box_quick(cs, tau, bx);
-                if (q == kBoxHit) blocked = true;
-                else if (q == kBoxUnsure) unsure[o >> 6] |= 1ull << (o & 63);
-            }
-            if (!blocked) {
-                const int tag = near_list ? -1 - i : i;
-                for (int w = 0; w < kMaxObs / 64; ++w) {
-                    unsigned long long m = unsure[w];
-                    while (m) {
-                        const int o = w * 64 + __ffsll((long long)m) - 1;
-                        m &= m - 1ull;
-                        const int slot = atomicAdd(gw.counts + 1, 1);
-                        if (slot < gw.xq_cap) {
-                            gw.xq_edge[slot] = tag;
-                            gw.xq_box[slot] = o;
-                        }
-                    }
+                if (q == kBoxHit) {
+                    keep = false;
+                } else if (q == kBoxUnsure) {
+                    unsure[o >> 6] |= 1ull << (o & 63);
+                    ++n_uns;
                 }
             }
         }
-        if (!blocked) atomicOr(&ebits[(size_t)src * words + (dst >> 5)], 1u << (dst & 31));
+        // wave-wide exclusive scan of the queued counts
+        const int cnt = keep ? n_uns : 0;
+        int x = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const int total = __shfl(x, 63, 64);
+        int slot0 = 0;
+        if (lane == 63 && total > 0) slot0 = atomicAdd(gw.counts + 1, total);
+        slot0 = __shfl(slot0, 63, 64);
+        if (cnt > 0) {
+            int slot = slot0 + x - cnt;
+            const int tag = near_list ? -1 - i : i;
+            for (int w = 0; w < kMaxObs / 64; ++w) {
+                unsigned long long m = unsure[w];
+                while (m) {
+                    const int o = w * 64 + __ffsll((long long)m) - 1;
+                    m &= m - 1ull;
+                    if (slot < gw.xq_cap) {
+                        gw.xq_edge[slot] = tag;
+                        gw.xq_box[slot] = o;
+                    }
+                    ++slot;
+                }
+            }
+        }
+        if (keep) atomicOr(&ebits[(size_t)src * words + (dst >> 5)], 1u << (dst & 31));
     }
 }
 
