@@ -292,9 +292,9 @@ __device__ __forceinline__ void mark_valid_dev(const float* __restrict__ X, int 
 //           box and, where they meet, the quick trajectory-box test; a hit
 //           blocks it, an unsure case goes to the exact queue; connections
 //           not blocked set their bit;
-//   exact   per queued (connection, box) the piecewise test with 64 pieces
-//           and, if still unsure, the exact trajectory-box test; a hit
-//           clears the bit;
+//   exact   per queued (connection, box), one wave: the piecewise test with
+//           64 pieces across the lanes and, if still unsure, the exact
+//           trajectory-box test; a hit clears the bit;
 //   degree  popcount of each row.
 // A connection's bit ends set iff no box blocks it, the decision of the exact
 // test on every box its range meets.
@@ -471,8 +471,14 @@ __device__ __forceinline__ void gw_exact(const float* __restrict__ X, const floa
                                          const double* __restrict__ rm_tau,
                                          uint32_t* __restrict__ ebits, int words, int gid,
                                          int stride) {
+    // One wave per queued (connection, box); lane k takes piece k of 64 (the
+    // piecewise test of trajectory_box_pieces, its pieces side by side), and
+    // only if no piece proves a hit and some piece stays unsure does the wave
+    // solve for the slab crossings (all lanes in step on the same inputs).
+    constexpr int kPieces = 64;
+    const int lane = threadIdx.x & 63;
     const int N = min(gw.counts[1], gw.xq_cap);
-    for (int i = gid; i < N; i += stride) {
+    for (int i = gid >> 6; i < N; i += stride >> 6) {
         const int tag = gw.xq_edge[i];
         int src, dst;
         double tau;
@@ -483,10 +489,34 @@ __device__ __forceinline__ void gw_exact(const float* __restrict__ X, const floa
         }
         Cubic cs[3];
         hermite(X + (size_t)src * 6, X + (size_t)dst * 6, tau, cs);
-        // 64 pieces settle most of the queued cases without solving for crossings
         const float* box = obs + (size_t)gw.xq_box[i] * 6;
-        const int q = trajectory_box_pieces(cs, tau, box, 64);
-        if (q == kBoxHit || (q == kBoxUnsure && trajectory_hits_box_exact(cs, tau, box)))
+        const double inv = 1.0 / (double)kPieces;
+        const double h = inv * tau;
+        const double h3 = h * (1.0 / 3.0), q3 = 0.25 * h3;
+        const double ta = tau * (inv * (double)lane);
+        const double tb = lane == kPieces - 1 ? tau : tau * (inv * (double)(lane + 1));
+        double pa[3], da[3], pb[3], db[3];
+        eval_pd(cs, ta, pa, da);
+        eval_pd(cs, tb, pb, db);
+        bool hit = lane < kPieces - 1 && point_in_box(pb, box);
+        bool unsure = false;
+        if (!hit && !piece_clear(pa, da, pb, db, h3, box)) {
+            double qa[3] = {pa[0], pa[1], pa[2]}, qd[3] = {da[0], da[1], da[2]};
+            for (int j = 1; j <= 4 && !hit; ++j) {
+                double qb[3], qe[3];
+                if (j == 4) {
+                    for (int a = 0; a < 3; ++a) { qb[a] = pb[a]; qe[a] = db[a]; }
+                } else {
+                    eval_pd(cs, ta + 0.25 * (double)j * h, qb, qe);
+                    hit = point_in_box(qb, box);
+                }
+                unsure |= !piece_clear(qa, qd, qb, qe, q3, box);
+                for (int a = 0; a < 3; ++a) { qa[a] = qb[a]; qd[a] = qe[a]; }
+            }
+        }
+        bool blocked = __ballot(hit) != 0ull;
+        if (!blocked && __ballot(unsure) != 0ull) blocked = trajectory_hits_box_exact(cs, tau, box);
+        if (blocked && lane == 0)
             atomicAnd(&ebits[(size_t)src * words + (dst >> 5)], ~(1u << (dst & 31)));
     }
 }
