@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_b_gw_boxes_rm(BatchQuery* qs) {
              gridDim.x * blockDim.x);
 }
 
-__global__ __launch_bounds__(256) void k_b_gw_near_rows(BatchQuery* qs) {
+__global__ __launch_bounds__(kNearThreads) void k_b_gw_near_rows(BatchQuery* qs) {
     __shared__ int s_list[kNearChunk];
     __shared__ int s_cnt;
     BatchQuery& Q = qs[blockIdx.y];
@@ -215,8 +215,12 @@ __global__ __launch_bounds__(256) void k_b_edge_steer(BatchQuery* qs) {
 // waits for slots that running workgroups will pop after their current work;
 // with every workgroup resident (the launch is sized by occupancy) the queue
 // drains.  A query's team sync words and totals were zeroed by k_b_reset.
-__global__ __launch_bounds__(256) void k_b_explore(BatchQuery* qs, BatchSched sch, int* counter,
-                                                   BatchOut* outs) {
+// One kernel per particle count N (a schedule holds only queries of that N),
+// so each gets the registers its own N needs: two workgroups of 256 per CU
+// fit for N <= 128, one for N = 256.
+template <int N>
+__global__ __launch_bounds__(256, N == 256 ? 1 : 2) void k_b_explore(BatchQuery* qs, BatchSched sch,
+                                                                    int* counter, BatchOut* outs) {
     __shared__ float s_raw[kMaxObs * 6];
     __shared__ float s_in[kMaxObs * 6];
     __shared__ float s_out[kMaxObs * 6];
@@ -254,12 +258,7 @@ __global__ __launch_bounds__(256) void k_b_explore(BatchQuery* qs, BatchSched sc
         t.open_cur = Q.open_a;
         t.open_next = Q.open_b;
         t.cap_pairs = Q.cap_pairs;
-        switch (Q.N) {
-            case 32: explore_team<32>(Q.ra, t, true, Q.n_nodes, s_raw, s_in, s_out, s_w, s_m, s_ll, &s_fail); break;
-            case 64: explore_team<64>(Q.ra, t, true, Q.n_nodes, s_raw, s_in, s_out, s_w, s_m, s_ll, &s_fail); break;
-            case 128: explore_team<128>(Q.ra, t, true, Q.n_nodes, s_raw, s_in, s_out, s_w, s_m, s_ll, &s_fail); break;
-            default: explore_team<256>(Q.ra, t, true, Q.n_nodes, s_raw, s_in, s_out, s_w, s_m, s_ll, &s_fail); break;
-        }
+        explore_team<N>(Q.ra, t, true, Q.n_nodes, s_raw, s_in, s_out, s_w, s_m, s_ll, &s_fail);
         if (t.rank == 0 && threadIdx.x == 0) {
             const Ctl* c = Q.ra[0].ctl;
             BatchOut& o = outs[qi];
@@ -418,17 +417,17 @@ __global__ __launch_bounds__(256) void k_b_smooth_final(BatchQuery* qs, BatchOut
     }
 }
 
-// Queue counter and every query's team barrier words and totals to zero.
+// Queue counters and every query's team barrier words and totals to zero.
 __global__ void k_b_reset(BatchQuery* qs, int* counter) {
     const BatchQuery& Q = qs[blockIdx.x];
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+    if (threadIdx.x < kBatchGroups && blockIdx.x == 0) counter[threadIdx.x] = 0;
     for (int t = threadIdx.x; t < 64 + kMaxTeam; t += blockDim.x) Q.team_sync[t] = 0u;
     for (int t = threadIdx.x; t < 2 * kMaxTeam; t += blockDim.x) Q.team_tot[t] = 0;
 }
 
 void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes, int S_max, int M,
-                  int words, int explore_blocks, int explore_threads, int* counter, BatchOut* out,
-                  const BatchSched& sch, bool smooth) {
+                  int words, int explore_threads, int* counter, BatchOut* out,
+                  const BatchGroup* groups, int n_groups, bool smooth) {
     const int max_elems = std::max(max_nodes * 6, kMaxObs * 6);
     k_b_load<<<dim3((max_elems + 255) / 256, q), 256, 0, s>>>(qs);
     {
@@ -444,7 +443,7 @@ void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes
     k_b_valid<<<dim3((vmax + 255) / 256, q), 256, 0, s>>>(qs);
     k_b_zero_ebits<<<dim3(256, q), 256, 0, s>>>(qs);
     k_b_rm_check<<<dim3((max_nodes * 6 + 255) / 256, q), 256, 0, s>>>(qs);
-    k_b_gw_near_rows<<<dim3(max_nodes, q), 256, 0, s>>>(qs);
+    k_b_gw_near_rows<<<dim3(max_nodes, q), kNearThreads, 0, s>>>(qs);
     k_b_gw_near_col0<<<dim3((max_nodes + 255) / 256, q), 256, 0, s>>>(qs);
     k_b_gw_boxes<<<dim3(256, q), 256, 0, s>>>(qs);
     k_b_gw_boxes_rm<<<dim3(256, q), 256, 0, s>>>(qs);
@@ -454,7 +453,16 @@ void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes
     k_b_graph_fill<<<dim3((max_nodes + 3) / 4, q), 256, 0, s>>>(qs);
     k_b_edge_steer<<<dim3(256, q), 256, 0, s>>>(qs);
     k_b_reset<<<q, 64, 0, s>>>(qs, counter);
-    k_b_explore<<<explore_blocks, explore_threads, 0, s>>>(qs, sch, counter, out);
+    for (int g = 0; g < n_groups; ++g) {
+        const BatchGroup& G = groups[g];
+        int* ctr = counter + g;
+        switch (G.N) {
+            case 32: k_b_explore<32><<<G.blocks, explore_threads, 0, s>>>(qs, G.sch, ctr, out); break;
+            case 64: k_b_explore<64><<<G.blocks, explore_threads, 0, s>>>(qs, G.sch, ctr, out); break;
+            case 128: k_b_explore<128><<<G.blocks, explore_threads, 0, s>>>(qs, G.sch, ctr, out); break;
+            default: k_b_explore<256><<<G.blocks, explore_threads, 0, s>>>(qs, G.sch, ctr, out); break;
+        }
+    }
     k_b_goal_collect<<<q, 1024, 0, s>>>(qs);
     k_b_front<<<q, 256, 0, s>>>(qs);
     k_b_waypoints<<<q, 64, 0, s>>>(qs);
@@ -472,11 +480,16 @@ void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes
     }
 }
 
-int batch_explore_per_cu(int threads) {
+int batch_explore_per_cu(int N, int threads) {
+    const void* fn;
+    switch (N) {
+        case 32: fn = (const void*)k_b_explore<32>; break;
+        case 64: fn = (const void*)k_b_explore<64>; break;
+        case 128: fn = (const void*)k_b_explore<128>; break;
+        default: fn = (const void*)k_b_explore<256>; break;
+    }
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_b_explore, threads, 0) !=
-        hipSuccess)
-        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, 0) != hipSuccess) return 0;
     return n;
 }
 

@@ -87,7 +87,7 @@ void launch_mark_valid(hipStream_t s, const float* X, int n_nodes, const float* 
 }
 
 // ---- BuildGraph pass 1 stages (setup_ops.hpp) ----
-__global__ __launch_bounds__(256) void k_gw_near_rows(const float* __restrict__ X,
+__global__ __launch_bounds__(kNearThreads) void k_gw_near_rows(const float* __restrict__ X,
                                                       const uint8_t* __restrict__ valid, int n,
                                                       int row0, double r_steer, double r_conn,
                                                       GraphWork gw) {
@@ -161,7 +161,7 @@ void launch_graph_mark(hipStream_t s, const float* X, const uint8_t* valid, int 
                        const float* obs, int n_obs, double r_steer, double r_conn,
                        uint32_t* ebits, int32_t* deg, int words, const GraphWork& gw) {
     (void)hipMemsetAsync(ebits, 0, (size_t)n_nodes * words * sizeof(uint32_t), s);
-    k_gw_near_rows<<<n_nodes, 256, 0, s>>>(X, valid, n_nodes, 0, r_steer, r_conn, gw);
+    k_gw_near_rows<<<n_nodes, kNearThreads, 0, s>>>(X, valid, n_nodes, 0, r_steer, r_conn, gw);
     k_gw_boxes<<<kStageBlocks, 256, 0, s>>>(X, valid, gw.near_src, gw.near_dst, gw.near_tau,
                                             nullptr, 0, 1, obs, n_obs, gw, ebits, words);
     k_gw_exact<<<kStageBlocks, 256, 0, s>>>(X, obs, gw, nullptr, nullptr, nullptr, ebits, words);
@@ -175,7 +175,7 @@ void launch_graph_pass1_roadmap(hipStream_t s, const float* X, const uint8_t* va
                                 uint32_t* ebits, int32_t* deg, int words, const GraphWork& gw) {
     (void)hipMemsetAsync(ebits, 0, (size_t)n_nodes * words * sizeof(uint32_t), s);
     // the pairs at node 0: its row, then its column
-    k_gw_near_rows<<<1, 256, 0, s>>>(X, valid, n_nodes, 0, r_steer, r_conn, gw);
+    k_gw_near_rows<<<1, kNearThreads, 0, s>>>(X, valid, n_nodes, 0, r_steer, r_conn, gw);
     const int col = n_nodes - 1;
     k_gw_near_col0<<<(col + 255) / 256 > 0 ? (col + 255) / 256 : 1, 256, 0, s>>>(
         X, valid, n_nodes, r_steer, r_conn, gw);

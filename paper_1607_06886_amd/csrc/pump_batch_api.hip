@@ -163,8 +163,8 @@ int pump_batch_create(const pump_config* cfg_in, int32_t max_queries, void* hip_
         take(&t1, (size_t)max_queries); o_out = (size_t)t1;
         take(&t2, (size_t)max_queries); o_order = (size_t)t2;
         int* t4;
-        take(&t4, (size_t)max_queries + 1); o_off = (size_t)t4;
-        take(&t3, 1); o_counter = (size_t)t3;
+        take(&t4, (size_t)max_queries + kBatchGroups); o_off = (size_t)t4;
+        take(&t3, kBatchGroups); o_counter = (size_t)t3;
     }
     b->arena_bytes = off;
     char* base = nullptr;
@@ -299,49 +299,66 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         max_nodes = std::max(max_nodes, Q.n_nodes);
         work[i] = (double)Q.n_nodes * Q.n_nodes * sqrt((double)N);
     }
-    // Schedule of the persistent Explore kernel: entries in input order or
-    // largest first; entry i gets a team of workgroups in proportion to its
-    // share of the estimated work (team_scale / 4 times the proportional
-    // share; 0 = one workgroup per query).  Teams need every workgroup of the
-    // launch resident at once, so the launch is capped by occupancy.
-    int per_cu = t.blocks_per_cu;
-    const int fit = batch_explore_per_cu(t.explore_threads);
-    if (fit > 0 && per_cu > fit) per_cu = fit;
-    const int grid = std::max(1, b->n_cu * per_cu);
-    std::vector<int> order(q), off(q + 1, 0);
-    for (int i = 0; i < q; ++i) order[i] = i;
-    if (t.order == 1)
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
-    double wsum = 0.0;
-    for (int i = 0; i < q; ++i) wsum += work[i];
-    const int team_cap = std::min(kMaxTeam, grid);
-    for (int e = 0; e < q; ++e) {
-        int size = 1;
-        if (t.team_scale > 0 && wsum > 0.0) {
-            const double share = 0.25 * t.team_scale * grid * work[order[e]] / wsum;
-            size = (int)std::min<double>(std::max(1.0, floor(share + 0.5)), (double)team_cap);
+    // Schedules of the persistent Explore kernels, one per particle count:
+    // entries in input order or largest first; entry i gets a team of
+    // workgroups in proportion to its share of its group's estimated work
+    // (team_scale / 4 times the proportional share; 0 = one workgroup per
+    // query).  Teams need every workgroup of a launch resident at once, so
+    // each launch is capped by its kernel's occupancy.
+    std::vector<int> order, off;
+    order.reserve(q);
+    off.reserve(q + kBatchGroups);
+    BatchGroup groups[kBatchGroups];
+    int n_groups = 0;
+    const int Ns[kBatchGroups] = {256, 128, 64, 32};
+    for (int gi = 0; gi < kBatchGroups; ++gi) {
+        std::vector<int> mem;
+        for (int i = 0; i < q; ++i)
+            if (b->qs[i].N == Ns[gi]) mem.push_back(i);
+        if (mem.empty()) continue;
+        int per_cu = t.blocks_per_cu;
+        const int fit = batch_explore_per_cu(Ns[gi], t.explore_threads);
+        if (fit > 0 && per_cu > fit) per_cu = fit;
+        const int grid = std::max(1, b->n_cu * per_cu);
+        if (t.order == 1)
+            std::stable_sort(mem.begin(), mem.end(), [&](int x, int y) { return work[x] > work[y]; });
+        double wsum = 0.0;
+        for (int i : mem) wsum += work[i];
+        const int team_cap = std::min(kMaxTeam, grid);
+        BatchGroup& G = groups[n_groups++];
+        G.N = Ns[gi];
+        const int e0 = (int)order.size(), f0 = (int)off.size();
+        off.push_back(0);
+        for (int i : mem) {
+            int size = 1;
+            if (t.team_scale > 0 && wsum > 0.0) {
+                const double share = 0.25 * t.team_scale * grid * work[i] / wsum;
+                size = (int)std::min<double>(std::max(1.0, floor(share + 0.5)), (double)team_cap);
+            }
+            order.push_back(i);
+            off.push_back(off.back() + size);
         }
-        off[e + 1] = off[e] + size;
+        G.sch.query = b->order_dev + e0;
+        G.sch.off = b->off_dev + f0;
+        G.sch.n_entries = (int)mem.size();
+        G.sch.total = off.back();
+        G.blocks = std::max(1, std::min(G.sch.total, grid));
     }
-    BatchSched sch;
-    sch.query = b->order_dev;
-    sch.off = b->off_dev;
-    sch.n_entries = q;
-    sch.total = off[q];
     b->outs.assign(q, BatchOut());
     memset(b->outs.data(), 0, sizeof(BatchOut) * q);
     BCHK(hipMemcpyAsync(b->qs_dev, b->qs.data(), sizeof(BatchQuery) * q, hipMemcpyHostToDevice, b->stream));
     BCHK(hipMemcpyAsync(b->out_dev, b->outs.data(), sizeof(BatchOut) * q, hipMemcpyHostToDevice, b->stream));
-    BCHK(hipMemcpyAsync(b->order_dev, order.data(), sizeof(int) * q, hipMemcpyHostToDevice, b->stream));
-    BCHK(hipMemcpyAsync(b->off_dev, off.data(), sizeof(int) * (q + 1), hipMemcpyHostToDevice, b->stream));
-    const int blocks = std::max(1, std::min(sch.total, grid));
+    BCHK(hipMemcpyAsync(b->order_dev, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice,
+                        b->stream));
+    BCHK(hipMemcpyAsync(b->off_dev, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice,
+                        b->stream));
     auto t0 = std::chrono::steady_clock::now();
     if (t.use_graph) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         launch_batch(b->stream, b->qs_dev, q, N_max, max_nodes, cfg.max_steps, cfg.mc_particles,
-                     b->words, blocks, t.explore_threads, b->counter, b->out_dev, sch,
+                     b->words, t.explore_threads, b->counter, b->out_dev, groups, n_groups,
                      cfg.smooth != 0);
         BCHK(hipStreamEndCapture(b->stream, &graph));
         BCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -351,7 +368,7 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
         (void)hipGraphDestroy(graph);
     } else {
         launch_batch(b->stream, b->qs_dev, q, N_max, max_nodes, cfg.max_steps, cfg.mc_particles,
-                     b->words, blocks, t.explore_threads, b->counter, b->out_dev, sch,
+                     b->words, t.explore_threads, b->counter, b->out_dev, groups, n_groups,
                      cfg.smooth != 0);
     }
     BCHK(hipGetLastError());

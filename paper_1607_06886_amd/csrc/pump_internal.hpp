@@ -368,11 +368,20 @@ struct BatchOut {
     int32_t smooth_count, smooth_steps;
 };
 
+// The persistent Explore runs once per particle count present: group g
+// plans the queries of its schedule with `blocks` workgroups of the kernel
+// for N (counters: one queue counter per group).
+constexpr int kBatchGroups = 4;   // N = 32, 64, 128, 256
+struct BatchGroup {
+    int N;
+    int blocks;
+    BatchSched sch;
+};
 void launch_batch(hipStream_t s, BatchQuery* qs_dev, int q, int N_max, int max_nodes, int S_max,
-                  int M, int words, int explore_blocks, int explore_threads, int* counters,
-                  BatchOut* out, const BatchSched& sch, bool smooth);
-// Workgroups of the batched Explore kernel that fit on one CU at once.
-int batch_explore_per_cu(int threads);
+                  int M, int words, int explore_threads, int* counters, BatchOut* out,
+                  const BatchGroup* groups, int n_groups, bool smooth);
+// Workgroups of the batched Explore kernel for N that fit on one CU at once.
+int batch_explore_per_cu(int N, int threads);
 
 void launch_select_front(hipStream_t s, const SelectArgs& a);
 void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths);

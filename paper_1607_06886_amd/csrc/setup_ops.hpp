@@ -300,6 +300,8 @@ __device__ __forceinline__ void mark_valid_dev(const float* __restrict__ X, int 
 // test on every box its range meets.
 // ---------------------------------------------------------------------------
 constexpr int kNearChunk = 4096;   // targets per LDS survivor list
+constexpr int kNearThreads = 512;  // workgroup of the near stage: a row's survivors
+                                   // (a few hundred) are steered in one pass
 
 // Append `ok` items of a wave to a list: one atomic per wave (all 64 lanes
 // call it).  Returns the slot of this lane's item.
@@ -322,7 +324,7 @@ __device__ __forceinline__ void gw_push_near(const GraphWork& gw, bool ok, int s
     }
 }
 
-// near: row v (whole workgroup of 256 threads; s_list holds kNearChunk ints)
+// near: row v (whole workgroup, blockDim a multiple of 64; s_list holds kNearChunk ints)
 __device__ __forceinline__ void gw_near_row(const float* __restrict__ X,
                                             const uint8_t* __restrict__ valid, int n, int v,
                                             double r_steer, double r_conn, const GraphWork& gw,
