@@ -109,8 +109,11 @@ __global__ __launch_bounds__(256) void k_b_gw_near_col0(BatchQuery* qs) {
                  graph_work(Q));
 }
 
-__global__ __launch_bounds__(256) void k_b_gw_boxes_rm(BatchQuery* qs) {
+__global__ __launch_bounds__(kBoxThreads) void k_b_gw_boxes_rm(BatchQuery* qs) {
     __shared__ float s_obs[kMaxObs * 6];
+    __shared__ uint32_t s_q[kBoxThreads / 64 * kBoxQueue];
+    __shared__ int s_src[kBoxThreads], s_dst[kBoxThreads], s_blk[kBoxThreads];
+    __shared__ double s_tau[kBoxThreads];
     BatchQuery& Q = qs[blockIdx.y];
     if (!Q.use_rm) return;
     const int n_obs = Q.ra[0].n_obs;
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(256) void k_b_gw_boxes_rm(BatchQuery* qs) {
     __syncthreads();
     gw_boxes(Q.X, Q.valid, Q.rm.esrc, Q.rm.col, Q.rm.tau, Q.rm.bbox, Q.rm.n_edges, false, true,
              s_obs, n_obs, graph_work(Q), Q.ebits, Q.words, blockIdx.x * blockDim.x + threadIdx.x,
-             gridDim.x * blockDim.x);
+             gridDim.x * blockDim.x, s_q, s_src, s_dst, s_tau, s_blk);
 }
 
 __global__ __launch_bounds__(kNearThreads) void k_b_gw_near_rows(BatchQuery* qs) {
@@ -130,8 +133,11 @@ __global__ __launch_bounds__(kNearThreads) void k_b_gw_near_rows(BatchQuery* qs)
                 &s_cnt);
 }
 
-__global__ __launch_bounds__(256) void k_b_gw_boxes(BatchQuery* qs) {
+__global__ __launch_bounds__(kBoxThreads) void k_b_gw_boxes(BatchQuery* qs) {
     __shared__ float s_obs[kMaxObs * 6];
+    __shared__ uint32_t s_q[kBoxThreads / 64 * kBoxQueue];
+    __shared__ int s_src[kBoxThreads], s_dst[kBoxThreads], s_blk[kBoxThreads];
+    __shared__ double s_tau[kBoxThreads];
     BatchQuery& Q = qs[blockIdx.y];
     const int n_obs = Q.ra[0].n_obs;
     for (int t = threadIdx.x; t < n_obs * 6; t += blockDim.x) s_obs[t] = Q.obs[t];
@@ -139,7 +145,8 @@ __global__ __launch_bounds__(256) void k_b_gw_boxes(BatchQuery* qs) {
     const GraphWork gw = graph_work(Q);
     gw_boxes(Q.X, Q.valid, gw.near_src, gw.near_dst, gw.near_tau, nullptr,
              min(gw.counts[0], gw.near_cap), true, false, s_obs, n_obs, gw, Q.ebits, Q.words,
-             blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+             blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, s_q, s_src, s_dst,
+             s_tau, s_blk);
 }
 
 __global__ __launch_bounds__(256) void k_b_gw_exact(BatchQuery* qs) {
@@ -445,8 +452,8 @@ void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes
     k_b_rm_check<<<dim3((max_nodes * 6 + 255) / 256, q), 256, 0, s>>>(qs);
     k_b_gw_near_rows<<<dim3(max_nodes, q), kNearThreads, 0, s>>>(qs);
     k_b_gw_near_col0<<<dim3((max_nodes + 255) / 256, q), 256, 0, s>>>(qs);
-    k_b_gw_boxes<<<dim3(256, q), 256, 0, s>>>(qs);
-    k_b_gw_boxes_rm<<<dim3(256, q), 256, 0, s>>>(qs);
+    k_b_gw_boxes<<<dim3(256, q), kBoxThreads, 0, s>>>(qs);
+    k_b_gw_boxes_rm<<<dim3(256, q), kBoxThreads, 0, s>>>(qs);
     k_b_gw_exact<<<dim3(64, q), 256, 0, s>>>(qs);
     k_b_row_deg<<<dim3((max_nodes + 3) / 4, q), 256, 0, s>>>(qs);
     k_b_row_scan<<<q, 1024, 0, s>>>(qs);

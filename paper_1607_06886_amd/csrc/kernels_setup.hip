@@ -104,21 +104,27 @@ __global__ __launch_bounds__(256) void k_gw_near_col0(const float* __restrict__ 
 }
 
 // boxes over the near list (count on the device) or a cached list (count given)
-__global__ __launch_bounds__(256) void k_gw_boxes(const float* __restrict__ X,
-                                                  const uint8_t* __restrict__ valid,
-                                                  const int32_t* __restrict__ src,
-                                                  const int32_t* __restrict__ dst,
-                                                  const double* __restrict__ tau,
-                                                  const double* __restrict__ bbox, int count,
-                                                  int near_list, const float* __restrict__ obs,
-                                                  int n_obs, GraphWork gw,
-                                                  uint32_t* __restrict__ ebits, int words) {
+__global__ __launch_bounds__(kBoxThreads) void k_gw_boxes(const float* __restrict__ X,
+                                                          const uint8_t* __restrict__ valid,
+                                                          const int32_t* __restrict__ src,
+                                                          const int32_t* __restrict__ dst,
+                                                          const double* __restrict__ tau,
+                                                          const double* __restrict__ bbox,
+                                                          int count, int near_list,
+                                                          const float* __restrict__ obs,
+                                                          int n_obs, GraphWork gw,
+                                                          uint32_t* __restrict__ ebits,
+                                                          int words) {
     __shared__ float s_obs[kMaxObs * 6];
+    __shared__ uint32_t s_q[kBoxThreads / 64 * kBoxQueue];
+    __shared__ int s_src[kBoxThreads], s_dst[kBoxThreads], s_blk[kBoxThreads];
+    __shared__ double s_tau[kBoxThreads];
     for (int t = threadIdx.x; t < n_obs * 6; t += blockDim.x) s_obs[t] = obs[t];
     __syncthreads();
     const int N = near_list ? min(gw.counts[0], gw.near_cap) : count;
     gw_boxes(X, valid, src, dst, tau, bbox, N, near_list != 0, near_list == 0, s_obs, n_obs, gw,
-             ebits, words, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+             ebits, words, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, s_q,
+             s_src, s_dst, s_tau, s_blk);
 }
 
 __global__ __launch_bounds__(256) void k_gw_exact(const float* __restrict__ X,
@@ -162,7 +168,7 @@ void launch_graph_mark(hipStream_t s, const float* X, const uint8_t* valid, int 
                        uint32_t* ebits, int32_t* deg, int words, const GraphWork& gw) {
     (void)hipMemsetAsync(ebits, 0, (size_t)n_nodes * words * sizeof(uint32_t), s);
     k_gw_near_rows<<<n_nodes, kNearThreads, 0, s>>>(X, valid, n_nodes, 0, r_steer, r_conn, gw);
-    k_gw_boxes<<<kStageBlocks, 256, 0, s>>>(X, valid, gw.near_src, gw.near_dst, gw.near_tau,
+    k_gw_boxes<<<kStageBlocks, kBoxThreads, 0, s>>>(X, valid, gw.near_src, gw.near_dst, gw.near_tau,
                                             nullptr, 0, 1, obs, n_obs, gw, ebits, words);
     k_gw_exact<<<kStageBlocks, 256, 0, s>>>(X, obs, gw, nullptr, nullptr, nullptr, ebits, words);
     k_row_deg<<<(n_nodes + 3) / 4, 256, 0, s>>>(ebits, n_nodes, words, deg);
@@ -179,12 +185,12 @@ void launch_graph_pass1_roadmap(hipStream_t s, const float* X, const uint8_t* va
     const int col = n_nodes - 1;
     k_gw_near_col0<<<(col + 255) / 256 > 0 ? (col + 255) / 256 : 1, 256, 0, s>>>(
         X, valid, n_nodes, r_steer, r_conn, gw);
-    k_gw_boxes<<<64, 256, 0, s>>>(X, valid, gw.near_src, gw.near_dst, gw.near_tau, nullptr, 0, 1, obs,
+    k_gw_boxes<<<64, kBoxThreads, 0, s>>>(X, valid, gw.near_src, gw.near_dst, gw.near_tau, nullptr, 0, 1, obs,
                                   n_obs, gw, ebits, words);
     int blocks = (rm_edges + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > kStageBlocks) blocks = kStageBlocks;
-    k_gw_boxes<<<blocks, 256, 0, s>>>(X, valid, rm_src, rm_dst, rm_tau, rm_bbox, rm_edges, 0, obs,
+    k_gw_boxes<<<blocks, kBoxThreads, 0, s>>>(X, valid, rm_src, rm_dst, rm_tau, rm_bbox, rm_edges, 0, obs,
                                       n_obs, gw, ebits, words);
     k_gw_exact<<<kStageBlocks, 256, 0, s>>>(X, obs, gw, rm_src, rm_dst, rm_tau, ebits, words);
     k_row_deg<<<(n_nodes + 3) / 4, 256, 0, s>>>(ebits, n_nodes, words, deg);

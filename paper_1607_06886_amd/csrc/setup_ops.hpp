@@ -382,6 +382,22 @@ __device__ __forceinline__ void gw_near_col0(const float* __restrict__ X,
 // Exact-queue entries name the connection by `tag` (>= 0: index into the
 // roadmap list, < 0: -1 - index into the near list).  check_valid: skip
 // connections with an invalid end (the cached roadmap list).
+//
+// Lane i of a wave takes connection i of the wave's 64 and finds the boxes
+// its range meets.  Those (connection, box) pairs are then spread over all 64
+// lanes through an LDS queue per wave, so a connection that meets many boxes
+// does not hold its wave: each pair gets the quick test, a hit blocks the
+// connection, an unsure pair goes to the exact queue; connections not blocked
+// set their bit.  Whole workgroup of kBoxThreads; s_q/s_src/s_dst/s_tau/s_blk
+// are per-wave LDS arrays (kBoxQueue, 64, 64, 64, 64 entries per wave).
+constexpr int kBoxThreads = 256;
+constexpr int kBoxQueue = 256;
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ void gw_boxes(const float* __restrict__ X,
                                          const uint8_t* __restrict__ valid,
                                          const int32_t* __restrict__ src_a,
@@ -390,79 +406,108 @@ __device__ __forceinline__ void gw_boxes(const float* __restrict__ X,
                                          const double* __restrict__ bbox, int count, bool near_list,
                                          bool check_valid, const float* s_obs, int n_obs,
                                          const GraphWork& gw, uint32_t* __restrict__ ebits,
-                                         int words, int gid, int stride) {
-    // all lanes of a wave iterate together (stride is a multiple of 64), so the
-    // exact-queue slots are claimed with one atomic per wave
-    const int lane = threadIdx.x & 63;
+                                         int words, int gid, int stride, uint32_t* s_q,
+                                         int* s_src, int* s_dst, double* s_tau, int* s_blk) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t* q = s_q + w * kBoxQueue;
+    int* qs = s_src + w * 64;
+    int* qd = s_dst + w * 64;
+    double* qt = s_tau + w * 64;
+    int* blk = s_blk + w * 64;
+    // all lanes of a wave iterate together (stride is a multiple of 64)
     for (int base = gid - lane; base < count; base += stride) {
         const int i = base + lane;
         bool keep = i < count;
         int src = 0, dst = 0;
+        double tau = 0.0;
         if (keep) {
             src = src_a[i];
             dst = dst_a[i];
+            tau = tau_a[i];
             keep = !check_valid || (valid[src] && valid[dst]);
         }
-        unsigned long long unsure[kMaxObs / 64] = {0ull, 0ull, 0ull, 0ull};
-        int n_uns = 0;
-        if (keep && n_obs > 0) {
-            const double tau = tau_a[i];
-            const float* xs = X + (size_t)src * 6;
-            const float* xd = X + (size_t)dst * 6;
-            Cubic cs[3];
-            hermite(xs, xd, tau, cs);
-            double mn[3], mx[3];
-            if (bbox) {
-                for (int a = 0; a < 3; ++a) {
-                    mn[a] = bbox[(size_t)i * 6 + a];
-                    mx[a] = bbox[(size_t)i * 6 + 3 + a];
+        unsigned long long ov[kMaxObs / 64] = {0ull, 0ull, 0ull, 0ull};
+        int n_ov = 0;
+        if (keep) {
+            if (n_obs > 0) {
+                double mn[3], mx[3];
+                if (bbox) {
+                    for (int a = 0; a < 3; ++a) {
+                        mn[a] = bbox[(size_t)i * 6 + a];
+                        mx[a] = bbox[(size_t)i * 6 + 3 + a];
+                    }
+                } else {
+                    Cubic cs[3];
+                    hermite(X + (size_t)src * 6, X + (size_t)dst * 6, tau, cs);
+                    for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
                 }
-            } else {
-                for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
-            }
-            for (int o = 0; o < n_obs && keep; ++o) {
-                const float* bx = s_obs + o * 6;
-                bool disjoint = false;
-                for (int a = 0; a < 3; ++a)
-                    disjoint |= (mx[a] < (double)bx[a]) | (mn[a] > (double)bx[3 + a]);
-                if (disjoint) continue;
-                const int q = trajectory_box_quick(cs, tau, bx);
-                if (q == kBoxHit) {
-                    keep = false;
-                } else if (q == kBoxUnsure) {
-                    unsure[o >> 6] |= 1ull << (o & 63);
-                    ++n_uns;
+                for (int o = 0; o < n_obs; ++o) {
+                    const float* bx = s_obs + o * 6;
+                    bool disjoint = false;
+                    for (int a = 0; a < 3; ++a)
+                        disjoint |= (mx[a] < (double)bx[a]) | (mn[a] > (double)bx[3 + a]);
+                    if (!disjoint) {
+                        ov[o >> 6] |= 1ull << (o & 63);
+                        ++n_ov;
+                    }
                 }
             }
         }
-        // wave-wide exclusive scan of the queued counts
-        const int cnt = keep ? n_uns : 0;
-        int x = cnt;
+        qs[lane] = src;
+        qd[lane] = dst;
+        qt[lane] = tau;
+        blk[lane] = 0;
+        // this lane's first pair within the wave's list
+        int x = n_ov;
         for (int o = 1; o < 64; o <<= 1) {
             const int y = __shfl_up(x, o, 64);
             if (lane >= o) x += y;
         }
         const int total = __shfl(x, 63, 64);
-        int slot0 = 0;
-        if (lane == 63 && total > 0) slot0 = atomicAdd(gw.counts + 1, total);
-        slot0 = __shfl(slot0, 63, 64);
-        if (cnt > 0) {
-            int slot = slot0 + x - cnt;
-            const int tag = near_list ? -1 - i : i;
-            for (int w = 0; w < kMaxObs / 64; ++w) {
-                unsigned long long m = unsure[w];
-                while (m) {
-                    const int o = w * 64 + __ffsll((long long)m) - 1;
-                    m &= m - 1ull;
-                    if (slot < gw.xq_cap) {
-                        gw.xq_edge[slot] = tag;
-                        gw.xq_box[slot] = o;
+        const int first = x - n_ov;
+        const int tag_base = near_list ? -1 - base : base;   // tag of lane 0's connection
+        for (int seg = 0; seg < total; seg += kBoxQueue) {
+            // this lane's pairs that fall in [seg, seg + kBoxQueue)
+            if (n_ov > 0 && first < seg + kBoxQueue && first + n_ov > seg) {
+                int k = first;
+                for (int wd = 0; wd < kMaxObs / 64; ++wd) {
+                    unsigned long long m = ov[wd];
+                    while (m) {
+                        const int o = wd * 64 + __ffsll((long long)m) - 1;
+                        m &= m - 1ull;
+                        if (k >= seg && k < seg + kBoxQueue) q[k - seg] = ((uint32_t)lane << 8) | (uint32_t)o;
+                        ++k;
                     }
-                    ++slot;
                 }
             }
+            wave_lds_sync();
+            const int m_seg = min(total - seg, kBoxQueue);
+            for (int j0 = 0; j0 < m_seg; j0 += 64) {
+                const int j = j0 + lane;
+                bool unsure = false;
+                int who = 0, o = 0;
+                if (j < m_seg) {
+                    who = (int)(q[j] >> 8);
+                    o = (int)(q[j] & 255u);
+                    const int cs_src = qs[who], cs_dst = qd[who];
+                    const double ct = qt[who];
+                    Cubic cs[3];
+                    hermite(X + (size_t)cs_src * 6, X + (size_t)cs_dst * 6, ct, cs);
+                    const int r = trajectory_box_quick(cs, ct, s_obs + o * 6);
+                    if (r == kBoxHit) blk[who] = 1;
+                    unsure = r == kBoxUnsure;
+                }
+                const int slot = wave_append(unsure, gw.counts + 1);
+                if (unsure && slot < gw.xq_cap) {
+                    gw.xq_edge[slot] = near_list ? tag_base - who : tag_base + who;
+                    gw.xq_box[slot] = o;
+                }
+            }
+            wave_lds_sync();
         }
-        if (keep) atomicOr(&ebits[(size_t)src * words + (dst >> 5)], 1u << (dst & 31));
+        wave_lds_sync();
+        if (keep && !blk[lane]) atomicOr(&ebits[(size_t)src * words + (dst >> 5)], 1u << (dst & 31));
+        wave_lds_sync();
     }
 }
 
