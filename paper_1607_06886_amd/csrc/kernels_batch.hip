@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_b_edge_steer(BatchQuery* qs) {
 // so each gets the registers its own N needs: two workgroups of 256 per CU
 // fit for N <= 128, one for N = 256.
 template <int N>
-__global__ __launch_bounds__(256, N == 256 ? 1 : 2) void k_b_explore(BatchQuery* qs, BatchSched sch,
+__global__ __launch_bounds__(256, 2) void k_b_explore(BatchQuery* qs, BatchSched sch,
                                                                     int* counter, BatchOut* outs) {
     __shared__ float s_raw[kMaxObs * 6];
     __shared__ float s_in[kMaxObs * 6];
