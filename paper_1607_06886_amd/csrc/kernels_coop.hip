@@ -5,12 +5,12 @@
 
 namespace pump {
 
-// Workgroup size: 512 threads (two waves per SIMD with one workgroup per CU)
-// where the kernel's registers allow it, 256 for N = 256.  More waves per
-// workgroup hide the latency of the wave-per-pair phases without adding
-// workgroups to the grid barriers.
+// Workgroup size: 512 threads, two waves per SIMD with one workgroup per CU
+// (the launch bound holds every N to 256 VGPRs).  More waves per workgroup
+// hide the latency of the wave-per-pair phases without adding workgroups to
+// the grid barriers.
 template <int N>
-constexpr int coop_threads() { return N == 256 ? 256 : 512; }
+constexpr int coop_threads() { return 512; }
 
 template <int N>
 __global__ __launch_bounds__(coop_threads<N>()) void k_explore_coop(const RoundArgs* __restrict__ ra,
