@@ -13,6 +13,16 @@ __device__ __forceinline__ double stair_get(const unsigned long long* st, int w,
     return __longlong_as_double((long long)st[(size_t)x * w + c]);
 }
 
+// The same entry read with an agent-scope atomic load: current even where
+// this XCD's L2 still holds the line from before other workgroups' atomic
+// minima (no cache invalidation in between).
+__device__ __forceinline__ double stair_get_coherent(const unsigned long long* st, int w, int x,
+                                                     int c) {
+    unsigned long long* p = const_cast<unsigned long long*>(st) + (size_t)x * w + c;
+    return __longlong_as_double(
+        (long long)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
     return lane ? ((1ull << lane) - 1ull) : 0ull;
 }
@@ -405,13 +415,19 @@ __device__ __forceinline__ void stair_update_pair(const RoundArgs& a, int q) {
 }
 
 // Candidate q: dominated -> flag 2; scan input = survivor.  Returns whether q
-// was kept before the test (counts toward `inserted`).
+// was kept before the test (counts toward `inserted`).  kCoherent: read the
+// staircase with atomic loads (the team loop, whose barrier after the
+// staircase update does not invalidate the caches).
+template <bool kCoherent = false>
 __device__ __forceinline__ bool mark_pair(const RoundArgs& a, int t) {
     uint8_t f = a.c_flag[t];
     bool kept = false;
     if (f == 1) {
         kept = true;
-        if (stair_get(a.stair, a.stair_w, a.c_head[t], a.c_pop[t]) < a.c_cost[t]) {
+        const int x = a.c_head[t], c = a.c_pop[t];
+        const double m = kCoherent ? stair_get_coherent(a.stair, a.stair_w, x, c)
+                                   : stair_get(a.stair, a.stair_w, x, c);
+        if (m < a.c_cost[t]) {
             f = 2;
             a.c_flag[t] = 2;
         }
@@ -421,9 +437,13 @@ __device__ __forceinline__ bool mark_pair(const RoundArgs& a, int t) {
 }
 
 // Open entry i: removed if dominated, closed if in B (P_open \ B), else kept.
+template <bool kCoherent = false>
 __device__ __forceinline__ void mark_open(const RoundArgs& a, int i) {
     const int p = a.open_in[i];
-    const bool dom = stair_get(a.stair, a.stair_w, a.p_head[p], a.p_pop[p]) < a.p_cost[p];
+    const int x = a.p_head[p], c = a.p_pop[p];
+    const double m = kCoherent ? stair_get_coherent(a.stair, a.stair_w, x, c)
+                               : stair_get(a.stair, a.stair_w, x, c);
+    const bool dom = m < a.p_cost[p];
     const bool inB = a.o_inB[i] != 0;
     const uint8_t stt = dom ? kRemoved : (inB ? kClosed : kOpen);
     a.p_state[p] = stt;

@@ -10,8 +10,8 @@
 // Work split: expansion strides over pairs by wave, the particle queue by
 // wave, the staircase update by thread.  Marking, compaction and the next
 // group use contiguous chunks of the pair and open lists, one chunk per
-// member, so each scan needs one barrier: a member publishes its chunk
-// total, and after the barrier adds the totals of the members before it.
+// member, so each scan needs one exchange of chunk totals: a member publishes
+// its totals and then adds those of the members before it.
 #pragma once
 
 #include "explore_ops.hpp"
@@ -28,8 +28,8 @@ struct TeamCtx {
     unsigned* release;         // last barrier member 0 released
     int* fail;                 // set when a wait ran out of patience
     int rank, size;
-    int32_t* tot_a;            // [size] chunk totals
-    int32_t* tot_b;            // [size]
+    unsigned long long* xa;    // [size] exchanged chunk totals, tagged (team_exchange)
+    unsigned long long* xb;    // [size]
     int32_t* b_deg;            // group degrees (scatter output)
     int32_t* open_cur;         // open list read by the first round
     int32_t* open_next;
@@ -46,12 +46,15 @@ struct TeamCtx {
 // the workgroup barrier.  A wait that exceeds the spin limit records a
 // failure, so the kernel always ends.  Returns true (the same in every thread
 // of the workgroup) when the team has failed; the caller then leaves its loop.
+// With kFenced false the barrier only synchronises (no cache maintenance);
+// team_exchange uses that form.
+template <bool kFenced = true>
 __device__ __forceinline__ bool team_barrier(const TeamCtx& g, unsigned& epoch, int* s_flag) {
     __syncthreads();
     if (g.size == 1) return false;
     epoch += 1u;
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (kFenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(g.arrive + g.rank, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (g.rank == 0) {
@@ -69,7 +72,7 @@ __device__ __forceinline__ bool team_barrier(const TeamCtx& g, unsigned& epoch, 
         if (!ok) atomicOr(g.fail, 1);
         __syncthreads();
         if (threadIdx.x == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (kFenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __hip_atomic_store(g.release, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     } else if (threadIdx.x == 0) {
@@ -83,7 +86,7 @@ __device__ __forceinline__ bool team_barrier(const TeamCtx& g, unsigned& epoch, 
         }
     }
     if (threadIdx.x == 0) {
-        if (g.rank != 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (kFenced && g.rank != 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_flag = __hip_atomic_load(g.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
@@ -113,17 +116,76 @@ __device__ __forceinline__ int block_sum_int(int v, int* s_w) {
     return t;
 }
 
-// Sum of tot[0..b) and of tot[0..G) (all threads get both).
-__device__ __forceinline__ void prefix_of(const int* tot, int b, int G, int* s_w, int& before,
-                                          int& all) {
-    int x = 0, y = 0;
-    for (int k = threadIdx.x; k < G; k += blockDim.x) {
-        const int v = __hip_atomic_load(tot + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        y += v;
-        if (k < b) x += v;
+// Totals gathered by team_exchange: sums of the members before this one and
+// of all members, for both values, and the OR of the flags.
+struct XSum {
+    int a_before, a_all, b_before, b_all, flag;
+};
+
+// Exchange of two chunk totals per member (va, vb >= 0, below 2^31) and a
+// flag between two phases, without cache maintenance.  Each member stores its
+// values in its own 64-bit words (value in the low half, the exchange's
+// number in the high half; the flag in bit 31 of the second word) with
+// relaxed agent-scope atomic stores, passes an unfenced barrier, and reads
+// every member's words with agent-scope atomic loads, waiting for any word
+// that does not yet carry the current number.  An atomic word is coherent
+// across the L2 caches of the XCDs by itself, so no write-back or
+// invalidation is needed as long as the totals are all that crosses
+// workgroups at this point: the phase before the exchange writes only the
+// member's own chunk (and the words), and the phase after it reads that chunk
+// back in the same workgroup.  The words are zero before the team's first
+// exchange.  Returns true when the team has failed, like team_barrier.
+__device__ __forceinline__ bool team_exchange(const TeamCtx& g, unsigned& epoch, int* s_flag,
+                                              int va, int vb, int flag, int* s_w, XSum& r) {
+    if (g.size == 1) {
+        __syncthreads();
+        r = XSum{0, va, 0, vb, flag};
+        return false;
     }
-    before = uni(block_sum_int(x, s_w));
-    all = uni(block_sum_int(y, s_w));
+    const unsigned long long tag = (unsigned long long)(epoch + 1u) << 32;
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(g.xa + g.rank, tag | (unsigned)va, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(g.xb + g.rank, tag | (unsigned)vb | (flag ? 0x80000000ull : 0ull),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (team_barrier<false>(g, epoch, s_flag)) return true;
+    int ab = 0, aa = 0, bb = 0, ba = 0, f = 0, ok = 1;
+    for (int k = threadIdx.x; k < g.size && ok; k += blockDim.x) {
+        unsigned long long w[2];
+        for (int h = 0; h < 2 && ok; ++h) {
+            unsigned long long* p = h ? g.xb + k : g.xa + k;
+            long long spins = 0;
+            while (((w[h] = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
+                    ~0xFFFFFFFFull) != tag) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit) {
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        if (!ok) break;
+        const int a = (int)(unsigned)w[0];
+        const int bv = (int)((unsigned)w[1] & 0x7FFFFFFFu);
+        aa += a;
+        ba += bv;
+        f |= (int)((unsigned)w[1] >> 31);
+        if (k < g.rank) {
+            ab += a;
+            bb += bv;
+        }
+    }
+    if (!ok) atomicOr(g.fail, 1);
+    r.a_before = uni(block_sum_int(ab, s_w));
+    r.a_all = uni(block_sum_int(aa, s_w));
+    r.b_before = uni(block_sum_int(bb, s_w));
+    r.b_all = uni(block_sum_int(ba, s_w));
+    r.flag = uni(block_sum_int(f, s_w));
+    if (threadIdx.x == 0)
+        *s_flag = __hip_atomic_load(g.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    return *s_flag != 0;
 }
 
 // Exclusive scan of v over the block's threads in thread order, for one
@@ -245,21 +307,21 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         }
         if (team_barrier(g, epoch, s_fail_p)) break;
         if (leader) tick(0);
-        // (2) particle simulation, one queued pair per wave
+        // (2) particle simulation, one queued pair per wave; the leader
+        //     resets the cheapest-open-cost accumulator of phase 5 (its store
+        //     is written back at the next barrier)
         const int n_tasks = uni(__hip_atomic_load(&c->n_tasks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (leader) c->min_cost_bits = 0x7FF0000000000000ull;
         for (int task = gwave; task < n_tasks; task += n_gwaves)
             simulate_pair<N>(a, a.tasks[task], s_raw, s_in, s_out, w_pre, w_flag, w_wp, w_bt);
         if (team_barrier(g, epoch, s_fail_p)) break;
         if (leader) tick(1);
-        // (3) staircase update; the leader resets the per-round accumulators
-        //     (nothing reads them until after the next barrier)
+        // (3) staircase update (atomic minima only).  The barrier after it
+        //     needs no cache maintenance: phase 4 reads the staircase with
+        //     atomic loads, and every other array it reads is unchanged since
+        //     the barrier before this phase.
         for (int q = b * T + tid; q < n_pairs; q += G * T) stair_update_pair(a, q);
-        if (leader) {
-            c->n_tasks = 0;
-            c->min_cost_bits = 0x7FF0000000000000ull;
-            c->goal_stop = 0;
-        }
-        if (team_barrier(g, epoch, s_fail_p)) break;
+        if (team_barrier<false>(g, epoch, s_fail_p)) break;
         if (leader) tick(2);
         // (4) marks over contiguous chunks; chunk totals of the survivor and
         //     kept-open flags
@@ -268,25 +330,23 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         chunk_of(n_open, b, G, o_lo, o_hi);
         int my_s = 0, my_k = 0;
         for (int t = p_lo + tid; t < p_hi; t += T) {
-            kept += mark_pair(a, t) ? 1 : 0;
+            kept += mark_pair<true>(a, t) ? 1 : 0;
             my_s += a.c_pos[t];
         }
         for (int t = o_lo + tid; t < o_hi; t += T) {
-            mark_open(a, t);
+            mark_open<true>(a, t);
             my_k += a.o_keep[t];
         }
         my_s = block_sum_int(my_s, s_w);
         my_k = block_sum_int(my_k, s_w);
-        if (tid == 0) {
-            g.tot_a[b] = my_s;
-            g.tot_b[b] = my_k;
-        }
-        if (team_barrier(g, epoch, s_fail_p)) break;
+        // (only the totals cross workgroups here: marks and scans stay in
+        //  the member's own chunks)
+        XSum xs;
+        if (team_exchange(g, epoch, s_fail_p, my_s, my_k, 0, s_w, xs)) break;
         if (leader) tick(3);
         // (5) scans of both flag arrays, compaction, cheapest new open plan
-        int s_before, n_surv, k_before, n_keep;
-        prefix_of(g.tot_a, b, G, s_w, s_before, n_surv);
-        prefix_of(g.tot_b, b, G, s_w, k_before, n_keep);
+        const int s_before = xs.a_before, n_surv = xs.a_all;
+        const int k_before = xs.b_before, n_keep = xs.b_all;
         const bool fits = (long long)n_plans + n_surv <= a.cap_plans;
         unsigned long long m = 0x7FF0000000000000ull;
         {
@@ -346,7 +406,10 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         }
         if (team_barrier(g, epoch, s_fail_p)) break;
         if (leader) tick(4);
-        // (6) next group index; flag the group and count it per chunk
+        // (6) next group index; flag the group and count it per chunk.  The
+        //     leader empties the simulation queue for the next round (written
+        //     back at the barrier after phase 7).
+        if (leader) c->n_tasks = 0;
         if (n_open == 0) {
             done = 1;
             i_cur += 1;
@@ -377,21 +440,19 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
                 my_d += a.row_ptr[h + 1] - a.row_ptr[h];
             }
         }
-        if (__any(stop) && lane == 0) atomicOr(&c->goal_stop, 1);
         my_b = block_sum_int(my_b, s_w);
         my_d = block_sum_int(my_d, s_w);
-        if (tid == 0) {
-            g.tot_a[b] = my_b;
-            g.tot_b[b] = my_d;
-        }
-        if (team_barrier(g, epoch, s_fail_p)) break;
+        stop = block_sum_int(stop, s_w);
+        // (the flags and scans stay in the member's own chunk of the new
+        //  open list; the stop flag travels with the totals)
+        XSum xg;
+        if (team_exchange(g, epoch, s_fail_p, my_b, my_d, stop, s_w, xg)) break;
         if (leader) tick(5);
         // (7) scans of the group flags and of the group's degrees in group
         //     order (= open-list order), per chunk: scatter of the group and
         //     its pair offsets
-        int b_before, nB, d_before, n_pairs_next;
-        prefix_of(g.tot_a, b, G, s_w, b_before, nB);
-        prefix_of(g.tot_b, b, G, s_w, d_before, n_pairs_next);
+        const int b_before = xg.a_before, nB = xg.a_all;
+        const int d_before = xg.b_before, n_pairs_next = xg.b_all;
         {
             int carry = b_before, dcarry = d_before;
             for (int t0 = n_lo; t0 < n_hi; t0 += T) {
@@ -413,11 +474,10 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         }
         __syncthreads();
         for (int t = n_lo + tid; t < n_hi; t += T) scatter_group_one(a, t, g.b_deg);
-        const int goal_stop = uni(__hip_atomic_load(&c->goal_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (leader) a.b_off[nB] = n_pairs_next;
         n_B = nB;
         n_pairs = n_pairs_next;
-        done = goal_stop ? 1 : 0;
+        done = xg.flag ? 1 : 0;
         if (team_barrier(g, epoch, s_fail_p)) break;
         if (leader) tick(6);
     }

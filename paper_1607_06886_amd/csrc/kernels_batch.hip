@@ -259,8 +259,8 @@ __global__ __launch_bounds__(256, 2) void k_b_explore(BatchQuery* qs, BatchSched
         t.release = Q.team_sync;
         t.fail = reinterpret_cast<int*>(Q.team_sync + 1);
         t.arrive = Q.team_sync + 64;
-        t.tot_a = Q.team_tot;
-        t.tot_b = Q.team_tot + kMaxTeam;
+        t.xa = Q.team_tot;
+        t.xb = Q.team_tot + kMaxTeam;
         t.b_deg = Q.b_deg;
         t.open_cur = Q.open_a;
         t.open_next = Q.open_b;
@@ -429,7 +429,7 @@ __global__ void k_b_reset(BatchQuery* qs, int* counter) {
     const BatchQuery& Q = qs[blockIdx.x];
     if (threadIdx.x < kBatchGroups && blockIdx.x == 0) counter[threadIdx.x] = 0;
     for (int t = threadIdx.x; t < 64 + kMaxTeam; t += blockDim.x) Q.team_sync[t] = 0u;
-    for (int t = threadIdx.x; t < 2 * kMaxTeam; t += blockDim.x) Q.team_tot[t] = 0;
+    for (int t = threadIdx.x; t < 2 * kMaxTeam; t += blockDim.x) Q.team_tot[t] = 0ull;
 }
 
 void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes, int S_max, int M,

@@ -28,8 +28,8 @@ __global__ __launch_bounds__(coop_threads<N>()) void k_explore_coop(const RoundA
     t.fail = ca.sync.fail;
     t.rank = blockIdx.x;
     t.size = gridDim.x;
-    t.tot_a = ca.tot_a;
-    t.tot_b = ca.tot_b;
+    t.xa = ca.xa;
+    t.xb = ca.xb;
     t.b_deg = ca.b_deg;
     t.open_cur = ca.open_cur;
     t.open_next = ca.open_next;

@@ -14,6 +14,9 @@
 
 using namespace pump;
 
+// Words of the single launch's barrier allocation (see pump_ctx::coop_sync).
+constexpr size_t kCoopSyncWords = 64 + 4096 + 4 * 4096;
+
 struct pump_ctx {
     pump_config cfg;
     hipStream_t stream = nullptr;
@@ -64,8 +67,9 @@ struct pump_ctx {
     uint32_t* c_mask = nullptr;
     uint8_t* c_flag = nullptr;
     int32_t* blk = nullptr;
-    unsigned* coop_sync = nullptr;  // grid barrier: release word, failure flag, arrival words
-    int32_t* coop_tot = nullptr;    // [2][coop_blocks] chunk totals
+    // grid barrier and exchange words: release word, failure flag (words 0-63),
+    // arrival words [4096], then the 64-bit exchange words [2][coop_blocks]
+    unsigned* coop_sync = nullptr;
     int coop_blocks = 0;            // resident workgroups of the single-launch Explore
     int explore_mode = 0;           // 0: one launch per phase, 1: single launch
     RoundArgs* ra_dev = nullptr;    // [2] round arguments of the single launch
@@ -316,7 +320,8 @@ int pump_destroy(pump_ctx* ctx) {
                     ctx->c_step, ctx->c_pop, ctx->c_pos, ctx->tasks, ctx->c_cost, ctx->c_mask, ctx->c_flag,
                     ctx->blk, ctx->ctl, ctx->goal_ids, ctx->front_ids, ctx->paths,
                     ctx->path_len, ctx->wp_len, ctx->mc_counts, ctx->wp, ctx->sm.st,
-                    ctx->sm.e_coef, ctx->sm.e_t0, ctx->sm.wp, ctx->sm.out_wp};
+                    ctx->sm.e_coef, ctx->sm.e_t0, ctx->sm.wp, ctx->sm.out_wp, ctx->coop_sync,
+                    ctx->ra_dev};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (ctx->ctl_h) (void)hipHostFree(ctx->ctl_h);
@@ -437,8 +442,7 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
         if (ctx->coop_blocks > 4096) ctx->coop_blocks = 4096;
         ctx->explore_mode = ctx->coop_blocks > 0 ? 1 : 0;
     }
-    A(dalloc(&ctx->coop_sync, 64 + 4096));
-    A(dalloc(&ctx->coop_tot, (size_t)2 * 4096));
+    A(dalloc(&ctx->coop_sync, (size_t)kCoopSyncWords));
     A(dalloc(&ctx->ra_dev, 2));
     A(hipHostMalloc((void**)&ctx->ra_h, 2 * sizeof(RoundArgs), hipHostMallocDefault));
     A(dalloc(&ctx->ctl, 1));
@@ -698,13 +702,13 @@ static int explore_single_launch(pump_ctx* ctx) {
     ca.sync.fail = reinterpret_cast<int*>(ctx->coop_sync + 1);
     ca.sync.arrive = ctx->coop_sync + 64;
     ca.sync.n_blocks = (unsigned)ctx->coop_blocks;
-    ca.tot_a = ctx->coop_tot;
-    ca.tot_b = ctx->coop_tot + 4096;
+    ca.xa = reinterpret_cast<unsigned long long*>(ctx->coop_sync + 64 + 4096);
+    ca.xb = ca.xa + ctx->coop_blocks;
     ca.b_deg = ctx->b_deg;
     ca.open_cur = ctx->open_cur;
     ca.open_next = ctx->open_next;
     ca.cap_pairs = ctx->cfg.cap_pairs;
-    HIPCHK(hipMemsetAsync(ctx->coop_sync, 0, (64 + (size_t)ctx->coop_blocks) * sizeof(unsigned),
+    HIPCHK(hipMemsetAsync(ctx->coop_sync, 0, (64 + 4096 + 4 * (size_t)ctx->coop_blocks) * sizeof(unsigned),
                           ctx->stream));
     tbeg(ctx, 9);
     ctx->ra_h[0] = a;

@@ -32,7 +32,7 @@ struct Slot {
     int32_t *goal_ids, *front_ids, *paths, *path_len, *wp_len, *mc_counts;
     double *etau, *ecost, *p_cost, *c_cost, *wp, *dev_scratch;
     unsigned* team_sync;
-    int32_t* team_tot;
+    unsigned long long* team_tot;
     unsigned long long* stair;
     SmoothState* sm_st;
     double *sm_coef, *sm_t0, *sm_wp, *sm_out;

@@ -289,8 +289,8 @@ struct CoopSync {
 
 struct CoopArgs {
     CoopSync sync;
-    int32_t* tot_a;            // [grid] chunk totals
-    int32_t* tot_b;            // [grid]
+    unsigned long long* xa;    // [grid] exchanged chunk totals (zero at launch)
+    unsigned long long* xb;    // [grid]
     int32_t* b_deg;            // group degrees (scatter output)
     int32_t* open_cur;         // open list read by the first round
     int32_t* open_next;
@@ -344,7 +344,7 @@ struct BatchQuery {
     double* dev_scratch;       // deviation-table chunk states
     SmoothBuf sm;              // Smooth(p*, alpha) state and buffers
     unsigned* team_sync;       // [64 + kMaxTeam] team barrier words (release, fail, arrivals)
-    int32_t* team_tot;         // [2 * kMaxTeam] team scan totals
+    unsigned long long* team_tot;   // [2 * kMaxTeam] team exchange words (zeroed per batch)
 };
 
 constexpr int kMaxTeam = 64;   // workgroups planning one batched query
