@@ -91,12 +91,14 @@ __device__ __forceinline__ void explore_init_root(const RoundArgs& a, int N) {
 // otherwise evaluate the nominal trajectory and mark the waypoints where the
 // particle cloud's bounding box, shifted onto the nominal point and widened by
 // the guard band, touches an obstacle.  Returns 1 if q keeps the parent's
-// bits (written here), 2 if its particles must be simulated, 0 if resolved.
+// bits (written here), 2 if its particles must be simulated (its queue record
+// in tk), 0 if resolved.
 // ---------------------------------------------------------------------------
 template <int N>
 __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int n_B, const float* s_raw,
                                            const float* s_out, const float* gl, const float* gh,
-                                           long long& n_sim, long long& n_pre, long long& n_drop) {
+                                           long long& n_sim, long long& n_pre, long long& n_drop,
+                                           SimTask& tk) {
     constexpr int W = N / 32;
     const int n_obs = a.n_obs;
     int lo = 0, hi = n_B;  // b_off[lo] <= q < b_off[hi]
@@ -166,7 +168,7 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int n_B, c
             for (int w = 0; w < W; ++w) a.c_mask[(size_t)q * W + w] = a.p_mask[(size_t)p * W + w];
             return 1;
         }
-        a.c_pos[q] = (int)near;
+        tk = SimTask{q, p, e, near, (uint32_t)head | ((uint32_t)x << 16), s_p, tau};
         return 2;
     }
     // obstacles the cloud can reach anywhere along the edge
@@ -219,18 +221,18 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int n_B, c
         for (int w = 0; w < W; ++w) a.c_mask[(size_t)q * W + w] = a.p_mask[(size_t)p * W + w];
         return 1;
     }
-    a.c_pos[q] = (int)near;   // waypoint mask for the simulation
+    tk = SimTask{q, p, e, near, (uint32_t)head | ((uint32_t)x << 16), s_p, tau};
     return 2;
 }
 
-// Append the wave's pairs with st == 2 to the simulation queue.
-__device__ __forceinline__ void queue_pairs(const RoundArgs& a, int q, int st) {
+// Append the wave's pairs with st == 2 (records tk) to the simulation queue.
+__device__ __forceinline__ void queue_pairs(const RoundArgs& a, int st, const SimTask& tk) {
     const int lane = threadIdx.x & 63;
     const unsigned long long need = __ballot(st == 2);
     int base = 0;
     if (lane == 0 && need) base = atomicAdd(&a.ctl->n_tasks, (int)__popcll(need));
     base = __shfl(base, 0, 64);
-    if (st == 2) a.tasks[base + (int)__popcll(need & lanemask_lt(lane))] = q;
+    if (st == 2) a.tasks[base + (int)__popcll(need & lanemask_lt(lane))] = tk;
 }
 
 // ---------------------------------------------------------------------------
@@ -242,7 +244,7 @@ __device__ __forceinline__ void queue_pairs(const RoundArgs& a, int q, int st) {
 // (n_wp: waypoints tested, n_bt: waypoint-box tests, each over all particles).
 // ---------------------------------------------------------------------------
 template <int N>
-__device__ __forceinline__ void simulate_pair(const RoundArgs& a, int qj, const float* s_raw,
+__device__ __forceinline__ void simulate_pair(const RoundArgs& a, int task, const float* s_raw,
                                               const float* s_in, const float* s_out,
                                               long long& n_pre, long long& n_flag, long long& n_wp,
                                               long long& n_bt) {
@@ -251,12 +253,13 @@ __device__ __forceinline__ void simulate_pair(const RoundArgs& a, int qj, const 
     const int n_obs = a.n_obs;
     const int lane = threadIdx.x & 63;
     const bool valid_lane = (N >= 64) || (lane < N);
-    const int pj = a.c_parent[qj], xj = a.c_head[qj], ej = a.c_edge[qj];
-    const double tj = a.etau[ej], cj = a.c_cost[qj];
+    const SimTask tk = a.tasks[task];
+    const int qj = tk.q, pj = tk.p;
+    const int hj = (int)(tk.nodes & 0xFFFFu), xj = (int)(tk.nodes >> 16);
+    const double tj = tk.tau, cj = a.c_cost[qj];
     const int Kj = max(1, (int)ceil(tj / a.dt));
-    const int spj = a.c_step[qj] - Kj;
-    const int hj = a.p_head[pj];
-    const unsigned nj = (unsigned)a.c_pos[qj];
+    const int spj = tk.s_p;
+    const unsigned nj = tk.near;
     Cubic cs[3];
     hermite(a.X + (size_t)hj * 6, a.X + (size_t)xj * 6, tj, cs);
     bool hit[PPL], deep[PPL], nearp[PPL];

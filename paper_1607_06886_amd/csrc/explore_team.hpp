@@ -302,8 +302,10 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         // (1) expansion, one pair per lane; particle simulations queued
         for (int tile = gwave * 64; tile < n_pairs; tile += n_gwaves * 64) {
             const int q = tile + lane;
-            const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_raw, s_out, gl, gh, n_sim, n_pre, n_drop) : 0;
-            queue_pairs(a, q, st);
+            SimTask tk;
+            const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_raw, s_out, gl, gh, n_sim, n_pre,
+                                                         n_drop, tk) : 0;
+            queue_pairs(a, st, tk);
         }
         if (team_barrier(g, epoch, s_fail_p)) break;
         if (leader) tick(0);
@@ -313,7 +315,7 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         const int n_tasks = uni(__hip_atomic_load(&c->n_tasks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (leader) c->min_cost_bits = 0x7FF0000000000000ull;
         for (int task = gwave; task < n_tasks; task += n_gwaves)
-            simulate_pair<N>(a, a.tasks[task], s_raw, s_in, s_out, w_pre, w_flag, w_wp, w_bt);
+            simulate_pair<N>(a, task, s_raw, s_in, s_out, w_pre, w_flag, w_wp, w_bt);
         if (team_barrier(g, epoch, s_fail_p)) break;
         if (leader) tick(1);
         // (3) staircase update (atomic minima only).  The barrier after it

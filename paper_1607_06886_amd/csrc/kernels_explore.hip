@@ -137,8 +137,10 @@ __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
     const int wave_stride = gridDim.x * 4;
     for (int tile = wave_global * 64; tile < n_pairs; tile += wave_stride * 64) {
         const int q = tile + lane;
-        const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_raw, s_out, gl, gh, n_sim, n_pre, n_drop) : 0;
-        queue_pairs(a, q, st);
+        SimTask tk;
+        const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_raw, s_out, gl, gh, n_sim, n_pre,
+                                                     n_drop, tk) : 0;
+        queue_pairs(a, st, tk);
     }
     for (int o = 32; o > 0; o >>= 1) {
         n_sim += __shfl_down(n_sim, o, 64);
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(256) void k_expand_sim(RoundArgs a) {
     const int n_tasks = a.ctl->n_tasks;
     long long n_pre = 0, n_flag = 0, n_wp = 0, n_bt = 0;
     for (int task = blockIdx.x * 4 + (threadIdx.x >> 6); task < n_tasks; task += gridDim.x * 4)
-        simulate_pair<N>(a, a.tasks[task], s_raw, s_in, s_out, n_pre, n_flag, n_wp, n_bt);
+        simulate_pair<N>(a, task, s_raw, s_in, s_out, n_pre, n_flag, n_wp, n_bt);
     // counts are wave-uniform
     if (lane == 0) {
         if (n_pre) atomicAdd((unsigned long long*)&a.ctl->preprune, (unsigned long long)n_pre);

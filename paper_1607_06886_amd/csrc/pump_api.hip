@@ -62,7 +62,8 @@ struct pump_ctx {
     int32_t *b_ids = nullptr, *b_off = nullptr, *b_deg = nullptr;
     // candidates
     int32_t *c_head = nullptr, *c_parent = nullptr, *c_edge = nullptr, *c_step = nullptr,
-            *c_pop = nullptr, *c_pos = nullptr, *tasks = nullptr;
+            *c_pop = nullptr, *c_pos = nullptr;
+    SimTask* tasks = nullptr;          // simulation queue records
     double* c_cost = nullptr;
     uint32_t* c_mask = nullptr;
     uint8_t* c_flag = nullptr;

@@ -28,7 +28,8 @@ struct Slot {
     uint32_t *ebits, *p_mask, *c_mask;
     int32_t *deg, *row_ptr, *col, *esrc, *p_head, *p_parent, *p_edge, *p_step, *p_pop, *p_round;
     int32_t *open_a, *open_b, *o_keep, *b_ids, *b_off, *b_deg;
-    int32_t *c_head, *c_parent, *c_edge, *c_step, *c_pop, *c_pos, *tasks;
+    int32_t *c_head, *c_parent, *c_edge, *c_step, *c_pop, *c_pos;
+    SimTask* tasks;
     int32_t *goal_ids, *front_ids, *paths, *path_len, *wp_len, *mc_counts;
     double *etau, *ecost, *p_cost, *c_cost, *wp, *dev_scratch;
     unsigned* team_sync;

@@ -75,6 +75,20 @@ struct Ctl {
     long long sim_box_tests;   // simulated (pair, waypoint, box) tests, each over N particles
 };
 
+// A pair queued for particle simulation, with what the simulation needs of
+// it (written by the expansion, so the simulation reads one record instead of
+// chasing the pair's parent and edge through the plan store and the graph).
+struct SimTask {
+    int32_t q;                 // pair index
+    int32_t p;                 // parent plan
+    int32_t e;                 // edge
+    uint32_t near;             // waypoints whose cloud box meets an obstacle (bit k-1)
+    uint32_t nodes;            // edge endpoints: head | x << 16 (node ids < 65536)
+    int32_t s_p;               // parent's step count
+    double tau;                // edge duration
+};
+static_assert(sizeof(SimTask) == 32, "SimTask is two 16-byte loads");
+
 // Kernel arguments of one Explore round.
 struct RoundArgs {
     // problem
@@ -125,8 +139,8 @@ struct RoundArgs {
     double* c_cost;
     uint32_t* c_mask;
     uint8_t* c_flag;
-    int32_t* c_pos;            // scan input/output over the pairs (waypoint mask before)
-    int32_t* tasks;            // pairs queued for particle simulation
+    int32_t* c_pos;            // scan input/output over the pairs
+    SimTask* tasks;            // pairs queued for particle simulation
     Ctl* ctl;
 };
 
