@@ -84,9 +84,48 @@ __device__ __forceinline__ void explore_init_root(const RoundArgs& a, int N) {
     c->sim_waypoints = c->sim_box_tests = 0;
 }
 
+// Group of pair q = tile + lane of the wave: the largest g < n_B with
+// b_off[g] <= q (b_off nondecreasing, b_off[0] = 0 <= tile < n_pairs =
+// b_off[n_B]).  The wave searches together: 64-way steps (one load per lane
+// and a ballot each) narrow the groups down to a window of 64 that holds the
+// tile's first pair, one more load brings the window's offsets into the
+// lanes, and each lane counts the offsets <= q with a binary search over the
+// lanes.  Only a lane whose pair lies past the window (a tile spanning more
+// than 64 groups, i.e. groups of degree 0 or 1) searches on in memory.  All
+// lanes must call this together.
+__device__ __forceinline__ int wave_group_of(const int32_t* __restrict__ b_off, int n_B, int tile,
+                                             int q) {
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = n_B;                  // b_off[lo] <= tile, and tile < b_off[hi] or hi = n_B
+    while (hi - lo > 64) {
+        const int step = (hi - lo + 63) >> 6;
+        const int idx = lo + lane * step;
+        const unsigned long long le = __ballot(idx < hi && b_off[idx] <= tile);
+        const int j = 63 - __clzll((long long)le);   // lane 0 always qualifies
+        lo += j * step;
+        hi = min(hi, lo + step);
+    }
+    const int idx = lo + 1 + lane;
+    const int v = idx < n_B ? b_off[idx] : INT_MAX;
+    int cnt = 0;                           // lanes j with v_j <= q (a prefix of the lanes)
+    for (int s = 32; s >= 1; s >>= 1) {
+        const int vv = __shfl(v, cnt + s - 1, 64);
+        if (vv <= q) cnt += s;
+    }
+    if (cnt == 63 && __shfl(v, 63, 64) <= q) {
+        int l2 = lo + 64, h2 = n_B;        // b_off[l2] <= q < b_off[h2]
+        while (h2 - l2 > 1) {
+            const int mid = (l2 + h2) >> 1;
+            if (b_off[mid] <= q) l2 = mid; else h2 = mid;
+        }
+        return l2;
+    }
+    return lo + cnt;
+}
+
 // ---------------------------------------------------------------------------
-// Expansion, first part (one pair per lane): locate pair q (q < n_pairs), its
-// edge and parent plan; cost, step count and K_e waypoints; drop it past
+// Expansion, first part (one pair per lane): pair q (q < n_pairs) of group
+// lo (wave_group_of), its edge and parent plan; cost, step count and K_e waypoints; drop it past
 // S_max; resolve it if the parent's own cp_hat already makes it dominated;
 // otherwise evaluate the nominal trajectory and mark the waypoints where the
 // particle cloud's bounding box, shifted onto the nominal point and widened by
@@ -95,17 +134,12 @@ __device__ __forceinline__ void explore_init_root(const RoundArgs& a, int N) {
 // in tk), 0 if resolved.
 // ---------------------------------------------------------------------------
 template <int N>
-__device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int n_B, const float* s_raw,
+__device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int lo, const float* s_raw,
                                            const float* s_out, const float* gl, const float* gh,
                                            long long& n_sim, long long& n_pre, long long& n_drop,
                                            SimTask& tk) {
     constexpr int W = N / 32;
     const int n_obs = a.n_obs;
-    int lo = 0, hi = n_B;  // b_off[lo] <= q < b_off[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.b_off[mid] <= q) lo = mid; else hi = mid;
-    }
     const int p = a.b_ids[lo];
     const int head = a.p_head[p];
     const int e = a.row_ptr[head] + (q - a.b_off[lo]);

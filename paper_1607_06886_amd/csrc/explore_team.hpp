@@ -303,7 +303,8 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         for (int tile = gwave * 64; tile < n_pairs; tile += n_gwaves * 64) {
             const int q = tile + lane;
             SimTask tk;
-            const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_raw, s_out, gl, gh, n_sim, n_pre,
+            const int grp = wave_group_of(a.b_off, n_B, tile, q);
+            const int st = q < n_pairs ? expand_pair<N>(a, q, grp, s_raw, s_out, gl, gh, n_sim, n_pre,
                                                          n_drop, tk) : 0;
             queue_pairs(a, st, tk);
         }

@@ -138,7 +138,8 @@ __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
     for (int tile = wave_global * 64; tile < n_pairs; tile += wave_stride * 64) {
         const int q = tile + lane;
         SimTask tk;
-        const int st = q < n_pairs ? expand_pair<N>(a, q, n_B, s_raw, s_out, gl, gh, n_sim, n_pre,
+        const int grp = wave_group_of(a.b_off, n_B, tile, q);
+        const int st = q < n_pairs ? expand_pair<N>(a, q, grp, s_raw, s_out, gl, gh, n_sim, n_pre,
                                                      n_drop, tk) : 0;
         queue_pairs(a, st, tk);
     }
