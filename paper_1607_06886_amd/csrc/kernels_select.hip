@@ -6,7 +6,10 @@
 
 namespace pump {
 
-__global__ __launch_bounds__(1024) void k_goal_collect(SelectArgs a) { goal_collect_block(a); }
+__global__ __launch_bounds__(1024) void k_goal_collect(SelectArgs a) {
+    for (int f = threadIdx.x; f < kMaxFront; f += blockDim.x) a.mc_counts[f] = 0;
+    goal_collect_block(a);
+}
 
 __global__ __launch_bounds__(256) void k_front(SelectArgs a) { front_block(a, kMaxFront); }
 
@@ -16,28 +19,88 @@ void launch_select_front(hipStream_t s, const SelectArgs& a) {
 }
 
 __global__ void k_waypoints(SelectArgs a, int n_paths) {
+    const int n = n_paths < 0 ? a.ctl->n_front : n_paths;
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < n_paths) waypoints_one(a, f);
+    if (f < n) waypoints_one(a, f);
 }
 
 void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths) {
-    k_waypoints<<<(n_paths + 63) / 64, 64, 0, s>>>(a, n_paths);
+    const int n = n_paths < 0 ? kMaxFront : n_paths;
+    if (n <= 0) return;
+    k_waypoints<<<(n + 63) / 64, 64, 0, s>>>(a, n_paths);
 }
 
-__global__ __launch_bounds__(kMcThreads) void k_mc(SelectArgs a) {
+// Rows of the MC grid when the front size is read on the device: each row
+// of workgroups takes front plans blockIdx.y, + kMcRows, ...
+constexpr int kMcRows = 16;
+
+__global__ __launch_bounds__(kMcThreads) void k_mc(SelectArgs a, int n_paths) {
     __shared__ float s_obs[kMaxObs * 6];
     __shared__ int s_hit[kMcParticles];
+    const int n = n_paths < 0 ? a.ctl->n_front : n_paths;
+    if ((int)blockIdx.y >= n) return;   // uniform per workgroup
     for (int t = threadIdx.x; t < a.n_obs * 6; t += blockDim.x) s_obs[t] = a.obs[t];
     __syncthreads();
-    const int f = blockIdx.y;
-    mc_block_count(a, a.wp + (size_t)f * (a.S_max + 1) * 3, a.wp_len[f], blockIdx.x * kMcParticles,
-                   s_obs, s_hit, &a.mc_counts[f]);
+    for (int f = blockIdx.y; f < n; f += gridDim.y) {
+        mc_block_count(a, a.wp + (size_t)f * (a.S_max + 1) * 3, a.wp_len[f],
+                       blockIdx.x * kMcParticles, s_obs, s_hit, &a.mc_counts[f]);
+        __syncthreads();   // s_hit is reused by the next plan
+    }
 }
 
 void launch_mc(hipStream_t s, const SelectArgs& a, int32_t n_paths) {
-    if (n_paths <= 0) return;
-    dim3 grid((a.M + kMcParticles - 1) / kMcParticles, n_paths);
-    k_mc<<<grid, kMcThreads, 0, s>>>(a);
+    if (n_paths == 0) return;
+    const int rows = n_paths < 0 ? kMcRows : n_paths;
+    dim3 grid((a.M + kMcParticles - 1) / kMcParticles, rows);
+    k_mc<<<grid, kMcThreads, 0, s>>>(a, n_paths);
+}
+
+// Alg. 5: with the front sorted by cp_hat, bisect (1-based m) on
+// MC(P_m) > alpha for the last plan certified below alpha; every front plan
+// must fit S_max steps.  One workgroup; thread 0 decides.
+__global__ __launch_bounds__(256) void k_select_final(SelectArgs a, double alpha) {
+    __shared__ int s_w[4];
+    int nv = 0;
+    for (int v = threadIdx.x; v < a.n_nodes; v += blockDim.x) nv += a.valid[v] ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) nv += __shfl_down(nv, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = nv;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    Ctl* c = a.ctl;
+    c->n_valid = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    c->sel_best = -1;
+    c->sel_plan = -1;
+    c->sel_bad_wp = 0;
+    const int nf = c->n_front;
+    if (c->n_goal == 0 || nf <= 0) {
+        c->sel_status = PUMP_NO_GOAL_PLAN;
+        return;
+    }
+    for (int f = 0; f < nf; ++f)
+        if (a.wp_len[f] < 0) c->sel_bad_wp = 1;
+    auto mc_gt = [&](int m) { return (double)a.mc_counts[m - 1] / (double)a.M > alpha; };
+    int l = 1, u = nf, m = (l + u + 1) / 2;
+    while (l != u) {
+        if (mc_gt(m)) u = m - 1; else l = m;
+        m = (l + u + 1) / 2;
+    }
+    if (mc_gt(m)) {
+        c->sel_status = PUMP_INFEASIBLE;
+        return;
+    }
+    const int id = a.front_ids[m - 1];
+    c->sel_status = PUMP_OK;
+    c->sel_best = m - 1;
+    c->sel_plan = id;
+    c->sel_mc = a.mc_counts[m - 1];
+    c->sel_len = a.path_len[m - 1];
+    c->sel_steps = a.wp_len[m - 1];
+    c->sel_pop = a.p_pop[id];
+    c->sel_cost = a.p_cost[id];
+}
+
+void launch_select_final(hipStream_t s, const SelectArgs& a, double alpha) {
+    k_select_final<<<1, 256, 0, s>>>(a, alpha);
 }
 
 // ---- Smooth(p*, alpha) ----

@@ -214,6 +214,8 @@ SelectArgs select_args(pump_ctx* c) {
     a.noise_mc_meas = c->noise_mc_meas;
     a.lqg = c->lqg;
     a.ctl = c->ctl;
+    a.valid = c->valid;
+    a.n_nodes = c->n_nodes;
     return a;
 }
 
@@ -814,87 +816,63 @@ int pump_select(pump_ctx* ctx, pump_result* out) {
     ctx->last_smoothed = false;
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
     SelectArgs a = select_args(ctx);
-    HIPCHK(hipMemsetAsync(ctx->mc_counts, 0, kMaxFront * sizeof(int32_t), ctx->stream));
+    // the whole of Alg. 5 on the device (front, waypoints, Monte Carlo,
+    // bisection), then one read-back of the control block
     tbeg(ctx, 7);
     launch_select_front(ctx->stream, a);
     tend(ctx);
+    launch_waypoints(ctx->stream, a, -1);
+    tbeg(ctx, 8);
+    launch_mc(ctx->stream, a, -1);
+    tend(ctx);
+    launch_select_final(ctx->stream, a, ctx->alpha);
+    HIPCHK(hipGetLastError());
     int r = read_ctl(ctx);
     if (r) return r;
-    if (ctx->ctl_h->err == 2) return fail(ctx, PUMP_E_CAPACITY, "Pareto front exceeds 256 plans");
-    if (ctx->ctl_h->n_goal > kMaxGoal) return fail(ctx, PUMP_E_CAPACITY, "P_goal exceeds 65536 plans");
-    const int nf = ctx->ctl_h->n_front;
-    res.n_goal_plans = ctx->ctl_h->n_goal;
-    res.n_front = nf;
-    if (ctx->ctl_h->n_goal == 0) {
-        res.status = PUMP_NO_GOAL_PLAN;
-    } else {
-        launch_waypoints(ctx->stream, a, nf);
-        tbeg(ctx, 8);
-        launch_mc(ctx->stream, a, nf);
-        tend(ctx);
-        HIPCHK(hipGetLastError());
-        std::vector<int32_t> ids(nf), mc(nf), wl(nf), plen(nf);
-        HIPCHK(hipMemcpyAsync(ids.data(), ctx->front_ids, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(hipMemcpyAsync(mc.data(), ctx->mc_counts, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(hipMemcpyAsync(wl.data(), ctx->wp_len, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(hipMemcpyAsync(plen.data(), ctx->path_len, nf * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
-        tresolve(ctx);
-        for (int f = 0; f < nf; ++f)
-            if (wl[f] < 0) return fail(ctx, PUMP_E_STATE, "front plan longer than max_steps");
-        // Alg. 5 bisection (1-based) on MC(P_m) > alpha
-        auto mc_gt = [&](int m) { return (double)mc[m - 1] / (double)ctx->M > ctx->alpha; };
-        int l = 1, u = nf, m = (l + u + 1) / 2;
-        while (l != u) {
-            if (mc_gt(m)) u = m - 1; else l = m;
-            m = (l + u + 1) / 2;
-        }
-        if (mc_gt(m)) {
-            res.status = PUMP_INFEASIBLE;
-        } else {
-            res.status = PUMP_OK;
-            res.best = m - 1;
-            res.best_plan = ids[m - 1];
-            res.best_mc_count = mc[m - 1];
-            res.best_cp_mc = (double)mc[m - 1] / (double)ctx->M;
-            res.best_len = plen[m - 1];
-            HIPCHK(hipMemcpy(&res.best_cost, ctx->p_cost + ids[m - 1], sizeof(double), hipMemcpyDeviceToHost));
-            HIPCHK(hipMemcpy(&res.best_pop, ctx->p_pop + ids[m - 1], sizeof(int32_t), hipMemcpyDeviceToHost));
-            ctx->last_best = m - 1;
-            res.smooth_beta = 0.0;
-            res.smooth_cost = res.best_cost;
-            res.smooth_mc_count = res.best_mc_count;
-            res.smooth_steps = wl[m - 1];
-            ctx->last_steps = wl[m - 1];
-            if (ctx->cfg.smooth) {
-                tbeg(ctx, 17);
-                launch_smooth(ctx->stream, a, ctx->sm, m - 1, ctx->p_cost + ids[m - 1], ctx->alpha,
-                              mc[m - 1], wl[m - 1]);
-                tend(ctx);
-                HIPCHK(hipGetLastError());
-                SmoothState st;
-                HIPCHK(hipMemcpyAsync(&st, ctx->sm.st, sizeof(st), hipMemcpyDeviceToHost, ctx->stream));
-                HIPCHK(hipStreamSynchronize(ctx->stream));
-                res.smooth_beta = st.beta;
-                res.smooth_cost = st.cost;
-                res.smooth_mc_count = st.count;
-                res.smooth_steps = st.steps;
-                ctx->last_steps = st.steps;
-                ctx->last_smoothed = true;
-            }
+    const Ctl* c = ctx->ctl_h;
+    if (c->err == 2) return fail(ctx, PUMP_E_CAPACITY, "Pareto front exceeds 256 plans");
+    if (c->n_goal > kMaxGoal) return fail(ctx, PUMP_E_CAPACITY, "P_goal exceeds 65536 plans");
+    if (c->sel_bad_wp) return fail(ctx, PUMP_E_STATE, "front plan longer than max_steps");
+    res.n_goal_plans = c->n_goal;
+    res.n_front = c->n_front;
+    res.status = c->sel_status;
+    if (res.status == PUMP_OK) {
+        const int m = c->sel_best + 1;   // 1-based, as in Alg. 5
+        res.best = m - 1;
+        res.best_plan = c->sel_plan;
+        res.best_mc_count = c->sel_mc;
+        res.best_cp_mc = (double)c->sel_mc / (double)ctx->M;
+        res.best_len = c->sel_len;
+        res.best_cost = c->sel_cost;
+        res.best_pop = c->sel_pop;
+        ctx->last_best = m - 1;
+        res.smooth_beta = 0.0;
+        res.smooth_cost = res.best_cost;
+        res.smooth_mc_count = res.best_mc_count;
+        res.smooth_steps = c->sel_steps;
+        ctx->last_steps = c->sel_steps;
+        if (ctx->cfg.smooth) {
+            tbeg(ctx, 17);
+            launch_smooth(ctx->stream, a, ctx->sm, m - 1, ctx->p_cost + c->sel_plan, ctx->alpha,
+                          c->sel_mc, c->sel_steps);
+            tend(ctx);
+            HIPCHK(hipGetLastError());
+            SmoothState st;
+            HIPCHK(hipMemcpyAsync(&st, ctx->sm.st, sizeof(st), hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            res.smooth_beta = st.beta;
+            res.smooth_cost = st.cost;
+            res.smooth_mc_count = st.count;
+            res.smooth_steps = st.steps;
+            ctx->last_steps = st.steps;
+            ctx->last_smoothed = true;
         }
     }
     HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev[3]));
     HIPCHK(hipEventElapsedTime(&ctx->ms_select, ctx->ev[2], ctx->ev[3]));
     fill_counters(ctx, &res);
-    int32_t nv = 0;
-    {
-        std::vector<uint8_t> v(ctx->n_nodes);
-        HIPCHK(hipMemcpy(v.data(), ctx->valid, ctx->n_nodes, hipMemcpyDeviceToHost));
-        for (uint8_t b : v) nv += b;
-    }
-    res.n_valid_nodes = nv;
+    res.n_valid_nodes = ctx->ctl_h->n_valid;
     if (out) *out = res;
     return res.status;
 }

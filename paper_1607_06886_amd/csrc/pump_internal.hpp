@@ -73,6 +73,18 @@ struct Ctl {
     long long phase_ticks[8];  // its phase wall times (real-time counter ticks)
     long long sim_waypoints;   // simulated (pair, waypoint) tests, each over N particles
     long long sim_box_tests;   // simulated (pair, waypoint, box) tests, each over N particles
+    // PlanSelection outcome (k_select_final)
+    int32_t sel_status;        // PUMP_OK, PUMP_NO_GOAL_PLAN or PUMP_INFEASIBLE
+    int32_t sel_best;          // front index of p* (-1: none)
+    int32_t sel_plan;          // plan id of p*
+    int32_t sel_mc;            // its Monte Carlo count
+    int32_t sel_len;           // its node count
+    int32_t sel_steps;         // its waypoint steps
+    int32_t sel_pop;           // its cp_hat count
+    int32_t sel_bad_wp;        // some front plan has more than S_max steps
+    int32_t n_valid;           // valid nodes
+    int32_t pad2_;
+    double sel_cost;           // cost of p*
 };
 
 // A pair queued for particle simulation, with what the simulation needs of
@@ -260,6 +272,8 @@ struct SelectArgs {
     const float* noise_mc_meas;  // [S_max][3][M]
     LqgCoef lqg;
     Ctl* ctl;
+    const uint8_t* valid;        // [n_nodes] (k_select_final counts them)
+    int32_t n_nodes;
 };
 
 // ---- Smooth(p*, alpha) (smooth_ops.hpp) ----
@@ -398,8 +412,12 @@ void launch_batch(hipStream_t s, BatchQuery* qs_dev, int q, int N_max, int max_n
 int batch_explore_per_cu(int N, int threads);
 
 void launch_select_front(hipStream_t s, const SelectArgs& a);
+// n_paths < 0: the front just built (its size read on the device).
 void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths);
 void launch_mc(hipStream_t s, const SelectArgs& a, int32_t n_paths);
+// Alg. 5's bisection over the certified front, on the device: fills the
+// sel_* fields and n_valid of the control block.
+void launch_select_final(hipStream_t s, const SelectArgs& a, double alpha);
 
 }  // namespace pump
 
