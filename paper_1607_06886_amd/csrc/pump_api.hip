@@ -100,7 +100,9 @@ struct pump_ctx {
     int32_t last_pairs = 0;
     int rounds = 0;
     float ms_setup = 0, ms_explore = 0, ms_select = 0;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // 0/4 setup begin/end, 1/2 Explore, 2/3 selection, 5/6 pump_plan
+    hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool setup_time_pending = false;   // ms_setup not yet read from ev[0], ev[4]
     std::string err;
     // per-kernel timing
     bool timing = false;
@@ -241,6 +243,9 @@ void tend(pump_ctx* c) {
 
 // After a stream synchronisation: accumulate the finished brackets.
 void tresolve(pump_ctx* c) {
+    if (c->setup_time_pending &&
+        hipEventElapsedTime(&c->ms_setup, c->ev[0], c->ev[4]) == hipSuccess)
+        c->setup_time_pending = false;
     for (auto& p : c->pending) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
@@ -627,16 +632,18 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
                           ctx->words_per_row, ctx->n_edges);
     }
     tend(ctx);
-    HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
-    HIPCHK(hipEventSynchronize(ctx->ev[1]));
-    tresolve(ctx);
+    // no wait here: the setup time is read at the next synchronisation
+    HIPCHK(hipEventRecord(ctx->ev[4], ctx->stream));
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventElapsedTime(&ctx->ms_setup, ctx->ev[0], ctx->ev[1]));
+    ctx->setup_time_pending = true;
     ctx->have_setup = true;
     return PUMP_OK;
 }
 
-int pump_explore_begin(pump_ctx* ctx) {
+// Root plan and empty staircases.  Without `sync` (pump_plan with the
+// single-launch Explore, which reads the loop state on the device) the host
+// does not wait for the root's state.
+static int explore_begin(pump_ctx* ctx, bool sync) {
     if (!ctx) return PUMP_E_ARG;
     if (!ctx->have_setup) return fail(ctx, PUMP_E_STATE, "pump_setup first");
     ctx->open_cur = ctx->open_b;
@@ -645,16 +652,21 @@ int pump_explore_begin(pump_ctx* ctx) {
     HIPCHK(hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream));
     launch_explore_init(ctx->stream, a, ctx->n_nodes, ctx->N);  // writes open_next
     std::swap(ctx->open_cur, ctx->open_next);
-    int r = read_ctl(ctx);
-    if (r) return r;
     HIPCHK(hipGetLastError());
     ctx->partial_plans = 0;
     ctx->rounds = 0;
     ctx->ms_explore = 0.0f;
     ctx->have_explore = true;
-    ctx->explore_done = ctx->ctl_h->done != 0;
+    ctx->explore_done = false;
+    if (sync) {
+        int r = read_ctl(ctx);
+        if (r) return r;
+        ctx->explore_done = ctx->ctl_h->done != 0;
+    }
     return PUMP_OK;
 }
+
+int pump_explore_begin(pump_ctx* ctx) { return explore_begin(ctx, true); }
 
 int pump_explore_round(pump_ctx* ctx, int32_t* done) {
     if (!ctx) return PUMP_E_ARG;
@@ -879,12 +891,10 @@ int pump_select(pump_ctx* ctx, pump_result* out) {
 
 int pump_plan(pump_ctx* ctx, const pump_problem* pr, pump_result* out) {
     if (!ctx || !pr) return PUMP_E_ARG;
-    hipEvent_t t0, t1;
-    HIPCHK(hipEventCreate(&t0));
-    HIPCHK(hipEventCreate(&t1));
+    hipEvent_t t0 = ctx->ev[5], t1 = ctx->ev[6];
     HIPCHK(hipEventRecord(t0, ctx->stream));
     int r = pump_setup(ctx, pr);
-    if (r == PUMP_OK) r = pump_explore_begin(ctx);
+    if (r == PUMP_OK) r = explore_begin(ctx, ctx->explore_mode != 1);
     if (r == PUMP_OK) r = pump_explore_run(ctx);
     pump_result res;
     memset(&res, 0, sizeof(res));
@@ -893,8 +903,6 @@ int pump_plan(pump_ctx* ctx, const pump_problem* pr, pump_result* out) {
     HIPCHK(hipEventSynchronize(t1));
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, t0, t1);
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
     res.ms_total = ms;
     if (out) *out = res;
     return r;
