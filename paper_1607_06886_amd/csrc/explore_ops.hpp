@@ -269,6 +269,29 @@ __device__ __forceinline__ void queue_pairs(const RoundArgs& a, int st, const Si
     if (st == 2) a.tasks[base + (int)__popcll(need & lanemask_lt(lane))] = tk;
 }
 
+// The same for a whole workgroup at once (all threads call it): one global
+// atomic per workgroup instead of one per wave.  s_w: [blockDim.x / 64].
+__device__ __forceinline__ void queue_pairs_block(const RoundArgs& a, int st, const SimTask& tk,
+                                                  int* s_w) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const unsigned long long need = __ballot(st == 2);
+    if (lane == 0) s_w[w] = (int)__popcll(need);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < nw; ++k) {
+            const int c = s_w[k];
+            s_w[k] = tot;
+            tot += c;
+        }
+        const int base = tot ? atomicAdd(&a.ctl->n_tasks, tot) : 0;
+        for (int k = 0; k < nw; ++k) s_w[k] += base;
+    }
+    __syncthreads();
+    if (st == 2) a.tasks[s_w[w] + (int)__popcll(need & lanemask_lt(lane))] = tk;
+    __syncthreads();   // s_w is reused
+}
+
 // ---------------------------------------------------------------------------
 // Expansion, second part (one queued pair per wave, particles across lanes):
 // at each marked waypoint, lanes test their particles against the obstacles

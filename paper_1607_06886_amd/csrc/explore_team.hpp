@@ -299,14 +299,20 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         partial += n_pairs;
         ++rounds;
         if (leader) t_prev = __builtin_amdgcn_s_memrealtime();
-        // (1) expansion, one pair per lane; particle simulations queued
-        for (int tile = gwave * 64; tile < n_pairs; tile += n_gwaves * 64) {
-            const int q = tile + lane;
+        // (1) expansion, one pair per lane (a wave per 64 pairs, the
+        //     workgroup's waves side by side); particle simulations queued
+        //     with one atomic per workgroup and pass
+        for (int base = b * T; base < n_pairs; base += G * T) {
+            const int tile = base + (tid & ~63);
+            const int q = base + tid;
             SimTask tk;
-            const int grp = wave_group_of(a.b_off, n_B, tile, q);
-            const int st = q < n_pairs ? expand_pair<N>(a, q, grp, s_raw, s_out, gl, gh, n_sim, n_pre,
-                                                         n_drop, tk) : 0;
-            queue_pairs(a, st, tk);
+            int st = 0;
+            if (tile < n_pairs) {   // the wave's pairs
+                const int grp = wave_group_of(a.b_off, n_B, tile, q);
+                st = q < n_pairs ? expand_pair<N>(a, q, grp, s_raw, s_out, gl, gh, n_sim, n_pre, n_drop,
+                                                  tk) : 0;
+            }
+            queue_pairs_block(a, st, tk, s_w);
         }
         if (team_barrier(g, epoch, s_fail_p)) break;
         if (leader) tick(0);
