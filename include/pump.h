@@ -389,9 +389,10 @@ typedef struct pump_batch_tuning {
     int32_t blocks_per_cu;   /* 1..8 persistent workgroups per compute unit */
     int32_t order;           /* 0: queue in input order; 1: largest query first */
     int32_t use_graph;       /* 1: capture the launches in a HIP graph and launch it */
-    int32_t team_scale;      /* workgroups per query: 0 = one; k > 0 = k/4 times the
+    int32_t team_scale;      /* workgroups per query: 0 = one; 1..256: k/4 times the
                                 query's share of the estimated work (samples^2 x
-                                sqrt(particles)) of all workgroups, at most 64 */
+                                sqrt(particles)) of all workgroups, at most 64
+                                workgroups per team */
 } pump_batch_tuning;
 
 /* Allocate per-query workspaces for up to max_queries queries, each sized by
@@ -405,7 +406,7 @@ int pump_batch_destroy(pump_batch* b);
  * the device, read only, kept alive until the call returns); n_particles[i]
  * is that query's N (32/64/128/256, at most cfg.n_particles; noise arrays are
  * [S_max][6][N] for that N).  tune may be NULL (256 threads, 2 per CU,
- * largest first, graph on, team_scale 4).  out[i] receives query i's result; the returned
+ * largest first, graph on, team_scale 64).  out[i] receives query i's result; the returned
  * code is PUMP_OK or the first negative per-query status.  ms_total holds the
  * wall time of the whole batch. */
 int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_particles,

@@ -675,7 +675,7 @@ class Batch:
         if tuning is not None:
             t = Tuning(*[int(tuning.get(k, d)) for k, d in (
                 ("explore_threads", 256), ("blocks_per_cu", 2), ("order", 1), ("use_graph", 1),
-                ("team_scale", 4))])
+                ("team_scale", 64))])
         rc = self.lib.pump_batch_plan(self.b, arr, ns, q, ctypes.byref(t) if t else None, out)
         if rc < 0 and raise_on_error:
             self._err(rc)

@@ -201,9 +201,9 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
     const pump_config& cfg = b->cfg;
     pump_batch_tuning t;
     if (tune) t = *tune;
-    else { t.explore_threads = 256; t.blocks_per_cu = 2; t.order = 1; t.use_graph = 1; t.team_scale = 4; }
+    else { t.explore_threads = 256; t.blocks_per_cu = 2; t.order = 1; t.use_graph = 1; t.team_scale = 64; }
     if (t.explore_threads != 256 ||
-        t.blocks_per_cu < 1 || t.blocks_per_cu > 8 || t.team_scale < 0 || t.team_scale > 64)
+        t.blocks_per_cu < 1 || t.blocks_per_cu > 8 || t.team_scale < 0 || t.team_scale > 256)
         return bfail(b, PUMP_E_ARG, "bad tuning");
     b->qs.assign(q, BatchQuery());
     int N_max = 0, max_nodes = 0;
@@ -449,10 +449,10 @@ int pump_batch_tune(pump_batch* b, const pump_problem* probs, const int32_t* n_p
     if (!b || !probs || !n_particles || !best) return PUMP_E_ARG;
     const int threads[1] = {256};
     const int per_cu[3] = {1, 2, 4};
-    const int scales[3] = {0, 4, 8};
+    const int scales[3] = {16, 64, 256};
     std::vector<pump_result> ref(q), cur(q);
     double bms = 1e30;
-    pump_batch_tuning bt{256, 2, 1, 1, 4};
+    pump_batch_tuning bt{256, 2, 1, 1, 64};
     std::string js = "{\"candidates\": [";
     bool first = true;
     bool have_ref = false;

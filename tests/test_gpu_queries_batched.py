@@ -92,7 +92,8 @@ def test_batch_matches_oracle():
 # query (team_scale > 0) and scales that give even the small queries teams
 TUNINGS = [dict(explore_threads=t, blocks_per_cu=c, order=o, use_graph=g, team_scale=k)
            for t, c, o, g, k in [(256, 2, 1, 1, 0), (256, 1, 0, 1, 0), (256, 4, 1, 1, 4),
-                                 (256, 1, 0, 0, 4), (256, 8, 1, 0, 8), (256, 2, 1, 1, 64)]]
+                                 (256, 1, 0, 0, 4), (256, 8, 1, 0, 8), (256, 2, 1, 1, 64),
+                                 (256, 2, 1, 1, 256)]]
 
 
 def test_batch_equals_single_query_path_under_every_shape():
