@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--batch-queries", type=int, default=256,
                     help="queries in the batched-engine leg (0 skips the leg)")
     ap.add_argument("--batch-steps", type=int, default=3)
-    ap.add_argument("--tune-queries", type=int, default=32)
+    ap.add_argument("--tune-queries", type=int, default=256)
     return ap.parse_args()
 
 
