@@ -710,7 +710,9 @@ int pump_explore_round(pump_ctx* ctx, int32_t* done) {
 }
 
 // Remaining rounds in one launch (see kernels_coop.hip).
-static int explore_single_launch(pump_ctx* ctx) {
+// The single launch in two halves: enqueue, and the bookkeeping once the
+// control block has been read back.
+static int explore_single_enqueue(pump_ctx* ctx) {
     RoundArgs a = round_args(ctx);
     CoopArgs ca;
     ca.sync.release = ctx->coop_sync;
@@ -736,8 +738,10 @@ static int explore_single_launch(pump_ctx* ctx) {
                           ctx->stream));
     HIPCHK(launch_explore_coop(ctx->stream, ctx->ra_dev, ca, ctx->N, ctx->coop_blocks));
     tend(ctx);
-    int r = read_ctl(ctx);
-    if (r) return r;
+    return PUMP_OK;
+}
+
+static int explore_single_finish(pump_ctx* ctx) {
     const Ctl* c = ctx->ctl_h;
     if (ctx->timing) {
         // the real-time counter runs at 100 MHz
@@ -753,9 +757,18 @@ static int explore_single_launch(pump_ctx* ctx) {
     if (c->err == 3) return fail(ctx, PUMP_E_STATE, "open plans without a finite cost");
     if (c->err == 5) return fail(ctx, PUMP_E_STATE, "grid barrier timed out");
     if (c->err == 6) return fail(ctx, PUMP_E_STATE, "Explore did not terminate");
-    if (c->err) return fail(ctx, PUMP_E_CAPACITY, "plan store exceeds cap_plans");
+    // (2 is the selection's code for an oversized front, set when the
+    // selection already ran behind the launch)
+    if (c->err && c->err != 2) return fail(ctx, PUMP_E_CAPACITY, "plan store exceeds cap_plans");
     ctx->explore_done = true;
     return PUMP_OK;
+}
+
+static int explore_single_launch(pump_ctx* ctx) {
+    int r = explore_single_enqueue(ctx);
+    if (r == PUMP_OK) r = read_ctl(ctx);
+    if (r == PUMP_OK) r = explore_single_finish(ctx);
+    return r;
 }
 
 int pump_explore_run(pump_ctx* ctx) {
@@ -817,9 +830,10 @@ static void fill_counters(pump_ctx* ctx, pump_result* o) {
     o->ms_select = ctx->ms_select;
 }
 
-int pump_select(pump_ctx* ctx, pump_result* out) {
-    if (!ctx) return PUMP_E_ARG;
-    if (!ctx->have_explore || !ctx->explore_done) return fail(ctx, PUMP_E_STATE, "explore not finished");
+// PlanSelection.  With explore_pending the single-launch Explore was only
+// enqueued: the selection kernels follow it on the stream (reading the plan
+// count on the device) and its bookkeeping runs after the one read-back.
+static int select_impl(pump_ctx* ctx, pump_result* out, bool explore_pending) {
     pump_result res;
     memset(&res, 0, sizeof(res));
     res.best = -1;
@@ -828,6 +842,7 @@ int pump_select(pump_ctx* ctx, pump_result* out) {
     ctx->last_smoothed = false;
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
     SelectArgs a = select_args(ctx);
+    if (explore_pending) a.n_plans = -1;
     // the whole of Alg. 5 on the device (front, waypoints, Monte Carlo,
     // bisection), then one read-back of the control block
     tbeg(ctx, 7);
@@ -841,6 +856,12 @@ int pump_select(pump_ctx* ctx, pump_result* out) {
     HIPCHK(hipGetLastError());
     int r = read_ctl(ctx);
     if (r) return r;
+    if (explore_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) ctx->ms_explore = ms;
+        r = explore_single_finish(ctx);
+        if (r) return r;
+    }
     const Ctl* c = ctx->ctl_h;
     if (c->err == 2) return fail(ctx, PUMP_E_CAPACITY, "Pareto front exceeds 256 plans");
     if (c->n_goal > kMaxGoal) return fail(ctx, PUMP_E_CAPACITY, "P_goal exceeds 65536 plans");
@@ -889,16 +910,33 @@ int pump_select(pump_ctx* ctx, pump_result* out) {
     return res.status;
 }
 
+int pump_select(pump_ctx* ctx, pump_result* out) {
+    if (!ctx) return PUMP_E_ARG;
+    if (!ctx->have_explore || !ctx->explore_done) return fail(ctx, PUMP_E_STATE, "explore not finished");
+    return select_impl(ctx, out, false);
+}
+
 int pump_plan(pump_ctx* ctx, const pump_problem* pr, pump_result* out) {
     if (!ctx || !pr) return PUMP_E_ARG;
     hipEvent_t t0 = ctx->ev[5], t1 = ctx->ev[6];
     HIPCHK(hipEventRecord(t0, ctx->stream));
     int r = pump_setup(ctx, pr);
-    if (r == PUMP_OK) r = explore_begin(ctx, ctx->explore_mode != 1);
-    if (r == PUMP_OK) r = pump_explore_run(ctx);
+    // with the single-launch Explore the host enqueues Explore and the
+    // selection back to back and waits once, at the end
+    const bool one_wait = ctx->explore_mode == 1;
+    if (r == PUMP_OK) r = explore_begin(ctx, !one_wait);
     pump_result res;
     memset(&res, 0, sizeof(res));
-    if (r == PUMP_OK) r = pump_select(ctx, &res);
+    if (one_wait) {
+        if (r == PUMP_OK) {
+            HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
+            r = explore_single_enqueue(ctx);
+        }
+        if (r == PUMP_OK) r = select_impl(ctx, &res, true);
+    } else {
+        if (r == PUMP_OK) r = pump_explore_run(ctx);
+        if (r == PUMP_OK) r = pump_select(ctx, &res);
+    }
     HIPCHK(hipEventRecord(t1, ctx->stream));
     HIPCHK(hipEventSynchronize(t1));
     float ms = 0.0f;

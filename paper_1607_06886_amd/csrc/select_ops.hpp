@@ -8,17 +8,20 @@
 namespace pump {
 
 // P_goal = plans still in P(v) for goal nodes v (Alg. 4 return), in id order
-// (whole block; blockDim.x a multiple of 64, at most 1024).
+// (whole block; blockDim.x a multiple of 64, at most 1024).  a.n_plans < 0:
+// the plan count is read from the control block (Explore still in flight on
+// the stream when the host enqueued this).
 __device__ __forceinline__ void goal_collect_block(const SelectArgs& a) {
+    const int n_plans = a.n_plans >= 0 ? a.n_plans : a.ctl->n_plans;
     __shared__ int s_w[16];
     __shared__ int s_base;
     const int nw = blockDim.x >> 6;
     if (threadIdx.x == 0) s_base = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int b0 = 0; b0 < a.n_plans; b0 += blockDim.x) {
+    for (int b0 = 0; b0 < n_plans; b0 += blockDim.x) {
         const int p = b0 + threadIdx.x;
-        const bool f = p < a.n_plans && a.p_state[p] != kRemoved && a.goal[a.p_head[p]];
+        const bool f = p < n_plans && a.p_state[p] != kRemoved && a.goal[a.p_head[p]];
         const unsigned long long m = __ballot(f);
         if (lane == 0) s_w[wave] = __popcll(m);
         __syncthreads();
