@@ -77,6 +77,8 @@ struct pump_ctx {
     RoundArgs* ra_h = nullptr;      // [2] pinned staging
     Ctl* ctl = nullptr;
     Ctl* ctl_h = nullptr;  // pinned mirror
+    int32_t* stage_h = nullptr;   // pinned: [0] n_nodes up, [4..8) flags and counters, [8] edges down
+    float* xinit_h = nullptr;     // pinned: x_init on its way to node 0
     // selection
     int32_t *goal_ids = nullptr, *front_ids = nullptr, *paths = nullptr, *path_len = nullptr,
             *wp_len = nullptr, *mc_counts = nullptr;
@@ -334,6 +336,8 @@ int pump_destroy(pump_ctx* ctx) {
         if (p) (void)hipFree(p);
     if (ctx->ctl_h) (void)hipHostFree(ctx->ctl_h);
     if (ctx->ra_h) (void)hipHostFree(ctx->ra_h);
+    if (ctx->stage_h) (void)hipHostFree(ctx->stage_h);
+    if (ctx->xinit_h) (void)hipHostFree(ctx->xinit_h);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& p : ctx->pending) ctx->pool.push_back({p.a, p.b});
@@ -467,6 +471,8 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     A(dalloc(&ctx->sm.out_wp, (S + 1) * 3));
     A(dalloc(&ctx->wp, (size_t)kMaxFront * (S + 1) * 3));
     A(hipHostMalloc((void**)&ctx->ctl_h, sizeof(Ctl), hipHostMallocDefault));
+    A(hipHostMalloc((void**)&ctx->stage_h, 16 * sizeof(int32_t), hipHostMallocDefault));
+    A(hipHostMalloc((void**)&ctx->xinit_h, 8 * sizeof(float), hipHostMallocDefault));
     for (auto& e : ctx->ev) A(hipEventCreate(&e));
     if (!ok) {
         pump_destroy(ctx);
@@ -538,7 +544,10 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
 
     HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
     // uploads: x_init is node 0, sample i is node i + 1
-    HIPCHK(hipMemcpyAsync(ctx->X, pr->x_init, 6 * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    // (small uploads go through pinned buffers, so the copies stay asynchronous;
+    //  the previous query's copies from them finished at its last wait)
+    memcpy(ctx->xinit_h, pr->x_init, 6 * sizeof(float));
+    HIPCHK(hipMemcpyAsync(ctx->X, ctx->xinit_h, 6 * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->X + 6, pr->samples, (size_t)pr->n * 6 * sizeof(float), kind, ctx->stream));
     if (pr->n_obs > 0)
         HIPCHK(hipMemcpyAsync(ctx->obs, pr->obstacles, (size_t)pr->n_obs * 6 * sizeof(float), kind, ctx->stream));
@@ -597,14 +606,19 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
                           (double)cfg.r_steer, (double)cfg.r_conn, ctx->ebits, ctx->deg,
                           ctx->words_per_row, gw);
     tend(ctx);
-    int32_t nn = ctx->n_nodes;
-    HIPCHK(hipMemcpyAsync(ctx->dev_ints, &nn, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-    scan_exclusive(ctx->stream, ctx->deg, ctx->row_ptr, ctx->dev_ints, nn, &ctx->ctl->scan_total[4],
+    const int32_t nn = ctx->n_nodes;
+    ctx->stage_h[0] = nn;
+    HIPCHK(hipMemcpyAsync(ctx->dev_ints, ctx->stage_h, sizeof(int32_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+    // the scan's total is the edge count, written to row_ptr[n_nodes]
+    scan_exclusive(ctx->stream, ctx->deg, ctx->row_ptr, ctx->dev_ints, nn, ctx->row_ptr + nn,
                    ctx->blk);
-    HIPCHK(hipMemcpyAsync(ctx->ctl_h, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
-    int32_t flags[4];
-    HIPCHK(hipMemcpyAsync(flags, ctx->dev_ints, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->stage_h + 4, ctx->dev_ints, 4 * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->stage_h + 8, ctx->row_ptr + nn, sizeof(int32_t),
+                          hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    const int32_t* flags = ctx->stage_h + 4;
     if (flags[1] & 1) return fail(ctx, PUMP_E_ARG, "a sample or obstacle is not finite or lies outside [-16, 16]");
     if (flags[1] & 2) return fail(ctx, PUMP_E_ARG, "x_init lies in an obstacle");
     if (flags[1] & 4) return fail(ctx, PUMP_E_ARG, "the samples differ from the roadmap's");
@@ -614,12 +628,10 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
     if ((long long)flags[3] > cfg.cap_pairs)
         return fail(ctx, PUMP_E_CAPACITY, "exact box tests " + std::to_string(flags[3]) +
                                               " exceed cap_pairs");
-    ctx->n_edges = ctx->ctl_h->scan_total[4];
+    ctx->n_edges = ctx->stage_h[8];
     if ((long long)ctx->n_edges > cfg.cap_edges)
         return fail(ctx, PUMP_E_CAPACITY, "graph edges " + std::to_string(ctx->n_edges) +
                                               " exceed cap_edges");
-    HIPCHK(hipMemcpyAsync(ctx->row_ptr + nn, &ctx->n_edges, sizeof(int32_t), hipMemcpyHostToDevice,
-                          ctx->stream));
     tbeg(ctx, 2);
     if (ctx->rm) {
         launch_graph_cols(ctx->stream, ctx->n_nodes, ctx->ebits, ctx->row_ptr, ctx->col, ctx->esrc,
