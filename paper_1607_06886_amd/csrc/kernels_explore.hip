@@ -98,20 +98,28 @@ void scan_exclusive(hipStream_t s, const int32_t* in, int32_t* out, const int32_
 // root = (x_init, [], 0, 0), i = 0.  The dominance staircase of every node
 // starts empty (+inf); the root puts cost 0 at every pop level of node 0.
 // ---------------------------------------------------------------------------
-__global__ void k_init_fill(RoundArgs a, int n_nodes) {
-    explore_init_fill(a, n_nodes, (size_t)blockIdx.x * blockDim.x + threadIdx.x,
-                      (size_t)gridDim.x * blockDim.x);
+__global__ void k_init_fill(RoundArgs a, int n_nodes, unsigned* zero, int n_zero) {
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    explore_init_fill(a, n_nodes, t0, stride);
+    for (size_t t = t0; t < (size_t)n_zero; t += stride) zero[t] = 0u;
 }
 
+// The whole control block is cleared before the root's fields are set.
 __global__ void k_root(RoundArgs a, int N) {
+    unsigned* w = reinterpret_cast<unsigned*>(a.ctl);
+    for (int t = threadIdx.x; t < (int)(sizeof(Ctl) / sizeof(unsigned)); t += blockDim.x) w[t] = 0u;
+    __syncthreads();
     if (threadIdx.x == 0 && blockIdx.x == 0) explore_init_root(a, N);
 }
 
-void launch_explore_init(hipStream_t s, const RoundArgs& a, int n_nodes, int N) {
+void launch_explore_init(hipStream_t s, const RoundArgs& a, int n_nodes, int N, unsigned* zero,
+                         int n_zero) {
     size_t n = (size_t)n_nodes * a.stair_w;
+    if ((size_t)n_zero > n) n = (size_t)n_zero;
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    k_init_fill<<<(unsigned)blocks, 256, 0, s>>>(a, n_nodes);
+    k_init_fill<<<(unsigned)blocks, 256, 0, s>>>(a, n_nodes, zero, n_zero);
     k_root<<<1, 64, 0, s>>>(a, N);
 }
 

@@ -661,8 +661,9 @@ static int explore_begin(pump_ctx* ctx, bool sync) {
     ctx->open_cur = ctx->open_b;
     ctx->open_next = ctx->open_a;
     RoundArgs a = round_args(ctx);
-    HIPCHK(hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream));
-    launch_explore_init(ctx->stream, a, ctx->n_nodes, ctx->N);  // writes open_next
+    // (also clears the control block and the single launch's barrier words)
+    launch_explore_init(ctx->stream, a, ctx->n_nodes, ctx->N, ctx->coop_sync,
+                        (int)(64 + 4096 + 4 * (size_t)ctx->coop_blocks));  // writes open_next
     std::swap(ctx->open_cur, ctx->open_next);
     HIPCHK(hipGetLastError());
     ctx->partial_plans = 0;
@@ -737,8 +738,7 @@ static int explore_single_enqueue(pump_ctx* ctx) {
     ca.open_cur = ctx->open_cur;
     ca.open_next = ctx->open_next;
     ca.cap_pairs = ctx->cfg.cap_pairs;
-    HIPCHK(hipMemsetAsync(ctx->coop_sync, 0, (64 + 4096 + 4 * (size_t)ctx->coop_blocks) * sizeof(unsigned),
-                          ctx->stream));
+    // (the barrier words were cleared by explore_begin)
     tbeg(ctx, 9);
     ctx->ra_h[0] = a;
     ctx->ra_h[0].open_in = ctx->open_cur;

@@ -235,7 +235,10 @@ void launch_graph_fill(hipStream_t s, const float* X, int n_nodes, double r_stee
 void scan_exclusive(hipStream_t s, const int32_t* in, int32_t* out, const int32_t* n_dev,
                     int32_t n_upper, int32_t* total_dev, int32_t* blk_scratch);
 
-void launch_explore_init(hipStream_t s, const RoundArgs& a, int n_nodes, int N);
+// Also clears the control block and n_zero words at `zero` (the single
+// launch's barrier words).
+void launch_explore_init(hipStream_t s, const RoundArgs& a, int n_nodes, int N, unsigned* zero,
+                         int n_zero);
 void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs);
 void launch_prune(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, int32_t n_open);
 void launch_compact(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs,
