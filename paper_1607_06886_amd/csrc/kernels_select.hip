@@ -18,16 +18,17 @@ void launch_select_front(hipStream_t s, const SelectArgs& a) {
     k_front<<<1, 256, 0, s>>>(a);
 }
 
-__global__ void k_waypoints(SelectArgs a, int n_paths) {
+// One wave per path (waypoints_wave).
+__global__ __launch_bounds__(64) void k_waypoints(SelectArgs a, int n_paths) {
     const int n = n_paths < 0 ? a.ctl->n_front : n_paths;
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < n) waypoints_one(a, f);
+    const int f = blockIdx.x;
+    if (f < n) waypoints_wave(a, f);
 }
 
 void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths) {
     const int n = n_paths < 0 ? kMaxFront : n_paths;
     if (n <= 0) return;
-    k_waypoints<<<(n + 63) / 64, 64, 0, s>>>(a, n_paths);
+    k_waypoints<<<n, 64, 0, s>>>(a, n_paths);
 }
 
 // Rows of the MC grid when the front size is read on the device: each row

@@ -145,6 +145,50 @@ __device__ __forceinline__ void waypoints_one(const SelectArgs& a, int f) {
     a.wp_len[f] = ok ? s : -1;
 }
 
+// The same for one path by a whole wave (all 64 lanes call it): lane l takes
+// the path's edges l + 1, l + 65, ...; the edges' waypoint counts are scanned
+// across the wave for their offsets, so the root solves run side by side.
+// Every waypoint is computed as in waypoints_one (same steer, same cubic,
+// same t_k), so the table is identical; a path past S_max gets wp_len -1.
+__device__ __forceinline__ void waypoints_wave(const SelectArgs& a, int f) {
+    const int lane = threadIdx.x & 63;
+    const int stride = a.S_max + 1;
+    const int* nodes = a.paths + (size_t)f * stride;
+    const int len = a.path_len[f];
+    double* wp = a.wp + (size_t)f * stride * 3;
+    if (lane == 0) {
+        const float* x0 = a.X + (size_t)nodes[0] * 6;
+        for (int ax = 0; ax < 3; ++ax) wp[ax] = (double)x0[ax];
+    }
+    int s0 = 0;                            // waypoints before this chunk of edges
+    for (int l0 = 1; l0 < len; l0 += 64) {
+        const int l = l0 + lane;
+        double tau = 0.0;
+        int K = 0;
+        if (l < len) {
+            double c;
+            steer64(a.X + (size_t)nodes[l - 1] * 6, a.X + (size_t)nodes[l] * 6, a.r_steer, tau, c);
+            K = max(1, (int)ceil(tau / a.dt));
+        }
+        int x = K;                         // inclusive scan of K over the lanes
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const int s = s0 + x - K;          // this edge's first step - 1
+        if (l < len) {
+            Cubic cs[3];
+            hermite(a.X + (size_t)nodes[l - 1] * 6, a.X + (size_t)nodes[l] * 6, tau, cs);
+            for (int k = 1; k <= K && s + k <= a.S_max; ++k) {
+                const double t = ((double)k * tau) / (double)K;
+                for (int ax = 0; ax < 3; ++ax) wp[(size_t)(s + k) * 3 + ax] = cs[ax].at(t);
+            }
+        }
+        s0 += __shfl(x, 63, 64);
+    }
+    if (lane == 0) a.wp_len[f] = s0 <= a.S_max ? s0 : -1;
+}
+
 // Does the segment prev -> cur meet one of the closed obstacle boxes
 // o0, o0 + ostep, ...?  Slab clipping in FP64 after a bounding-box reject.
 __device__ __forceinline__ bool segment_hits_boxes(const double prev[3], const double cur[3],
