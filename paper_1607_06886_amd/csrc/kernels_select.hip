@@ -6,17 +6,16 @@
 
 namespace pump {
 
-__global__ __launch_bounds__(1024) void k_goal_collect(SelectArgs a) {
+// P_goal and its sorted Pareto front in one workgroup (the front reads the
+// goal count thread 0 stored, after the workgroup barrier).
+__global__ __launch_bounds__(1024) void k_goal_front(SelectArgs a) {
     for (int f = threadIdx.x; f < kMaxFront; f += blockDim.x) a.mc_counts[f] = 0;
     goal_collect_block(a);
+    __syncthreads();
+    front_block(a, kMaxFront);
 }
 
-__global__ __launch_bounds__(256) void k_front(SelectArgs a) { front_block(a, kMaxFront); }
-
-void launch_select_front(hipStream_t s, const SelectArgs& a) {
-    k_goal_collect<<<1, 1024, 0, s>>>(a);
-    k_front<<<1, 256, 0, s>>>(a);
-}
+void launch_select_front(hipStream_t s, const SelectArgs& a) { k_goal_front<<<1, 1024, 0, s>>>(a); }
 
 // One wave per path (waypoints_wave).
 __global__ __launch_bounds__(64) void k_waypoints(SelectArgs a, int n_paths) {
