@@ -46,7 +46,8 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const int32_t* __restrict__
 }
 
 __global__ __launch_bounds__(256) void k_scan_blocks(int32_t* __restrict__ blk, int nblk,
-                                                     int32_t* __restrict__ total_dev) {
+                                                     int32_t* __restrict__ total_dev,
+                                                     int32_t* __restrict__ total2_dev) {
     __shared__ int s_tmp[4];
     int carry = 0;
     for (int b0 = 0; b0 < nblk; b0 += 256) {
@@ -57,7 +58,10 @@ __global__ __launch_bounds__(256) void k_scan_blocks(int32_t* __restrict__ blk, 
         if (idx < nblk) blk[idx] = carry + ex;
         carry += total;
     }
-    if (threadIdx.x == 0) *total_dev = carry;
+    if (threadIdx.x == 0) {
+        *total_dev = carry;
+        if (total2_dev) *total2_dev = carry;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_scan_down(const int32_t* __restrict__ in,
@@ -85,11 +89,11 @@ __global__ __launch_bounds__(256) void k_scan_down(const int32_t* __restrict__ i
 }
 
 void scan_exclusive(hipStream_t s, const int32_t* in, int32_t* out, const int32_t* n_dev,
-                    int32_t n_upper, int32_t* total_dev, int32_t* blk) {
+                    int32_t n_upper, int32_t* total_dev, int32_t* blk, int32_t* total2_dev) {
     int nblk = (n_upper + kScanBlock - 1) / kScanBlock;
     if (nblk < 1) nblk = 1;
     k_scan_reduce<<<nblk, 256, 0, s>>>(in, n_dev, blk);
-    k_scan_blocks<<<1, 256, 0, s>>>(blk, nblk, total_dev);
+    k_scan_blocks<<<1, 256, 0, s>>>(blk, nblk, total_dev, total2_dev);
     k_scan_down<<<nblk, 256, 0, s>>>(in, out, n_dev, blk);
 }
 

@@ -77,7 +77,7 @@ struct pump_ctx {
     RoundArgs* ra_h = nullptr;      // [2] pinned staging
     Ctl* ctl = nullptr;
     Ctl* ctl_h = nullptr;  // pinned mirror
-    int32_t* stage_h = nullptr;   // pinned: [0] n_nodes up, [4..8) flags and counters, [8] edges down
+    int32_t* stage_h = nullptr;   // pinned: [0] n_nodes up; [4..9) flags, counters and edges down
     float* xinit_h = nullptr;     // pinned: x_init on its way to node 0
     // selection
     int32_t *goal_ids = nullptr, *front_ids = nullptr, *paths = nullptr, *path_len = nullptr,
@@ -610,12 +610,11 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
     ctx->stage_h[0] = nn;
     HIPCHK(hipMemcpyAsync(ctx->dev_ints, ctx->stage_h, sizeof(int32_t), hipMemcpyHostToDevice,
                           ctx->stream));
-    // the scan's total is the edge count, written to row_ptr[n_nodes]
+    // the scan's total is the edge count, written to row_ptr[n_nodes] and to
+    // dev_ints[4], so one read-back brings it with the flags and counters
     scan_exclusive(ctx->stream, ctx->deg, ctx->row_ptr, ctx->dev_ints, nn, ctx->row_ptr + nn,
-                   ctx->blk);
-    HIPCHK(hipMemcpyAsync(ctx->stage_h + 4, ctx->dev_ints, 4 * sizeof(int32_t),
-                          hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->stage_h + 8, ctx->row_ptr + nn, sizeof(int32_t),
+                   ctx->blk, ctx->dev_ints + 4);
+    HIPCHK(hipMemcpyAsync(ctx->stage_h + 4, ctx->dev_ints, 5 * sizeof(int32_t),
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     const int32_t* flags = ctx->stage_h + 4;
@@ -628,7 +627,7 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
     if ((long long)flags[3] > cfg.cap_pairs)
         return fail(ctx, PUMP_E_CAPACITY, "exact box tests " + std::to_string(flags[3]) +
                                               " exceed cap_pairs");
-    ctx->n_edges = ctx->stage_h[8];
+    ctx->n_edges = flags[4];
     if ((long long)ctx->n_edges > cfg.cap_edges)
         return fail(ctx, PUMP_E_CAPACITY, "graph edges " + std::to_string(ctx->n_edges) +
                                               " exceed cap_edges");

@@ -232,8 +232,10 @@ void launch_graph_fill(hipStream_t s, const float* X, int n_nodes, double r_stee
                        const uint32_t* ebits, const int32_t* row_ptr, int32_t* col,
                        int32_t* esrc, double* etau, double* ecost, int words, int n_edges);
 
+// The total goes to *total_dev and, if given, also to *total2_dev.
 void scan_exclusive(hipStream_t s, const int32_t* in, int32_t* out, const int32_t* n_dev,
-                    int32_t n_upper, int32_t* total_dev, int32_t* blk_scratch);
+                    int32_t n_upper, int32_t* total_dev, int32_t* blk_scratch,
+                    int32_t* total2_dev = nullptr);
 
 // Also clears the control block and n_zero words at `zero` (the single
 // launch's barrier words).
