@@ -12,9 +12,8 @@ V_c = sigma^2 * I on the 6 state derivatives; the tracking law is the
 steady-state discrete LQR gain with full-state feedback (du = -K dx),
 Q = diag(q_pos, q_vel), R = r_track; the deviation process starts at zero at
 the start state and its noise is indexed by (tracking step, particle), shared by
-every plan, so the deviation at plan step s does not depend on the plan; the
-deviation table is stored in FP32 (the kernel's storage precision), which is
-the one place the oracle rounds.
+every plan, so the deviation at plan step s does not depend on the plan.  Every
+quantity here stays in FP64.
 """
 
 from __future__ import annotations
@@ -96,9 +95,9 @@ def deviation_states(A_cl, L, noise, steps):
 
 
 def deviation_table(A_cl, L, noise, steps):
-    """Position part of the deviations, D[s][a][j], rounded to FP32 storage."""
+    """Position part of the deviations, D[s][a][j] (FP64)."""
     dev = deviation_states(A_cl, L, noise, steps)
-    return dev[:, :, 0, :].astype(np.float32)
+    return np.ascontiguousarray(dev[:, :, 0, :])
 
 
 # ---------------------------------------------------------------------------
@@ -169,5 +168,5 @@ def lqg_deviation_states(M, E, noise, noise_meas, steps):
 
 
 def lqg_deviation_table(M, E, noise, noise_meas, steps):
-    """Position part of the true deviation, D[s][a][j], rounded to FP32."""
-    return lqg_deviation_states(M, E, noise, noise_meas, steps)[:, :, 0, :].astype(np.float32)
+    """Position part of the true deviation, D[s][a][j] (FP64)."""
+    return np.ascontiguousarray(lqg_deviation_states(M, E, noise, noise_meas, steps)[:, :, 0, :])

@@ -24,7 +24,7 @@ Readings used here:
 from __future__ import annotations
 
 import dataclasses
-from typing import Dict, List
+from typing import Dict, List, Optional
 
 import numpy as np
 
@@ -40,6 +40,9 @@ class Plan:
     step: int           # tracking steps covered so far
     mask: np.ndarray    # bool [N]: particle j invalid
     parent: int
+    # bool [N]: particles whose bit was decided within EPS_FLAG of a face
+    # somewhere along the plan while still valid (None: not tracked)
+    fmask: Optional[np.ndarray] = None
     pop: int = dataclasses.field(init=False)   # number of invalid particles
 
     def __post_init__(self):
@@ -60,7 +63,11 @@ def extend_batch(V, graph, D, boxes, dt, S_max, parents: List[Plan], edges: np.n
     half-spaces (hsmc.py).  hs_cache (dict) keeps the half-spaces of each
     (edge, waypoint).
 
-    Returns (x, cost, step, mask [m, N], over_steps [m], flagged [m])."""
+    A (pair, particle) decision is flagged when the parent's bit is 0, the
+    particle comes within EPS_FLAG of a face (or a half-space boundary) at one
+    of the edge's waypoints and nowhere lies EPS_FLAG or more inside.
+
+    Returns (x, cost, step, mask [m, N], over_steps [m], flagged [m, N])."""
     if cp_model == "hsmc":
         return _extend_hsmc(V, graph, D, boxes, dt, S_max, parents, edges,
                             {} if hs_cache is None else hs_cache)
@@ -79,8 +86,8 @@ def extend_batch(V, graph, D, boxes, dt, S_max, parents: List[Plan], edges: np.n
     over = step > S_max
     mask = np.stack([p.mask for p in parents]) if m else np.zeros((0, N), bool)
     mask = mask.copy()
-    flagged = np.zeros(m, np.int64)
-    Dd = D.astype(np.float64)
+    flagged = np.zeros((m, N), bool)
+    Dd = np.asarray(D, np.float64)
     for c0 in range(0, m, chunk):
         sl = slice(c0, min(m, c0 + chunk))
         idx = np.arange(sl.start, sl.stop)
@@ -109,7 +116,7 @@ def extend_batch(V, graph, D, boxes, dt, S_max, parents: List[Plan], edges: np.n
             best = np.maximum(best, depth.max(axis=1))
             near |= ((np.abs(depth) < EPS_FLAG) & live[..., None]).any(axis=1)
         par = mask[idx]
-        flagged[idx] = ((~par) & near & (best < EPS_FLAG)).sum(axis=1)
+        flagged[idx] = (~par) & near & (best < EPS_FLAG)
         mask[idx] = par | hit
     return x, cost, step, mask, over, flagged
 
@@ -131,8 +138,8 @@ def _extend_hsmc(V, graph, D, boxes, dt, S_max, parents, edges, cache):
     over = step > S_max
     mask = np.stack([p.mask for p in parents]) if m else np.zeros((0, N), bool)
     mask = mask.copy()
-    flagged = np.zeros(m, np.int64)
-    Dd = D.astype(np.float64)
+    flagged = np.zeros((m, N), bool)
+    Dd = np.asarray(D, np.float64)
     for q in range(m):
         if over[q]:
             continue
@@ -161,9 +168,36 @@ def _extend_hsmc(V, graph, D, boxes, dt, S_max, parents, edges, cache):
             best = np.maximum(best, mg.max(axis=0))
             near |= (np.abs(mg) < EPS_FLAG).any(axis=0)
         par = mask[q]
-        flagged[q] = int(((~par) & near & (best < EPS_FLAG)).sum())
+        flagged[q] = (~par) & near & (best < EPS_FLAG)
         mask[q] = par | hit
     return x, cost, step, mask, over, flagged
+
+
+def dominates(d: Plan, p: Plan) -> bool:
+    """d dominates p (Sec. IV, RemoveDominated): d is strictly cheaper and its
+    particle CP estimate is no larger (cp_hat = pop / N with the same N, so
+    comparing pops is comparing cp_hat)."""
+    return d.cost < p.cost and d.pop <= p.pop
+
+
+def remove_dominated(plans: List[Plan], P: Dict[int, List[int]], P_open: set) -> set:
+    """RemoveDominated(P, P_open) (Sec. IV primitives; called once per round in
+    Alg. 4 after every candidate of the group has been inserted).
+
+    Only plans of P_open are candidates for removal -- the group just expanded
+    is still in P_open at this point -- and each is tested against every plan
+    of P(head) (open or closed), all tests taking the sets as they are on entry.
+    A removed plan leaves both P(head) and P_open; closed plans are never
+    removed.  Returns the set of removed plan ids."""
+    removed = set()
+    for p in P_open:
+        pp = plans[p]
+        if any(dominates(plans[d], pp) for d in P[pp.head] if d != p):
+            removed.add(p)
+    for p in removed:
+        P[plans[p].head].remove(p)
+        P_open.discard(p)
+    return removed
 
 
 def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
@@ -171,7 +205,8 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
     """Alg. 4.  Returns (plans, P, stats, rounds) where P maps head -> plan ids
     still in P(head) at exit and `rounds` holds per-round snapshots if `record`."""
     N = D.shape[2]
-    root = Plan(nodes=(0,), cost=0.0, step=0, mask=np.zeros(N, bool), parent=-1)
+    root = Plan(nodes=(0,), cost=0.0, step=0, mask=np.zeros(N, bool), parent=-1,
+                fmask=np.zeros(N, bool))
     plans: List[Plan] = [root]
     P: Dict[int, List[int]] = {0: [0]}
     P_open = {0}
@@ -213,26 +248,17 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
                 continue
             cp_hat = mask[q].sum() / N
             if cp_hat < alpha_max:                      # CP cutoff
+                pf = parents[q].fmask
                 plan = Plan(nodes=parents[q].nodes + (int(x[q]),), cost=float(cost[q]),
-                            step=int(step[q]), mask=mask[q].copy(), parent=parent_ids[q])
+                            step=int(step[q]), mask=mask[q].copy(), parent=parent_ids[q],
+                            fmask=flagged[q] if pf is None else (pf | flagged[q]))
                 plans.append(plan)
                 pid = len(plans) - 1
                 P.setdefault(int(x[q]), []).append(pid)
                 P_open.add(pid)
                 inserted.append(pid)
         stats["inserted"] += len(inserted)
-        # RemoveDominated(P, P_open)
-        dominated = set()
-        for p in P_open:
-            pp = plans[p]
-            for d in P[pp.head]:
-                dd = plans[d]
-                if pp.cost > dd.cost and pp.pop >= dd.pop:
-                    dominated.add(p)
-                    break
-        for p in dominated:
-            P[plans[p].head].remove(p)
-            P_open.discard(p)
+        dominated = remove_dominated(plans, P, P_open)
         P_open -= set(B)
         if record:
             snap["candidates"] = {plans[p].nodes: (plans[p].cost, plans[p].pop,
@@ -242,9 +268,14 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
             snap["removed"] = sorted(plans[p].nodes for p in dominated)
             snap["open"] = sorted(plans[p].nodes for p in P_open)
             snap["pairs"] = len(parents)
+            # per formed pair: cost, pop (-2: past S_max), packed bits and the
+            # packed bits whose decisions are flagged along the whole plan
             snap["pairs_all"] = {
-                parents[q].nodes + (int(x[q]),): (float(cost[q]), -2 if over[q] else int(mask[q].sum()),
-                                                  np.packbits(mask[q], bitorder="little"))
+                parents[q].nodes + (int(x[q]),): (
+                    float(cost[q]), -2 if over[q] else int(mask[q].sum()),
+                    np.packbits(mask[q], bitorder="little"),
+                    np.packbits(flagged[q] if parents[q].fmask is None
+                                else (parents[q].fmask | flagged[q]), bitorder="little"))
                 for q in range(len(parents))}
             rounds.append(snap)
         i += 1

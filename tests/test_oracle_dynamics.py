@@ -65,14 +65,14 @@ def test_deviation_covariance_follows_lyapunov():
                 assert np.all(np.abs(C - Sig) < 5 * se), (s, a, C, Sig)
 
 
-def test_deviation_table_is_fp32_position_part():
+def test_deviation_table_is_fp64_position_part():
     rng = np.random.default_rng(3)
     A_cl, L, _ = dynamics.closed_loop(0.05, 0.01, 100.0, 10.0, 1.0)
     noise = rng.standard_normal((9, 6, 64)).astype(np.float32)
     dev = dynamics.deviation_states(A_cl, L, noise, 9)
     D = dynamics.deviation_table(A_cl, L, noise, 9)
-    assert D.dtype == np.float32 and D.shape == (10, 3, 64)
+    assert D.dtype == np.float64 and D.shape == (10, 3, 64)
     assert np.all(D[0] == 0)
-    np.testing.assert_array_equal(D, dev[:, :, 0, :].astype(np.float32))
+    np.testing.assert_array_equal(D, dev[:, :, 0, :])
     # the first step is pure noise: dx_1 = L xi_0
     np.testing.assert_allclose(dev[1, 1, 0], L[0, 0] * noise[0, 2].astype(np.float64), rtol=1e-15)

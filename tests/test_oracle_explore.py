@@ -289,3 +289,155 @@ def test_pump_end_to_end_on_the_three_box_workload():
     assert frac <= sc.alpha
     assert best.nodes[0] == 0 and best.head in set(out["goal_nodes"].tolist())
     assert out["stats"]["partial_plans"] >= out["stats"]["inserted"] > 0
+
+
+# ---------------------------------------------------------------------------
+# RemoveDominated in isolation (Sec. IV primitive, applied once per round of
+# Alg. 4).  Hand-derived cases from the definition: a plan of P_open is removed
+# when a plan of the same head is strictly cheaper with a CP estimate no larger;
+# closed plans are never removed.
+# ---------------------------------------------------------------------------
+def _plan(head, cost, pop, N=8):
+    m = np.zeros(N, bool)
+    m[:pop] = True
+    return ex.Plan(nodes=(0, head), cost=cost, step=1, mask=m, parent=0)
+
+
+def _run_prune(fn, spec):
+    """spec: list of (head, cost, pop, is_open); returns the removed indices
+    and what stays in P (as index sets)."""
+    plans = [_plan(h, c, k) for h, c, k, _ in spec]
+    P = {}
+    for i, (h, _, _, _) in enumerate(spec):
+        P.setdefault(h, []).append(i)
+    P_open = {i for i, s in enumerate(spec) if s[3]}
+    removed = fn(plans, P, P_open)
+    kept = {i for ids in P.values() for i in ids}
+    return set(removed), kept, P_open
+
+
+# (name, spec, expected removed indices)
+PRUNE_CASES = [
+    # a closed plan stays even when a new open plan dominates it
+    ("closed_dominated_stays", [(5, 2.0, 1, False), (5, 1.5, 0, True)], set()),
+    # equal (cost, pop) plans coexist
+    ("exact_tie_coexists", [(5, 1.0, 2, True), (5, 1.0, 2, True)], set()),
+    # a plan of the group just expanded is still open and is removed
+    ("group_member_removed", [(5, 3.0, 1, True), (5, 2.0, 1, True)], {0}),
+    # equal cost never dominates, whatever the pops
+    ("cost_is_strict", [(5, 1.0, 3, True), (5, 1.0, 1, True)], set()),
+    # equal pop with a strictly lower cost dominates
+    ("cp_is_not_strict", [(5, 1.0, 1, True), (5, 1.5, 1, True)], {1}),
+    # cheaper but riskier: incomparable
+    ("incomparable", [(5, 1.0, 2, True), (5, 1.5, 1, True)], set()),
+    # plans at different heads never interact
+    ("heads_separate", [(5, 1.0, 0, True), (6, 2.0, 3, True)], set()),
+    # a closed plan removes an open one
+    ("closed_dominator", [(5, 1.0, 0, False), (5, 2.0, 0, True)], {1}),
+    # a chain: every dominated open plan goes, tested against the sets on entry
+    ("chain", [(5, 1.0, 0, True), (5, 2.0, 1, True), (5, 3.0, 2, True)], {1, 2}),
+    # the cheapest plan survives a tie on pop with several costlier ones
+    ("many_costlier", [(7, 2.5, 1, True), (7, 0.5, 1, False), (7, 1.5, 1, True),
+                       (7, 0.5, 1, True)], {0, 2}),
+]
+
+
+def _pin_failures(fn):
+    bad = []
+    for name, spec, want in PRUNE_CASES:
+        removed, kept, P_open = _run_prune(fn, spec)
+        if removed != want or kept != set(range(len(spec))) - want or (P_open & removed):
+            bad.append(name)
+    return bad
+
+
+def test_remove_dominated_hand_derived_cases():
+    assert _pin_failures(ex.remove_dominated) == []
+
+
+def _mutant_removes_closed(plans, P, P_open):
+    """Planted mistake: closed plans are removed too."""
+    removed = set()
+    for ids in P.values():
+        for p in ids:
+            if any(ex.dominates(plans[d], plans[p]) for d in ids if d != p):
+                removed.add(p)
+    for p in removed:
+        P[plans[p].head].remove(p)
+        P_open.discard(p)
+    return removed
+
+
+def _mutant_tie_break(plans, P, P_open):
+    """Planted mistake: of two equal (cost, pop) plans the later one goes."""
+    removed = set()
+    for p in P_open:
+        for d in P[plans[p].head]:
+            if d == p:
+                continue
+            a, b = plans[d], plans[p]
+            if (a.cost < b.cost and a.pop <= b.pop) or (a.cost == b.cost and a.pop == b.pop and d < p):
+                removed.add(p)
+    for p in removed:
+        P[plans[p].head].remove(p)
+        P_open.discard(p)
+    return removed
+
+
+def _mutant_strict_pop(plans, P, P_open):
+    """Planted mistake: dominance needs a strictly lower pop."""
+    removed = {p for p in P_open
+               if any(plans[d].cost < plans[p].cost and plans[d].pop < plans[p].pop
+                      for d in P[plans[p].head])}
+    for p in removed:
+        P[plans[p].head].remove(p)
+        P_open.discard(p)
+    return removed
+
+
+def _mutant_sequential(plans, P, P_open):
+    """Planted mistake: removals take effect while the pass is running, and the
+    pass visits the costliest plans last, comparing only with survivors."""
+    removed = set()
+    for p in sorted(P_open, key=lambda i: -plans[i].cost):
+        if any(ex.dominates(plans[d], plans[p]) for d in P[plans[p].head]
+               if d != p and d not in removed and d in P_open):
+            removed.add(p)
+    for p in removed:
+        P[plans[p].head].remove(p)
+        P_open.discard(p)
+    return removed
+
+
+@pytest.mark.parametrize("mutant", [_mutant_removes_closed, _mutant_tie_break,
+                                    _mutant_strict_pop, _mutant_sequential])
+def test_remove_dominated_pins_catch_planted_mistakes(mutant):
+    assert _pin_failures(mutant), mutant.__doc__
+
+
+def test_remove_dominated_matches_a_sorted_sweep():
+    """Random multisets with exact ties (cost on a coarse grid, few pop levels),
+    open and closed: the removed set equals a per-head sweep in cost order that
+    keeps the least pop seen among strictly cheaper plans (a different route to
+    the same definition)."""
+    rng = np.random.default_rng(17)
+    for trial in range(300):
+        k = int(rng.integers(1, 14))
+        spec = [(int(rng.integers(0, 3)), float(rng.integers(1, 6)) * 0.25,
+                 int(rng.integers(0, 4)), bool(rng.random() < 0.7)) for _ in range(k)]
+        removed, kept, _ = _run_prune(ex.remove_dominated, spec)
+        want = set()
+        for h in {s[0] for s in spec}:
+            ids = sorted((i for i, s in enumerate(spec) if s[0] == h), key=lambda i: spec[i][1])
+            best_pop = np.inf           # least pop among plans strictly cheaper
+            j = 0
+            while j < len(ids):
+                c = spec[ids[j]][1]
+                grp = [i for i in ids[j:] if spec[i][1] == c]
+                for i in grp:
+                    if spec[i][3] and best_pop <= spec[i][2]:
+                        want.add(i)
+                best_pop = min(best_pop, min(spec[i][2] for i in grp))
+                j += len(grp)
+        assert removed == want, (trial, spec)
+        assert kept == set(range(k)) - want
