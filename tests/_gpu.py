@@ -86,3 +86,31 @@ SIGMA_MEAS = 0.01
 @functools.lru_cache(maxsize=None)
 def oracle_run_lqg(kind, seed):
     return opump.run(scene(kind, seed, SIGMA_MEAS), opump.Config(estimator="lqg"), record=True)
+
+
+def assert_bits_except_flagged(got, want, flagged, what=""):
+    """Particle bits equal the oracle's except where the oracle flags the
+    decision (the particle came within 1e-5 of a face and nowhere lay 1e-5 or
+    more inside).  Returns how many flagged bits differ, for reporting."""
+    diff = np.asarray(got, bool) ^ np.asarray(want, bool)
+    fl = np.zeros_like(diff) if flagged is None else np.asarray(flagged, bool)
+    bad = diff & ~fl
+    assert not bad.any(), (what, np.nonzero(bad)[0])
+    return int((diff & fl).sum())
+
+
+def assert_table_is_fp32_of(D, Dref, tol=1e-5):
+    """An FP32 table from the device against the oracle's FP64 table: within
+    `tol` relative to max(|x|, 1) everywhere, and equal to the FP64 value
+    rounded to FP32 except in rare entries one FP32 ulp away (the two sides
+    compute their gains and recurrences independently)."""
+    D = np.asarray(D, np.float32)
+    assert D.shape == Dref.shape
+    scale = max(1.0, float(np.abs(Dref).max()))
+    np.testing.assert_allclose(D.astype(np.float64), Dref, rtol=0, atol=tol * scale)
+    R = Dref.astype(np.float32)
+    diff = D != R
+    assert diff.mean() < 1e-4, int(diff.sum())
+    ulp = np.abs(D.view(np.int32)[diff].astype(np.int64) - R.view(np.int32)[diff])
+    assert ulp.size == 0 or ulp.max() <= 1
+    return int(diff.sum())

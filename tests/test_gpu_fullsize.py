@@ -10,7 +10,8 @@ import pytest
 from oracle import dynamics, explore as oex, graph as ogr, pump as opump, select as osel
 from oracle import smooth as osm, steer as ost
 from paper_1607_06886_amd import _lib, scenes
-from tests._gpu import gpu_plans, print_case, unpack_mask
+from tests._gpu import (assert_bits_except_flagged, assert_table_is_fp32_of, gpu_plans,
+                        print_case, unpack_mask)
 
 pytestmark = pytest.mark.gpu
 
@@ -57,9 +58,8 @@ def test_deviation_table(run):
     sc, D = run["sc"], run["D"]
     A_cl, L, _ = dynamics.closed_loop(CFG.dt, sc.sigma, CFG.q_pos, CFG.q_vel, CFG.r_track)
     Dref = dynamics.deviation_table(A_cl, L, sc.noise, sc.S_max)
-    diff = D != Dref
-    assert diff.mean() < 1e-4
-    np.testing.assert_allclose(D, Dref, rtol=0, atol=1e-6)
+    print("  entries one FP32 ulp from the rounded FP64 value:",
+          assert_table_is_fp32_of(D, Dref, tol=1e-6), flush=True)
 
 
 def _resimulate(sc, nodes, D):
@@ -68,13 +68,14 @@ def _resimulate(sc, nodes, D):
     u = np.array(nodes[:-1]), np.array(nodes[1:])
     tau, cost = ost.steer(V[u[0]], V[u[1]], CFG.r_steer)
     graph = dict(col=u[1], tau=tau, cost=cost)
-    p = oex.Plan(nodes=(0,), cost=0.0, step=0, mask=np.zeros(sc.N, bool), parent=-1)
+    p = oex.Plan(nodes=(0,), cost=0.0, step=0, mask=np.zeros(sc.N, bool), parent=-1,
+                 fmask=np.zeros(sc.N, bool))
     for e in range(len(nodes) - 1):
-        x, c, s, m, over, _ = oex.extend_batch(V, graph, D, sc.obstacles, CFG.dt, sc.S_max, [p],
-                                               np.array([e]))
+        x, c, s, m, over, fl = oex.extend_batch(V, graph, D, sc.obstacles, CFG.dt, sc.S_max, [p],
+                                                np.array([e]))
         assert not over[0]
         p = oex.Plan(nodes=p.nodes + (int(x[0]),), cost=float(c[0]), step=int(s[0]), mask=m[0],
-                     parent=-1)
+                     parent=-1, fmask=p.fmask | fl[0])
     return p
 
 
@@ -85,13 +86,19 @@ def test_sampled_plans_resimulated(run):
     alive = np.nonzero(st["state"] != 2)[0]
     assert alive.shape[0] > 1000
     picks = np.random.default_rng(2).choice(alive[alive > 0], 120, replace=False)
+    flagged, flagged_diff = 0, 0
     for pid in picks:
         nodes = st["paths"][pid]
         ref = _resimulate(sc, nodes, D)
         assert st["step"][pid] == ref.step, pid
         assert abs(st["cost"][pid] - ref.cost) <= REL * max(1.0, ref.cost), pid
-        np.testing.assert_array_equal(unpack_mask(st["mask"][pid], sc.N), ref.mask)
-        assert st["pop"][pid] == ref.pop
+        nf = assert_bits_except_flagged(unpack_mask(st["mask"][pid], sc.N), ref.mask, ref.fmask,
+                                        nodes)
+        assert st["pop"][pid] == ref.pop or abs(int(st["pop"][pid]) - ref.pop) <= nf
+        flagged += int(ref.fmask.sum())
+        flagged_diff += nf
+    print("  flagged particle bits on the sampled plans:", flagged, "differing:", flagged_diff,
+          flush=True)
 
 
 def test_no_alive_plan_dominated_at_its_head(run):

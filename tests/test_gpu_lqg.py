@@ -9,8 +9,9 @@ import pytest
 
 from oracle import dynamics, pump as opump, select as osel
 from paper_1607_06886_amd import _lib, scenes
-from tests._gpu import (SIGMA_MEAS, gpu_plans, oracle_run_lqg, planner_for, print_case, scene,
-                        small_spec, unpack_mask)
+from tests._gpu import (SIGMA_MEAS, assert_bits_except_flagged, assert_table_is_fp32_of,
+                        gpu_plans, oracle_run_lqg, planner_for, print_case, scene, small_spec,
+                        unpack_mask)
 
 pytestmark = pytest.mark.gpu
 
@@ -33,14 +34,8 @@ def test_lqg_deviation_table(N):
     D = pl.deviation()
     M, E, _, _ = _lqg(sc)
     Dref = dynamics.lqg_deviation_table(M, E, sc.noise, sc.noise_meas, sc.S_max)
-    assert D.shape == Dref.shape
-    diff = D != Dref
-    # FP64 recurrences with independently computed gains may round to a
-    # neighbouring FP32 value in rare entries
-    assert diff.mean() < 1e-4, diff.sum()
-    np.testing.assert_allclose(D, Dref, rtol=0, atol=1e-5 * max(1.0, float(np.abs(Dref).max())))
-    ulp = np.abs(D.view(np.int32)[diff].astype(np.int64) - Dref.view(np.int32)[diff])
-    assert ulp.size == 0 or ulp.max() <= 1
+    print("  entries one FP32 ulp from the rounded FP64 value:", assert_table_is_fp32_of(D, Dref),
+          flush=True)
     # and the table is not the full-state one
     A_cl, L, _ = dynamics.closed_loop(CFG.dt, sc.sigma, CFG.q_pos, CFG.q_vel, CFG.r_track)
     assert np.abs(D - dynamics.deviation_table(A_cl, L, sc.noise, sc.S_max)).max() > 1e-4
@@ -68,11 +63,14 @@ def test_lqg_plan_end_to_end(kind, seed, mode):
     gpu_P = {st["paths"][p]: p for p in np.nonzero(alive)[0]}
     ref_P = {ref["plans"][q].nodes: ref["plans"][q] for ids in ref["P"].values() for q in ids}
     assert set(gpu_P) == set(ref_P)
+    flagged_diff = 0
     for nodes, p in gpu_P.items():
         rp = ref_P[nodes]
-        assert st["pop"][p] == rp.pop
         assert abs(st["cost"][p] - rp.cost) <= REL * max(1.0, rp.cost)
-        np.testing.assert_array_equal(unpack_mask(st["mask"][p], sc.N), rp.mask)
+        nf = assert_bits_except_flagged(unpack_mask(st["mask"][p], sc.N), rp.mask, rp.fmask, nodes)
+        assert st["pop"][p] == rp.pop or abs(int(st["pop"][p]) - rp.pop) <= nf
+        flagged_diff += nf
+    print("  flagged particle bits that differ from the oracle:", flagged_diff, flush=True)
     assert res["status"] == ref["status"]
     ids, mc = pl.front()
     assert [st["paths"][p] for p in ids] == [p.nodes for p in ref["front"]]

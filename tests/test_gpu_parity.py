@@ -15,8 +15,9 @@ import pytest
 
 from oracle import dynamics, graph as ogr, pump as opump, select as osel
 from paper_1607_06886_amd import _lib, scenes
-from tests._gpu import (gpu_plans, oracle_mask_bool, oracle_run, planner_for, print_case, scene,
-                        small_spec, unpack_mask)
+from tests._gpu import (assert_bits_except_flagged, assert_table_is_fp32_of, gpu_plans,
+                        oracle_mask_bool, oracle_run, planner_for, print_case, scene, small_spec,
+                        unpack_mask)
 
 pytestmark = pytest.mark.gpu
 
@@ -37,14 +38,8 @@ def test_deviation_table(N):
     D = pl.deviation()
     A_cl, L, _ = dynamics.closed_loop(CFG.dt, sc.sigma, CFG.q_pos, CFG.q_vel, CFG.r_track)
     Dref = dynamics.deviation_table(A_cl, L, sc.noise, sc.S_max)
-    assert D.shape == Dref.shape
-    diff = D != Dref
-    # FP64 recurrences with independently computed gains may round to a
-    # neighbouring FP32 value in rare entries; states agree far inside 1e-5
-    assert diff.mean() < 1e-4, diff.sum()
-    np.testing.assert_allclose(D, Dref, rtol=0, atol=1e-5 * max(1.0, float(np.abs(Dref).max())))
-    ulp = np.abs(D.view(np.int32)[diff].astype(np.int64) - Dref.view(np.int32)[diff])
-    assert ulp.size == 0 or ulp.max() <= 1
+    print("  entries one FP32 ulp from the rounded FP64 value:", assert_table_is_fp32_of(D, Dref),
+          flush=True)
     pl.close()
 
 
@@ -73,18 +68,21 @@ def _compare_end_state(pl, ref, sc):
     gpu_P = {st["paths"][p]: p for p in np.nonzero(alive)[0]}
     ref_P = {ref["plans"][q].nodes: ref["plans"][q] for ids in ref["P"].values() for q in ids}
     assert set(gpu_P) == set(ref_P)
+    flagged_diff = 0
     for nodes, p in gpu_P.items():
         rp = ref_P[nodes]
         assert abs(st["cost"][p] - rp.cost) <= REL * max(1.0, rp.cost)
-        assert st["pop"][p] == rp.pop
         assert st["step"][p] == rp.step
-        np.testing.assert_array_equal(unpack_mask(st["mask"][p], N), rp.mask)
+        nf = assert_bits_except_flagged(unpack_mask(st["mask"][p], N), rp.mask, rp.fmask, nodes)
+        assert st["pop"][p] == rp.pop or abs(int(st["pop"][p]) - rp.pop) <= nf
+        flagged_diff += nf
     # plans created per group index
     by_round = {}
     for p in range(1, st["head"].shape[0]):
         by_round.setdefault(int(st["round"][p]), set()).add(st["paths"][p])
     for snap in ref["rounds"]:
         assert by_round.get(snap["i"], set()) == set(snap["survivors"]), snap["i"]
+    print("  flagged particle bits that differ from the oracle:", flagged_diff, flush=True)
     return st
 
 
@@ -135,6 +133,7 @@ def test_rounds_candidate_by_candidate():
     pl.explore_begin()
     done = False
     r = 0
+    flagged_diff = 0
     while not done:
         done = pl.explore_round()
         cand = pl.candidates()
@@ -145,15 +144,18 @@ def test_rounds_candidate_by_candidate():
         for q in range(cand["flag"].shape[0]):
             nodes = st["paths"][cand["parent"][q]] + (int(cand["head"][q]),)
             seen.add(nodes)
-            cost, pop, packed = snap["pairs_all"][nodes]
-            assert cand["pop"][q] == pop, (r, nodes)
+            cost, pop, packed, fpacked = snap["pairs_all"][nodes]
+            fl = oracle_mask_bool(fpacked, sc.N)
+            assert cand["pop"][q] == pop or abs(int(cand["pop"][q]) - pop) <= int(fl.sum()), \
+                (r, nodes)
             if cand["flag"][q]:
                 assert abs(cand["cost"][q] - cost) <= REL * max(1.0, cost)
-                np.testing.assert_array_equal(unpack_mask(cand["mask"][q], sc.N),
-                                              oracle_mask_bool(packed, sc.N))
+                flagged_diff += assert_bits_except_flagged(
+                    unpack_mask(cand["mask"][q], sc.N), oracle_mask_bool(packed, sc.N), fl, nodes)
         assert seen == set(snap["pairs_all"])
         r += 1
     assert r == len(snaps)
+    print("  flagged particle bits that differ from the oracle:", flagged_diff, flush=True)
     pl.close()
 
 
