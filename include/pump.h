@@ -320,6 +320,17 @@ int pump_get_timing(pump_ctx* ctx, double* ms, int64_t* launches, int32_t n);
 int pump_set_explore_mode(pump_ctx* ctx, int32_t mode);
 int pump_get_explore_mode(pump_ctx* ctx, int32_t* mode, int32_t* blocks);
 
+/* Patience of the single launch's barrier waits, in milliseconds (default
+ * 4000; 0 < ms <= 600000, else PUMP_E_ARG).  A workgroup that waits longer
+ * (its team members were not all resident together, e.g. because other work
+ * held compute units) makes every workgroup leave the launch; pump_plan and
+ * pump_explore_run then redo Explore from the root with one launch per phase
+ * (mode 0 for that call only), which gives the same plan store, and count
+ * the event.  pump_get_explore_fallbacks reports how many times that
+ * happened on this context. */
+int pump_set_barrier_patience(pump_ctx* ctx, double ms);
+int pump_get_explore_fallbacks(pump_ctx* ctx, int64_t* n);
+
 /* ---------------------------------------------------------------------------
  * Learned sampling proposal.  The paper draws SampleFree(n) uniformly (Alg. 3;
  * Halton in Sec. V-A); a learned proposal only changes that sample set (half

@@ -16,7 +16,6 @@ sequence.  Smooth(p, alpha) is in smooth.py.
 
 from __future__ import annotations
 
-import math
 
 import numpy as np
 
@@ -137,14 +136,21 @@ def plan_selection(goal_plans, alpha, mc):
             evals[m] = mc(P[m - 1])
         return evals[m]
 
-    l, u = 1, len(P)
-    m = math.ceil((l + u) / 2)
-    while l != u:
-        if MC(m)[1] > alpha:
-            u = m - 1
+    # Alg. 5 bisects the risk-sorted front for the riskiest plan whose MC
+    # estimate is within alpha, premised on MC growing along the order.
+    # `good` is the plan the search stands on (it starts on the safest plan,
+    # not yet evaluated); plans from `bad` on are ruled out.  A probe in the
+    # middle of the open range moves `good` up when within alpha and `bad`
+    # down otherwise; when nothing lies strictly between them, `good` gets
+    # one last evaluation (it may never have been probed) before it is
+    # returned, and the query is infeasible if it fails.
+    good, bad = 1, len(P) + 1
+    while bad - good > 1:
+        mid = (good + bad) // 2
+        if MC(mid)[1] <= alpha:
+            good = mid
         else:
-            l = m
-        m = math.ceil((l + u) / 2)
-    if MC(m)[1] > alpha:
+            bad = mid
+    if MC(good)[1] > alpha:
         return None, P, evals
-    return P[m - 1], P, evals
+    return P[good - 1], P, evals

@@ -19,7 +19,18 @@
 namespace pump {
 
 
-constexpr long long kSpinLimit = 1ll << 25;   // about 1-2 s of polling per wait
+__device__ __forceinline__ unsigned long long rt_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+// Deadline of one wait: the counter is read once every 64 polls.
+struct WaitClock {
+    unsigned long long t0, limit;
+    unsigned polls;
+    __device__ __forceinline__ explicit WaitClock(unsigned long long patience)
+        : t0(rt_ticks()), limit(patience), polls(0) {}
+    __device__ __forceinline__ bool expired() {
+        return (++polls & 63u) == 0u && rt_ticks() - t0 > limit;
+    }
+};
 
 // Team of workgroups working on one query: its rank/size, barrier words,
 // per-workgroup scan totals and buffers.
@@ -27,6 +38,7 @@ struct TeamCtx {
     unsigned* arrive;          // [size] last barrier each member reached
     unsigned* release;         // last barrier member 0 released
     int* fail;                 // set when a wait ran out of patience
+    unsigned long long patience;   // longest wait, in 100 MHz ticks
     int rank, size;
     unsigned long long* xa;    // [size] exchanged chunk totals, tagged (team_exchange)
     unsigned long long* xb;    // [size]
@@ -60,10 +72,10 @@ __device__ __forceinline__ bool team_barrier(const TeamCtx& g, unsigned& epoch, 
     if (g.rank == 0) {
         int ok = 1;
         for (int k = threadIdx.x; k < g.size && ok; k += blockDim.x) {
-            long long spins = 0;
+            WaitClock wc(g.patience);
             while (__hip_atomic_load(g.arrive + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins > kSpinLimit) {
+                if (wc.expired()) {
                     ok = 0;
                     break;
                 }
@@ -76,10 +88,10 @@ __device__ __forceinline__ bool team_barrier(const TeamCtx& g, unsigned& epoch, 
             __hip_atomic_store(g.release, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     } else if (threadIdx.x == 0) {
-        long long spins = 0;
+        WaitClock wc(g.patience);
         while (__hip_atomic_load(g.release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
+            if (wc.expired()) {
                 atomicOr(g.fail, 1);
                 break;
             }
@@ -155,11 +167,11 @@ __device__ __forceinline__ bool team_exchange(const TeamCtx& g, unsigned& epoch,
         unsigned long long w[2];
         for (int h = 0; h < 2 && ok; ++h) {
             unsigned long long* p = h ? g.xb + k : g.xa + k;
-            long long spins = 0;
+            WaitClock wc(g.patience);
             while (((w[h] = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
                     ~0xFFFFFFFFull) != tag) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins > kSpinLimit) {
+                if (wc.expired()) {
                     ok = 0;
                     break;
                 }

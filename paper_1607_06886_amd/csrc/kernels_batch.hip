@@ -14,7 +14,12 @@
 
 namespace pump {
 
-constexpr int kBatchFront = 32;   // Pareto-front entries certified per query
+// Pareto-front entries kept per query: as many as the single-query path
+// keeps, so a batched query's result is the one pump_plan returns; the
+// certification grid has kBatchMcRows rows of front plans and strides over
+// larger fronts.
+constexpr int kBatchFront = kMaxFront;
+constexpr int kBatchMcRows = 32;
 
 // ----------------------------- setup ---------------------------------------
 __global__ void k_b_load(BatchQuery* qs) {
@@ -258,6 +263,7 @@ __global__ __launch_bounds__(256, 2) void k_b_explore(BatchQuery* qs, BatchSched
         }
         t.release = Q.team_sync;
         t.fail = reinterpret_cast<int*>(Q.team_sync + 1);
+        t.patience = kDefaultPatience;
         t.arrive = Q.team_sync + 64;
         t.xa = Q.team_tot;
         t.xb = Q.team_tot + kMaxTeam;
@@ -299,22 +305,25 @@ __global__ __launch_bounds__(256) void k_b_front(BatchQuery* qs) {
 
 __global__ void k_b_waypoints(BatchQuery* qs) {
     const BatchQuery& Q = qs[blockIdx.x];
-    const int f = threadIdx.x;
-    if (f < kBatchFront) Q.s.mc_counts[f] = 0;
+    for (int f = threadIdx.x; f < kBatchFront; f += blockDim.x) Q.s.mc_counts[f] = 0;
     if (Q.bad || Q.ra[0].ctl->err) return;
-    if (f < Q.ra[0].ctl->n_front) waypoints_one(Q.s, f);
+    const int nf = Q.ra[0].ctl->n_front;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) waypoints_one(Q.s, f);
 }
 
 __global__ __launch_bounds__(kMcThreads) void k_b_mc(BatchQuery* qs) {
     __shared__ float s_obs[kMaxObs * 6];
     __shared__ int s_hit[kMcParticles];
     const BatchQuery& Q = qs[blockIdx.z];
-    const int f = blockIdx.y;
-    if (Q.bad || Q.ra[0].ctl->err || f >= Q.ra[0].ctl->n_front) return;   // uniform per block
+    if (Q.bad || Q.ra[0].ctl->err || (int)blockIdx.y >= Q.ra[0].ctl->n_front) return;   // uniform per block
+    const int nf = Q.ra[0].ctl->n_front;
     for (int t = threadIdx.x; t < Q.s.n_obs * 6; t += blockDim.x) s_obs[t] = Q.s.obs[t];
     __syncthreads();
-    mc_block_count(Q.s, Q.s.wp + (size_t)f * (Q.s.S_max + 1) * 3, Q.s.wp_len[f],
-                   blockIdx.x * kMcParticles, s_obs, s_hit, &Q.s.mc_counts[f]);
+    for (int f = blockIdx.y; f < nf; f += gridDim.y) {   // trip count uniform per block
+        mc_block_count(Q.s, Q.s.wp + (size_t)f * (Q.s.S_max + 1) * 3, Q.s.wp_len[f],
+                       blockIdx.x * kMcParticles, s_obs, s_hit, &Q.s.mc_counts[f]);
+        __syncthreads();   // the next plan's clear of s_hit waits for this plan's ballot
+    }
 }
 
 // Alg. 5 bisection on the certified counts, and the per-query outcome.
@@ -353,30 +362,25 @@ __global__ void k_b_finalize(BatchQuery* qs, int q, BatchOut* outs) {
             return;
         }
     const int M = Q.s.M;
-    auto gt = [&](int m1) { return (double)Q.s.mc_counts[m1 - 1] / (double)M > Q.alpha; };
-    int l = 1, u = nf, m = (l + u + 1) / 2;
-    while (l != u) {
-        if (gt(m)) u = m - 1; else l = m;
-        m = (l + u + 1) / 2;
-    }
-    if (gt(m)) {
+    const int k = certified_pick(Q.s.mc_counts, nf, M, Q.alpha);
+    if (k < 0) {
         o.status = PUMP_INFEASIBLE;
         return;
     }
-    const int p = Q.s.front_ids[m - 1];
+    const int p = Q.s.front_ids[k];
     o.status = PUMP_OK;
-    o.best = m - 1;
+    o.best = k;
     o.best_plan = p;
     o.best_pop = Q.ra[0].p_pop[p];
-    o.best_mc = Q.s.mc_counts[m - 1];
-    o.best_len = Q.s.path_len[m - 1];
+    o.best_mc = Q.s.mc_counts[k];
+    o.best_len = Q.s.path_len[k];
     o.best_cost = Q.ra[0].p_cost[p];
     o.best_cp_mc = (double)o.best_mc / (double)M;
     // the identity Smooth (replaced when smoothing runs)
     o.smooth_beta = 0.0;
     o.smooth_cost = o.best_cost;
     o.smooth_count = o.best_mc;
-    o.smooth_steps = Q.s.wp_len[m - 1];
+    o.smooth_steps = Q.s.wp_len[k];
 }
 
 // Smooth(p*, alpha) per query (smooth_ops.hpp), after the outcome records:
@@ -473,7 +477,7 @@ void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes
     k_b_goal_collect<<<q, 1024, 0, s>>>(qs);
     k_b_front<<<q, 256, 0, s>>>(qs);
     k_b_waypoints<<<q, 64, 0, s>>>(qs);
-    k_b_mc<<<dim3((M + kMcParticles - 1) / kMcParticles, kBatchFront, q), kMcThreads, 0, s>>>(qs);
+    k_b_mc<<<dim3((M + kMcParticles - 1) / kMcParticles, kBatchMcRows, q), kMcThreads, 0, s>>>(qs);
     k_b_finalize<<<(q + 63) / 64, 64, 0, s>>>(qs, q, out);
     if (smooth) {
         k_b_smooth_prep<<<q, 256, 0, s>>>(qs, out);

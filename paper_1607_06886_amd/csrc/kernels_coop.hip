@@ -26,6 +26,7 @@ __global__ __launch_bounds__(coop_threads<N>()) void k_explore_coop(const RoundA
     t.arrive = ca.sync.arrive;
     t.release = ca.sync.release;
     t.fail = ca.sync.fail;
+    t.patience = ca.sync.patience;
     t.rank = blockIdx.x;
     t.size = gridDim.x;
     t.xa = ca.xa;

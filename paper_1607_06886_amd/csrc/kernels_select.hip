@@ -78,23 +78,18 @@ __global__ __launch_bounds__(256) void k_select_final(SelectArgs a, double alpha
     }
     for (int f = 0; f < nf; ++f)
         if (a.wp_len[f] < 0) c->sel_bad_wp = 1;
-    auto mc_gt = [&](int m) { return (double)a.mc_counts[m - 1] / (double)a.M > alpha; };
-    int l = 1, u = nf, m = (l + u + 1) / 2;
-    while (l != u) {
-        if (mc_gt(m)) u = m - 1; else l = m;
-        m = (l + u + 1) / 2;
-    }
-    if (mc_gt(m)) {
+    const int k = certified_pick(a.mc_counts, nf, a.M, alpha);
+    if (k < 0) {
         c->sel_status = PUMP_INFEASIBLE;
         return;
     }
-    const int id = a.front_ids[m - 1];
+    const int id = a.front_ids[k];
     c->sel_status = PUMP_OK;
-    c->sel_best = m - 1;
+    c->sel_best = k;
     c->sel_plan = id;
-    c->sel_mc = a.mc_counts[m - 1];
-    c->sel_len = a.path_len[m - 1];
-    c->sel_steps = a.wp_len[m - 1];
+    c->sel_mc = a.mc_counts[k];
+    c->sel_len = a.path_len[k];
+    c->sel_steps = a.wp_len[k];
     c->sel_pop = a.p_pop[id];
     c->sel_cost = a.p_cost[id];
 }

@@ -73,6 +73,8 @@ struct pump_ctx {
     unsigned* coop_sync = nullptr;
     int coop_blocks = 0;            // resident workgroups of the single-launch Explore
     int explore_mode = 0;           // 0: one launch per phase, 1: single launch
+    unsigned long long patience = kDefaultPatience;   // single launch's barrier waits (100 MHz ticks)
+    long long fallbacks = 0;        // single launches that timed out and were redone per phase
     RoundArgs* ra_dev = nullptr;    // [2] round arguments of the single launch
     RoundArgs* ra_h = nullptr;      // [2] pinned staging
     Ctl* ctl = nullptr;
@@ -731,6 +733,7 @@ static int explore_single_enqueue(pump_ctx* ctx) {
     ca.sync.fail = reinterpret_cast<int*>(ctx->coop_sync + 1);
     ca.sync.arrive = ctx->coop_sync + 64;
     ca.sync.n_blocks = (unsigned)ctx->coop_blocks;
+    ca.sync.patience = ctx->patience;
     ca.xa = reinterpret_cast<unsigned long long*>(ctx->coop_sync + 64 + 4096);
     ca.xb = ca.xa + ctx->coop_blocks;
     ca.b_deg = ctx->b_deg;
@@ -788,6 +791,14 @@ int pump_explore_run(pump_ctx* ctx) {
     HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
     if (ctx->explore_mode == 1 && !ctx->explore_done) {
         int r = explore_single_launch(ctx);
+        if (r == PUMP_E_STATE && ctx->ctl_h->err == 5) {
+            // a barrier wait ran out of patience (workgroups not resident
+            // together): redo Explore with one launch per phase
+            ctx->fallbacks += 1;
+            r = explore_begin(ctx, true);
+            int32_t done = ctx->explore_done ? 1 : 0;
+            while (r == PUMP_OK && !done) r = pump_explore_round(ctx, &done);
+        }
         if (r) return r;
     } else {
         int32_t done = ctx->explore_done ? 1 : 0;
@@ -809,6 +820,19 @@ int pump_set_explore_mode(pump_ctx* ctx, int32_t mode) {
     if (mode == 1 && ctx->coop_blocks <= 0)
         return fail(ctx, PUMP_E_ARG, "the single-launch Explore does not fit on this device");
     ctx->explore_mode = mode;
+    return PUMP_OK;
+}
+
+int pump_set_barrier_patience(pump_ctx* ctx, double ms) {
+    if (!ctx || !(ms > 0.0) || !(ms <= 600000.0)) return PUMP_E_ARG;
+    ctx->patience = (unsigned long long)(ms * 1e5);   // 100 MHz ticks
+    if (ctx->patience < 1) ctx->patience = 1;
+    return PUMP_OK;
+}
+
+int pump_get_explore_fallbacks(pump_ctx* ctx, int64_t* n) {
+    if (!ctx || !n) return PUMP_E_ARG;
+    *n = ctx->fallbacks;
     return PUMP_OK;
 }
 
@@ -944,6 +968,19 @@ int pump_plan(pump_ctx* ctx, const pump_problem* pr, pump_result* out) {
             r = explore_single_enqueue(ctx);
         }
         if (r == PUMP_OK) r = select_impl(ctx, &res, true);
+        if (r == PUMP_E_STATE && ctx->ctl_h->err == 5) {
+            // the single launch's barrier wait ran out of patience (its
+            // workgroups were not all resident): Explore again from the root
+            // with one launch per phase, then select
+            ctx->fallbacks += 1;
+            memset(&res, 0, sizeof(res));
+            r = explore_begin(ctx, true);
+            const int mode = ctx->explore_mode;
+            ctx->explore_mode = 0;
+            if (r == PUMP_OK) r = pump_explore_run(ctx);
+            ctx->explore_mode = mode;
+            if (r == PUMP_OK) r = pump_select(ctx, &res);
+        }
     } else {
         if (r == PUMP_OK) r = pump_explore_run(ctx);
         if (r == PUMP_OK) r = pump_select(ctx, &res);

@@ -19,7 +19,7 @@ using namespace pump;
 
 namespace {
 
-constexpr int kBatchFrontHost = 32;
+constexpr int kBatchFrontHost = kMaxFront;
 
 struct Slot {
     // per-query buffers (sized for the batch's maxima)

@@ -14,6 +14,9 @@ constexpr int kMaxObs = 256;          // obstacle boxes per query
 constexpr int kMaxWaypoints = 32;     // ceil(r_n / dt) bound (u32 waypoint masks)
 constexpr int kScanBlock = 1024;      // items per block in the device-wide scans
 constexpr int kMaxFront = 256;        // Pareto front entries handled by selection
+// Patience of a team-barrier wait, in ticks of the 100 MHz real-time counter:
+// 4 s unless the host sets another bound.
+constexpr unsigned long long kDefaultPatience = 400000000ull;
 constexpr int kMaxGoal = 1 << 16;     // goal plans gathered for selection
 // FP32 guard band of the particle test: a particle whose FP32 position is
 // within kGuard of a face is re-tested in FP64 (2^-14, far above the FP32
@@ -318,6 +321,7 @@ struct CoopSync {
     unsigned* release;         // last barrier workgroup 0 released
     int* fail;                 // set when a wait ran out of patience
     unsigned n_blocks;
+    unsigned long long patience;   // longest barrier wait, 100 MHz ticks
 };
 
 struct CoopArgs {

@@ -189,6 +189,26 @@ __device__ __forceinline__ void waypoints_wave(const SelectArgs& a, int f) {
     if (lane == 0) a.wp_len[f] = s0 <= a.S_max ? s0 : -1;
 }
 
+// Alg. 5's choice among the risk-sorted front (cp_hat ascending): a
+// bisection for the riskiest plan whose certification count stays within
+// alpha, premised on MC growing along that order.  `good` (1-based) is the
+// plan the search stands on -- it starts on the safest plan, not yet
+// evaluated -- and plans from `bad` on are ruled out.  Each probe takes the
+// middle of the open range: a count within alpha moves `good` up to it, one
+// above alpha moves `bad` down to it.  Once nothing lies strictly between the
+// two, `good` is checked once more (it may never have been probed).  Returns
+// its 0-based index, or -1 when that check fails (infeasible) or nf < 1.
+__device__ __forceinline__ int certified_pick(const int* mc_counts, int nf, int M, double alpha) {
+    if (nf < 1) return -1;
+    auto within = [&](int k) { return (double)mc_counts[k - 1] / (double)M <= alpha; };
+    int good = 1, bad = nf + 1;
+    while (bad - good > 1) {
+        const int mid = (good + bad) >> 1;
+        if (within(mid)) good = mid; else bad = mid;
+    }
+    return within(good) ? good - 1 : -1;
+}
+
 // Does the segment prev -> cur meet one of the closed obstacle boxes
 // o0, o0 + ostep, ...?  Slab clipping in FP64 after a bounding-box reject.
 __device__ __forceinline__ bool segment_hits_boxes(const double prev[3], const double cur[3],

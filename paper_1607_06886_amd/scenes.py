@@ -309,3 +309,11 @@ def batch_map(spec, seed: int):
     """(x_init, goal, boxes, samples) of one batched query; its noise arrays
     are drawn by the caller (on the device for large batches)."""
     return _map_of(spec, seed)
+
+
+def batch_scene(seed: int, i: int, *, M: int = 10_000, S_max: int = 512) -> Scene:
+    """Query i of the batch with batch seed `seed` (the shape batch_specs
+    gives it and the map batch_map draws for it), with host-drawn noise
+    arrays so that both implementations can consume the same values."""
+    spec = batch_specs(seed, i + 1)[i]
+    return make_scene(spec, workload_seed(4, 1000 * seed + i), M=M, S_max=S_max)

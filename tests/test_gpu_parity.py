@@ -299,3 +299,37 @@ def test_hsmc_plan_end_to_end(kind, seed, mode, preprune):
         k = ref["front"].index(ref["best"]) + 1
         assert res["best_mc_count"] == ref["evals"][k][0]
     pl.close()
+
+
+def test_single_launch_timeout_falls_back_to_per_phase():
+    """A single-launch barrier wait that runs out of patience (forced from the
+    host with a one-tick patience) makes every workgroup leave the launch;
+    pump_plan then redoes Explore per phase and returns the same result."""
+    print_case("explore_fallback", kind="boxes20", seed=1)
+    sc = _scene("boxes20", 1)
+    pl = planner_for(sc)
+    pr = pl.scene_problem(sc, device=True)
+    a = pl.plan(pr)
+    sa = pl.plans()
+    assert pl.explore_fallbacks() == 0
+    pl.set_barrier_patience(1e-5)      # one tick of the 100 MHz counter
+    b = pl.plan(pr)
+    sb = pl.plans()
+    print("  fallbacks", pl.explore_fallbacks(), flush=True)
+    assert pl.explore_fallbacks() == 1
+    for k in ("status", "partial_plans", "inserted", "rounds", "final_i", "n_plans", "best_plan",
+              "best_cost", "best_mc_count", "n_front"):
+        assert a[k] == b[k], k
+    for k in sa:
+        np.testing.assert_array_equal(sa[k], sb[k])
+    # the step-by-step entry points fall back the same way
+    pl.setup(pr)
+    pl.explore_begin()
+    pl.explore_run()
+    assert pl.explore_fallbacks() == 2
+    c = pl.select()
+    assert c["best_plan"] == a["best_plan"] and c["partial_plans"] == a["partial_plans"]
+    pl.set_barrier_patience(4000.0)
+    d = pl.plan(pr)
+    assert pl.explore_fallbacks() == 2 and d["best_plan"] == a["best_plan"]
+    pl.close()
