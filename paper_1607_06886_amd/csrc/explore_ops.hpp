@@ -296,13 +296,214 @@ __device__ __forceinline__ void queue_pairs_block(const RoundArgs& a, int st, co
 // Expansion, second part (one queued pair per wave, particles across lanes):
 // at each marked waypoint, lanes test their particles against the obstacles
 // the cloud touches (FP32 with an FP64 re-test inside the guard band); hits
-// are gathered with ballots into the N-bit mask, ORed with the parent's bits
-// and counted; the pair is cut if pop >= c_cut.  Counters are wave-uniform
-// (n_wp: waypoints tested, n_bt: waypoint-box tests, each over all particles).
+// are gathered into the N-bit mask, ORed with the parent's bits and counted;
+// the pair is cut if pop >= c_cut.  Counters are wave-uniform (n_wp:
+// waypoints tested, n_bt: waypoint-box tests, each over all particles).
+//
+// Lane l holds particles l*PPL .. l*PPL + PPL-1, so one waypoint's deviations
+// are one vector load per axis and lane.  The loads of the next marked
+// waypoint are issued before the current one is tested, and the parent's
+// bits, the pair's cost and the head's staircase entries are loaded before
+// the waypoint loop, so a pair costs about one memory latency per waypoint
+// instead of two, plus one at its start.
 // ---------------------------------------------------------------------------
 template <int N>
-__device__ __forceinline__ void simulate_pair(const RoundArgs& a, int task, const float* s_raw,
-                                              const float* s_in, const float* s_out,
+__device__ __forceinline__ void load_deviations(const float* __restrict__ D, int s, int lane,
+                                                float (&d)[(N >= 64 ? N / 64 : 1)][3]) {
+    constexpr int PPL = N >= 64 ? N / 64 : 1;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const float* row = D + ((size_t)s * 3 + ax) * N;
+        if constexpr (PPL == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(row + lane * 4);
+            d[0][ax] = v.x; d[1][ax] = v.y; d[2][ax] = v.z; d[3][ax] = v.w;
+        } else if constexpr (PPL == 2) {
+            const float2 v = *reinterpret_cast<const float2*>(row + lane * 2);
+            d[0][ax] = v.x; d[1][ax] = v.y;
+        } else {
+            d[0][ax] = row[lane & (N - 1)];   // N = 32: lanes 32..63 repeat (ignored)
+        }
+    }
+}
+
+// Depth of a point in a closed box: min over axes of the distances to the two
+// faces (> 0 inside).  FP32; with positions below 16 in magnitude its error is
+// below 2^-18, far inside the guard band kGuard.
+__device__ __forceinline__ float box_depth32(float y0, float y1, float y2, const float* b) {
+    const float lo = fminf(fminf(y0 - b[0], y1 - b[1]), y2 - b[2]);
+    const float hi = fminf(fminf(b[3] - y0, b[4] - y1), b[5] - y2);
+    return fminf(lo, hi);
+}
+
+// Broadcast of lane k's double to the whole wave (wave-uniform result).
+__device__ __forceinline__ double readlane_f64(double v, int k) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)(bits & 0xFFFFFFFFll), k);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), k);
+    return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ float readlane_f32(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+template <int N>
+__device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, const float* s_raw,
+                                                  const float* s_out, long long& n_pre,
+                                                  long long& n_flag, long long& n_wp,
+                                                  long long& n_bt) {
+    constexpr int W = N / 32;                      // u32 mask words
+    constexpr int PPL = N >= 64 ? N / 64 : 1;      // particles per lane
+    constexpr int LPW = 32 / PPL;                  // lanes per mask word
+    const int n_obs = a.n_obs;
+    const int lane = threadIdx.x & 63;
+    const bool valid_lane = (N >= 64) || (lane < N);
+    const SimTask tk = a.tasks[task];
+    const int qj = tk.q, pj = tk.p;
+    const int hj = (int)(tk.nodes & 0xFFFFu), xj = (int)(tk.nodes >> 16);
+    const double tj = tk.tau;
+    const int Kj = max(1, (int)ceil(tj / a.dt));
+    const int spj = tk.s_p;
+    unsigned wm = tk.near;                         // non-zero for a queued pair
+    n_wp += __popc(wm);
+    // loads that do not depend on the waypoint loop, issued first
+    int k = __ffs((int)wm);
+    float dc[PPL][3], dn[PPL][3];
+    load_deviations<N>(a.D, spj + k, lane, dc);
+    uint32_t pm[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) pm[w] = a.p_mask[(size_t)pj * W + w];
+    const double cj = a.c_cost[qj];
+    const bool pre = a.preprune != 0;
+    const int c_cut = a.c_cut;
+    // staircase entries M_x(c) of the pair's head for c = lane (c < c_cut)
+    double st_lane = 0.0;
+    if (pre && lane < c_cut) st_lane = stair_get(a.stair, a.stair_w, xj, lane);
+    // lane k-1 holds waypoint k (k = 1..K_e <= 32): its nominal position
+    // (FP64 and FP32) and the particle cloud's box around it
+    double my_nom[3] = {0.0, 0.0, 0.0};
+    float my_n32[3] = {0.f, 0.f, 0.f}, my_lo[3] = {0.f, 0.f, 0.f}, my_hi[3] = {0.f, 0.f, 0.f};
+    {
+        Cubic cs[3];
+        hermite(a.X + (size_t)hj * 6, a.X + (size_t)xj * 6, tj, cs);
+        if (lane < Kj) {
+            const double t = ((double)(lane + 1) * tj) / (double)Kj;
+            const float* cl = a.cloud + (size_t)(spj + lane + 1) * 6;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                my_nom[ax] = cs[ax].at(t);
+                my_n32[ax] = (float)my_nom[ax];
+                my_lo[ax] = my_n32[ax] + cl[ax] - 1e-6f;
+                my_hi[ax] = my_n32[ax] + cl[3 + ax] + 1e-6f;
+            }
+        }
+    }
+    uint32_t hm = 0u, dm = 0u, nm = 0u;           // per particle r: hit, deep, near a face
+    for (;;) {
+        const unsigned rest = wm & (wm - 1u);
+        const int kn = rest ? __ffs((int)rest) : 0;
+        if (kn) load_deviations<N>(a.D, spj + kn, lane, dn);   // next waypoint, in flight
+        double nom64[3];
+        float nom32[3], lo3[3], hi3[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            nom64[ax] = readlane_f64(my_nom[ax], k - 1);
+            nom32[ax] = readlane_f32(my_n32[ax], k - 1);
+            lo3[ax] = readlane_f32(my_lo[ax], k - 1);
+            hi3[ax] = readlane_f32(my_hi[ax], k - 1);
+        }
+        float y[PPL][3];
+#pragma unroll
+        for (int r = 0; r < PPL; ++r)
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) y[r][ax] = nom32[ax] + dc[r][ax];
+        for (int c0 = 0; c0 < n_obs; c0 += 64) {
+            const int o = c0 + lane;
+            const bool ov = o < n_obs && boxes_overlap(lo3, hi3, s_out + o * 6);
+            unsigned long long om = __ballot(ov);
+            n_bt += __popcll(om);   // boxes tested against every particle
+            while (om) {
+                const int ob = c0 + __ffsll((long long)om) - 1;
+                om &= om - 1ull;
+                const float* br = s_raw + ob * 6;
+#pragma unroll
+                for (int r = 0; r < PPL; ++r) {
+                    const float dep = box_depth32(y[r][0], y[r][1], y[r][2], br);
+                    if (dep >= kGuard) {
+                        hm |= 1u << r;
+                        dm |= 1u << r;
+                    } else if (dep >= -kGuard && valid_lane) {
+                        // within the guard band of a face: decide in FP64
+                        double dmin = INFINITY;
+#pragma unroll
+                        for (int ax = 0; ax < 3; ++ax) {
+                            const double yy = nom64[ax] + (double)dc[r][ax];
+                            dmin = fmin(dmin, fmin(yy - (double)br[ax], (double)br[3 + ax] - yy));
+                        }
+                        if (dmin >= 0.0) hm |= 1u << r;
+                        if (dmin >= kFlagEps) dm |= 1u << r;
+                        if (fabs(dmin) < kFlagEps) nm |= 1u << r;
+                    }
+                }
+            }
+        }
+        if (!kn) break;
+        k = kn;
+        wm = rest;
+#pragma unroll
+        for (int r = 0; r < PPL; ++r)
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) dc[r][ax] = dn[r][ax];
+    }
+    // this lane's PPL bits go to bit (lane * PPL) % 32 of word lane / LPW;
+    // OR them together across the LPW lanes of each word
+    uint32_t hv = valid_lane ? hm : 0u;
+    uint32_t fv = valid_lane ? (nm & ~dm) : 0u;
+    hv <<= (lane * PPL) & 31;
+    fv <<= (lane * PPL) & 31;
+#pragma unroll
+    for (int o = 1; o < LPW; o <<= 1) {
+        hv |= (uint32_t)__shfl_xor((int)hv, o, 64);
+        fv |= (uint32_t)__shfl_xor((int)fv, o, 64);
+    }
+    uint32_t words[W];
+    int popc = 0;
+    long long flg = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t hw = (uint32_t)__builtin_amdgcn_readlane((int)hv, w * LPW);
+        const uint32_t fw = (uint32_t)__builtin_amdgcn_readlane((int)fv, w * LPW);
+        words[w] = pm[w] | hw;
+        flg += __popc(fw & ~pm[w]);
+        popc += __popc(words[w]);
+    }
+    bool keep = popc < c_cut;
+    if (keep && pre) {
+        const double m = popc < 64 ? readlane_f64(st_lane, popc)
+                                   : stair_get(a.stair, a.stair_w, xj, popc);
+        if (m < cj) {
+            keep = false;
+            ++n_pre;
+        }
+    }
+    if (lane == 0) {
+        a.c_flag[qj] = keep ? 1 : 0;
+        a.c_pop[qj] = popc;
+    }
+    if (keep && lane < W) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            if (w == lane) v = words[w];
+        a.c_mask[(size_t)qj * W + lane] = v;
+    }
+    n_flag += flg;
+}
+
+// Half-space model (Sec. III-B, eq. (7)) of the same step: per marked waypoint
+// the planes of the local convex region against every particle, in FP64.
+template <int N>
+__device__ __forceinline__ void simulate_pair_hsmc(const RoundArgs& a, int task, const float* s_raw,
                                               long long& n_pre, long long& n_flag, long long& n_wp,
                                               long long& n_bt) {
     constexpr int W = N / 32;                      // u32 mask words
@@ -323,9 +524,9 @@ __device__ __forceinline__ void simulate_pair(const RoundArgs& a, int task, cons
     for (int r = 0; r < PPL; ++r) { hit[r] = false; deep[r] = false; nearp[r] = false; }
     unsigned wm = nj;
     n_wp += __popc(wm);   // waypoints whose cloud box meets an obstacle (or a plane)
-    if (a.cp_model == 1) {
-        // HSMC: at each marked waypoint, every plane of the local region
-        // against every particle's deviation, in FP64
+    {
+        // at each marked waypoint, every plane of the local region against
+        // every particle's deviation, in FP64
         while (wm) {
             const int k = __ffs((int)wm);
             wm &= wm - 1u;
@@ -356,67 +557,6 @@ __device__ __forceinline__ void simulate_pair(const RoundArgs& a, int task, cons
                     if (g > b) hit[r] = true;
                     if (mg >= kFlagEps) deep[r] = true;
                     if (fabs(mg) < kFlagEps) nearp[r] = true;
-                }
-            }
-        }
-        wm = 0u;
-    }
-    while (wm) {
-        const int k = __ffs((int)wm);
-        wm &= wm - 1u;
-        const int s = spj + k;
-        const double t = ((double)k * tj) / (double)Kj;
-        double nom64[3];
-        float nom32[3];
-        for (int ax = 0; ax < 3; ++ax) { nom64[ax] = cs[ax].at(t); nom32[ax] = (float)nom64[ax]; }
-        const float* cl = a.cloud + (size_t)s * 6;
-        float lo3[3], hi3[3];
-        for (int ax = 0; ax < 3; ++ax) {
-            lo3[ax] = nom32[ax] + cl[ax] - 1e-6f;
-            hi3[ax] = nom32[ax] + cl[3 + ax] + 1e-6f;
-        }
-        float y[PPL][3];
-        bool loaded = false;
-        for (int c0 = 0; c0 < n_obs; c0 += 64) {
-            const int o = c0 + lane;
-            const bool ov = o < n_obs && boxes_overlap(lo3, hi3, s_out + o * 6);
-            unsigned long long om = __ballot(ov);
-            n_bt += __popcll(om);   // boxes tested against every particle
-            if (om && !loaded) {
-                for (int r = 0; r < PPL; ++r) {
-                    const int jj = valid_lane ? r * 64 + lane : 0;
-                    for (int ax = 0; ax < 3; ++ax)
-                        y[r][ax] = nom32[ax] + a.D[((size_t)s * 3 + ax) * N + jj];
-                }
-                loaded = true;
-            }
-            while (om) {
-                const int ob = c0 + __ffsll((long long)om) - 1;
-                om &= om - 1ull;
-                const float* bi = s_in + ob * 6;
-                const float* bo = s_out + ob * 6;
-                for (int r = 0; r < PPL; ++r) {
-                    const float y0 = y[r][0], y1 = y[r][1], y2 = y[r][2];
-                    const bool inner = (y0 >= bi[0]) & (y0 <= bi[3]) & (y1 >= bi[1]) &
-                                       (y1 <= bi[4]) & (y2 >= bi[2]) & (y2 <= bi[5]);
-                    const bool outer = (y0 >= bo[0]) & (y0 <= bo[3]) & (y1 >= bo[1]) &
-                                       (y1 <= bo[4]) & (y2 >= bo[2]) & (y2 <= bo[5]);
-                    if (inner) {
-                        hit[r] = true;
-                        deep[r] = true;
-                    } else if (outer && valid_lane) {
-                        // within the guard band of a face: decide in FP64
-                        const int jj = r * 64 + lane;
-                        const float* br = s_raw + ob * 6;
-                        double dmin = INFINITY;
-                        for (int ax = 0; ax < 3; ++ax) {
-                            const double yy = nom64[ax] + (double)a.D[((size_t)s * 3 + ax) * N + jj];
-                            dmin = fmin(dmin, fmin(yy - (double)br[ax], (double)br[3 + ax] - yy));
-                        }
-                        if (dmin >= 0.0) hit[r] = true;
-                        if (dmin >= kFlagEps) deep[r] = true;
-                        if (fabs(dmin) < kFlagEps) nearp[r] = true;
-                    }
                 }
             }
         }
@@ -457,6 +597,20 @@ __device__ __forceinline__ void simulate_pair(const RoundArgs& a, int task, cons
         a.c_mask[(size_t)qj * W + lane] = v;
     }
     n_flag += flg;
+}
+
+
+// One queued pair: the box predicate (default) or the half-space model.
+template <int N>
+__device__ __forceinline__ void simulate_pair(const RoundArgs& a, int task, const float* s_raw,
+                                              const float* s_in, const float* s_out,
+                                              long long& n_pre, long long& n_flag, long long& n_wp,
+                                              long long& n_bt) {
+    (void)s_in;
+    if (a.cp_model == 1)
+        simulate_pair_hsmc<N>(a, task, s_raw, n_pre, n_flag, n_wp, n_bt);
+    else
+        simulate_pair_box<N>(a, task, s_raw, s_out, n_pre, n_flag, n_wp, n_bt);
 }
 
 // ---------------------------------------------------------------------------

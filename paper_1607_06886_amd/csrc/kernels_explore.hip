@@ -167,18 +167,23 @@ __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
     }
 }
 
-template <int N>
+// CP = 0: the box predicate, 1: the half-space model (one instantiation each,
+// so the box kernel keeps only its own registers: 4 waves per SIMD).
+template <int N, int CP>
 __global__ __launch_bounds__(256) void k_expand_sim(RoundArgs a) {
     __shared__ float s_raw[kMaxObs * 6];
-    __shared__ float s_in[kMaxObs * 6];
     __shared__ float s_out[kMaxObs * 6];
-    stage_obstacles_block(a.obs, a.n_obs, s_raw, s_in, s_out);
+    stage_obstacles_block(a.obs, a.n_obs, s_raw, nullptr, s_out);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int n_tasks = a.ctl->n_tasks;
     long long n_pre = 0, n_flag = 0, n_wp = 0, n_bt = 0;
-    for (int task = blockIdx.x * 4 + (threadIdx.x >> 6); task < n_tasks; task += gridDim.x * 4)
-        simulate_pair<N>(a, task, s_raw, s_in, s_out, n_pre, n_flag, n_wp, n_bt);
+    for (int task = blockIdx.x * 4 + (threadIdx.x >> 6); task < n_tasks; task += gridDim.x * 4) {
+        if (CP == 1)
+            simulate_pair_hsmc<N>(a, task, s_raw, n_pre, n_flag, n_wp, n_bt);
+        else
+            simulate_pair_box<N>(a, task, s_raw, s_out, n_pre, n_flag, n_wp, n_bt);
+    }
     // counts are wave-uniform
     if (lane == 0) {
         if (n_pre) atomicAdd((unsigned long long*)&a.ctl->preprune, (unsigned long long)n_pre);
@@ -186,6 +191,15 @@ __global__ __launch_bounds__(256) void k_expand_sim(RoundArgs a) {
         if (n_wp) atomicAdd((unsigned long long*)&a.ctl->sim_waypoints, (unsigned long long)n_wp);
         if (n_bt) atomicAdd((unsigned long long*)&a.ctl->sim_box_tests, (unsigned long long)n_bt);
     }
+}
+
+template <int N>
+static void launch_expand_n(hipStream_t s, const RoundArgs& a, unsigned blocks, unsigned sim_blocks) {
+    k_expand_pairs<N><<<blocks, 256, 0, s>>>(a);
+    if (a.cp_model == 1)
+        k_expand_sim<N, 1><<<sim_blocks, 256, 0, s>>>(a);
+    else
+        k_expand_sim<N, 0><<<sim_blocks, 256, 0, s>>>(a);
 }
 
 void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs) {
@@ -198,22 +212,10 @@ void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs) {
     long long sim_blocks = (n_pairs + 3) / 4;
     if (sim_blocks > 4096) sim_blocks = 4096;
     switch (N) {
-        case 32:
-            k_expand_pairs<32><<<(unsigned)blocks, 256, 0, s>>>(a);
-            k_expand_sim<32><<<(unsigned)sim_blocks, 256, 0, s>>>(a);
-            break;
-        case 64:
-            k_expand_pairs<64><<<(unsigned)blocks, 256, 0, s>>>(a);
-            k_expand_sim<64><<<(unsigned)sim_blocks, 256, 0, s>>>(a);
-            break;
-        case 128:
-            k_expand_pairs<128><<<(unsigned)blocks, 256, 0, s>>>(a);
-            k_expand_sim<128><<<(unsigned)sim_blocks, 256, 0, s>>>(a);
-            break;
-        default:
-            k_expand_pairs<256><<<(unsigned)blocks, 256, 0, s>>>(a);
-            k_expand_sim<256><<<(unsigned)sim_blocks, 256, 0, s>>>(a);
-            break;
+        case 32: launch_expand_n<32>(s, a, (unsigned)blocks, (unsigned)sim_blocks); break;
+        case 64: launch_expand_n<64>(s, a, (unsigned)blocks, (unsigned)sim_blocks); break;
+        case 128: launch_expand_n<128>(s, a, (unsigned)blocks, (unsigned)sim_blocks); break;
+        default: launch_expand_n<256>(s, a, (unsigned)blocks, (unsigned)sim_blocks); break;
     }
 }
 
