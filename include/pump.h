@@ -297,26 +297,30 @@ int pump_sample_halton(int32_t n, int32_t n_goal, const float* lo, const float* 
  * bracketed by HIP events on the context's stream and the elapsed times are
  * accumulated per kind:
  *   0 deviation table   1 graph pass 1 (all pairs)   2 graph pass 2 (fill)
- *   3 expand            4 prune (staircase update + mark)
+ *   3 expand, pair stage (per-phase mode)   4 prune (staircase update + mark)
  *   5 compact (scans + scatter)   6 next group (min, flags, scans)
  *   7 front selection   8 MC certification   9 Explore as one launch
  *   10..16 phases of the single-launch Explore as seen by its first
  *   workgroup (expand, simulate, staircase, marks, scans + compaction,
  *   next group, group scatter + pair offsets; each includes its barrier;
  *   "launches" counts rounds)   17 Smooth (all of its launches)
+ *   18 expand, particle stage (per-phase mode)
  * pump_set_timing(ctx, on) switches it and clears the totals;
  * pump_get_timing copies min(n, PUMP_TIMING_KINDS) totals (ms) and launch
  * counts (either pointer may be NULL). */
-#define PUMP_TIMING_KINDS 18
+#define PUMP_TIMING_KINDS 19
 int pump_set_timing(pump_ctx* ctx, int32_t on);
 int pump_get_timing(pump_ctx* ctx, double* ms, int64_t* launches, int32_t n);
 
-/* How pump_explore_run (and so pump_plan) runs Alg. 4's loop: mode 1 (the
- * default) runs all remaining rounds in one launch whose workgroups (all
- * resident at once) meet at grid-wide barriers; mode 0
- * launches each phase of each round separately and reads the loop state back
- * after every round (as pump_explore_round always does).  Both build the same
- * plan store.  get reports the mode and the workgroups of the single launch. */
+/* How pump_explore_run (and so pump_plan) runs Alg. 4's loop: mode 1 runs all
+ * remaining rounds in one launch whose workgroups (all resident at once) meet
+ * at grid-wide barriers; mode 0 launches each phase of each round separately
+ * and reads the loop state back after every round (as pump_explore_round
+ * always does); mode 2 (the default where the single launch fits) chooses
+ * per query from the graph's edge count: the single launch below 4 * 2^20
+ * edges, per-phase launches from there on, where the particle simulation's
+ * own kernel is faster.  All modes build the same plan store.  get reports
+ * the configured mode and the workgroups of the single launch. */
 int pump_set_explore_mode(pump_ctx* ctx, int32_t mode);
 int pump_get_explore_mode(pump_ctx* ctx, int32_t* mode, int32_t* blocks);
 
@@ -358,6 +362,19 @@ int pump_mlp_num_params(void);
 /* Load FP32 parameters from the host (resets the Adam moments) / read them. */
 int pump_mlp_set_params(pump_mlp* m, const float* params, int64_t n);
 int pump_mlp_get_params(pump_mlp* m, float* params, int64_t n);
+/* Checkpoint and resume of training: the FP32 parameters, Adam's first and
+ * second moment estimates (each [n] host arrays, n = pump_mlp_num_params())
+ * and the step counter t.  set restores all four (the BF16 copies are
+ * refreshed), so training resumed from a saved state takes exactly the
+ * steps the uninterrupted run would.  pump_mlp_set_params instead resets the
+ * moments and t to zero. */
+int pump_mlp_get_state(pump_mlp* m, float* params, float* m1, float* m2, int64_t n, int32_t* t);
+int pump_mlp_set_state(pump_mlp* m, const float* params, const float* m1, const float* m2,
+                       int64_t n, int32_t t);
+/* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrections at step t + 1) on the given gradient vector grads [n] (host or
+ * device per mem) instead of the network's own; the training step's update. */
+int pump_mlp_adam_step(pump_mlp* m, const float* grads, int64_t n, float lr, int32_t mem);
 /* out [B][208] = network outputs for cond [B][396]. */
 int pump_mlp_forward(pump_mlp* m, const float* cond, int32_t B, float* out, int32_t mem);
 /* Mean mixture negative log-likelihood of target states [B][6] and its

@@ -24,6 +24,7 @@ Readings used here:
 from __future__ import annotations
 
 import dataclasses
+import time
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -173,6 +174,46 @@ def _extend_hsmc(V, graph, D, boxes, dt, S_max, parents, edges, cache):
     return x, cost, step, mask, over, flagged
 
 
+def row_range(graph, u):
+    """Edge-id range of N(u): a CSR row, or a row built on demand
+    (graph.RowsOnDemand)."""
+    rows = getattr(graph, "rows", None)
+    if rows is not None:
+        return rows(u)
+    return int(graph["row_ptr"][u]), int(graph["row_ptr"][u + 1])
+
+
+# Worker state of the process pool that splits a round's pairs (set by
+# pool_init in each worker process).
+_POOL_ARGS = None
+
+
+def pool_init(V, D, boxes, dt, S_max):
+    global _POOL_ARGS
+    _POOL_ARGS = (np.asarray(V, np.float64), D, boxes, dt, S_max)
+
+
+def _pool_extend(job):
+    parents, col, tau, cost = job
+    V, D, boxes, dt, S_max = _POOL_ARGS
+    g = dict(col=col, tau=tau, cost=cost)
+    return extend_batch(V, g, D, boxes, dt, S_max, parents, np.arange(col.shape[0]))
+
+
+def extend_split(pool, V, graph, D, boxes, dt, S_max, parents, edges, pieces):
+    """extend_batch over the pairs of one round split into `pieces`
+    contiguous slices, each run by a worker of `pool` (pool_init), the results
+    concatenated in slice order: the same arrays as one call."""
+    m = len(parents)
+    cuts = np.linspace(0, m, pieces + 1).astype(np.int64)
+    jobs = [(parents[a:b], graph["col"][edges[a:b]], graph["tau"][edges[a:b]],
+             graph["cost"][edges[a:b]]) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+    outs = pool.map(_pool_extend, jobs)
+    if not outs:
+        return extend_batch(V, graph, D, boxes, dt, S_max, parents, edges)
+    return tuple(np.concatenate([o[k] for o in outs]) for k in range(6))
+
+
 def dominates(d: Plan, p: Plan) -> bool:
     """d dominates p (Sec. IV, RemoveDominated): d is strictly cheaper and its
     particle CP estimate is no larger (cp_hat = pop / N with the same N, so
@@ -201,9 +242,14 @@ def remove_dominated(plans: List[Plan], P: Dict[int, List[int]], P_open: set) ->
 
 
 def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
-            S_max, record=False, cp_model="box"):
+            S_max, record=False, cp_model="box", time_budget=None, pool=None, pieces=1):
     """Alg. 4.  Returns (plans, P, stats, rounds) where P maps head -> plan ids
-    still in P(head) at exit and `rounds` holds per-round snapshots if `record`."""
+    still in P(head) at exit and `rounds` holds per-round snapshots if `record`.
+
+    For timing runs only: with `time_budget` (seconds) the loop also ends
+    after the first round that finishes past the budget (stats["truncated"]);
+    with a process pool (pool_init) each round's pairs are split into
+    `pieces` slices that workers extend side by side."""
     N = D.shape[2]
     root = Plan(nodes=(0,), cost=0.0, step=0, mask=np.zeros(N, bool), parent=-1,
                 fmask=np.zeros(N, bool))
@@ -219,6 +265,8 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
                  dropped_steps=0, flagged_particles=0)
     hs_cache = {}
     rounds = []
+    t_start = time.perf_counter()
+    stats["truncated"] = False
 
     def stop_now():
         return any(goal[plans[g].head] and plans[g].pop / N < alpha_min for g in B)
@@ -229,16 +277,21 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
         parents, edges, parent_ids = [], [], []
         for p in sorted(B):
             u = plans[p].head
-            for e in range(graph["row_ptr"][u], graph["row_ptr"][u + 1]):
+            e0, e1 = row_range(graph, u)
+            for e in range(e0, e1):
                 parents.append(plans[p])
                 parent_ids.append(p)
                 edges.append(e)
         edges = np.asarray(edges, np.int64)
         if B:
             stats["rounds"] += 1
-        x, cost, step, mask, over, flagged = extend_batch(
-            V, graph, D, boxes, dt, S_max, parents, edges, cp_model=cp_model,
-            hs_cache=hs_cache)
+        if pool is not None and cp_model == "box" and len(parents) > pieces:
+            x, cost, step, mask, over, flagged = extend_split(
+                pool, V, graph, D, boxes, dt, S_max, parents, edges, pieces)
+        else:
+            x, cost, step, mask, over, flagged = extend_batch(
+                V, graph, D, boxes, dt, S_max, parents, edges, cp_model=cp_model,
+                hs_cache=hs_cache)
         stats["partial_plans"] += len(parents)
         stats["dropped_steps"] += int(over.sum())
         stats["flagged_particles"] += int(flagged.sum())
@@ -280,6 +333,9 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
             rounds.append(snap)
         i += 1
         B = sorted(p for p in P_open if plans[p].cost <= i * h)
+        if time_budget is not None and time.perf_counter() - t_start > time_budget:
+            stats["truncated"] = True
+            break
     stats["final_i"] = i
     stats["stopped_at_goal"] = bool(P_open) and stop_now()
     return plans, P, stats, rounds

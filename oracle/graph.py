@@ -14,6 +14,8 @@ its index but gets no edges).
 
 from __future__ import annotations
 
+import time
+
 import numpy as np
 
 from . import steer as st
@@ -191,3 +193,48 @@ def build_graph(V, obstacles, r_n, r_u, chunk=1 << 18):
     np.add.at(row_ptr, src + 1, 1)
     row_ptr = np.cumsum(row_ptr)
     return dict(valid=valid, row_ptr=row_ptr, col=col.astype(np.int64), tau=tau, cost=cost)
+
+
+class RowsOnDemand(dict):
+    """The graph of build_graph, each row N(v) built by graph_rows the first
+    time Explore asks for it.  The rows are the same; a bounded run of Explore
+    on a graph too large to build whole then builds only the rows it expands.
+    `col`, `tau`, `cost` hold the rows built so far (edge ids in build order);
+    rows(v) returns the edge-id range of N(v); `seconds` is the time spent
+    building rows."""
+
+    def __init__(self, V, obstacles, r_n, r_u):
+        V = np.asarray(V, np.float64)
+        super().__init__(valid=~points_in_boxes(V[:, :3], obstacles))
+        self._args = (V, obstacles, r_n, r_u)
+        self._range = {}
+        self._buf = dict(col=np.zeros(1024, np.int64), tau=np.zeros(1024), cost=np.zeros(1024))
+        self._size = 0
+        self.seconds = 0.0
+        self._publish()
+
+    def _publish(self):
+        for k, a in self._buf.items():
+            self[k] = a[:self._size]
+
+    def rows(self, v):
+        r = self._range.get(int(v))
+        if r is None:
+            t0 = time.perf_counter()
+            V, obs, r_n, r_u = self._args
+            _, dst, tau, cost = graph_rows(V, self["valid"], obs, r_n, r_u, [int(v)])
+            lo, hi = self._size, self._size + dst.shape[0]
+            if hi > self._buf["col"].shape[0]:
+                cap = max(hi, 2 * self._buf["col"].shape[0])
+                for k in self._buf:
+                    grown = np.zeros(cap, self._buf[k].dtype)
+                    grown[:lo] = self._buf[k][:lo]
+                    self._buf[k] = grown
+            self._buf["col"][lo:hi] = dst
+            self._buf["tau"][lo:hi] = tau
+            self._buf["cost"][lo:hi] = cost
+            self._size = hi
+            self._publish()
+            r = self._range[int(v)] = (lo, hi)
+            self.seconds += time.perf_counter() - t0
+        return r

@@ -95,7 +95,8 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
            "pump_set_barrier_patience", "pump_get_explore_fallbacks",
            "pump_status_str", "pump_last_error", "pump_mlp_create",
            "pump_mlp_destroy", "pump_mlp_num_params", "pump_mlp_set_params",
-           "pump_mlp_get_params", "pump_mlp_forward", "pump_mlp_loss_grad",
+           "pump_mlp_get_params", "pump_mlp_get_state", "pump_mlp_set_state",
+           "pump_mlp_adam_step", "pump_mlp_forward", "pump_mlp_loss_grad",
            "pump_mlp_train_step", "pump_mlp_condition", "pump_mlp_sample",
            "pump_mlp_last_error", "pump_batch_create", "pump_batch_destroy",
            "pump_batch_plan", "pump_batch_get_path", "pump_batch_tune",
@@ -104,7 +105,7 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
 TIMING_KINDS = ["deviation", "graph_mark", "graph_fill", "expand", "prune", "compact",
                 "next_group", "select_front", "mc", "explore_single", "ph_expand",
                 "ph_simulate", "ph_stair", "ph_mark", "ph_compact", "ph_next_group",
-                "ph_group", "smooth"]
+                "ph_group", "smooth", "expand_sim"]
 
 
 def load(path: Optional[str] = None):
@@ -161,6 +162,9 @@ def load(path: Optional[str] = None):
         "pump_mlp_num_params": (_i32, []),
         "pump_mlp_set_params": (_i32, [_p, _p, _i64]),
         "pump_mlp_get_params": (_i32, [_p, _p, _i64]),
+        "pump_mlp_get_state": (_i32, [_p, _p, _p, _p, _i64, P(_i32)]),
+        "pump_mlp_set_state": (_i32, [_p, _p, _p, _p, _i64, _i32]),
+        "pump_mlp_adam_step": (_i32, [_p, _p, _i64, _f, _i32]),
         "pump_mlp_forward": (_i32, [_p, _p, _i32, _p, _i32]),
         "pump_mlp_loss_grad": (_i32, [_p, _p, _p, _i32, P(_f), _p, _i32]),
         "pump_mlp_train_step": (_i32, [_p, _p, _p, _i32, _f, P(_f), _i32]),
@@ -411,7 +415,8 @@ class Planner:
         return tuple(int(v) for v in buf[:ln.value])
 
     def set_explore_mode(self, mode: int):
-        """1: all rounds in one cooperative launch; 0: one launch per phase."""
+        """1: all rounds in one launch; 0: one launch per phase; 2: chosen
+        per query from the graph's size (the default)."""
         self._check(self.lib.pump_set_explore_mode(self.ctx, int(mode)))
 
     def explore_mode(self):
@@ -514,6 +519,37 @@ class MLP:
         f = np.zeros(self.n_params, np.float32)
         self._check(self.lib.pump_mlp_get_params(self.m, f.ctypes.data, f.size))
         return f
+
+    def get_state(self) -> dict:
+        """Parameters, Adam moments and step counter (a training checkpoint)."""
+        st = {k: np.zeros(self.n_params, np.float32) for k in ("params", "m1", "m2")}
+        t = _i32(0)
+        self._check(self.lib.pump_mlp_get_state(self.m, st["params"].ctypes.data,
+                                                st["m1"].ctypes.data, st["m2"].ctypes.data,
+                                                self.n_params, ctypes.byref(t)))
+        st["t"] = int(t.value)
+        return st
+
+    def set_state(self, st: dict):
+        a = {k: _np(st[k], np.float32) for k in ("params", "m1", "m2")}
+        self._check(self.lib.pump_mlp_set_state(self.m, a["params"].ctypes.data,
+                                                a["m1"].ctypes.data, a["m2"].ctypes.data,
+                                                self.n_params, int(st["t"])))
+
+    def save(self, path):
+        """The training state to an .npz file (plain arrays, no pickles)."""
+        st = self.get_state()
+        np.savez(path, params=st["params"], m1=st["m1"], m2=st["m2"],
+                 t=np.array([st["t"]], np.int64))
+
+    def load(self, path):
+        with np.load(path, allow_pickle=False) as z:
+            self.set_state(dict(params=z["params"], m1=z["m1"], m2=z["m2"], t=int(z["t"][0])))
+
+    def adam_step(self, grads, lr):
+        """One Adam update with the given gradient vector."""
+        g = _np(grads, np.float32)
+        self._check(self.lib.pump_mlp_adam_step(self.m, g.ctypes.data, g.size, float(lr), MEM_HOST))
 
     def forward(self, cond):
         if isinstance(cond, np.ndarray):

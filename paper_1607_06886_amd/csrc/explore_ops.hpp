@@ -133,7 +133,9 @@ __device__ __forceinline__ int wave_group_of(const int32_t* __restrict__ b_off, 
 // bits (written here), 2 if its particles must be simulated (its queue record
 // in tk), 0 if resolved.
 // ---------------------------------------------------------------------------
-template <int N>
+// CP: 0 the box model, 1 the half-space model, 2 whichever a.cp_model names
+// (a kernel instantiated for one model keeps only that model's registers).
+template <int N, int CP = 2>
 __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int lo, const float* s_raw,
                                            const float* s_out, const float* gl, const float* gh,
                                            long long& n_sim, long long& n_pre, long long& n_drop,
@@ -166,7 +168,7 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int lo, co
     ++n_sim;
     Cubic cs[3];
     hermite(a.X + (size_t)head * 6, a.X + (size_t)x * 6, tau, cs);
-    if (a.cp_model == 1) {
+    if (CP == 1 || (CP == 2 && a.cp_model == 1)) {
         // HSMC: mark the waypoints where some particle of the cloud box can
         // reach a plane of the local region, or come within the flag distance
         unsigned near = 0u;
@@ -696,6 +698,7 @@ __device__ __forceinline__ void compact_finalize(Ctl* c, int64_t cap) {
     if ((long long)c->n_plans + n_surv > cap) {
         c->err = 1;
         c->done = 1;
+        c->n_surv = n_surv;   // the plan store needs n_plans + n_surv entries
         return;
     }
     c->n_plans += n_surv;

@@ -289,6 +289,7 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
     long long w_pre = 0, w_flag = 0, w_wp = 0, w_bt = 0;     // wave-uniform
     long long partial = 0;
     int rounds = 0, err = 0;
+    int fail_surv = 0;            // survivors of the round that overflowed the plan store
     // phase wall times seen by the leader (constant-rate real-time counter)
     unsigned long long t_prev = 0, ticks[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     auto tick = [&](int k) {
@@ -413,6 +414,7 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         if (tid == 0 && m != 0x7FF0000000000000ull) atomicMin(&c->min_cost_bits, m);
         if (!fits) {
             err = 1;
+            fail_surv = n_surv;
             break;
         }
         n_plans += n_surv;
@@ -523,6 +525,7 @@ __device__ void explore_team(const RoundArgs* __restrict__ ra, const TeamCtx& g,
         const bool failed =
             __hip_atomic_load(g.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
         c->n_plans = n_plans;
+        c->n_surv = fail_surv;
         c->n_open = n_open;
         c->n_B = done ? 0 : n_B;
         c->n_pairs = done ? 0 : n_pairs;

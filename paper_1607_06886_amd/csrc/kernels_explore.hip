@@ -133,7 +133,7 @@ void launch_explore_init(hipStream_t s, const RoundArgs& a, int n_nodes, int N, 
 // with one pair per lane and queues the pairs whose particles must be
 // simulated; k_expand_sim simulates them with one pair per wave.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int CP>
 __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
     __shared__ float s_raw[kMaxObs * 6];
     __shared__ float s_out[kMaxObs * 6];
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
         const int q = tile + lane;
         SimTask tk;
         const int grp = wave_group_of(a.b_off, n_B, tile, q);
-        const int st = q < n_pairs ? expand_pair<N>(a, q, grp, s_raw, s_out, gl, gh, n_sim, n_pre,
+        const int st = q < n_pairs ? expand_pair<N, CP>(a, q, grp, s_raw, s_out, gl, gh, n_sim, n_pre,
                                                      n_drop, tk) : 0;
         queue_pairs(a, st, tk);
     }
@@ -194,15 +194,23 @@ __global__ __launch_bounds__(256) void k_expand_sim(RoundArgs a) {
 }
 
 template <int N>
-static void launch_expand_n(hipStream_t s, const RoundArgs& a, unsigned blocks, unsigned sim_blocks) {
-    k_expand_pairs<N><<<blocks, 256, 0, s>>>(a);
-    if (a.cp_model == 1)
-        k_expand_sim<N, 1><<<sim_blocks, 256, 0, s>>>(a);
-    else
-        k_expand_sim<N, 0><<<sim_blocks, 256, 0, s>>>(a);
+static void launch_expand_n(hipStream_t s, const RoundArgs& a, unsigned blocks, unsigned sim_blocks,
+                            int part) {
+    if (part & 1) {
+        if (a.cp_model == 1)
+            k_expand_pairs<N, 1><<<blocks, 256, 0, s>>>(a);
+        else
+            k_expand_pairs<N, 0><<<blocks, 256, 0, s>>>(a);
+    }
+    if (part & 2) {
+        if (a.cp_model == 1)
+            k_expand_sim<N, 1><<<sim_blocks, 256, 0, s>>>(a);
+        else
+            k_expand_sim<N, 0><<<sim_blocks, 256, 0, s>>>(a);
+    }
 }
 
-void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs) {
+void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, int part) {
     if (n_pairs <= 0) return;
     long long waves = (n_pairs + 63) / 64;
     long long blocks = (waves + 3) / 4;
@@ -212,10 +220,10 @@ void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs) {
     long long sim_blocks = (n_pairs + 3) / 4;
     if (sim_blocks > 4096) sim_blocks = 4096;
     switch (N) {
-        case 32: launch_expand_n<32>(s, a, (unsigned)blocks, (unsigned)sim_blocks); break;
-        case 64: launch_expand_n<64>(s, a, (unsigned)blocks, (unsigned)sim_blocks); break;
-        case 128: launch_expand_n<128>(s, a, (unsigned)blocks, (unsigned)sim_blocks); break;
-        default: launch_expand_n<256>(s, a, (unsigned)blocks, (unsigned)sim_blocks); break;
+        case 32: launch_expand_n<32>(s, a, (unsigned)blocks, (unsigned)sim_blocks, part); break;
+        case 64: launch_expand_n<64>(s, a, (unsigned)blocks, (unsigned)sim_blocks, part); break;
+        case 128: launch_expand_n<128>(s, a, (unsigned)blocks, (unsigned)sim_blocks, part); break;
+        default: launch_expand_n<256>(s, a, (unsigned)blocks, (unsigned)sim_blocks, part); break;
     }
 }
 
@@ -294,6 +302,10 @@ void launch_compact(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, i
 
 // Next group (Alg. 4: i <- i + 1, B <- cheap open plans) and the loop test.
 __global__ __launch_bounds__(256) void k_open_min(RoundArgs a) {
+    // after a failed compaction (plan store full: err set, done set) the
+    // open list holds only the kept plans while n_open still counts the
+    // previous round's, so there is nothing to read
+    if (a.ctl->err || a.ctl->done) return;
     const int n_open = a.ctl->n_open;
     unsigned long long m = 0x7FF0000000000000ull;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_open; i += gridDim.x * blockDim.x) {

@@ -222,14 +222,16 @@ void launch_grad_prep(hipStream_t s, const float* G, int ldg, int Bp, int width,
 // Adam (Kingma & Ba) on the FP32 master parameters, then the BF16 copies
 // (row-major [out_p][in_p] and transposed [in_p][out_p], zero padded).
 // ---------------------------------------------------------------------------
+// (1 - beta) is passed rounded from its exact value: 1 - 0.999f in FP32 would be
+// 1.3e-5 relatively off 0.001.
 __global__ void k_adam(float* __restrict__ p, float* __restrict__ m1, float* __restrict__ m2,
                        const float* __restrict__ g, int n, float lr, float b1, float b2,
-                       float eps, float c1, float c2) {
+                       float omb1, float omb2, float eps, float c1, float c2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
-    const float a = b1 * m1[i] + (1.0f - b1) * gi;
-    const float b = b2 * m2[i] + (1.0f - b2) * gi * gi;
+    const float a = b1 * m1[i] + omb1 * gi;
+    const float b = b2 * m2[i] + omb2 * gi * gi;
     m1[i] = a;
     m2[i] = b;
     p[i] = p[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
@@ -237,9 +239,10 @@ __global__ void k_adam(float* __restrict__ p, float* __restrict__ m1, float* __r
 
 void launch_adam(hipStream_t s, float* p, float* m1, float* m2, const float* g, int n, float lr,
                  int t) {
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = (float)(1.0 - pow(0.9, t)), c2 = (float)(1.0 - pow(0.999, t));
-    k_adam<<<(n + 255) / 256, 256, 0, s>>>(p, m1, m2, g, n, lr, b1, b2, 1e-8f, c1, c2);
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - pow(b1, t)), c2 = (float)(1.0 - pow(b2, t));
+    k_adam<<<(n + 255) / 256, 256, 0, s>>>(p, m1, m2, g, n, lr, (float)b1, (float)b2,
+                                           (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, c1, c2);
 }
 
 __global__ void k_refresh_bf16(const float* __restrict__ W, int out, int in, int out_p, int in_p,

@@ -72,7 +72,7 @@ struct pump_ctx {
     // arrival words [4096], then the 64-bit exchange words [2][coop_blocks]
     unsigned* coop_sync = nullptr;
     int coop_blocks = 0;            // resident workgroups of the single-launch Explore
-    int explore_mode = 0;           // 0: one launch per phase, 1: single launch
+    int explore_mode = 0;           // 0: one launch per phase, 1: single launch, 2: by graph size
     unsigned long long patience = kDefaultPatience;   // single launch's barrier waits (100 MHz ticks)
     long long fallbacks = 0;        // single launches that timed out and were redone per phase
     RoundArgs* ra_dev = nullptr;    // [2] round arguments of the single launch
@@ -454,7 +454,7 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
             n_cu > 0 && ctx->coop_blocks > per_cu * n_cu)
             ctx->coop_blocks = per_cu * n_cu;
         if (ctx->coop_blocks > 4096) ctx->coop_blocks = 4096;
-        ctx->explore_mode = ctx->coop_blocks > 0 ? 1 : 0;
+        ctx->explore_mode = ctx->coop_blocks > 0 ? 2 : 0;
     }
     A(dalloc(&ctx->coop_sync, (size_t)kCoopSyncWords));
     A(dalloc(&ctx->ra_dev, 2));
@@ -695,7 +695,10 @@ int pump_explore_round(pump_ctx* ctx, int32_t* done) {
         return fail(ctx, PUMP_E_CAPACITY, "round pairs " + std::to_string(n_pairs) + " exceed cap_pairs");
     RoundArgs a = round_args(ctx);
     tbeg(ctx, 3);
-    launch_expand(ctx->stream, a, ctx->N, n_pairs);
+    launch_expand(ctx->stream, a, ctx->N, n_pairs, 1);
+    tend(ctx);
+    tbeg(ctx, 18);
+    launch_expand(ctx->stream, a, ctx->N, n_pairs, 2);
     tend(ctx);
     tbeg(ctx, 4);
     launch_prune(ctx->stream, a, ctx->N, n_pairs, n_open);
@@ -716,7 +719,10 @@ int pump_explore_round(pump_ctx* ctx, int32_t* done) {
     std::swap(ctx->open_cur, ctx->open_next);
     if (ctx->ctl_h->err == 3) return fail(ctx, PUMP_E_STATE, "open plans without a finite cost");
     if (ctx->ctl_h->err)
-        return fail(ctx, PUMP_E_CAPACITY, "plan store exceeds cap_plans");
+        return fail(ctx, PUMP_E_CAPACITY,
+                    "plan store needs " +
+                        std::to_string((long long)ctx->ctl_h->n_plans + ctx->ctl_h->n_surv) +
+                        " plans, over cap_plans");
     if (ctx->rounds > (1 << 24)) return fail(ctx, PUMP_E_STATE, "Explore did not terminate");
     ctx->explore_done = ctx->ctl_h->done != 0;
     if (done) *done = ctx->explore_done ? 1 : 0;
@@ -767,13 +773,18 @@ static int explore_single_finish(pump_ctx* ctx) {
     ctx->partial_plans += c->partial;
     ctx->rounds += c->rounds;
     if (c->open_final) std::swap(ctx->open_cur, ctx->open_next);
-    if (c->err == 4) return fail(ctx, PUMP_E_CAPACITY, "round pairs exceed cap_pairs");
+    if (c->err == 4)
+        return fail(ctx, PUMP_E_CAPACITY, "round pairs " + std::to_string(c->n_pairs) +
+                                              " exceed cap_pairs");
     if (c->err == 3) return fail(ctx, PUMP_E_STATE, "open plans without a finite cost");
     if (c->err == 5) return fail(ctx, PUMP_E_STATE, "grid barrier timed out");
     if (c->err == 6) return fail(ctx, PUMP_E_STATE, "Explore did not terminate");
     // (2 is the selection's code for an oversized front, set when the
     // selection already ran behind the launch)
-    if (c->err && c->err != 2) return fail(ctx, PUMP_E_CAPACITY, "plan store exceeds cap_plans");
+    if (c->err && c->err != 2)
+        return fail(ctx, PUMP_E_CAPACITY,
+                    "plan store needs " + std::to_string((long long)c->n_plans + c->n_surv) +
+                        " plans, over cap_plans");
     ctx->explore_done = true;
     return PUMP_OK;
 }
@@ -785,11 +796,26 @@ static int explore_single_launch(pump_ctx* ctx) {
     return r;
 }
 
+// Mode 2 picks per query: the single launch holds every phase in one kernel
+// at two waves per SIMD and meets at grid barriers, which pays on graphs of
+// a few million edges or less (one query then is a short chain of dependent
+// steps); on larger graphs the particle simulation dominates and its own
+// kernel, at four waves per SIMD with dynamically scheduled workgroups, is
+// faster than the single launch despite a host round trip per round
+// (indoor 20,000-sample query: 16.4 against 19.9 ms; 4,000-sample query:
+// 1.86 against 0.76 ms).
+constexpr long long kPerPhaseEdges = 4ll << 20;
+
+static int effective_mode(const pump_ctx* ctx) {
+    if (ctx->explore_mode != 2) return ctx->explore_mode;
+    return (long long)ctx->n_edges >= kPerPhaseEdges ? 0 : 1;
+}
+
 int pump_explore_run(pump_ctx* ctx) {
     if (!ctx) return PUMP_E_ARG;
     if (!ctx->have_explore) return fail(ctx, PUMP_E_STATE, "pump_explore_begin first");
     HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
-    if (ctx->explore_mode == 1 && !ctx->explore_done) {
+    if (effective_mode(ctx) == 1 && !ctx->explore_done) {
         int r = explore_single_launch(ctx);
         if (r == PUMP_E_STATE && ctx->ctl_h->err == 5) {
             // a barrier wait ran out of patience (workgroups not resident
@@ -816,8 +842,8 @@ int pump_explore_run(pump_ctx* ctx) {
 }
 
 int pump_set_explore_mode(pump_ctx* ctx, int32_t mode) {
-    if (!ctx || (mode != 0 && mode != 1)) return PUMP_E_ARG;
-    if (mode == 1 && ctx->coop_blocks <= 0)
+    if (!ctx || mode < 0 || mode > 2) return PUMP_E_ARG;
+    if (mode != 0 && ctx->coop_blocks <= 0)
         return fail(ctx, PUMP_E_ARG, "the single-launch Explore does not fit on this device");
     ctx->explore_mode = mode;
     return PUMP_OK;
@@ -958,7 +984,7 @@ int pump_plan(pump_ctx* ctx, const pump_problem* pr, pump_result* out) {
     int r = pump_setup(ctx, pr);
     // with the single-launch Explore the host enqueues Explore and the
     // selection back to back and waits once, at the end
-    const bool one_wait = ctx->explore_mode == 1;
+    const bool one_wait = r == PUMP_OK && effective_mode(ctx) == 1;
     if (r == PUMP_OK) r = explore_begin(ctx, !one_wait);
     pump_result res;
     memset(&res, 0, sizeof(res));

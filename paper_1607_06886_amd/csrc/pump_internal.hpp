@@ -244,7 +244,8 @@ void scan_exclusive(hipStream_t s, const int32_t* in, int32_t* out, const int32_
 // launch's barrier words).
 void launch_explore_init(hipStream_t s, const RoundArgs& a, int n_nodes, int N, unsigned* zero,
                          int n_zero);
-void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs);
+// part: 1 the pair stage, 2 the particle stage, 3 both
+void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, int part = 3);
 void launch_prune(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, int32_t n_open);
 void launch_compact(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs,
                     int32_t n_open, int32_t* blk_scratch);

@@ -219,6 +219,48 @@ int pump_mlp_get_params(pump_mlp* m, float* params, int64_t n) {
     return PUMP_OK;
 }
 
+int pump_mlp_get_state(pump_mlp* m, float* params, float* m1, float* m2, int64_t n, int32_t* t) {
+    if (!m || !params || !m1 || !m2 || !t) return PUMP_E_ARG;
+    if (n != m->n_params) return mfail(m, PUMP_E_ARG, "parameter count mismatch");
+    MCHK(hipMemcpyAsync(params, m->params, (size_t)n * 4, hipMemcpyDeviceToHost, m->stream));
+    MCHK(hipMemcpyAsync(m1, m->m1, (size_t)n * 4, hipMemcpyDeviceToHost, m->stream));
+    MCHK(hipMemcpyAsync(m2, m->m2, (size_t)n * 4, hipMemcpyDeviceToHost, m->stream));
+    MCHK(hipStreamSynchronize(m->stream));
+    *t = m->t;
+    return PUMP_OK;
+}
+
+int pump_mlp_set_state(pump_mlp* m, const float* params, const float* m1, const float* m2,
+                       int64_t n, int32_t t) {
+    if (!m || !params || !m1 || !m2) return PUMP_E_ARG;
+    if (n != m->n_params) return mfail(m, PUMP_E_ARG, "parameter count mismatch");
+    if (t < 0) return mfail(m, PUMP_E_ARG, "negative step count");
+    MCHK(hipMemcpyAsync(m->params, params, (size_t)n * 4, hipMemcpyHostToDevice, m->stream));
+    MCHK(hipMemcpyAsync(m->m1, m1, (size_t)n * 4, hipMemcpyHostToDevice, m->stream));
+    MCHK(hipMemcpyAsync(m->m2, m2, (size_t)n * 4, hipMemcpyHostToDevice, m->stream));
+    refresh_all(m);
+    m->t = t;
+    MCHK(hipStreamSynchronize(m->stream));
+    return PUMP_OK;
+}
+
+int pump_mlp_adam_step(pump_mlp* m, const float* grads, int64_t n, float lr, int32_t mem) {
+    if (!m || !grads) return PUMP_E_ARG;
+    if (n != m->n_params) return mfail(m, PUMP_E_ARG, "parameter count mismatch");
+    if (!(lr > 0.0f)) return mfail(m, PUMP_E_ARG, "learning rate must be positive");
+    if (mem == PUMP_MEM_DEVICE) {
+        MCHK(hipMemcpyAsync(m->grads, grads, (size_t)n * 4, hipMemcpyDeviceToDevice, m->stream));
+    } else {
+        MCHK(hipMemcpyAsync(m->grads, grads, (size_t)n * 4, hipMemcpyHostToDevice, m->stream));
+    }
+    m->t += 1;
+    launch_adam(m->stream, m->params, m->m1, m->m2, m->grads, m->n_params, lr, m->t);
+    refresh_all(m);
+    MCHK(hipStreamSynchronize(m->stream));
+    MCHK(hipGetLastError());
+    return PUMP_OK;
+}
+
 int pump_mlp_forward(pump_mlp* m, const float* cond, int32_t B, float* out, int32_t mem) {
     if (!m || !cond || !out) return PUMP_E_ARG;
     if (B < 1 || B > m->max_batch) return mfail(m, PUMP_E_ARG, "batch out of range");

@@ -105,6 +105,57 @@ def generate(n_queries, kinds, n_samples, N, alpha, sigma, seed0, log=None):
     return maps, plans
 
 
+def _map_and_samples(args):
+    """One training map and its uniform samples (worker of generate_batched)."""
+    kind, seed, n = args
+    x0, g, b = scenes.random_map(kind, seed)
+    return x0, g, b, scenes.uniform_samples(seed, n, b, g)
+
+
+def map_pool(procs=0):
+    """Worker processes that draw maps and samples.  Create it before the
+    process first touches the GPU: the workers are forked copies."""
+    import multiprocessing as mp
+    return mp.get_context("fork").Pool(procs or min(16, os.cpu_count() or 1))
+
+
+def generate_batched(pool, n_queries, kinds, n_samples, N, alpha, sigma, seed0, want_plans=None,
+                     batch=256, log=None):
+    """generate() through the batched engine: maps are drawn by `pool`
+    (map_pool) and planned `batch` at a time in one graph launch each (shared
+    particle noise, as Runner does).  Stops early once `want_plans` certified
+    plans are in hand.  Returns (maps, plans) like generate()."""
+    torch = _torch()
+    S_max, M = 256, 2000
+    noise, noise_mc = device_noise(S_max, N, M, seed0)
+    b = _lib.Batch(batch, n_particles=N, max_nodes=n_samples + 1, max_obstacles=MAX_BOXES,
+                   max_steps=S_max, mc_particles=M, cap_plans=1 << 20, cap_pairs=1 << 21,
+                   cap_edges=1 << 22)
+    maps, plans = [], []
+    t0 = time.time()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    for q0 in range(0, n_queries, batch):
+        jobs = [(kinds[q % len(kinds)], seed0 + q, n_samples)
+                for q in range(q0, min(n_queries, q0 + batch))]
+        drawn = pool.map(_map_and_samples, jobs, chunksize=8)
+        queries = [(dev(smp), dev(bx), x0, g, alpha, sigma, noise, noise_mc)
+                   for x0, g, bx, smp in drawn]
+        res = b.plan(queries, raise_on_error=False)
+        for i, (r, (x0, g, bx, smp)) in enumerate(zip(res, drawn)):
+            maps.append((x0, g, bx))
+            if r["status"] == 0:
+                path = b.path(i, r["best_plan"])
+                if len(path) > 1:
+                    plans.append((q0 + i, smp[np.asarray(path[1:]) - 1]))
+        if log:
+            log(f"generated {len(maps)}/{n_queries} queries, {len(plans)} certified plans, "
+                f"{time.time() - t0:.0f} s")
+        if want_plans and len(plans) >= want_plans:
+            break
+    b.close()
+    return maps, plans
+
+
 def train(mlp, maps, plans, steps, batch, lr, seed, log=None):
     """Adam on the mean mixture NLL of certified-plan node states given their
     map's condition vector."""
@@ -144,9 +195,10 @@ def learned_samples(mlp, x0, g, b, n, seed):
     return out, 1e3 * (time.perf_counter() - t0)
 
 
-def evaluate(mlp, n_maps, kinds, sizes, N, alpha, sigma, seed0, log=None):
-    """Plain (n uniform) vs learned (n/2 mixture + n/2 uniform) on held-out maps."""
-    run = Runner(max(sizes), N, seed=seed0 + 99, cap_pairs=1 << 24)
+def evaluate(mlp, n_maps, kinds, sizes, N, alpha, sigma, seed0, log=None, M=10_000, S_max=512):
+    """Plain (n uniform) vs learned (n/2 mixture + n/2 uniform) on held-out maps,
+    certified with M particles over S_max steps."""
+    run = Runner(max(sizes), N, S_max=S_max, M=M, seed=seed0 + 99, cap_pairs=1 << 24)
     rows = []
     for q in range(n_maps):
         kind = kinds[q % len(kinds)]
@@ -219,36 +271,48 @@ def summarise(rows, sizes):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--queries", type=int, default=6000)
-    ap.add_argument("--n-train", type=int, default=4000)
-    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--queries", type=int, default=72000)
+    ap.add_argument("--want-plans", type=int, default=50000)
+    ap.add_argument("--n-train", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--eval-maps", type=int, default=40)
+    ap.add_argument("--eval-maps", type=int, default=100)
     ap.add_argument("--sizes", type=str, default="1000,2000,4000,8000")
     ap.add_argument("--out", type=str, default="learned.json")
-    ap.add_argument("--weights", type=str, default="")
+    ap.add_argument("--state", type=str, default="", help="save the training state (.npz)")
+    ap.add_argument("--params", type=str, default="",
+                    help="save the trained FP32 parameters (.npy) for inference")
     args = ap.parse_args()
+    pool = map_pool()                 # before the GPU is touched: forked workers
     torch = _torch()
     torch.cuda.set_device(0)
     log = lambda m: print(m, flush=True)
     kinds = ["boxes", "indoor"]
     t0 = time.time()
-    maps, plans = generate(args.queries, kinds, args.n_train, 128, 0.01, 0.02, 10_000, log)
-    log(f"data: {len(plans)} certified plans of {args.queries} queries in {time.time() - t0:.0f} s")
+    maps, plans = generate_batched(pool, args.queries, kinds, args.n_train, 128, 0.01, 0.02,
+                                   10_000, want_plans=args.want_plans, log=log)
+    pool.close()
+    t_gen = time.time() - t0
+    log(f"data: {len(plans)} certified plans of {len(maps)} queries in {t_gen:.0f} s")
     mlp = _lib.MLP(max(args.batch, 64))
     mlp.set_params(init_params(7))
     t1 = time.time()
     losses = train(mlp, maps, plans, args.steps, args.batch, args.lr, 8, log)
-    log(f"trained {args.steps} steps in {time.time() - t1:.1f} s: "
+    t_train = time.time() - t1
+    log(f"trained {args.steps} steps in {t_train:.1f} s: "
         f"loss {np.mean(losses[:50]):.3f} -> {np.mean(losses[-50:]):.3f}")
-    if args.weights:
-        mlp.get_params().tofile(args.weights)
+    if args.state:
+        mlp.save(args.state)
+    if args.params:
+        os.makedirs(os.path.dirname(args.params) or ".", exist_ok=True)
+        np.save(args.params, mlp.get_params())
     sizes = [int(x) for x in args.sizes.split(",")]
     rows = evaluate(mlp, args.eval_maps, kinds, sizes, 256, 0.01, 0.02, 900_000, log)
-    summary = dict(queries=args.queries, certified_plans=len(plans),
-                   targets=int(sum(len(st) for _, st in plans)), steps=args.steps,
-                   batch=args.batch, lr=args.lr, loss_first=float(np.mean(losses[:50])),
+    summary = dict(queries=len(maps), certified_plans=len(plans),
+                   targets=int(sum(len(st) for _, st in plans)), generate_s=t_gen,
+                   steps=args.steps, batch=args.batch, lr=args.lr, train_s=t_train,
+                   loss_first=float(np.mean(losses[:50])),
                    loss_last=float(np.mean(losses[-50:])), eval=summarise(rows, sizes))
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
     with open(args.out, "w") as f:

@@ -168,3 +168,75 @@ def test_training_reduces_the_loss():
         last = loss
     assert np.isfinite(last) and last < first - 5.0, (first, last)
     m.close()
+
+
+def test_adam_matches_oracle_elementwise():
+    """Two Adam steps on given gradient vectors (the same FP32 values on both
+    sides): parameters and both moment estimates equal the FP64 oracle's
+    element by element, to FP32 rounding."""
+    print_case("mlp_adam_elementwise")
+    rng = np.random.default_rng(57)
+    params = pp.init_params(33)
+    m = _lib.MLP(8)
+    m.set_params(flat(params))
+    n = m.n_params
+    grads = [rng.standard_normal(n).astype(np.float32) * np.float32(s) for s in (1e-2, 3e-3)]
+    lr = 1e-3
+    ref_p = [(W.astype(np.float64), b.astype(np.float64)) for W, b in params]
+    state = pp.adam_state(params)
+    for t, g in enumerate(grads, start=1):
+        m.adam_step(g, lr)
+        ref_p, state = pp.adam(ref_p, unflat(g), state, lr, t)
+        ref_p = [(W.astype(np.float64), b.astype(np.float64)) for W, b in ref_p]
+    st = m.get_state()
+    assert st["t"] == 2
+    want_p = flat(ref_p).astype(np.float64)
+    want_m1 = np.concatenate([np.concatenate([a[0].ravel(), b[0].ravel()]) for a, b in state])
+    want_m2 = np.concatenate([np.concatenate([a[1].ravel(), b[1].ravel()]) for a, b in state])
+    p0 = flat(params).astype(np.float64)
+    step = np.abs(want_p - p0)
+    ulp = np.spacing(np.abs(want_p).astype(np.float32)).astype(np.float64)
+    err = np.abs(st["params"].astype(np.float64) - want_p)
+    assert (err <= 2 * ulp + 1e-5 * step).all(), float((err / (2 * ulp + 1e-5 * step)).max())
+    # m1 = 0.9 m1' + 0.1 g can cancel: its FP32 error is relative to the two
+    # terms' magnitudes, not to the result
+    g1, g2 = grads[0].astype(np.float64), grads[1].astype(np.float64)
+    scale1 = 0.9 * np.abs(0.1 * g1) + 0.1 * np.abs(g2)
+    assert (np.abs(st["m1"] - want_m1) <= 2e-6 * scale1 + 1e-30).all()
+    np.testing.assert_allclose(st["m2"], want_m2, rtol=2e-6, atol=1e-16)
+    m.close()
+
+
+def test_checkpoint_resume_continues_training(tmp_path):
+    """Training state saved after some steps and loaded into a fresh network
+    continues as the uninterrupted run: the same parameters, moments and step
+    count after the same further steps."""
+    print_case("mlp_checkpoint")
+    X, Z = _inputs(61, 128)
+    a = _lib.MLP(128)
+    a.set_params(flat(pp.init_params(35)))
+    for _ in range(4):
+        a.train_step(X[:64], Z[:64], 1e-3)
+    path = str(tmp_path / "mlp_state.npz")
+    a.save(path)
+    b = _lib.MLP(128)
+    b.set_params(flat(pp.init_params(99)))      # overwritten by load
+    b.load(path)
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("params", "m1", "m2"):
+        np.testing.assert_array_equal(sa[k], sb[k])
+    assert sa["t"] == sb["t"] == 4 and np.abs(sa["m2"]).max() > 0
+    for _ in range(3):
+        la = a.train_step(X[64:], Z[64:], 1e-3)
+        lb = b.train_step(X[64:], Z[64:], 1e-3)
+        assert abs(la - lb) <= 1e-5 * max(1.0, abs(la))
+    sa, sb = a.get_state(), b.get_state()
+    assert sa["t"] == sb["t"] == 7
+    for k in ("params", "m1", "m2"):
+        np.testing.assert_allclose(sa[k], sb[k], rtol=1e-5, atol=1e-8)
+    # set_params starts over: moments and step count back to zero
+    b.set_params(sa["params"])
+    sb = b.get_state()
+    assert sb["t"] == 0 and not sb["m1"].any() and not sb["m2"].any()
+    a.close()
+    b.close()

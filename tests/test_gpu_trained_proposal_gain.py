@@ -30,7 +30,8 @@ def test_learned_proposal_gain():
     mlp.set_params(learned.init_params(7))
     losses = learned.train(mlp, maps, plans, 3000, 2048, 1e-3, 8, log)
     assert np.mean(losses[-50:]) < np.mean(losses[:50]) - 3.0
-    rows = learned.evaluate(mlp, 30, kinds, [1000, 2000], 256, ALPHA, 0.02, 900_000, log)
+    rows = learned.evaluate(mlp, 30, kinds, [1000, 2000], 256, ALPHA, 0.02, 900_000, log,
+                            M=2000, S_max=256)
     summ = learned.summarise(rows, [1000, 2000])
     log(str(summ["per_n"]))
     mlp.close()

@@ -441,3 +441,42 @@ def test_remove_dominated_matches_a_sorted_sweep():
                 j += len(grp)
         assert removed == want, (trial, spec)
         assert kept == set(range(k)) - want
+
+
+def test_rows_on_demand_and_split_rounds_equal_the_whole_graph():
+    """Explore over rows built on demand, and with each round's pairs split
+    over worker processes, gives the plans, P and counters of Explore over
+    the graph built whole (timing aids of the CPU baseline)."""
+    import multiprocessing as mp
+
+    from oracle import graph as gr, pump as opump
+    from paper_1607_06886_amd import scenes
+    sc = scenes.make_scene(dict(n=120, n_obs=3, side=(0.1, 0.3), N=32, sigma=0.02, alpha=0.05,
+                                indoor=False), 77, M=64, S_max=128)
+    cfg = opump.Config()
+    V = np.concatenate([sc.x_init[None], sc.samples]).astype(np.float64)
+    A_cl, L, _ = dynamics.closed_loop(cfg.dt, sc.sigma, cfg.q_pos, cfg.q_vel, cfg.r_track)
+    D = dynamics.deviation_table(A_cl, L, sc.noise, sc.S_max)
+    g = gr.build_graph(V, sc.obstacles, cfg.r_conn, cfg.r_steer)
+    lazy = gr.RowsOnDemand(V, sc.obstacles, cfg.r_conn, cfg.r_steer)
+    gl = sc.goal.astype(np.float64)
+    goal = np.nonzero(np.all((V[:, :3] >= gl[:3]) & (V[:, :3] <= gl[3:]), axis=1) & g["valid"])[0]
+    amin, amax = opump.thresholds(float(sc.alpha), opump.eta_rule(float(sc.alpha)))
+    args = (D, sc.obstacles, goal, amin, amax, cfg.lam, cfg.r_conn, cfg.dt, sc.S_max)
+    ref = ex.explore(V, g, *args)
+    got = ex.explore(V, lazy, *args)
+    with mp.get_context("fork").Pool(2, initializer=ex.pool_init,
+                                     initargs=(V, D, sc.obstacles, cfg.dt, sc.S_max)) as pool:
+        par = ex.explore(V, g, *args, pool=pool, pieces=3)
+    assert ref[2]["partial_plans"] > 100
+    for other in (got, par):
+        assert [p.nodes for p in other[0]] == [p.nodes for p in ref[0]]
+        assert [p.cost for p in other[0]] == [p.cost for p in ref[0]]
+        assert all((a.mask == b.mask).all() for a, b in zip(other[0], ref[0]))
+        assert other[1] == ref[1]
+        for k in ("partial_plans", "inserted", "rounds", "final_i", "flagged_particles"):
+            assert other[2][k] == ref[2][k], k
+    # the rows built on demand are the whole graph's rows
+    for v in {p.head for p in ref[0]}:
+        a, b = lazy.rows(v)
+        np.testing.assert_array_equal(lazy["col"][a:b], g["col"][g["row_ptr"][v]:g["row_ptr"][v + 1]])
