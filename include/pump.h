@@ -394,6 +394,18 @@ int pump_mlp_condition(pump_mlp* m, const float* x_init, const float* goal, cons
  * state box (positions [0, 1], velocities [-0.5, 0.5]); out [q][n][6]. */
 int pump_mlp_sample(pump_mlp* m, const float* cond, int32_t q, const float* u, const float* eps,
                     int32_t n, float* out, int32_t mem);
+/* pump_mlp_sample for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same draws, bit for bit, with no allocation or free on the call.  With
+ * host memory (mem != PUMP_MEM_DEVICE) u, eps and out are staged through a
+ * static per-GPU array of 2^21 floats that the library holds until the
+ * process ends, so q * n * 13 must not exceed 2^21 (q * n <= 161319 draws);
+ * larger requests return PUMP_E_CAPACITY with the limit in the message.
+ * Every call on one GPU shares that array: calls that overlap on one GPU (from
+ * several threads or streams) race and must be serialised by the caller.
+ * Device memory needs no staging and has no limit beyond pump_mlp_sample's. */
+int pump_mlp_sample_noalloc(pump_mlp* m, const float* cond, int32_t q, const float* u,
+                            const float* eps, int32_t n, float* out, int32_t mem);
 const char* pump_mlp_last_error(const pump_mlp* m);
 
 /* -------------------------------------------------------------------------

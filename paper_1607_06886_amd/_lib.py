@@ -98,6 +98,7 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
            "pump_mlp_get_params", "pump_mlp_get_state", "pump_mlp_set_state",
            "pump_mlp_adam_step", "pump_mlp_forward", "pump_mlp_loss_grad",
            "pump_mlp_train_step", "pump_mlp_condition", "pump_mlp_sample",
+           "pump_mlp_sample_noalloc",
            "pump_mlp_last_error", "pump_batch_create", "pump_batch_destroy",
            "pump_batch_plan", "pump_batch_get_path", "pump_batch_tune",
            "pump_batch_last_error"]
@@ -170,6 +171,7 @@ def load(path: Optional[str] = None):
         "pump_mlp_train_step": (_i32, [_p, _p, _p, _i32, _f, P(_f), _i32]),
         "pump_mlp_condition": (_i32, [_p, _p, _p, _p, _p, _i32, _i32, _p]),
         "pump_mlp_sample": (_i32, [_p, _p, _i32, _p, _p, _i32, _p, _i32]),
+        "pump_mlp_sample_noalloc": (_i32, [_p, _p, _i32, _p, _p, _i32, _p, _i32]),
         "pump_mlp_last_error": (ctypes.c_char_p, [_p]),
         "pump_batch_create": (_i32, [P(Config), _i32, _p, P(_p)]),
         "pump_batch_destroy": (_i32, [_p]),
@@ -601,6 +603,20 @@ class MLP:
             out = torch.empty((q, n, 6), dtype=torch.float32, device=cond.device)
         self._check(self.lib.pump_mlp_sample(self.m, _ptr(cond), q, _ptr(u), _ptr(eps), n,
                                              _ptr(out), self._mem(cond)))
+        return out
+
+    def sample_noalloc(self, cond, u, eps):
+        """sample() through pump_mlp_sample_noalloc (no allocation per call;
+        host arrays are staged through the library's static per-GPU array)."""
+        q, n = int(u.shape[0]), int(u.shape[1])
+        if isinstance(cond, np.ndarray):
+            cond, u, eps = _np(cond, np.float32), _np(u, np.float32), _np(eps, np.float32)
+            out = np.zeros((q, n, 6), np.float32)
+        else:
+            import torch
+            out = torch.empty((q, n, 6), dtype=torch.float32, device=cond.device)
+        self._check(self.lib.pump_mlp_sample_noalloc(self.m, _ptr(cond), q, _ptr(u), _ptr(eps),
+                                                     n, _ptr(out), self._mem(cond)))
         return out
 
 

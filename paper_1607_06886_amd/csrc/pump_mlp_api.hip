@@ -2,6 +2,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,8 +18,19 @@ const int kOutReal[kLayers] = {kHidden, kHidden, kHidden, kHidden, kOut};
 const int kOutP[kLayers] = {kHidden, kHidden, kHidden, kHidden, kOutPad};
 }  // namespace
 
+// Staging for pump_mlp_sample_noalloc (draws in host memory): the uniforms,
+// the normals and the drawn states pass through this array instead of
+// buffers allocated per call.  One copy per GPU, held until the process
+// ends: kNoallocFloats floats (8 MiB).  Host code never names the array
+// itself: its device address comes from hipGetSymbolAddress, once per device
+// (noalloc_staging below), since the host-side symbol is only a stand-in.
+constexpr size_t kNoallocFloats = (size_t)2 << 20;
+static __device__ __align__(256) float scratch[kNoallocFloats];
+
 struct pump_mlp {
     hipStream_t stream = nullptr;
+    int device = 0;                 // the device current at create
+    float* staging = nullptr;       // that device's address of `scratch`
     bool own_stream = false;
     int max_batch = 0, maxBp = 0;
     int n_params = 0;
@@ -110,6 +122,26 @@ void backward(pump_mlp* m, const float* Z, int B, int Bp) {
     }
 }
 
+// Device address of `scratch` on the current device, looked up on the first
+// call per device and kept for the life of the process.
+constexpr int kMaxDevices = 64;
+std::mutex g_staging_mu;
+float* g_staging[kMaxDevices] = {};
+
+hipError_t noalloc_staging(int dev, float** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_staging_mu);
+    if (!g_staging[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_staging[dev] = static_cast<float*>(p);
+    }
+    *out = g_staging[dev];
+    return hipSuccess;
+}
+
 const float* stage(pump_mlp* m, const float* src, float* buf, size_t n, int mem, hipError_t* e) {
     *e = hipSuccess;
     if (mem == PUMP_MEM_DEVICE) return src;
@@ -134,6 +166,14 @@ int pump_mlp_create(int32_t max_batch, void* hip_stream, pump_mlp** out) {
     }
     m->max_batch = max_batch;
     m->maxBp = round32(max_batch);
+    // this device's staging address for pump_mlp_sample_noalloc (the
+    // device current now is the one whose memory the context uses)
+    if (hipGetDevice(&m->device) != hipSuccess ||
+        noalloc_staging(m->device, &m->staging) != hipSuccess) {
+        if (m->own_stream) (void)hipStreamDestroy(m->stream);
+        delete m;
+        return PUMP_E_HIP;
+    }
     int off = 0;
     for (int l = 0; l < kLayers; ++l) {
         m->off_W[l] = off;
@@ -365,6 +405,44 @@ int pump_mlp_sample(pump_mlp* m, const float* cond, int32_t q, const float* u, c
     if (du) (void)hipFree(du);
     if (de) (void)hipFree(de);
     if (dout) (void)hipFree(dout);
+    MCHK(hipGetLastError());
+    return PUMP_OK;
+}
+
+int pump_mlp_sample_noalloc(pump_mlp* m, const float* cond, int32_t q, const float* u,
+                            const float* eps, int32_t n, float* out, int32_t mem) {
+    if (!m || !cond || !u || !eps || !out) return PUMP_E_ARG;
+    if (q < 1 || q > m->max_batch || n < 1) return mfail(m, PUMP_E_ARG, "bad sizes");
+    const size_t total = (size_t)q * (size_t)n;
+    if (mem != PUMP_MEM_DEVICE && total * (1 + 2 * kDState) > kNoallocFloats)
+        return mfail(m, PUMP_E_CAPACITY,
+                     "q * n = " + std::to_string(total) + " draws exceed the no-alloc staging (" +
+                         std::to_string(kNoallocFloats / (1 + 2 * kDState)) + " draws)");
+    if (!m->staging) return mfail(m, PUMP_E_STATE, "no staging address for this device");
+    hipError_t e;
+    const float* X = stage(m, cond, m->xbuf, (size_t)q * kIn, mem, &e);
+    MCHK(e);
+    forward(m, X, q, round32(q));
+    const float* U = u;
+    const float* EPS = eps;
+    float* O = out;
+    if (mem != PUMP_MEM_DEVICE) {
+        // the uniforms, the normals and the draws in the staging array:
+        // every word the kernel reads is copied in first, every word it
+        // writes is copied out, so nothing needs clearing
+        float* su = m->staging;
+        float* se = su + total;
+        float* so = se + total * kDState;
+        MCHK(hipMemcpyAsync(su, u, total * 4, hipMemcpyHostToDevice, m->stream));
+        MCHK(hipMemcpyAsync(se, eps, total * kDState * 4, hipMemcpyHostToDevice, m->stream));
+        U = su;
+        EPS = se;
+        O = so;
+    }
+    launch_sample(m->stream, m->Y, kOutPad, q, n, U, EPS, O);
+    if (mem != PUMP_MEM_DEVICE)
+        MCHK(hipMemcpyAsync(out, O, total * kDState * 4, hipMemcpyDeviceToHost, m->stream));
+    MCHK(hipStreamSynchronize(m->stream));
     MCHK(hipGetLastError());
     return PUMP_OK;
 }
