@@ -401,24 +401,22 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
         }
     }
     uint32_t hm = 0u, dm = 0u, nm = 0u;           // per particle r: hit, deep, near a face
-    for (;;) {
-        const unsigned rest = wm & (wm - 1u);
-        const int kn = rest ? __ffs((int)rest) : 0;
-        if (kn) load_deviations<N>(a.D, spj + kn, lane, dn);   // next waypoint, in flight
+    // one marked waypoint k with its deviations d (the next one's are in flight)
+    auto test_waypoint = [&](const float (&d)[PPL][3], int kk) {
         double nom64[3];
         float nom32[3], lo3[3], hi3[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            nom64[ax] = readlane_f64(my_nom[ax], k - 1);
-            nom32[ax] = readlane_f32(my_n32[ax], k - 1);
-            lo3[ax] = readlane_f32(my_lo[ax], k - 1);
-            hi3[ax] = readlane_f32(my_hi[ax], k - 1);
+            nom64[ax] = readlane_f64(my_nom[ax], kk - 1);
+            nom32[ax] = readlane_f32(my_n32[ax], kk - 1);
+            lo3[ax] = readlane_f32(my_lo[ax], kk - 1);
+            hi3[ax] = readlane_f32(my_hi[ax], kk - 1);
         }
         float y[PPL][3];
 #pragma unroll
         for (int r = 0; r < PPL; ++r)
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) y[r][ax] = nom32[ax] + dc[r][ax];
+            for (int ax = 0; ax < 3; ++ax) y[r][ax] = nom32[ax] + d[r][ax];
         for (int c0 = 0; c0 < n_obs; c0 += 64) {
             const int o = c0 + lane;
             const bool ov = o < n_obs && boxes_overlap(lo3, hi3, s_out + o * 6);
@@ -428,18 +426,32 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
                 const int ob = c0 + __ffsll((long long)om) - 1;
                 om &= om - 1ull;
                 const float* br = s_raw + ob * 6;
+                // inside by more than the guard band: a hit, deep; within
+                // the band: decided below in FP64 (rare, so the wave
+                // branches once per box rather than once per particle)
+                uint32_t in_bits = 0u, band = 0u;
 #pragma unroll
                 for (int r = 0; r < PPL; ++r) {
                     const float dep = box_depth32(y[r][0], y[r][1], y[r][2], br);
-                    if (dep >= kGuard) {
-                        hm |= 1u << r;
-                        dm |= 1u << r;
-                    } else if (dep >= -kGuard && valid_lane) {
-                        // within the guard band of a face: decide in FP64
+                    in_bits |= (dep >= kGuard ? 1u : 0u) << r;
+                    band |= (dep >= -kGuard && dep < kGuard ? 1u : 0u) << r;
+                }
+                hm |= in_bits;
+                dm |= in_bits;
+                if (!valid_lane) band = 0u;
+                if (band) {
+#pragma unroll
+                    for (int r = 0; r < PPL; ++r) {
+                        if (!(band & (1u << r))) continue;
                         double dmin = INFINITY;
 #pragma unroll
                         for (int ax = 0; ax < 3; ++ax) {
-                            const double yy = nom64[ax] + (double)dc[r][ax];
+                            // (kept inside the branch: without the empty
+                            // asm the compiler hoists these FP64 sums out of
+                            // the box loop for every waypoint)
+                            float dv = d[r][ax];
+                            asm volatile("" : "+v"(dv));
+                            const double yy = nom64[ax] + (double)dv;
                             dmin = fmin(dmin, fmin(yy - (double)br[ax], (double)br[3 + ax] - yy));
                         }
                         if (dmin >= 0.0) hm |= 1u << r;
@@ -449,13 +461,26 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
                 }
             }
         }
+    };
+    // the waypoint loop unrolled by two so the in-flight buffer alternates
+    // between dc and dn without copies
+    // (the next load is issued unconditionally -- the last waypoint reloads
+    // its own row -- so no branch has to wait for it before merging)
+    for (;;) {
+        unsigned rest = wm & (wm - 1u);
+        int kn = rest ? __ffs((int)rest) : 0;
+        load_deviations<N>(a.D, spj + (kn ? kn : k), lane, dn);
+        test_waypoint(dc, k);
         if (!kn) break;
         k = kn;
         wm = rest;
-#pragma unroll
-        for (int r = 0; r < PPL; ++r)
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) dc[r][ax] = dn[r][ax];
+        rest = wm & (wm - 1u);
+        kn = rest ? __ffs((int)rest) : 0;
+        load_deviations<N>(a.D, spj + (kn ? kn : k), lane, dc);
+        test_waypoint(dn, k);
+        if (!kn) break;
+        k = kn;
+        wm = rest;
     }
     // this lane's PPL bits go to bit (lane * PPL) % 32 of word lane / LPW;
     // OR them together across the LPW lanes of each word

@@ -306,6 +306,7 @@ __global__ __launch_bounds__(256) void k_open_min(RoundArgs a) {
     // open list holds only the kept plans while n_open still counts the
     // previous round's, so there is nothing to read
     if (a.ctl->err || a.ctl->done) return;
+    __shared__ unsigned long long s_m[4];
     const int n_open = a.ctl->n_open;
     unsigned long long m = 0x7FF0000000000000ull;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_open; i += gridDim.x * blockDim.x) {
@@ -316,7 +317,14 @@ __global__ __launch_bounds__(256) void k_open_min(RoundArgs a) {
         unsigned long long y = __shfl_down(m, o, 64);
         m = y < m ? y : m;
     }
-    if ((threadIdx.x & 63) == 0) atomicMin(&a.ctl->min_cost_bits, m);
+    // one atomic per workgroup (one per wave on a single word was the
+    // kernel's cost: 0.23 ms a round on the indoor query)
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = s_m[w] < m ? s_m[w] : m;
+        if (m != 0x7FF0000000000000ull) atomicMin(&a.ctl->min_cost_bits, m);
+    }
 }
 
 __global__ void k_pick_i(RoundArgs a) { pick_next_i(a.ctl, a.h); }
@@ -363,7 +371,9 @@ void launch_next_group(hipStream_t s, const RoundArgs& a, int32_t n_open_upper, 
     int b = (n_open_upper + 255) / 256;
     if (b < 1) b = 1;
     if (b > 16384) b = 16384;
-    k_open_min<<<b, 256, 0, s>>>(a);
+    // (the bound counts this round's pairs too; the open list is much
+    // shorter, so the minimum strides over it with at most 512 workgroups)
+    k_open_min<<<b < 512 ? b : 512, 256, 0, s>>>(a);
     k_pick_i<<<1, 1, 0, s>>>(a);
     k_flag_group<<<b, 256, 0, s>>>(a);
     scan_exclusive(s, a.o_keep, a.o_keep, &a.ctl->n_open, n_open_upper, &a.ctl->scan_total[2],
