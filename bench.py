@@ -47,8 +47,8 @@ def parse():
                     help="queries in the batched-engine leg (0 skips the leg)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--tune-queries", type=int, default=256)
-    ap.add_argument("--legs", default="cfg2,roadmap,batch,learned",
-                    help="comma list of the extra legs to run (cfg2, roadmap, batch, learned)")
+    ap.add_argument("--legs", default="cfg2,roadmap,batch,learned,hsmc",
+                    help="comma list of the extra legs to run (cfg2, roadmap, batch, learned, hsmc)")
     ap.add_argument("--learned-maps", type=int, default=20)
     return ap.parse_args()
 
@@ -342,6 +342,28 @@ def smooth_leg(sc, stream, samples, obstacles, noise, noise_mc):
             "ms": kt["smooth"][0], "ms_to_certified_smoothed_plan": r["ms_total"]}
 
 
+def hsmc_leg(stream, seed, warmup, steps):
+    """The paper's own exploration model (Half-Space Monte Carlo, Sec. III-B,
+    eq. (7); run there with N = 128) on the 4000-sample, 20-box, N = 128
+    query: time to the certified plan and partial plans per second."""
+    import torch
+    sc = boxes_inputs(seed)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    pl = planner_for(sc, stream, cap_pairs=1 << 23, cap_edges=1 << 24, cp_model=1)
+    pr = pl.problem(dev(sc.samples), dev(sc.obstacles), sc.x_init, sc.goal, sc.alpha, sc.sigma,
+                    dev(sc.noise), dev(sc.noise_mc))
+    results, total, _ = timed_queries(pl, pr, warmup, steps)
+    pl.close()
+    r0 = results[0]
+    return {"workload": "HSMC exploration model, 20 random boxes, 4000 samples, 128 particles, "
+                        "sigma 0.02, alpha 0.01, M 10000",
+            "status": STATUS[r0["status"]],
+            "ms_to_certified_plan": statistics.median(r["ms_total"] for r in results),
+            "partial_plans_per_s": r0["partial_plans"] * steps / total,
+            "partial_plans_per_query": r0["partial_plans"], "best_cost": r0["best_cost"],
+            "best_cp_mc": r0["best_cp_mc"]}
+
+
 # Trained weights of the learned proposal (FP32, the library's flat layout),
 # written by `python -m paper_1607_06886_amd.learned --params <file>`.
 WEIGHTS = os.path.join(ROOT, "paper_1607_06886_amd", "weights", "proposal_params.npy")
@@ -562,6 +584,8 @@ def main():
     if "batch" in legs and args.batch_queries > 0:
         line["batched"] = batched_leg(args.batch_queries, args.seed, args.batch_steps,
                                       min(args.tune_queries, args.batch_queries))
+    if "hsmc" in legs:
+        line["hsmc_4000"] = hsmc_leg(stream, args.seed, args.warmup, min(args.steps, 10))
     if "learned" in legs:
         line["learned"] = learned_leg(args.learned_maps)
     if cpu is not None:

@@ -155,6 +155,37 @@ __device__ __forceinline__ bool surely_not_near(const BSums& s, double r, double
     return true;
 }
 
+// A cheap first look, in FP32, at the level-0 Bernstein bound that
+// surely_not_near starts with: true only where the FP64 test is true too.
+// Every FP32 coefficient is within about 20 units of 2^-24 of the magnitudes
+// that enter it (tv bounds those of S_Pv, whose terms can cancel), which is
+// far below the margin of 1e-4 times their sum, while the FP64 test's margin
+// is 1e-9 times a smaller sum; pairs the bound cannot settle go to the FP64
+// test.  r and R are FP32 values (the configuration's), so their casts are
+// exact.
+__device__ __forceinline__ bool surely_not_near32(const float* x0, const float* x1, float r,
+                                                  float R) {
+    float pp = 0.f, pv = 0.f, tv = 0.f, vv = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float P = x1[a] - x0[a];
+        const float v0 = x0[3 + a], v1 = x1[3 + a];
+        const float sv = v0 + v1;
+        pp += P * P;
+        pv += P * sv;
+        tv += fabsf(P * sv);
+        vv += v0 * v0 + v0 * v1 + v1 * v1;
+    }
+    const float R2 = R * R, R4 = R2 * R2;
+    const float a0 = 12.f * r * pp, a1 = -12.f * r * pv * R, a2 = 4.f * r * vv * R2;
+    const float m = 1e-4f * (fabsf(a0) + 12.f * r * tv * R + fabsf(a2) + 2.f * R4);
+    const float b1 = a0 + 0.25f * a1;
+    const float b2 = a0 + 0.5f * a1 + a2 * (1.f / 6.f);
+    const float b3 = a0 + 0.75f * a1 + 0.5f * a2 - 0.25f * R4;
+    const float b4 = a0 + a1 + a2;                 // + a3 + a4 = 0
+    return fminf(fminf(fminf(a0, b1), fminf(b2, b3)), b4) > m;
+}
+
 // Minimum-effort nominal trajectory per axis (cubic Hermite):
 //   p(t) = p0 + v0 t + c2 t^2 + c3 t^3,
 //   c2 = (3P - (2 v0 + v1) tau) / tau^2,  c3 = (-2P + (v0 + v1) tau) / tau^3.

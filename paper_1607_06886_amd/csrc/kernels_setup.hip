@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_gw_near_col0(const float* __restrict__ 
 }
 
 // boxes over the near list (count on the device) or a cached list (count given)
-__global__ __launch_bounds__(kBoxThreads) void k_gw_boxes(const float* __restrict__ X,
+__global__ __launch_bounds__(kBoxThreads, 3) void k_gw_boxes(const float* __restrict__ X,
                                                           const uint8_t* __restrict__ valid,
                                                           const int32_t* __restrict__ src,
                                                           const int32_t* __restrict__ dst,

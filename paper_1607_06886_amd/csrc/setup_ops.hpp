@@ -339,6 +339,7 @@ __device__ __forceinline__ void gw_near_row(const float* __restrict__ X,
             if (u == v || !valid[u]) continue;
             float xu[6];
             for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)u * 6 + k];
+            if (surely_not_near32(xv, xu, (float)r_steer, (float)r_conn)) continue;
             if (!surely_not_near(boundary_sums(xv, xu), r_steer, r_conn))
                 s_list[atomicAdd(s_cnt, 1)] = u;
         }
@@ -370,6 +371,7 @@ __device__ __forceinline__ void gw_near_col0(const float* __restrict__ X,
     bool ok = false;
     double tau = 0.0;
     if (src < n && valid[0] && valid[src] &&
+        !surely_not_near32(X + (size_t)src * 6, X, (float)r_steer, (float)r_conn) &&
         !surely_not_near(boundary_sums(X + (size_t)src * 6, X), r_steer, r_conn)) {
         double c;
         steer64(X + (size_t)src * 6, X, r_steer, tau, c);
@@ -441,11 +443,19 @@ __device__ __forceinline__ void gw_boxes(const float* __restrict__ X,
                     hermite(X + (size_t)src * 6, X + (size_t)dst * 6, tau, cs);
                     for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
                 }
+                // the range rounded outwards to FP32: a box it misses in FP32
+                // the FP64 range misses too; the few it then meets that the
+                // FP64 range would not go to the exact tests, which decide
+                // them the same way
+                float mnf[3], mxf[3];
+                for (int a = 0; a < 3; ++a) {
+                    mnf[a] = __double2float_rd(mn[a]);
+                    mxf[a] = __double2float_ru(mx[a]);
+                }
                 for (int o = 0; o < n_obs; ++o) {
                     const float* bx = s_obs + o * 6;
-                    bool disjoint = false;
-                    for (int a = 0; a < 3; ++a)
-                        disjoint |= (mx[a] < (double)bx[a]) | (mn[a] > (double)bx[3 + a]);
+                    const bool disjoint = (mxf[0] < bx[0]) | (mnf[0] > bx[3]) | (mxf[1] < bx[1]) |
+                                          (mnf[1] > bx[4]) | (mxf[2] < bx[2]) | (mnf[2] > bx[5]);
                     if (!disjoint) {
                         ov[o >> 6] |= 1ull << (o & 63);
                         ++n_ov;
