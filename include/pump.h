@@ -101,7 +101,12 @@ typedef struct pump_config {
     int32_t reserved_;     /* zero                                               */
     int64_t cap_edges;     /* capacity: graph edges                                 */
     int64_t cap_plans;     /* capacity: plan records over a whole query             */
-    int64_t cap_pairs;     /* capacity: (plan, neighbour) pairs in one round        */
+    int64_t cap_pairs;     /* capacity: candidate slots ((plan, neighbour) pairs
+                              held at once) and BuildGraph's exact queue.  A
+                              round of Explore with more pairs runs in chunks
+                              of cap_pairs pairs (pump_explore_round), with the
+                              same result; the batched engine fails such a
+                              query with PUMP_E_CAPACITY.                      */
 } pump_config;
 
 /* One planning query: Alg. 2's inputs plus the noise the particle models
@@ -208,8 +213,18 @@ int pump_setup(pump_ctx* ctx, const pump_problem* prob);
 /* Alg. 4 initialisation: P_open = B = {root}, i = 0. */
 int pump_explore_begin(pump_ctx* ctx);
 /* One iteration of Alg. 4's while loop; *done = 1 once the loop test fails
- * (no open plan, or a goal plan of the group has cp_hat < alpha_min). */
+ * (no open plan, or a goal plan of the group has cp_hat < alpha_min).
+ * A round whose pairs (sum of the group's out-degrees) exceed cap_pairs runs
+ * in chunks of cap_pairs pairs and two passes: the first expands each chunk
+ * and enters its candidates into the dominance staircases, the second
+ * expands each chunk again and keeps the candidates the final staircases do
+ * not dominate.  RemoveDominated depends only on the final staircases, so
+ * the plan store is the one the round in one piece makes (same plan ids);
+ * the counters of pump_result count the first pass.
+ * pump_get_chunked_rounds reports how many rounds of the current Explore ran
+ * in chunks. */
 int pump_explore_round(pump_ctx* ctx, int32_t* done);
+int pump_get_chunked_rounds(pump_ctx* ctx, int64_t* n);
 /* Rounds until done. */
 int pump_explore_run(pump_ctx* ctx);
 /* Alg. 5 on the explored plans; fills *out (status and p*). */
@@ -234,7 +249,8 @@ int pump_get_plans(pump_ctx* ctx, int32_t* head, int32_t* parent, int32_t* edge,
 /* Candidates of the last round, one per (plan, neighbour) pair in pair order:
  * flag (0 dropped, 1 kept and not dominated, 2 kept but dominated),
  * pop (-1 pre-pruned before simulation, -2 over S_max), and for kept ones
- * parent plan, head, cost and particle bits.  Any pointer may be NULL. */
+ * parent plan, head, cost and particle bits.  Any pointer may be NULL.
+ * PUMP_E_STATE if that round ran in chunks (its candidates are not kept). */
 int pump_get_candidates(pump_ctx* ctx, uint8_t* flag, int32_t* pop, int32_t* parent,
                         int32_t* head, double* cost, uint32_t* mask, int64_t cap,
                         int64_t* n_pairs);
@@ -330,7 +346,8 @@ int pump_get_explore_mode(pump_ctx* ctx, int32_t* mode, int32_t* blocks);
  * held compute units) makes every workgroup leave the launch; pump_plan and
  * pump_explore_run then redo Explore from the root with one launch per phase
  * (mode 0 for that call only), which gives the same plan store, and count
- * the event.  pump_get_explore_fallbacks reports how many times that
+ * the event.  They do the same when a round of the single launch has more
+ * pairs than cap_pairs (the per-phase rounds run it in chunks).  pump_get_explore_fallbacks reports how many times that
  * happened on this context. */
 int pump_set_barrier_patience(pump_ctx* ctx, double ms);
 int pump_get_explore_fallbacks(pump_ctx* ctx, int64_t* n);

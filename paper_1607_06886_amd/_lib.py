@@ -92,7 +92,7 @@ EXPORTS = ["pump_config_default", "pump_create", "pump_destroy", "pump_plan", "p
            "pump_roadmap_info", "pump_set_roadmap", "pump_batch_set_roadmaps",
            "pump_set_timing",
            "pump_get_timing", "pump_set_explore_mode", "pump_get_explore_mode",
-           "pump_set_barrier_patience", "pump_get_explore_fallbacks",
+           "pump_set_barrier_patience", "pump_get_explore_fallbacks", "pump_get_chunked_rounds",
            "pump_status_str", "pump_last_error", "pump_mlp_create",
            "pump_mlp_destroy", "pump_mlp_num_params", "pump_mlp_set_params",
            "pump_mlp_get_params", "pump_mlp_get_state", "pump_mlp_set_state",
@@ -156,6 +156,7 @@ def load(path: Optional[str] = None):
         "pump_get_explore_mode": (_i32, [_p, P(_i32), P(_i32)]),
         "pump_set_barrier_patience": (_i32, [_p, _d]),
         "pump_get_explore_fallbacks": (_i32, [_p, P(_i64)]),
+        "pump_get_chunked_rounds": (_i32, [_p, P(_i64)]),
         "pump_status_str": (ctypes.c_char_p, [_i32]),
         "pump_last_error": (ctypes.c_char_p, [_p]),
         "pump_mlp_create": (_i32, [_i32, _p, P(_p)]),
@@ -433,6 +434,12 @@ class Planner:
     def explore_fallbacks(self) -> int:
         n = _i64(0)
         self._check(self.lib.pump_get_explore_fallbacks(self.ctx, ctypes.byref(n)))
+        return int(n.value)
+
+    def chunked_rounds(self) -> int:
+        """Rounds of the current Explore that ran in chunks of cap_pairs."""
+        n = _i64(0)
+        self._check(self.lib.pump_get_chunked_rounds(self.ctx, ctypes.byref(n)))
         return int(n.value)
 
     def set_timing(self, on: bool):

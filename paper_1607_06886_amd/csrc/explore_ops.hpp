@@ -125,7 +125,7 @@ __device__ __forceinline__ int wave_group_of(const int32_t* __restrict__ b_off, 
 
 // ---------------------------------------------------------------------------
 // Expansion, first part (one pair per lane): pair q (q < n_pairs) of group
-// lo (wave_group_of), its edge and parent plan; cost, step count and K_e waypoints; drop it past
+// lo (wave_group_of), written to candidate slot q - a.q0, its edge and parent plan; cost, step count and K_e waypoints; drop it past
 // S_max; resolve it if the parent's own cp_hat already makes it dominated;
 // otherwise evaluate the nominal trajectory and mark the waypoints where the
 // particle cloud's bounding box, shifted onto the nominal point and widened by
@@ -146,22 +146,23 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int lo, co
     const int head = a.p_head[p];
     const int e = a.row_ptr[head] + (q - a.b_off[lo]);
     const int x = a.col[e];
-    a.c_parent[q] = p;   // every formed pair records its identity
-    a.c_head[q] = x;
+    const int sl = q - a.q0;   // candidate slot
+    a.c_parent[sl] = p;   // every formed pair records its identity
+    a.c_head[sl] = x;
     const double tau = a.etau[e];
     const double cost = a.p_cost[p] + a.ecost[e];
     const int K = max(1, (int)ceil(tau / a.dt));
     const int s_p = a.p_step[p];
     const int pop_p = a.p_pop[p];
     if (s_p + K > a.S_max) {
-        a.c_flag[q] = 0;
-        a.c_pop[q] = -2;
+        a.c_flag[sl] = 0;
+        a.c_pop[sl] = -2;
         ++n_drop;
         return 0;
     }
     if (a.preprune && stair_get(a.stair, a.stair_w, x, pop_p) < cost) {
-        a.c_flag[q] = 0;
-        a.c_pop[q] = -1;
+        a.c_flag[sl] = 0;
+        a.c_pop[sl] = -1;
         ++n_pre;
         return 0;
     }
@@ -195,16 +196,16 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int lo, co
                 }
             }
         }
-        a.c_edge[q] = e;
-        a.c_cost[q] = cost;
-        a.c_step[q] = s_p + K;
+        a.c_edge[sl] = e;
+        a.c_cost[sl] = cost;
+        a.c_step[sl] = s_p + K;
         if (near == 0u) {
-            a.c_flag[q] = 1;
-            a.c_pop[q] = pop_p;
-            for (int w = 0; w < W; ++w) a.c_mask[(size_t)q * W + w] = a.p_mask[(size_t)p * W + w];
+            a.c_flag[sl] = 1;
+            a.c_pop[sl] = pop_p;
+            for (int w = 0; w < W; ++w) a.c_mask[(size_t)sl * W + w] = a.p_mask[(size_t)p * W + w];
             return 1;
         }
-        tk = SimTask{q, p, e, near, (uint32_t)head | ((uint32_t)x << 16), s_p, tau};
+        tk = SimTask{sl, p, e, near, (uint32_t)head | ((uint32_t)x << 16), s_p, tau};
         return 2;
     }
     // obstacles the cloud can reach anywhere along the edge
@@ -247,17 +248,17 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int lo, co
             if (hitk) near |= 1u << (k - 1);
         }
     }
-    a.c_edge[q] = e;
-    a.c_cost[q] = cost;
-    a.c_step[q] = s_p + K;
+    a.c_edge[sl] = e;
+    a.c_cost[sl] = cost;
+    a.c_step[sl] = s_p + K;
     if (near == 0u) {
         // no particle can touch an obstacle on this edge: q keeps p's bits
-        a.c_flag[q] = 1;
-        a.c_pop[q] = pop_p;
-        for (int w = 0; w < W; ++w) a.c_mask[(size_t)q * W + w] = a.p_mask[(size_t)p * W + w];
+        a.c_flag[sl] = 1;
+        a.c_pop[sl] = pop_p;
+        for (int w = 0; w < W; ++w) a.c_mask[(size_t)sl * W + w] = a.p_mask[(size_t)p * W + w];
         return 1;
     }
-    tk = SimTask{q, p, e, near, (uint32_t)head | ((uint32_t)x << 16), s_p, tau};
+    tk = SimTask{sl, p, e, near, (uint32_t)head | ((uint32_t)x << 16), s_p, tau};
     return 2;
 }
 

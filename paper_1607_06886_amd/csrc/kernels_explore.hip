@@ -140,19 +140,20 @@ __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
     stage_obstacles_block(a.obs, a.n_obs, s_raw, nullptr, s_out);
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int n_pairs = a.ctl->n_pairs;
+    // pairs [a.q0, q_end) of the round: all of them, or one chunk
+    const int q_end = a.chunked ? a.q0 + a.ctl->chunk_n : a.ctl->n_pairs;
     const int n_B = a.ctl->n_B;
     float gl[3], gh[3];
     for (int k = 0; k < 3; ++k) { gl[k] = a.gcloud[k]; gh[k] = a.gcloud[3 + k]; }
     long long n_sim = 0, n_pre = 0, n_drop = 0;
     const int wave_global = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int wave_stride = gridDim.x * 4;
-    for (int tile = wave_global * 64; tile < n_pairs; tile += wave_stride * 64) {
+    for (int tile = a.q0 + wave_global * 64; tile < q_end; tile += wave_stride * 64) {
         const int q = tile + lane;
         SimTask tk;
         const int grp = wave_group_of(a.b_off, n_B, tile, q);
-        const int st = q < n_pairs ? expand_pair<N, CP>(a, q, grp, s_raw, s_out, gl, gh, n_sim, n_pre,
-                                                     n_drop, tk) : 0;
+        const int st = q < q_end ? expand_pair<N, CP>(a, q, grp, s_raw, s_out, gl, gh, n_sim, n_pre,
+                                                   n_drop, tk) : 0;
         queue_pairs(a, st, tk);
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
         n_drop += __shfl_down(n_drop, o, 64);
         n_pre += __shfl_down(n_pre, o, 64);
     }
-    if (lane == 0) {
+    if (lane == 0 && !a.quiet) {
         if (n_sim) atomicAdd((unsigned long long*)&a.ctl->simulated, (unsigned long long)n_sim);
         if (n_pre) atomicAdd((unsigned long long*)&a.ctl->preprune, (unsigned long long)n_pre);
         if (n_drop) atomicAdd((unsigned long long*)&a.ctl->dropped_steps, (unsigned long long)n_drop);
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(256) void k_expand_sim(RoundArgs a) {
             simulate_pair_box<N>(a, task, s_raw, s_out, n_pre, n_flag, n_wp, n_bt);
     }
     // counts are wave-uniform
-    if (lane == 0) {
+    if (lane == 0 && !a.quiet) {
         if (n_pre) atomicAdd((unsigned long long*)&a.ctl->preprune, (unsigned long long)n_pre);
         if (n_flag) atomicAdd((unsigned long long*)&a.ctl->flagged, (unsigned long long)n_flag);
         if (n_wp) atomicAdd((unsigned long long*)&a.ctl->sim_waypoints, (unsigned long long)n_wp);
@@ -229,7 +230,7 @@ void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, in
 
 // RemoveDominated (staircase update, then marks; see explore_ops.hpp).
 __global__ __launch_bounds__(256) void k_stair_update(RoundArgs a) {
-    const int n_pairs = a.ctl->n_pairs;
+    const int n_pairs = a.chunked ? a.ctl->chunk_n : a.ctl->n_pairs;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_pairs; q += gridDim.x * blockDim.x)
         stair_update_pair(a, q);
 }
@@ -246,6 +247,13 @@ __global__ __launch_bounds__(256) void k_mark(RoundArgs a) {
     for (int o = 32; o > 0; o >>= 1) kept += __shfl_down(kept, o, 64);
     if ((threadIdx.x & 63) == 0 && kept)
         atomicAdd((unsigned long long*)&a.ctl->inserted, (unsigned long long)kept);
+}
+
+static int grid_of(long long n) {
+    long long b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 16384) b = 16384;
+    return (int)b;
 }
 
 void launch_prune(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, int32_t n_open) {
@@ -298,6 +306,107 @@ void launch_compact(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, i
         default: k_compact<8><<<b, 256, 0, s>>>(a); break;
     }
     k_compact_finalize<<<1, 1, 0, s>>>(a.ctl, a.cap_plans);
+}
+
+// ---------------------------------------------------------------------------
+// A round with more pairs than candidate slots runs in chunks of the pair
+// list, in two passes.  RemoveDominated's outcome depends only on the final
+// staircase of each node (the minimum over every kept candidate of the round
+// and the plans before it), so
+//   pass 1: per chunk, expansion and the staircase update (the candidates
+//           are then dropped);
+//   then:   the open list is marked against the final staircase and
+//           compacted (P_open \ B \ removed);
+//   pass 2: per chunk, the expansion again (the same candidates), marks
+//           against the final staircase and compaction of the survivors
+//           after those of the chunks before it.
+// Survivors get the plan ids and open-list places the round would give them
+// in one piece (pair order).  A pass-1 expansion already sees the entries of
+// earlier chunks, so it may resolve a pair without simulating it that the
+// round in one piece would simulate and then remove: that pair is dominated
+// either way, and the staircase it would have updated already holds a lower
+// cost at every level it reaches.  The counters count pass 1 (and the
+// candidates kept before the test in pass 2).
+// ---------------------------------------------------------------------------
+__global__ void k_chunk_begin(Ctl* c, int32_t n) {
+    c->chunk_n = n;
+    c->n_tasks = 0;
+}
+
+__global__ __launch_bounds__(256) void k_mark_open_only(RoundArgs a) {
+    const int n_open = a.ctl->n_open;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_open; i += gridDim.x * blockDim.x)
+        mark_open(a, i);
+}
+
+__global__ __launch_bounds__(256) void k_compact_open_only(RoundArgs a) {
+    const int n_open = a.ctl->n_open;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_open; i += gridDim.x * blockDim.x)
+        compact_open(a, i);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->chunk_base = 0;
+}
+
+__global__ __launch_bounds__(256) void k_mark_chunk(RoundArgs a) {
+    const int n = a.ctl->chunk_n;
+    long long kept = 0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+        kept += mark_pair(a, t) ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) kept += __shfl_down(kept, o, 64);
+    if ((threadIdx.x & 63) == 0 && kept)
+        atomicAdd((unsigned long long*)&a.ctl->inserted, (unsigned long long)kept);
+}
+
+// survivors of this chunk after those of the chunks before it; nothing is
+// written once the plan store would overflow (the final check reports it)
+template <int W>
+__global__ __launch_bounds__(256) void k_compact_chunk(RoundArgs a) {
+    const int n = a.ctl->chunk_n;
+    const int base = a.ctl->chunk_base;
+    const int n_plans = a.ctl->n_plans;
+    const int n_keep = a.ctl->scan_total[1];
+    const bool fits = (long long)n_plans + base + a.ctl->scan_total[0] <= a.cap_plans;
+    if (!fits) return;
+    const int i_round = a.ctl->i;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+        compact_pair<W>(a, t, n_plans + base, n_keep + base, i_round);
+}
+
+__global__ void k_chunk_end(Ctl* c) { c->chunk_base += c->scan_total[0]; }
+
+__global__ void k_chunks_finalize(Ctl* c, int64_t cap) {
+    c->scan_total[0] = c->chunk_base;
+    compact_finalize(c, cap);
+}
+
+void launch_chunk_begin(hipStream_t s, const RoundArgs& a, int32_t n) {
+    k_chunk_begin<<<1, 1, 0, s>>>(a.ctl, n);
+}
+
+void launch_stair_update(hipStream_t s, const RoundArgs& a, int32_t n) {
+    k_stair_update<<<grid_of(n), 256, 0, s>>>(a);
+}
+
+void launch_open_compact(hipStream_t s, const RoundArgs& a, int32_t n_open, int32_t* blk) {
+    k_mark_open_only<<<grid_of(n_open), 256, 0, s>>>(a);
+    scan_exclusive(s, a.o_keep, a.o_keep, &a.ctl->n_open, n_open, &a.ctl->scan_total[1],
+                   blk + 65536);
+    k_compact_open_only<<<grid_of(n_open), 256, 0, s>>>(a);
+}
+
+void launch_chunk_compact(hipStream_t s, const RoundArgs& a, int N, int32_t n, int32_t* blk) {
+    k_mark_chunk<<<grid_of(n), 256, 0, s>>>(a);
+    scan_exclusive(s, a.c_pos, a.c_pos, &a.ctl->chunk_n, n, &a.ctl->scan_total[0], blk);
+    switch (N / 32) {
+        case 1: k_compact_chunk<1><<<grid_of(n), 256, 0, s>>>(a); break;
+        case 2: k_compact_chunk<2><<<grid_of(n), 256, 0, s>>>(a); break;
+        case 4: k_compact_chunk<4><<<grid_of(n), 256, 0, s>>>(a); break;
+        default: k_compact_chunk<8><<<grid_of(n), 256, 0, s>>>(a); break;
+    }
+    k_chunk_end<<<1, 1, 0, s>>>(a.ctl);
+}
+
+void launch_chunks_finalize(hipStream_t s, const RoundArgs& a) {
+    k_chunks_finalize<<<1, 1, 0, s>>>(a.ctl, a.cap_plans);
 }
 
 // Next group (Alg. 4: i <- i + 1, B <- cheap open plans) and the loop test.

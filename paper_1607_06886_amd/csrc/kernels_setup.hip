@@ -91,9 +91,9 @@ __global__ __launch_bounds__(kNearThreads) void k_gw_near_rows(const float* __re
                                                       const uint8_t* __restrict__ valid, int n,
                                                       int row0, double r_steer, double r_conn,
                                                       GraphWork gw) {
-    __shared__ int s_list[kNearChunk];
-    __shared__ int s_cnt;
-    gw_near_row(X, valid, n, row0 + blockIdx.x, r_steer, r_conn, gw, s_list, &s_cnt);
+    __shared__ int s_list[2 * kNearChunk];
+    __shared__ int s_cnt[2];
+    gw_near_row(X, valid, n, row0 + blockIdx.x, r_steer, r_conn, gw, s_list, s_cnt);
 }
 
 __global__ __launch_bounds__(256) void k_gw_near_col0(const float* __restrict__ X,

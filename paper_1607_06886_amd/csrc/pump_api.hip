@@ -102,6 +102,8 @@ struct pump_ctx {
     int32_t* open_next = nullptr;
     long long partial_plans = 0;
     int32_t last_pairs = 0;
+    int32_t last_chunks = 1;        // chunks the last round ran in (1: in one piece)
+    long long chunked_rounds = 0;   // rounds of this Explore run in chunks
     int rounds = 0;
     float ms_setup = 0, ms_explore = 0, ms_select = 0;
     // 0/4 setup begin/end, 1/2 Explore, 2/3 selection, 5/6 pump_plan
@@ -669,6 +671,8 @@ static int explore_begin(pump_ctx* ctx, bool sync) {
     HIPCHK(hipGetLastError());
     ctx->partial_plans = 0;
     ctx->rounds = 0;
+    ctx->last_chunks = 1;
+    ctx->chunked_rounds = 0;
     ctx->ms_explore = 0.0f;
     ctx->have_explore = true;
     ctx->explore_done = false;
@@ -691,21 +695,63 @@ int pump_explore_round(pump_ctx* ctx, int32_t* done) {
     }
     const int32_t n_pairs = ctx->ctl_h->n_pairs;
     const int32_t n_open = ctx->ctl_h->n_open;
-    if ((long long)n_pairs > ctx->cfg.cap_pairs)
-        return fail(ctx, PUMP_E_CAPACITY, "round pairs " + std::to_string(n_pairs) + " exceed cap_pairs");
     RoundArgs a = round_args(ctx);
-    tbeg(ctx, 3);
-    launch_expand(ctx->stream, a, ctx->N, n_pairs, 1);
-    tend(ctx);
-    tbeg(ctx, 18);
-    launch_expand(ctx->stream, a, ctx->N, n_pairs, 2);
-    tend(ctx);
-    tbeg(ctx, 4);
-    launch_prune(ctx->stream, a, ctx->N, n_pairs, n_open);
-    tend(ctx);
-    tbeg(ctx, 5);
-    launch_compact(ctx->stream, a, ctx->N, n_pairs, n_open, ctx->blk);
-    tend(ctx);
+    const long long slots = ctx->cfg.cap_pairs;
+    if ((long long)n_pairs <= slots) {
+        tbeg(ctx, 3);
+        launch_expand(ctx->stream, a, ctx->N, n_pairs, 1);
+        tend(ctx);
+        tbeg(ctx, 18);
+        launch_expand(ctx->stream, a, ctx->N, n_pairs, 2);
+        tend(ctx);
+        tbeg(ctx, 4);
+        launch_prune(ctx->stream, a, ctx->N, n_pairs, n_open);
+        tend(ctx);
+        tbeg(ctx, 5);
+        launch_compact(ctx->stream, a, ctx->N, n_pairs, n_open, ctx->blk);
+        tend(ctx);
+        ctx->last_chunks = 1;
+    } else {
+        // more pairs than candidate slots: the round in chunks of cap_pairs
+        // pairs, in two passes (kernels_explore.hip)
+        a.chunked = 1;
+        int chunks = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            a.quiet = pass;
+            if (pass == 1) {
+                tbeg(ctx, 5);
+                launch_open_compact(ctx->stream, a, n_open, ctx->blk);
+                tend(ctx);
+            }
+            for (long long q0 = 0; q0 < n_pairs; q0 += slots) {
+                const int32_t n = (int32_t)std::min<long long>(slots, (long long)n_pairs - q0);
+                a.q0 = (int32_t)q0;
+                launch_chunk_begin(ctx->stream, a, n);
+                tbeg(ctx, 3);
+                launch_expand(ctx->stream, a, ctx->N, n, 1);
+                tend(ctx);
+                tbeg(ctx, 18);
+                launch_expand(ctx->stream, a, ctx->N, n, 2);
+                tend(ctx);
+                if (pass == 0) {
+                    tbeg(ctx, 4);
+                    launch_stair_update(ctx->stream, a, n);
+                    tend(ctx);
+                    ++chunks;
+                } else {
+                    tbeg(ctx, 5);
+                    launch_chunk_compact(ctx->stream, a, ctx->N, n, ctx->blk);
+                    tend(ctx);
+                }
+            }
+        }
+        launch_chunks_finalize(ctx->stream, a);
+        a.chunked = 0;
+        a.q0 = 0;
+        a.quiet = 0;
+        ctx->last_chunks = chunks;
+        ctx->chunked_rounds += 1;
+    }
     long long upper = std::min<long long>((long long)n_open + n_pairs, ctx->cfg.cap_plans);
     tbeg(ctx, 6);
     launch_next_group(ctx->stream, a, (int32_t)upper, ctx->b_deg, ctx->blk);
@@ -789,6 +835,15 @@ static int explore_single_finish(pump_ctx* ctx) {
     return PUMP_OK;
 }
 
+// The single launch gave up in a way the per-phase rounds do not: a barrier
+// wait ran out of patience (its workgroups were not all resident), or a
+// round had more pairs than candidate slots (the per-phase rounds run such a
+// round in chunks).
+static bool single_needs_fallback(const pump_ctx* ctx, int r) {
+    return (r == PUMP_E_STATE && ctx->ctl_h->err == 5) ||
+           (r == PUMP_E_CAPACITY && ctx->ctl_h->err == 4);
+}
+
 static int explore_single_launch(pump_ctx* ctx) {
     int r = explore_single_enqueue(ctx);
     if (r == PUMP_OK) r = read_ctl(ctx);
@@ -817,9 +872,8 @@ int pump_explore_run(pump_ctx* ctx) {
     HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
     if (effective_mode(ctx) == 1 && !ctx->explore_done) {
         int r = explore_single_launch(ctx);
-        if (r == PUMP_E_STATE && ctx->ctl_h->err == 5) {
-            // a barrier wait ran out of patience (workgroups not resident
-            // together): redo Explore with one launch per phase
+        if (single_needs_fallback(ctx, r)) {
+            // redo Explore with one launch per phase
             ctx->fallbacks += 1;
             r = explore_begin(ctx, true);
             int32_t done = ctx->explore_done ? 1 : 0;
@@ -853,6 +907,12 @@ int pump_set_barrier_patience(pump_ctx* ctx, double ms) {
     if (!ctx || !(ms > 0.0) || !(ms <= 600000.0)) return PUMP_E_ARG;
     ctx->patience = (unsigned long long)(ms * 1e5);   // 100 MHz ticks
     if (ctx->patience < 1) ctx->patience = 1;
+    return PUMP_OK;
+}
+
+int pump_get_chunked_rounds(pump_ctx* ctx, int64_t* n) {
+    if (!ctx || !n) return PUMP_E_ARG;
+    *n = ctx->chunked_rounds;
     return PUMP_OK;
 }
 
@@ -994,10 +1054,9 @@ int pump_plan(pump_ctx* ctx, const pump_problem* pr, pump_result* out) {
             r = explore_single_enqueue(ctx);
         }
         if (r == PUMP_OK) r = select_impl(ctx, &res, true);
-        if (r == PUMP_E_STATE && ctx->ctl_h->err == 5) {
-            // the single launch's barrier wait ran out of patience (its
-            // workgroups were not all resident): Explore again from the root
-            // with one launch per phase, then select
+        if (single_needs_fallback(ctx, r)) {
+            // Explore again from the root with one launch per phase, then
+            // select
             ctx->fallbacks += 1;
             memset(&res, 0, sizeof(res));
             r = explore_begin(ctx, true);
@@ -1135,6 +1194,9 @@ int pump_get_candidates(pump_ctx* ctx, uint8_t* flag, int32_t* pop, int32_t* par
     if (!ctx->have_explore) return fail(ctx, PUMP_E_STATE, "pump_explore_begin first");
     // the pair count of the round just run is the previous round's n_pairs;
     // kept as the number the caller saw before the round
+    if (ctx->last_chunks > 1)
+        return fail(ctx, PUMP_E_STATE, "the last round ran in " + std::to_string(ctx->last_chunks) +
+                                           " chunks; its candidates are not kept");
     const int32_t n = ctx->last_pairs;
     if (n_pairs) *n_pairs = n;
     if ((int64_t)n > cap && (flag || pop || parent || head || cost || mask))

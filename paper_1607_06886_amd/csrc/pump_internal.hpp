@@ -88,6 +88,10 @@ struct Ctl {
     int32_t n_valid;           // valid nodes
     int32_t pad2_;
     double sel_cost;           // cost of p*
+    // a round run in chunks: the current chunk's pair count and the
+    // survivors of the chunks before it
+    int32_t chunk_n;
+    int32_t chunk_base;
 };
 
 // A pair queued for particle simulation, with what the simulation needs of
@@ -157,6 +161,12 @@ struct RoundArgs {
     int32_t* c_pos;            // scan input/output over the pairs
     SimTask* tasks;            // pairs queued for particle simulation
     Ctl* ctl;
+    // a round run in chunks (more pairs than candidate slots): pair q of the
+    // round is slot q - q0 (q0 = 0 otherwise); quiet = 1 in the second pass
+    // over the chunks, whose expansion adds nothing to the counters
+    int32_t chunked;           // 1: the launch covers pairs q0 .. q0 + ctl->chunk_n - 1
+    int32_t q0;
+    int32_t quiet;
 };
 
 // Work lists of BuildGraph's pass 1 (setup_ops.hpp): the near list lives in
@@ -251,6 +261,15 @@ void launch_compact(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs,
                     int32_t n_open, int32_t* blk_scratch);
 void launch_next_group(hipStream_t s, const RoundArgs& a, int32_t n_open_upper,
                        int32_t* deg_scratch, int32_t* blk_scratch);
+// A round in chunks (a.chunked = 1): chunk_begin sets the chunk's pair count
+// (and empties the simulation queue) before its expansion; stair_update after
+// each pass-1 expansion; open_compact once between the passes; chunk_compact
+// after each pass-2 expansion; chunks_finalize at the end.
+void launch_chunk_begin(hipStream_t s, const RoundArgs& a, int32_t n);
+void launch_stair_update(hipStream_t s, const RoundArgs& a, int32_t n);
+void launch_open_compact(hipStream_t s, const RoundArgs& a, int32_t n_open, int32_t* blk_scratch);
+void launch_chunk_compact(hipStream_t s, const RoundArgs& a, int N, int32_t n, int32_t* blk_scratch);
+void launch_chunks_finalize(hipStream_t s, const RoundArgs& a);
 
 struct SelectArgs {
     const float* X;

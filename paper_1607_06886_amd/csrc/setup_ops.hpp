@@ -324,34 +324,54 @@ __device__ __forceinline__ void gw_push_near(const GraphWork& gw, bool ok, int s
     }
 }
 
-// near: row v (whole workgroup, blockDim a multiple of 64; s_list holds kNearChunk ints)
+// near: row v (whole workgroup, blockDim a multiple of 64; s_list holds
+// 2 * kNearChunk ints, s_cnt 2).  Per chunk of targets, three passes, each
+// over a list compacted by the one before it so that no wave carries lanes
+// the pass has no work for (a few per cent of the targets pass the FP32
+// bound, so a wave of 64 targets taken in place would nearly always run the
+// FP64 test, and the root solve, for one or two lanes):
+//   1. the FP32 first look at the Bernstein bound over every target;
+//   2. the FP64 rejection test over the targets it could not settle;
+//   3. the root solve (tau*, c*) over the targets that test keeps.
 __device__ __forceinline__ void gw_near_row(const float* __restrict__ X,
                                             const uint8_t* __restrict__ valid, int n, int v,
                                             double r_steer, double r_conn, const GraphWork& gw,
                                             int* s_list, int* s_cnt) {
     if (!valid[v]) return;
+    int* s_l1 = s_list;                 // pass 1 -> 2
+    int* s_l2 = s_list + kNearChunk;    // pass 2 -> 3
     float xv[6];
     for (int k = 0; k < 6; ++k) xv[k] = X[(size_t)v * 6 + k];
+    const float r32 = (float)r_steer, R32 = (float)r_conn;
     for (int c0 = 0; c0 < n; c0 += kNearChunk) {
-        if (threadIdx.x == 0) *s_cnt = 0;
+        if (threadIdx.x == 0) {
+            s_cnt[0] = 0;
+            s_cnt[1] = 0;
+        }
         __syncthreads();
         for (int u = c0 + threadIdx.x; u < c0 + kNearChunk && u < n; u += blockDim.x) {
             if (u == v || !valid[u]) continue;
-            float xu[6];
-            for (int k = 0; k < 6; ++k) xu[k] = X[(size_t)u * 6 + k];
-            if (surely_not_near32(xv, xu, (float)r_steer, (float)r_conn)) continue;
-            if (!surely_not_near(boundary_sums(xv, xu), r_steer, r_conn))
-                s_list[atomicAdd(s_cnt, 1)] = u;
+            const float2* xu2 = reinterpret_cast<const float2*>(X + (size_t)u * 6);
+            const float2 p01 = xu2[0], p2v0 = xu2[1], v12 = xu2[2];
+            const float xu[6] = {p01.x, p01.y, p2v0.x, p2v0.y, v12.x, v12.y};
+            if (!surely_not_near32(xv, xu, r32, R32)) s_l1[atomicAdd(&s_cnt[0], 1)] = u;
         }
         __syncthreads();
-        const int cnt = *s_cnt;
-        for (int base = 0; base < cnt; base += blockDim.x) {
+        const int cnt1 = s_cnt[0];
+        for (int i = threadIdx.x; i < cnt1; i += blockDim.x) {
+            const int u = s_l1[i];
+            if (!surely_not_near(boundary_sums(xv, X + (size_t)u * 6), r_steer, r_conn))
+                s_l2[atomicAdd(&s_cnt[1], 1)] = u;
+        }
+        __syncthreads();
+        const int cnt2 = s_cnt[1];
+        for (int base = 0; base < cnt2; base += blockDim.x) {
             const int i = base + threadIdx.x;
             bool ok = false;
             int u = 0;
             double tau = 0.0;
-            if (i < cnt) {
-                u = s_list[i];
+            if (i < cnt2) {
+                u = s_l2[i];
                 double c;
                 steer64(xv, X + (size_t)u * 6, r_steer, tau, c);
                 ok = c < r_conn && tau > kTauMin;

@@ -2,15 +2,17 @@
 query make pump_plan return PUMP_E_CAPACITY (-2) with the size it needed in
 the message, never write past a buffer, and leave the context usable; a
 context sized from the reported numbers then plans the query and matches a
-roomy context.  Checked for the graph (cap_edges), the round's pairs
-(cap_pairs) and the plan store (cap_plans), in both Explore modes."""
+roomy context.  Checked for the graph (cap_edges), BuildGraph's exact
+queue (cap_pairs) and the plan store (cap_plans), in both Explore modes.
+(A round with more pairs than cap_pairs runs in chunks instead:
+tests/test_gpu_chunked_rounds.py.)"""
 
 import re
 
 import pytest
 
-from paper_1607_06886_amd import _lib, scenes
-from tests._gpu import planner_for, print_case, scene, small_spec
+from paper_1607_06886_amd import _lib
+from tests._gpu import planner_for, print_case, scene
 
 pytestmark = pytest.mark.gpu
 
@@ -52,14 +54,12 @@ def test_edges_pairs_and_plans_too_small(ref, mode):
     assert ei.value.code == -2
     need_e = _needed(ei.value, r"(?:near connections|graph edges) (\d+) exceed cap_edges")
     assert need_e > 1000
-    # the pairs of a round, on an obstacle-free map (no exact box tests
-    # share cap_pairs there); its rounds form hundreds of pairs
-    free = scenes.make_scene(small_spec(n=300, N=32, n_obs=0), 31, M=256, S_max=128)
+    # BuildGraph's exact queue (connection, box) shares cap_pairs
     with pytest.raises(_lib.PumpError) as ei:
-        _plan(free, mode, cap_pairs=100)
+        _plan(sc, mode, cap_pairs=4)
     assert ei.value.code == -2
-    need_q = _needed(ei.value, r"round pairs (\d+) exceed cap_pairs")
-    assert need_q > 100
+    need_q = _needed(ei.value, r"exact box tests (\d+) exceed cap_pairs")
+    assert need_q > 4
     # the plan store
     with pytest.raises(_lib.PumpError) as ei:
         _plan(sc, mode, cap_plans=r["n_plans"] // 3)
@@ -75,12 +75,12 @@ def test_edges_pairs_and_plans_too_small(ref, mode):
     pl.close()
     # a failed call leaves the context as it was: the same call fails the
     # same way again
-    pl = planner_for(free, cap_pairs=100)
+    pl = planner_for(sc, cap_plans=r["n_plans"] // 3)
     pl.set_explore_mode(mode)
     msgs = []
     for _ in range(2):
         with pytest.raises(_lib.PumpError) as ei:
-            pl.plan(pl.scene_problem(free))
+            pl.plan(pl.scene_problem(sc))
         msgs.append(str(ei.value))
     assert msgs[0] == msgs[1]
     pl.close()
