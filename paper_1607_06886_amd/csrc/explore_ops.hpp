@@ -262,18 +262,9 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int lo, co
     return 2;
 }
 
-// Append the wave's pairs with st == 2 (records tk) to the simulation queue.
-__device__ __forceinline__ void queue_pairs(const RoundArgs& a, int st, const SimTask& tk) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long need = __ballot(st == 2);
-    int base = 0;
-    if (lane == 0 && need) base = atomicAdd(&a.ctl->n_tasks, (int)__popcll(need));
-    base = __shfl(base, 0, 64);
-    if (st == 2) a.tasks[base + (int)__popcll(need & lanemask_lt(lane))] = tk;
-}
-
-// The same for a whole workgroup at once (all threads call it): one global
-// atomic per workgroup instead of one per wave.  s_w: [blockDim.x / 64].
+// Append the workgroup's pairs with st == 2 (records tk) to the simulation
+// queue (all threads call it): one global atomic per workgroup.
+// s_w: [blockDim.x / 64].
 __device__ __forceinline__ void queue_pairs_block(const RoundArgs& a, int st, const SimTask& tk,
                                                   int* s_w) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;

@@ -128,16 +128,99 @@ void launch_explore_init(hipStream_t s, const RoundArgs& a, int n_nodes, int N, 
 }
 
 // ---------------------------------------------------------------------------
+// Counter partials: each workgroup adds its sums to its own slots of a.part
+// (no atomics on the control block, whose one line every workgroup would
+// otherwise queue on); k_counters_reduce folds them in once a round.
+// ---------------------------------------------------------------------------
+// Sum over the workgroup, valid in thread 0 (all threads call it; s holds
+// blockDim.x / 64 entries).
+__device__ __forceinline__ long long block_sum(long long v, long long* s) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    long long t = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s[w];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ void part_add(const RoundArgs& a, int k, long long v) {
+    if (v) a.part[(size_t)blockIdx.x * kPartK + k] += v;   // this workgroup's slot
+}
+
+__global__ __launch_bounds__(1024) void k_counters_reduce(RoundArgs a, int add) {
+    __shared__ long long s[16];
+    long long v[kPartK];
+    for (int k = 0; k < kPartK; ++k) v[k] = 0;
+    for (int t = threadIdx.x; t < kPartSlots; t += blockDim.x) {
+        for (int k = 0; k < kPartK; ++k) {
+            v[k] += a.part[(size_t)t * kPartK + k];
+            a.part[(size_t)t * kPartK + k] = 0;
+        }
+    }
+    long long tot[kPartK];
+    for (int k = 0; k < kPartK; ++k) tot[k] = block_sum(v[k], s);
+    if (threadIdx.x == 0 && add) {
+        Ctl* c = a.ctl;
+        c->simulated += tot[kPartSimulated];
+        c->preprune += tot[kPartPreprune];
+        c->dropped_steps += tot[kPartDropped];
+        c->flagged += tot[kPartFlagged];
+        c->sim_waypoints += tot[kPartWaypoints];
+        c->sim_box_tests += tot[kPartBoxTests];
+        c->inserted += tot[kPartInserted];
+    }
+}
+
+void launch_counters_reduce(hipStream_t s, const RoundArgs& a) {
+    k_counters_reduce<<<1, 1024, 0, s>>>(a, 1);
+}
+
+void launch_counters_clear(hipStream_t s, const RoundArgs& a) {
+    k_counters_reduce<<<1, 1024, 0, s>>>(a, 0);
+}
+
+static int part_grid(long long n, int per_block) {
+    long long b = (n + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > kPartSlots) b = kPartSlots;
+    return (int)b;
+}
+
+// ---------------------------------------------------------------------------
 // Expansion (Alg. 4: every pair (p in B, x in N(p.head)) forms q with
 // Cost and CP_hat, then the CP cutoff): k_expand_pairs runs the first part
 // with one pair per lane and queues the pairs whose particles must be
 // simulated; k_expand_sim simulates them with one pair per wave.
+//
+// The queue records of a workgroup gather in LDS (one LDS atomic per wave)
+// and go out in one coalesced copy, behind one global atomic, whenever the
+// next pass could overfill the stage, and at the end.
 // ---------------------------------------------------------------------------
+constexpr int kTaskStage = 768;   // records staged per workgroup (24 KB)
+
+__device__ __forceinline__ void flush_tasks(const RoundArgs& a, SimTask* s_tq, int* s_tn, int* s_tb) {
+    const int n = *s_tn;   // (read after a barrier: the same in every thread)
+    if (n == 0) return;
+    if (threadIdx.x == 0) *s_tb = atomicAdd(&a.ctl->n_tasks, n);
+    __syncthreads();
+    const int b = *s_tb;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a.tasks[b + i] = s_tq[i];
+    __syncthreads();
+    if (threadIdx.x == 0) *s_tn = 0;
+    __syncthreads();
+}
+
 template <int N, int CP>
 __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
     __shared__ float s_raw[kMaxObs * 6];
     __shared__ float s_out[kMaxObs * 6];
+    __shared__ SimTask s_tq[kTaskStage];
+    __shared__ int s_tn, s_tb;
+    __shared__ long long s_ll[4];
     stage_obstacles_block(a.obs, a.n_obs, s_raw, nullptr, s_out);
+    if (threadIdx.x == 0) s_tn = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     // pairs [a.q0, q_end) of the round: all of them, or one chunk
@@ -146,25 +229,33 @@ __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
     float gl[3], gh[3];
     for (int k = 0; k < 3; ++k) { gl[k] = a.gcloud[k]; gh[k] = a.gcloud[3 + k]; }
     long long n_sim = 0, n_pre = 0, n_drop = 0;
-    const int wave_global = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int wave_stride = gridDim.x * 4;
-    for (int tile = a.q0 + wave_global * 64; tile < q_end; tile += wave_stride * 64) {
-        const int q = tile + lane;
+    // workgroup passes of 256 pairs (the same count in every thread)
+    for (int base = a.q0 + blockIdx.x * 256; base < q_end; base += gridDim.x * 256) {
+        const int tile = base + (threadIdx.x & ~63);
+        const int q = base + threadIdx.x;
         SimTask tk;
-        const int grp = wave_group_of(a.b_off, n_B, tile, q);
-        const int st = q < q_end ? expand_pair<N, CP>(a, q, grp, s_raw, s_out, gl, gh, n_sim, n_pre,
-                                                   n_drop, tk) : 0;
-        queue_pairs(a, st, tk);
+        int st = 0;
+        if (tile < q_end) {   // the wave's pairs
+            const int grp = wave_group_of(a.b_off, n_B, tile, q);
+            st = q < q_end ? expand_pair<N, CP>(a, q, grp, s_raw, s_out, gl, gh, n_sim, n_pre, n_drop,
+                                                tk) : 0;
+        }
+        const unsigned long long need = __ballot(st == 2);
+        int wb = 0;
+        if (lane == 0 && need) wb = atomicAdd(&s_tn, (int)__popcll(need));
+        wb = __shfl(wb, 0, 64);
+        if (st == 2) s_tq[wb + (int)__popcll(need & lanemask_lt(lane))] = tk;
+        __syncthreads();
+        if (s_tn > kTaskStage - 256) flush_tasks(a, s_tq, &s_tn, &s_tb);
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        n_sim += __shfl_down(n_sim, o, 64);
-        n_drop += __shfl_down(n_drop, o, 64);
-        n_pre += __shfl_down(n_pre, o, 64);
-    }
-    if (lane == 0 && !a.quiet) {
-        if (n_sim) atomicAdd((unsigned long long*)&a.ctl->simulated, (unsigned long long)n_sim);
-        if (n_pre) atomicAdd((unsigned long long*)&a.ctl->preprune, (unsigned long long)n_pre);
-        if (n_drop) atomicAdd((unsigned long long*)&a.ctl->dropped_steps, (unsigned long long)n_drop);
+    flush_tasks(a, s_tq, &s_tn, &s_tb);
+    const long long t_sim = block_sum(n_sim, s_ll);
+    const long long t_pre = block_sum(n_pre, s_ll);
+    const long long t_drop = block_sum(n_drop, s_ll);
+    if (threadIdx.x == 0 && !a.quiet) {
+        part_add(a, kPartSimulated, t_sim);
+        part_add(a, kPartPreprune, t_pre);
+        part_add(a, kPartDropped, t_drop);
     }
 }
 
@@ -174,6 +265,7 @@ template <int N, int CP>
 __global__ __launch_bounds__(256) void k_expand_sim(RoundArgs a) {
     __shared__ float s_raw[kMaxObs * 6];
     __shared__ float s_out[kMaxObs * 6];
+    __shared__ long long s_ll[4];
     stage_obstacles_block(a.obs, a.n_obs, s_raw, nullptr, s_out);
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -185,12 +277,16 @@ __global__ __launch_bounds__(256) void k_expand_sim(RoundArgs a) {
         else
             simulate_pair_box<N>(a, task, s_raw, s_out, n_pre, n_flag, n_wp, n_bt);
     }
-    // counts are wave-uniform
-    if (lane == 0 && !a.quiet) {
-        if (n_pre) atomicAdd((unsigned long long*)&a.ctl->preprune, (unsigned long long)n_pre);
-        if (n_flag) atomicAdd((unsigned long long*)&a.ctl->flagged, (unsigned long long)n_flag);
-        if (n_wp) atomicAdd((unsigned long long*)&a.ctl->sim_waypoints, (unsigned long long)n_wp);
-        if (n_bt) atomicAdd((unsigned long long*)&a.ctl->sim_box_tests, (unsigned long long)n_bt);
+    // the counts are wave-uniform: lane 0 brings them
+    const long long t_pre = block_sum(lane == 0 ? n_pre : 0, s_ll);
+    const long long t_flag = block_sum(lane == 0 ? n_flag : 0, s_ll);
+    const long long t_wp = block_sum(lane == 0 ? n_wp : 0, s_ll);
+    const long long t_bt = block_sum(lane == 0 ? n_bt : 0, s_ll);
+    if (threadIdx.x == 0 && !a.quiet) {
+        part_add(a, kPartPreprune, t_pre);
+        part_add(a, kPartFlagged, t_flag);
+        part_add(a, kPartWaypoints, t_wp);
+        part_add(a, kPartBoxTests, t_bt);
     }
 }
 
@@ -213,13 +309,12 @@ static void launch_expand_n(hipStream_t s, const RoundArgs& a, unsigned blocks, 
 
 void launch_expand(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, int part) {
     if (n_pairs <= 0) return;
-    long long waves = (n_pairs + 63) / 64;
-    long long blocks = (waves + 3) / 4;
-    if (blocks > 65536) blocks = 65536;
+    // pair stage: workgroups of 256 pairs a pass, at most kPartSlots of them
+    // (each owns a counter slot); about 4 passes each on large rounds
+    const int blocks = part_grid(n_pairs, 4 * 256);
     // the particle kernel's grid covers the worst case (every pair queued),
     // capped; its waves stride over the queue length read on the device
-    long long sim_blocks = (n_pairs + 3) / 4;
-    if (sim_blocks > 4096) sim_blocks = 4096;
+    const int sim_blocks = part_grid(n_pairs, 4);
     switch (N) {
         case 32: launch_expand_n<32>(s, a, (unsigned)blocks, (unsigned)sim_blocks, part); break;
         case 64: launch_expand_n<64>(s, a, (unsigned)blocks, (unsigned)sim_blocks, part); break;
@@ -236,6 +331,7 @@ __global__ __launch_bounds__(256) void k_stair_update(RoundArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_mark(RoundArgs a) {
+    __shared__ long long s_ll[4];
     const int n_pairs = a.ctl->n_pairs;
     const int n_open = a.ctl->n_open;
     const int total = n_pairs + n_open;
@@ -244,9 +340,8 @@ __global__ __launch_bounds__(256) void k_mark(RoundArgs a) {
         if (t < n_pairs) kept += mark_pair(a, t) ? 1 : 0;
         else mark_open(a, t - n_pairs);
     }
-    for (int o = 32; o > 0; o >>= 1) kept += __shfl_down(kept, o, 64);
-    if ((threadIdx.x & 63) == 0 && kept)
-        atomicAdd((unsigned long long*)&a.ctl->inserted, (unsigned long long)kept);
+    const long long t_kept = block_sum(kept, s_ll);
+    if (threadIdx.x == 0) part_add(a, kPartInserted, t_kept);
 }
 
 static int grid_of(long long n) {
@@ -262,10 +357,7 @@ void launch_prune(hipStream_t s, const RoundArgs& a, int N, int32_t n_pairs, int
     if (b1 < 1) b1 = 1;
     if (b1 > 16384) b1 = 16384;
     k_stair_update<<<b1, 256, 0, s>>>(a);
-    int b2 = (n_pairs + n_open + 255) / 256;
-    if (b2 < 1) b2 = 1;
-    if (b2 > 16384) b2 = 16384;
-    k_mark<<<b2, 256, 0, s>>>(a);
+    k_mark<<<part_grid((long long)n_pairs + n_open, 256), 256, 0, s>>>(a);
 }
 
 // Compaction: P_open <- (P_open \ B \ removed) U survivors.
@@ -347,13 +439,13 @@ __global__ __launch_bounds__(256) void k_compact_open_only(RoundArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_mark_chunk(RoundArgs a) {
+    __shared__ long long s_ll[4];
     const int n = a.ctl->chunk_n;
     long long kept = 0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
         kept += mark_pair(a, t) ? 1 : 0;
-    for (int o = 32; o > 0; o >>= 1) kept += __shfl_down(kept, o, 64);
-    if ((threadIdx.x & 63) == 0 && kept)
-        atomicAdd((unsigned long long*)&a.ctl->inserted, (unsigned long long)kept);
+    const long long t_kept = block_sum(kept, s_ll);
+    if (threadIdx.x == 0) part_add(a, kPartInserted, t_kept);
 }
 
 // survivors of this chunk after those of the chunks before it; nothing is
@@ -394,7 +486,7 @@ void launch_open_compact(hipStream_t s, const RoundArgs& a, int32_t n_open, int3
 }
 
 void launch_chunk_compact(hipStream_t s, const RoundArgs& a, int N, int32_t n, int32_t* blk) {
-    k_mark_chunk<<<grid_of(n), 256, 0, s>>>(a);
+    k_mark_chunk<<<part_grid(n, 256), 256, 0, s>>>(a);
     scan_exclusive(s, a.c_pos, a.c_pos, &a.ctl->chunk_n, n, &a.ctl->scan_total[0], blk);
     switch (N / 32) {
         case 1: k_compact_chunk<1><<<grid_of(n), 256, 0, s>>>(a); break;

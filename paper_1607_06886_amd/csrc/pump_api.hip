@@ -68,6 +68,7 @@ struct pump_ctx {
     uint32_t* c_mask = nullptr;
     uint8_t* c_flag = nullptr;
     int32_t* blk = nullptr;
+    long long* part = nullptr;      // [kPartSlots][kPartK] counter partials
     // grid barrier and exchange words: release word, failure flag (words 0-63),
     // arrival words [4096], then the 64-bit exchange words [2][coop_blocks]
     unsigned* coop_sync = nullptr;
@@ -188,6 +189,7 @@ RoundArgs round_args(pump_ctx* c) {
     a.c_flag = c->c_flag;
     a.c_pos = c->c_pos;
     a.tasks = c->tasks;
+    a.part = c->part;
     a.ctl = c->ctl;
     return a;
 }
@@ -332,7 +334,7 @@ int pump_destroy(pump_ctx* ctx) {
                     ctx->p_state, ctx->stair, ctx->open_a, ctx->open_b, ctx->o_keep, ctx->o_inB,
                     ctx->b_ids, ctx->b_off, ctx->b_deg, ctx->c_head, ctx->c_parent, ctx->c_edge,
                     ctx->c_step, ctx->c_pop, ctx->c_pos, ctx->tasks, ctx->c_cost, ctx->c_mask, ctx->c_flag,
-                    ctx->blk, ctx->ctl, ctx->goal_ids, ctx->front_ids, ctx->paths,
+                    ctx->blk, ctx->part, ctx->ctl, ctx->goal_ids, ctx->front_ids, ctx->paths,
                     ctx->path_len, ctx->wp_len, ctx->mc_counts, ctx->wp, ctx->sm.st,
                     ctx->sm.e_coef, ctx->sm.e_t0, ctx->sm.wp, ctx->sm.out_wp, ctx->coop_sync,
                     ctx->ra_dev};
@@ -443,6 +445,8 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     A(dalloc(&ctx->c_mask, Q * ctx->W));
     A(dalloc(&ctx->c_flag, Q));
     A(dalloc(&ctx->blk, (size_t)2 * 65536));
+    A(dalloc(&ctx->part, (size_t)kPartSlots * kPartK));
+    A(hipMemset(ctx->part, 0, sizeof(long long) * kPartSlots * kPartK));
     {
         int dev = 0;
         if (hipGetDevice(&dev) == hipSuccess) ctx->coop_blocks = coop_max_blocks(N);
@@ -667,6 +671,7 @@ static int explore_begin(pump_ctx* ctx, bool sync) {
     // (also clears the control block and the single launch's barrier words)
     launch_explore_init(ctx->stream, a, ctx->n_nodes, ctx->N, ctx->coop_sync,
                         (int)(64 + 4096 + 4 * (size_t)ctx->coop_blocks));  // writes open_next
+    launch_counters_clear(ctx->stream, a);   // (partials a failed round may have left)
     std::swap(ctx->open_cur, ctx->open_next);
     HIPCHK(hipGetLastError());
     ctx->partial_plans = 0;
@@ -752,6 +757,7 @@ int pump_explore_round(pump_ctx* ctx, int32_t* done) {
         ctx->last_chunks = chunks;
         ctx->chunked_rounds += 1;
     }
+    launch_counters_reduce(ctx->stream, a);
     long long upper = std::min<long long>((long long)n_open + n_pairs, ctx->cfg.cap_plans);
     tbeg(ctx, 6);
     launch_next_group(ctx->stream, a, (int32_t)upper, ctx->b_deg, ctx->blk);

@@ -108,6 +108,17 @@ struct SimTask {
 };
 static_assert(sizeof(SimTask) == 32, "SimTask is two 16-byte loads");
 
+// Counter partials of the per-phase Explore kernels: workgroup b of a kernel
+// adds its sums to part[b * kPartK + k] (its own slot, no atomics), and one
+// small kernel per round adds the slots into the control block and clears
+// them.  Grids of those kernels stay within kPartSlots workgroups.
+constexpr int kPartSlots = 4096;
+constexpr int kPartK = 8;
+enum PartCounter : int {
+    kPartSimulated = 0, kPartPreprune = 1, kPartDropped = 2, kPartFlagged = 3,
+    kPartWaypoints = 4, kPartBoxTests = 5, kPartInserted = 6
+};
+
 // Kernel arguments of one Explore round.
 struct RoundArgs {
     // problem
@@ -164,6 +175,9 @@ struct RoundArgs {
     // a round run in chunks (more pairs than candidate slots): pair q of the
     // round is slot q - q0 (q0 = 0 otherwise); quiet = 1 in the second pass
     // over the chunks, whose expansion adds nothing to the counters
+    // per-workgroup counter partials of the per-phase kernels
+    // ([kPartSlots][kPartK], summed into the control block once a round)
+    long long* part;
     int32_t chunked;           // 1: the launch covers pairs q0 .. q0 + ctl->chunk_n - 1
     int32_t q0;
     int32_t quiet;
@@ -270,6 +284,10 @@ void launch_stair_update(hipStream_t s, const RoundArgs& a, int32_t n);
 void launch_open_compact(hipStream_t s, const RoundArgs& a, int32_t n_open, int32_t* blk_scratch);
 void launch_chunk_compact(hipStream_t s, const RoundArgs& a, int N, int32_t n, int32_t* blk_scratch);
 void launch_chunks_finalize(hipStream_t s, const RoundArgs& a);
+// Adds the counter partials into the control block and clears them; clear
+// only drops them (start of Explore).
+void launch_counters_reduce(hipStream_t s, const RoundArgs& a);
+void launch_counters_clear(hipStream_t s, const RoundArgs& a);
 
 struct SelectArgs {
     const float* X;

@@ -2,6 +2,7 @@
 // (Alg. 3), shared by the single-query kernels and the batched engine.
 #pragma once
 
+#include "box_bins.hpp"
 #include "device_math.hpp"
 #include "pump_internal.hpp"
 
@@ -400,18 +401,87 @@ __device__ __forceinline__ void gw_near_col0(const float* __restrict__ X,
     gw_push_near(gw, ok, src, 0, tau);
 }
 
+// The quick test's 8 pieces of one connection against the boxes its range
+// meets (bit set ov, n_ov boxes), each piece's hull computed once for all of
+// them.  A hull that misses a box clears that piece for that box (as in
+// trajectory_box_pieces).  A piece whose hull lies inside a box's slabs on
+// two axes, by kHullMargin, while its end values on the third axis enclose a
+// value inside that slab by the same margin, proves a hit: the third
+// coordinate passes through its slab while the other two stay in theirs (a
+// thin wall crossed inside its extent is settled this way).  Returns true on
+// a proved hit; otherwise ov / n_ov keep the boxes that some piece's hull
+// meets without a proof (left to the quick test) and the others are missed.
+__device__ __forceinline__ bool pieces_vs_boxes(const Cubic* cs, double tau, const float* s_obs,
+                                                unsigned long long* ov, int& n_ov) {
+    constexpr int kP = 8;
+    const double inv = 1.0 / (double)kP;
+    const double h3 = (inv * tau) * (1.0 / 3.0);
+    double pa[3], da[3];
+    for (int a = 0; a < 3; ++a) {
+        pa[a] = cs[a].c0;
+        da[a] = cs[a].c1;
+    }
+    unsigned long long unres[kMaxObsWords] = {0ull, 0ull, 0ull, 0ull};
+    for (int k = 1; k <= kP; ++k) {
+        const double t = k == kP ? tau : tau * (inv * (double)k);
+        double pb[3], db[3];
+        eval_pd(cs, t, pb, db);
+        double lo[3], hi[3], emin[3], emax[3];
+        for (int a = 0; a < 3; ++a) {
+            const double b1 = pa[a] + h3 * da[a], b2 = pb[a] - h3 * db[a];
+            emin[a] = fmin(pa[a], pb[a]);
+            emax[a] = fmax(pa[a], pb[a]);
+            lo[a] = fmin(emin[a], fmin(b1, b2)) - kHullMargin;
+            hi[a] = fmax(emax[a], fmax(b1, b2)) + kHullMargin;
+        }
+        for (int w = 0; w < kMaxObsWords; ++w) {
+            unsigned long long m = ov[w];
+            while (m) {
+                const int o = w * 64 + __ffsll((long long)m) - 1;
+                const unsigned long long bit = m & (~m + 1ull);
+                m &= m - 1ull;
+                const float* bx = s_obs + o * 6;
+                bool sep = false, in[3], cr[3];
+                for (int a = 0; a < 3; ++a) {
+                    const double blo = (double)bx[a], bhi = (double)bx[3 + a];
+                    sep |= (hi[a] < blo) | (lo[a] > bhi);
+                    in[a] = (lo[a] >= blo) & (hi[a] <= bhi);
+                    const double ilo = blo + kHullMargin, ihi = bhi - kHullMargin;
+                    cr[a] = (ilo <= ihi) & (emin[a] <= ihi) & (emax[a] >= ilo);
+                }
+                if (sep) continue;
+                if ((in[0] & in[1] & cr[2]) | (in[0] & cr[1] & in[2]) | (cr[0] & in[1] & in[2]))
+                    return true;
+                unres[w] |= bit;
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            pa[a] = pb[a];
+            da[a] = db[a];
+        }
+    }
+    n_ov = 0;
+    for (int w = 0; w < kMaxObsWords; ++w) {
+        ov[w] = unres[w];
+        n_ov += __popcll(unres[w]);
+    }
+    return false;
+}
+
 // boxes over one list of connections (src, dst, tau, optional cached range).
 // Exact-queue entries name the connection by `tag` (>= 0: index into the
 // roadmap list, < 0: -1 - index into the near list).  check_valid: skip
 // connections with an invalid end (the cached roadmap list).
 //
 // Lane i of a wave takes connection i of the wave's 64 and finds the boxes
-// its range meets.  Those (connection, box) pairs are then spread over all 64
-// lanes through an LDS queue per wave, so a connection that meets many boxes
-// does not hold its wave: each pair gets the quick test, a hit blocks the
-// connection, an unsure pair goes to the exact queue; connections not blocked
-// set their bit.  Whole workgroup of kBoxThreads; s_q/s_src/s_dst/s_tau/s_blk
-// are per-wave LDS arrays (kBoxQueue, 64, 64, 64, 64 entries per wave).
+// its range meets (candidates from the workspace partition `bins`, then the
+// range test), then runs pieces_vs_boxes over them.  The (connection, box)
+// pairs that leaves open are spread over all 64 lanes through an LDS queue
+// per wave, so a connection with many of them does not hold its wave: each
+// pair gets the quick test, a hit blocks the connection, an unsure pair goes
+// to the exact queue; connections not blocked set their bit.  Whole
+// workgroup of kBoxThreads; s_q/s_src/s_dst/s_tau/s_blk are per-wave LDS
+// arrays (kBoxQueue, 64, 64, 64, 64 entries per wave).
 constexpr int kBoxThreads = 256;
 constexpr int kBoxQueue = 256;
 
@@ -427,6 +497,7 @@ __device__ __forceinline__ void gw_boxes(const float* __restrict__ X,
                                          const double* __restrict__ tau_a,
                                          const double* __restrict__ bbox, int count, bool near_list,
                                          bool check_valid, const float* s_obs, int n_obs,
+                                         const BoxBins* bins,
                                          const GraphWork& gw, uint32_t* __restrict__ ebits,
                                          int words, int gid, int stride, uint32_t* s_q,
                                          int* s_src, int* s_dst, double* s_tau, int* s_blk) {
@@ -448,45 +519,59 @@ __device__ __forceinline__ void gw_boxes(const float* __restrict__ X,
             tau = tau_a[i];
             keep = !check_valid || (valid[src] && valid[dst]);
         }
-        unsigned long long ov[kMaxObs / 64] = {0ull, 0ull, 0ull, 0ull};
+        unsigned long long ov[kMaxObsWords] = {0ull, 0ull, 0ull, 0ull};
         int n_ov = 0;
+        bool proved = false;
         if (keep) {
             if (n_obs > 0) {
                 double mn[3], mx[3];
+                Cubic cs[3];
                 if (bbox) {
                     for (int a = 0; a < 3; ++a) {
                         mn[a] = bbox[(size_t)i * 6 + a];
                         mx[a] = bbox[(size_t)i * 6 + 3 + a];
                     }
                 } else {
-                    Cubic cs[3];
                     hermite(X + (size_t)src * 6, X + (size_t)dst * 6, tau, cs);
                     for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
                 }
                 // the range rounded outwards to FP32: a box it misses in FP32
                 // the FP64 range misses too; the few it then meets that the
-                // FP64 range would not go to the exact tests, which decide
-                // them the same way
+                // FP64 range would not go to the piece and exact tests, which
+                // decide them the same way
                 float mnf[3], mxf[3];
                 for (int a = 0; a < 3; ++a) {
                     mnf[a] = __double2float_rd(mn[a]);
                     mxf[a] = __double2float_ru(mx[a]);
                 }
-                for (int o = 0; o < n_obs; ++o) {
-                    const float* bx = s_obs + o * 6;
-                    const bool disjoint = (mxf[0] < bx[0]) | (mnf[0] > bx[3]) | (mxf[1] < bx[1]) |
-                                          (mnf[1] > bx[4]) | (mxf[2] < bx[2]) | (mnf[2] > bx[5]);
-                    if (!disjoint) {
-                        ov[o >> 6] |= 1ull << (o & 63);
-                        ++n_ov;
+                unsigned long long cand[kMaxObsWords];
+                box_bins_query(bins, mnf, mxf, cand);
+                for (int w = 0; w < kMaxObsWords; ++w) {
+                    unsigned long long m = cand[w];
+                    while (m) {
+                        const int o = w * 64 + __ffsll((long long)m) - 1;
+                        m &= m - 1ull;
+                        const float* bx = s_obs + o * 6;
+                        const bool disjoint = (mxf[0] < bx[0]) | (mnf[0] > bx[3]) |
+                                              (mxf[1] < bx[1]) | (mnf[1] > bx[4]) |
+                                              (mxf[2] < bx[2]) | (mnf[2] > bx[5]);
+                        if (!disjoint) {
+                            ov[w] |= 1ull << (o & 63);
+                            ++n_ov;
+                        }
                     }
+                }
+                if (n_ov > 0) {
+                    if (bbox) hermite(X + (size_t)src * 6, X + (size_t)dst * 6, tau, cs);
+                    proved = pieces_vs_boxes(cs, tau, s_obs, ov, n_ov);
+                    if (proved) n_ov = 0;
                 }
             }
         }
         qs[lane] = src;
         qd[lane] = dst;
         qt[lane] = tau;
-        blk[lane] = 0;
+        blk[lane] = proved ? 1 : 0;
         // this lane's first pair within the wave's list
         int x = n_ov;
         for (int o = 1; o < 64; o <<= 1) {
