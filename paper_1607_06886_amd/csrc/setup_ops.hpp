@@ -325,8 +325,36 @@ __device__ __forceinline__ void gw_push_near(const GraphWork& gw, bool ok, int s
     }
 }
 
-// near: row v (whole workgroup, blockDim a multiple of 64; s_list holds
-// 2 * kNearChunk ints, s_cnt 2).  Per chunk of targets, three passes, each
+// The same for a whole workgroup (all threads call it): one global atomic
+// per workgroup and call, since every near connection of every row bumps the
+// same counter.  s_w: [blockDim.x / 64 + 1] ints of LDS.
+__device__ __forceinline__ void gw_push_near_block(const GraphWork& gw, bool ok, int src, int dst,
+                                                   double tau, int* s_w) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const unsigned long long m = __ballot(ok);
+    if (lane == 0) s_w[w] = (int)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < nw; ++k) {
+            const int c = s_w[k];
+            s_w[k] = tot;
+            tot += c;
+        }
+        s_w[nw] = tot ? atomicAdd(gw.counts + 0, tot) : 0;
+    }
+    __syncthreads();
+    const int slot = s_w[nw] + s_w[w] + (int)__popcll(m & (lane ? ((1ull << lane) - 1ull) : 0ull));
+    if (ok && slot < gw.near_cap) {
+        gw.near_src[slot] = src;
+        gw.near_dst[slot] = dst;
+        gw.near_tau[slot] = tau;
+    }
+    __syncthreads();   // s_w is reused
+}
+
+// near: row v (whole workgroup, blockDim a multiple of 64, at most 1024;
+// s_list holds 2 * kNearChunk ints, s_cnt 2 + 17).  Per chunk of targets, three passes, each
 // over a list compacted by the one before it so that no wave carries lanes
 // the pass has no work for (a few per cent of the targets pass the FP32
 // bound, so a wave of 64 targets taken in place would nearly always run the
@@ -377,7 +405,7 @@ __device__ __forceinline__ void gw_near_row(const float* __restrict__ X,
                 steer64(xv, X + (size_t)u * 6, r_steer, tau, c);
                 ok = c < r_conn && tau > kTauMin;
             }
-            gw_push_near(gw, ok, v, u, tau);
+            gw_push_near_block(gw, ok, v, u, tau, s_cnt + 2);
         }
         __syncthreads();
     }
