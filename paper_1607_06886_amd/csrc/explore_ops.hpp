@@ -32,14 +32,20 @@ __device__ __forceinline__ bool boxes_overlap(const float* lo3, const float* hi3
            (lo3[2] <= b[5]) & (hi3[2] >= b[2]);
 }
 
-// Obstacles as stored (raw), shrunk by the guard band (in) and grown by it (out).
+// Obstacles as stored (raw), grown by the guard band (out), and as centre and
+// half extent shrunk by the band (in: c xyz, h - kGuard xyz), the form the
+// particle test takes.  FP32; the rounding of c and h is far below kGuard.
 __device__ __forceinline__ void stage_obstacles_block(const float* obs, int n_obs, float* s_raw,
                                                       float* s_in, float* s_out) {
     for (int t = threadIdx.x; t < n_obs * 6; t += blockDim.x) {
         const float v = obs[t];
-        const bool is_lo = (t % 6) < 3;
+        const int a = t % 6;
+        const bool is_lo = a < 3;
         if (s_raw) s_raw[t] = v;
-        if (s_in) s_in[t] = is_lo ? v + kGuard : v - kGuard;
+        if (s_in) {
+            const float lo = is_lo ? v : obs[t - 3], hi = is_lo ? obs[t + 3] : v;
+            s_in[t] = is_lo ? 0.5f * (lo + hi) : 0.5f * (hi - lo) - kGuard;
+        }
         s_out[t] = is_lo ? v - kGuard : v + kGuard;
     }
 }
@@ -320,15 +326,6 @@ __device__ __forceinline__ void load_deviations(const float* __restrict__ D, int
     }
 }
 
-// Depth of a point in a closed box: min over axes of the distances to the two
-// faces (> 0 inside).  FP32; with positions below 16 in magnitude its error is
-// below 2^-18, far inside the guard band kGuard.
-__device__ __forceinline__ float box_depth32(float y0, float y1, float y2, const float* b) {
-    const float lo = fminf(fminf(y0 - b[0], y1 - b[1]), y2 - b[2]);
-    const float hi = fminf(fminf(b[3] - y0, b[4] - y1), b[5] - y2);
-    return fminf(lo, hi);
-}
-
 // Broadcast of lane k's double to the whole wave (wave-uniform result).
 __device__ __forceinline__ double readlane_f64(double v, int k) {
     const long long bits = __double_as_longlong(v);
@@ -343,9 +340,9 @@ __device__ __forceinline__ float readlane_f32(float v, int k) {
 
 template <int N>
 __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, const float* s_raw,
-                                                  const float* s_out, long long& n_pre,
-                                                  long long& n_flag, long long& n_wp,
-                                                  long long& n_bt) {
+                                                  const float* s_in, const float* s_out,
+                                                  long long& n_pre, long long& n_flag,
+                                                  long long& n_wp, long long& n_bt) {
     constexpr int W = N / 32;                      // u32 mask words
     constexpr int PPL = N >= 64 ? N / 64 : 1;      // particles per lane
     constexpr int LPW = 32 / PPL;                  // lanes per mask word
@@ -417,24 +414,30 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
             while (om) {
                 const int ob = c0 + __ffsll((long long)om) - 1;
                 om &= om - 1ull;
-                const float* br = s_raw + ob * 6;
-                // inside by more than the guard band: a hit, deep; within
-                // the band: decided below in FP64 (rare, so the wave
-                // branches once per box rather than once per particle)
-                uint32_t in_bits = 0u, band = 0u;
+                // u = max over axes of |y - c| - (h - g): u <= 0, inside by
+                // more than the guard band (a hit, deep); 0 < u <= 2g,
+                // within the band, decided below in FP64 (rare, so the wave
+                // branches once per box rather than once per particle).  The
+                // FP32 error of u is far below the band.
+                const float* bc = s_in + ob * 6;
+                const float cx = bc[0], cy = bc[1], cz = bc[2];
+                const float hx = bc[3], hy = bc[4], hz = bc[5];
+                uint32_t inb = 0u, bnd = 0u;
 #pragma unroll
                 for (int r = 0; r < PPL; ++r) {
-                    const float dep = box_depth32(y[r][0], y[r][1], y[r][2], br);
-                    in_bits |= (dep >= kGuard ? 1u : 0u) << r;
-                    band |= (dep >= -kGuard && dep < kGuard ? 1u : 0u) << r;
+                    const float u = fmaxf(fmaxf(fabsf(y[r][0] - cx) - hx, fabsf(y[r][1] - cy) - hy),
+                                          fabsf(y[r][2] - cz) - hz);
+                    inb |= (u <= 0.0f ? 1u : 0u) << r;
+                    bnd |= (u > 0.0f && u <= 2.0f * kGuard ? 1u : 0u) << r;
                 }
-                hm |= in_bits;
-                dm |= in_bits;
-                if (!valid_lane) band = 0u;
-                if (band) {
+                hm |= inb;
+                dm |= inb;
+                if (!valid_lane) bnd = 0u;
+                if (bnd) {
+                    const float* br = s_raw + ob * 6;
 #pragma unroll
                     for (int r = 0; r < PPL; ++r) {
-                        if (!(band & (1u << r))) continue;
+                        if (!(bnd & (1u << r))) continue;
                         double dmin = INFINITY;
 #pragma unroll
                         for (int ax = 0; ax < 3; ++ax) {
@@ -625,11 +628,10 @@ __device__ __forceinline__ void simulate_pair(const RoundArgs& a, int task, cons
                                               const float* s_in, const float* s_out,
                                               long long& n_pre, long long& n_flag, long long& n_wp,
                                               long long& n_bt) {
-    (void)s_in;
     if (a.cp_model == 1)
         simulate_pair_hsmc<N>(a, task, s_raw, n_pre, n_flag, n_wp, n_bt);
     else
-        simulate_pair_box<N>(a, task, s_raw, s_out, n_pre, n_flag, n_wp, n_bt);
+        simulate_pair_box<N>(a, task, s_raw, s_in, s_out, n_pre, n_flag, n_wp, n_bt);
 }
 
 // ---------------------------------------------------------------------------

@@ -149,11 +149,15 @@ __device__ __forceinline__ void part_add(const RoundArgs& a, int k, long long v)
     if (v) a.part[(size_t)blockIdx.x * kPartK + k] += v;   // this workgroup's slot
 }
 
-__global__ __launch_bounds__(1024) void k_counters_reduce(RoundArgs a, int add) {
-    __shared__ long long s[16];
+// kReduceBlocks workgroups, each over its share of the slots; each adds its
+// sums into the control block (a handful of atomics in all).
+constexpr int kReduceBlocks = 16;
+
+__global__ __launch_bounds__(256) void k_counters_reduce(RoundArgs a, int add) {
+    __shared__ long long s[4];
     long long v[kPartK];
     for (int k = 0; k < kPartK; ++k) v[k] = 0;
-    for (int t = threadIdx.x; t < kPartSlots; t += blockDim.x) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < kPartSlots; t += gridDim.x * blockDim.x) {
         for (int k = 0; k < kPartK; ++k) {
             v[k] += a.part[(size_t)t * kPartK + k];
             a.part[(size_t)t * kPartK + k] = 0;
@@ -163,22 +167,25 @@ __global__ __launch_bounds__(1024) void k_counters_reduce(RoundArgs a, int add) 
     for (int k = 0; k < kPartK; ++k) tot[k] = block_sum(v[k], s);
     if (threadIdx.x == 0 && add) {
         Ctl* c = a.ctl;
-        c->simulated += tot[kPartSimulated];
-        c->preprune += tot[kPartPreprune];
-        c->dropped_steps += tot[kPartDropped];
-        c->flagged += tot[kPartFlagged];
-        c->sim_waypoints += tot[kPartWaypoints];
-        c->sim_box_tests += tot[kPartBoxTests];
-        c->inserted += tot[kPartInserted];
+        auto add_ll = [](long long* dst, long long x) {
+            if (x) atomicAdd((unsigned long long*)dst, (unsigned long long)x);
+        };
+        add_ll(&c->simulated, tot[kPartSimulated]);
+        add_ll(&c->preprune, tot[kPartPreprune]);
+        add_ll(&c->dropped_steps, tot[kPartDropped]);
+        add_ll(&c->flagged, tot[kPartFlagged]);
+        add_ll(&c->sim_waypoints, tot[kPartWaypoints]);
+        add_ll(&c->sim_box_tests, tot[kPartBoxTests]);
+        add_ll(&c->inserted, tot[kPartInserted]);
     }
 }
 
 void launch_counters_reduce(hipStream_t s, const RoundArgs& a) {
-    k_counters_reduce<<<1, 1024, 0, s>>>(a, 1);
+    k_counters_reduce<<<kReduceBlocks, 256, 0, s>>>(a, 1);
 }
 
 void launch_counters_clear(hipStream_t s, const RoundArgs& a) {
-    k_counters_reduce<<<1, 1024, 0, s>>>(a, 0);
+    k_counters_reduce<<<kReduceBlocks, 256, 0, s>>>(a, 0);
 }
 
 static int part_grid(long long n, int per_block) {
@@ -264,9 +271,10 @@ __global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
 template <int N, int CP>
 __global__ __launch_bounds__(256) void k_expand_sim(RoundArgs a) {
     __shared__ float s_raw[kMaxObs * 6];
+    __shared__ float s_in[kMaxObs * 6];
     __shared__ float s_out[kMaxObs * 6];
     __shared__ long long s_ll[4];
-    stage_obstacles_block(a.obs, a.n_obs, s_raw, nullptr, s_out);
+    stage_obstacles_block(a.obs, a.n_obs, s_raw, s_in, s_out);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int n_tasks = a.ctl->n_tasks;
@@ -275,7 +283,7 @@ __global__ __launch_bounds__(256) void k_expand_sim(RoundArgs a) {
         if (CP == 1)
             simulate_pair_hsmc<N>(a, task, s_raw, n_pre, n_flag, n_wp, n_bt);
         else
-            simulate_pair_box<N>(a, task, s_raw, s_out, n_pre, n_flag, n_wp, n_bt);
+            simulate_pair_box<N>(a, task, s_raw, s_in, s_out, n_pre, n_flag, n_wp, n_bt);
     }
     // the counts are wave-uniform: lane 0 brings them
     const long long t_pre = block_sum(lane == 0 ? n_pre : 0, s_ll);
