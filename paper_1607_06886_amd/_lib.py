@@ -7,8 +7,10 @@ structures and reads results back.  It raises if the built library is absent.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -107,6 +109,31 @@ TIMING_KINDS = ["deviation", "graph_mark", "graph_fill", "expand", "prune", "com
                 "next_group", "select_front", "mc", "explore_single", "ph_expand",
                 "ph_simulate", "ph_stair", "ph_mark", "ph_compact", "ph_next_group",
                 "ph_group", "smooth", "expand_sim"]
+
+
+# Contexts, roadmaps, batches and MLPs still open; closed by an exit handler
+# registered after torch's (exit handlers run last-registered first), so the
+# library frees its device memory, events and pinned buffers while the HIP
+# runtime is whole rather than from object finalisers during interpreter
+# teardown.
+_LIVE = weakref.WeakSet()
+_EXIT_HOOKED = False
+
+
+def _close_all():
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+def _track(obj):
+    global _EXIT_HOOKED
+    if not _EXIT_HOOKED:
+        atexit.register(_close_all)
+        _EXIT_HOOKED = True
+    _LIVE.add(obj)
 
 
 def load(path: Optional[str] = None):
@@ -253,6 +280,7 @@ class Planner:
         if rc != 0:
             raise PumpError(rc, "pump_create failed")
         self._keep = []
+        _track(self)
 
     def close(self):
         if self.ctx:
@@ -500,6 +528,7 @@ class MLP:
             raise PumpError(rc, "pump_mlp_create failed")
         self.n_params = self.lib.pump_mlp_num_params()
         self.max_batch = int(max_batch)
+        _track(self)
 
     def close(self):
         if self.m:
@@ -646,6 +675,7 @@ class Roadmap:
                                           s, ctypes.byref(self.rm))
         if rc != 0:
             raise PumpError(rc, "pump_roadmap_create failed")
+        _track(self)
 
     def info(self):
         n, e, ms = _i32(0), _i64(0), _f(0.0)
@@ -681,6 +711,7 @@ class Batch:
         if rc != 0:
             raise PumpError(rc, "pump_batch_create failed")
         self._keep = []
+        _track(self)
 
     def close(self):
         if self.b:

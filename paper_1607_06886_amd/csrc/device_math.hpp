@@ -32,7 +32,26 @@ __device__ __forceinline__ BSums boundary_sums(const float* x0, const float* x1)
 }
 
 __device__ __forceinline__ double cost_of(double t, const BSums& s, double r) {
-    return t + r * (12.0 * s.pp / (t * t * t) - 12.0 * s.pv / (t * t) + 4.0 * s.vv / t);
+    const double it = 1.0 / t;
+    return t + r * (it * (it * (12.0 * s.pp * it - 12.0 * s.pv) + 4.0 * s.vv));
+}
+
+// a / b for a Newton or Halley step: the hardware reciprocal refined by one
+// Newton step (relative error far below what the step needs; the iteration's
+// fixed point, where the numerator vanishes, does not depend on it).
+__device__ __forceinline__ double step_div(double a, double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, 1.0), r, r);
+    return a * r;
+}
+
+// An upper bound of the cube root of x >= 0 (for root bounds, where any
+// larger value also bounds): an FP32 estimate raised by 0.1 %, far above its
+// error; below 1e-30 the bound 1e-10, above 1e30 the FP64 cube root.
+__device__ __forceinline__ double cbrt_upper(double x) {
+    if (!(x >= 1e-30)) return 1e-10;
+    if (x > 1e30) return cbrt(x);
+    return (double)exp2f(log2f((float)x) * (1.0f / 3.0f)) * 1.001;
 }
 
 // Stationarity of c: f(t) = t^4 + a2 t^2 + a1 t + a0 with a2 = -4 r S_vv <= 0,
@@ -65,7 +84,7 @@ __device__ __forceinline__ double bracket_root(const Quartic& q, int which, doub
         if (v == 0.0) return t;
         if ((v < 0.0) == rising) lo = t; else hi = t;
         const double d = h1(t);
-        const double tn = t - 2.0 * v * d / (2.0 * d * d - v * h2(t));
+        const double tn = t - step_div(2.0 * v * d, 2.0 * d * d - v * h2(t));
         if (fabs(tn - t) <= 4.0 * 2.220446049250313e-16 * fabs(t)) return tn;
         const double tb = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
         if (tb == t || !(hi > lo)) break;
@@ -74,6 +93,17 @@ __device__ __forceinline__ double bracket_root(const Quartic& q, int which, doub
         t = tb;
     }
     return t;
+}
+
+// Which branch steer64 takes for these boundary sums: true when f' >= 0 at its
+// inflection point ti, so f has one upward crossing and one root solve
+// settles it; false for the branch with up to four root solves.  (The same
+// arithmetic as steer64, so the two always agree.)
+__device__ __forceinline__ bool steer_one_root(const BSums& s, double r) {
+    if (s.pp == 0.0 && s.vv == 0.0) return true;
+    const Quartic q{-4.0 * r * s.vv, 24.0 * r * s.pv, -36.0 * r * s.pp};
+    const double ti = sqrt(-q.a2 * (1.0 / 6.0));
+    return q.g(ti) >= 0.0;
 }
 
 // Optimal duration and cost of the connection x0 -> x1 (FP64).  The global
@@ -88,9 +118,10 @@ __device__ __forceinline__ void steer64(const float* x0, const float* x1, double
     if (s.pp == 0.0 && s.vv == 0.0) { tau = 0.0; cost = 0.0; return; }
     Quartic q{-4.0 * r * s.vv, 24.0 * r * s.pv, -36.0 * r * s.pp};
     // Fujiwara bound on the roots of f and of f'/4
-    double Bf = 2.0 * fmax(fmax(sqrt(fabs(q.a2)), cbrt(fabs(q.a1))), sqrt(sqrt(0.5 * fabs(q.a0))));
-    double Bg = 2.0 * fmax(sqrt(0.5 * fabs(q.a2)), cbrt(0.25 * fabs(q.a1)));
-    double ti = sqrt(-q.a2 / 6.0);
+    // (cube roots raised to an upper bound: the bounds only need to bound)
+    double Bf = 2.0 * fmax(fmax(sqrt(fabs(q.a2)), cbrt_upper(fabs(q.a1))), sqrt(sqrt(0.5 * fabs(q.a0))));
+    double Bg = 2.0 * fmax(sqrt(0.5 * fabs(q.a2)), cbrt_upper(0.25 * fabs(q.a1)));
+    double ti = sqrt(-q.a2 * (1.0 / 6.0));
     double cand[2];
     int nc = 0;
     if (q.g(ti) >= 0.0) {

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kBoxThreads, 2) void k_b_gw_boxes_rm(BatchQuery* qs
 
 __global__ __launch_bounds__(kNearThreads) void k_b_gw_near_rows(BatchQuery* qs) {
     __shared__ int s_list[2 * kNearChunk];
-    __shared__ int s_cnt[2 + 17];
+    __shared__ int s_cnt[3 + 17];
     BatchQuery& Q = qs[blockIdx.y];
     if ((int)blockIdx.x >= Q.n_nodes || (Q.use_rm && blockIdx.x > 0)) return;
     gw_near_row(Q.X, Q.valid, Q.n_nodes, blockIdx.x, Q.r_steer, Q.r_conn, graph_work(Q), s_list,

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kNearThreads) void k_gw_near_rows(const float* __re
                                                       int row0, double r_steer, double r_conn,
                                                       GraphWork gw) {
     __shared__ int s_list[2 * kNearChunk];
-    __shared__ int s_cnt[2 + 17];
+    __shared__ int s_cnt[3 + 17];
     gw_near_row(X, valid, n, row0 + blockIdx.x, r_steer, r_conn, gw, s_list, s_cnt);
 }
 

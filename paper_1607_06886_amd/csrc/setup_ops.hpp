@@ -354,14 +354,16 @@ __device__ __forceinline__ void gw_push_near_block(const GraphWork& gw, bool ok,
 }
 
 // near: row v (whole workgroup, blockDim a multiple of 64, at most 1024;
-// s_list holds 2 * kNearChunk ints, s_cnt 2 + 17).  Per chunk of targets, three passes, each
-// over a list compacted by the one before it so that no wave carries lanes
-// the pass has no work for (a few per cent of the targets pass the FP32
-// bound, so a wave of 64 targets taken in place would nearly always run the
-// FP64 test, and the root solve, for one or two lanes):
+// s_list holds 2 * kNearChunk ints, s_cnt 3 + 17).  Per chunk of targets,
+// three passes, each over a list compacted by the one before it so that no
+// wave carries lanes the pass has no work for (a few per cent of the targets
+// pass the FP32 bound, so a wave of 64 targets taken in place would nearly
+// always run the FP64 test, and the root solve, for one or two lanes):
 //   1. the FP32 first look at the Bernstein bound over every target;
 //   2. the FP64 rejection test over the targets it could not settle;
-//   3. the root solve (tau*, c*) over the targets that test keeps.
+//   3. the root solve (tau*, c*) over the targets that test keeps, those
+//      whose solve takes steer64's one-root branch listed first and the
+//      others from the end of the list, so that a wave runs one branch.
 __device__ __forceinline__ void gw_near_row(const float* __restrict__ X,
                                             const uint8_t* __restrict__ valid, int n, int v,
                                             double r_steer, double r_conn, const GraphWork& gw,
@@ -376,6 +378,7 @@ __device__ __forceinline__ void gw_near_row(const float* __restrict__ X,
         if (threadIdx.x == 0) {
             s_cnt[0] = 0;
             s_cnt[1] = 0;
+            s_cnt[2] = 0;
         }
         __syncthreads();
         for (int u = c0 + threadIdx.x; u < c0 + kNearChunk && u < n; u += blockDim.x) {
@@ -389,23 +392,29 @@ __device__ __forceinline__ void gw_near_row(const float* __restrict__ X,
         const int cnt1 = s_cnt[0];
         for (int i = threadIdx.x; i < cnt1; i += blockDim.x) {
             const int u = s_l1[i];
-            if (!surely_not_near(boundary_sums(xv, X + (size_t)u * 6), r_steer, r_conn))
-                s_l2[atomicAdd(&s_cnt[1], 1)] = u;
+            const BSums bs = boundary_sums(xv, X + (size_t)u * 6);
+            if (!surely_not_near(bs, r_steer, r_conn)) {
+                if (steer_one_root(bs, r_steer))
+                    s_l2[atomicAdd(&s_cnt[1], 1)] = u;
+                else
+                    s_l2[kNearChunk - 1 - atomicAdd(&s_cnt[2], 1)] = u;
+            }
         }
         __syncthreads();
-        const int cnt2 = s_cnt[1];
+        const int n_one = s_cnt[1], n_many = s_cnt[2];
+        const int cnt2 = n_one + n_many;
         for (int base = 0; base < cnt2; base += blockDim.x) {
             const int i = base + threadIdx.x;
             bool ok = false;
             int u = 0;
             double tau = 0.0;
             if (i < cnt2) {
-                u = s_l2[i];
+                u = s_l2[i < n_one ? i : kNearChunk - n_many + (i - n_one)];
                 double c;
                 steer64(xv, X + (size_t)u * 6, r_steer, tau, c);
                 ok = c < r_conn && tau > kTauMin;
             }
-            gw_push_near_block(gw, ok, v, u, tau, s_cnt + 2);
+            gw_push_near_block(gw, ok, v, u, tau, s_cnt + 3);
         }
         __syncthreads();
     }
