@@ -226,14 +226,16 @@ struct Cubic {
 };
 
 __device__ __forceinline__ void hermite(const float* x0, const float* x1, double tau, Cubic* out) {
+    const double it = 1.0 / tau;   // one division for all six coefficients
+    const double it2 = it * it, it3 = it2 * it;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double p0 = (double)x0[a], v0 = (double)x0[3 + a], v1 = (double)x1[3 + a];
         double P = (double)x1[a] - p0;
         out[a].c0 = p0;
         out[a].c1 = v0;
-        out[a].c2 = (3.0 * P - (2.0 * v0 + v1) * tau) / (tau * tau);
-        out[a].c3 = (-2.0 * P + (v0 + v1) * tau) / (tau * tau * tau);
+        out[a].c2 = (3.0 * P - (2.0 * v0 + v1) * tau) * it2;
+        out[a].c3 = (-2.0 * P + (v0 + v1) * tau) * it3;
     }
 }
 

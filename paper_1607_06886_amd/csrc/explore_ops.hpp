@@ -233,8 +233,9 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int lo, co
     }
     unsigned near = 0u;
     if (any) {
+        const double dtk = tau / (double)K;   // waypoint spacing
         for (int k = 1; k <= K; ++k) {
-            const double t = ((double)k * tau) / (double)K;
+            const double t = (double)k * dtk;
             const float* cl = a.cloud + (size_t)(s_p + k) * 6;
             float lo3[3], hi3[3];
             for (int ax = 0; ax < 3; ++ax) {
@@ -378,7 +379,7 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
         Cubic cs[3];
         hermite(a.X + (size_t)hj * 6, a.X + (size_t)xj * 6, tj, cs);
         if (lane < Kj) {
-            const double t = ((double)(lane + 1) * tj) / (double)Kj;
+            const double t = (double)(lane + 1) * (tj / (double)Kj);
             const float* cl = a.cloud + (size_t)(spj + lane + 1) * 6;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
@@ -392,11 +393,9 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
     uint32_t hm = 0u, dm = 0u, nm = 0u;           // per particle r: hit, deep, near a face
     // one marked waypoint k with its deviations d (the next one's are in flight)
     auto test_waypoint = [&](const float (&d)[PPL][3], int kk) {
-        double nom64[3];
         float nom32[3], lo3[3], hi3[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            nom64[ax] = readlane_f64(my_nom[ax], kk - 1);
             nom32[ax] = readlane_f32(my_n32[ax], kk - 1);
             lo3[ax] = readlane_f32(my_lo[ax], kk - 1);
             hi3[ax] = readlane_f32(my_hi[ax], kk - 1);
@@ -433,7 +432,11 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
                 hm |= inb;
                 dm |= inb;
                 if (!valid_lane) bnd = 0u;
-                if (bnd) {
+                if (__ballot(bnd != 0u)) {
+                    // the FP64 nominal point only where some particle needs it
+                    double nom64[3];
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax) nom64[ax] = readlane_f64(my_nom[ax], kk - 1);
                     const float* br = s_raw + ob * 6;
 #pragma unroll
                     for (int r = 0; r < PPL; ++r) {
