@@ -15,7 +15,46 @@ __global__ __launch_bounds__(1024) void k_goal_front(SelectArgs a) {
     front_block(a, kMaxFront);
 }
 
-void launch_select_front(hipStream_t s, const SelectArgs& a) { k_goal_front<<<1, 1024, 0, s>>>(a); }
+// The same with P_goal gathered by the whole device (plan stores of many
+// plans): flags, an exclusive scan over them in plan order, a scatter; the
+// goal list is the one goal_collect_block writes.
+__device__ __forceinline__ bool is_goal_plan(const SelectArgs& a, int p) {
+    return a.p_state[p] != kRemoved && a.goal[a.p_head[p]];
+}
+
+__global__ __launch_bounds__(256) void k_goal_flags(SelectArgs a, int32_t* flag) {
+    const int n = a.ctl->n_plans;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
+        flag[p] = is_goal_plan(a, p) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_goal_scatter(SelectArgs a, const int32_t* pos) {
+    const int n = a.ctl->n_plans;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
+        if (is_goal_plan(a, p) && pos[p] < kMaxGoal) a.goal_ids[pos[p]] = p;
+}
+
+__global__ __launch_bounds__(1024) void k_front(SelectArgs a) {
+    for (int f = threadIdx.x; f < kMaxFront; f += blockDim.x) a.mc_counts[f] = 0;
+    front_block(a, kMaxFront);
+}
+
+// Below this many plans (or when the count is not known on the host) one
+// workgroup gathers P_goal; above it the device-wide gather is faster.
+constexpr int32_t kGoalGatherWide = 1 << 16;
+
+void launch_select_front(hipStream_t s, const SelectArgs& a, int32_t* scratch, int32_t* blk) {
+    if (a.n_plans < kGoalGatherWide) {
+        k_goal_front<<<1, 1024, 0, s>>>(a);
+        return;
+    }
+    int b = (a.n_plans + 255) / 256;
+    if (b > 4096) b = 4096;
+    k_goal_flags<<<b, 256, 0, s>>>(a, scratch);
+    scan_exclusive(s, scratch, scratch, &a.ctl->n_plans, a.n_plans, &a.ctl->n_goal, blk);
+    k_goal_scatter<<<b, 256, 0, s>>>(a, scratch);
+    k_front<<<1, 1024, 0, s>>>(a);
+}
 
 // One wave per path (waypoints_wave).
 __global__ __launch_bounds__(64) void k_waypoints(SelectArgs a, int n_paths) {

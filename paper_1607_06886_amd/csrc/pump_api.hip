@@ -973,7 +973,7 @@ static int select_impl(pump_ctx* ctx, pump_result* out, bool explore_pending) {
     // the whole of Alg. 5 on the device (front, waypoints, Monte Carlo,
     // bisection), then one read-back of the control block
     tbeg(ctx, 7);
-    launch_select_front(ctx->stream, a);
+    launch_select_front(ctx->stream, a, ctx->o_keep, ctx->blk);
     tend(ctx);
     launch_waypoints(ctx->stream, a, -1);
     tbeg(ctx, 8);

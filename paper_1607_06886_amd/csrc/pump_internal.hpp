@@ -458,7 +458,9 @@ void launch_batch(hipStream_t s, BatchQuery* qs_dev, int q, int N_max, int max_n
 // Workgroups of the batched Explore kernel for N that fit on one CU at once.
 int batch_explore_per_cu(int N, int threads);
 
-void launch_select_front(hipStream_t s, const SelectArgs& a);
+// P_goal and its front; scratch: an int per plan (free after Explore), blk:
+// the scan's block scratch.
+void launch_select_front(hipStream_t s, const SelectArgs& a, int32_t* scratch, int32_t* blk);
 // n_paths < 0: the front just built (its size read on the device).
 void launch_waypoints(hipStream_t s, const SelectArgs& a, int32_t n_paths);
 void launch_mc(hipStream_t s, const SelectArgs& a, int32_t n_paths);

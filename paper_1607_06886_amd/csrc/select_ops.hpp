@@ -64,55 +64,85 @@ __device__ __forceinline__ bool front_less(const SelectArgs& a, int fa, int fb) 
 }
 
 // Whole block; `max_front` bounds the front kept (kMaxFront or less).
+// The dominance test takes the goal plans' (cost, pop) in LDS tiles; the
+// front's paths are rebuilt by a thread each, ordered by one thread on an
+// index array, and rebuilt once more in that order (no path is moved).
+constexpr int kFrontTile = 256;
+
 __device__ __forceinline__ void front_block(const SelectArgs& a, int max_front) {
     __shared__ int s_flag[kMaxFront];
+    __shared__ int s_ord[kMaxFront];
+    __shared__ double s_c[kFrontTile];
+    __shared__ int s_k[kFrontTile];
     __shared__ int s_n;
     const int G = a.ctl->n_goal < kMaxGoal ? a.ctl->n_goal : kMaxGoal;
     if (threadIdx.x == 0) s_n = 0;
-    __syncthreads();
-    for (int g = threadIdx.x; g < G; g += blockDim.x) {
-        const int p = a.goal_ids[g];
-        const double c = a.p_cost[p];
-        const int k = a.p_pop[p];
-        bool dom = false;
-        for (int h = 0; h < G && !dom; ++h) {
-            const int d = a.goal_ids[h];
-            dom = (c > a.p_cost[d]) && (k >= a.p_pop[d]);
+    for (int g0 = 0; g0 < G; g0 += blockDim.x) {   // (the same trip count in every thread)
+        const int g = g0 + threadIdx.x;
+        const bool have = g < G;
+        double c = 0.0;
+        int k = 0;
+        if (have) {
+            const int p = a.goal_ids[g];
+            c = a.p_cost[p];
+            k = a.p_pop[p];
         }
-        if (!dom) {
+        bool dom = false;
+        for (int h0 = 0; h0 < G; h0 += kFrontTile) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < kFrontTile && h0 + t < G; t += blockDim.x) {
+                const int d = a.goal_ids[h0 + t];
+                s_c[t] = a.p_cost[d];
+                s_k[t] = a.p_pop[d];
+            }
+            __syncthreads();
+            const int hn = min(kFrontTile, G - h0);
+            if (have)
+                for (int h = 0; h < hn && !dom; ++h) dom = (c > s_c[h]) && (k >= s_k[h]);
+        }
+        if (have && !dom) {
             const int slot = atomicAdd(&s_n, 1);
             if (slot < max_front) s_flag[slot] = g;
         }
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
     const int n = s_n < max_front ? s_n : max_front;
-    if (s_n > max_front) a.ctl->err = 2;
-    // deterministic order of discovery: sort slots by goal index
-    for (int i = 1; i < n; ++i) {
-        const int v = s_flag[i];
-        int j = i - 1;
-        while (j >= 0 && s_flag[j] > v) { s_flag[j + 1] = s_flag[j]; --j; }
-        s_flag[j + 1] = v;
-    }
-    const int stride = a.S_max + 1;
-    for (int f = 0; f < n; ++f) {
-        a.front_ids[f] = a.goal_ids[s_flag[f]];
-        a.path_len[f] = path_of(a, a.front_ids[f], a.paths + (size_t)f * stride, stride);
-    }
-    // insertion sort of the front (entries carry their paths)
-    for (int i = 1; i < n; ++i) {
-        int j = i;
-        while (j > 0 && front_less(a, j, j - 1)) {
-            int t = a.front_ids[j]; a.front_ids[j] = a.front_ids[j - 1]; a.front_ids[j - 1] = t;
-            int l = a.path_len[j]; a.path_len[j] = a.path_len[j - 1]; a.path_len[j - 1] = l;
-            int* xa = a.paths + (size_t)j * stride;
-            int* xb = a.paths + (size_t)(j - 1) * stride;
-            for (int k = 0; k < stride; ++k) { int u = xa[k]; xa[k] = xb[k]; xb[k] = u; }
-            --j;
+    if (threadIdx.x == 0) {
+        if (s_n > max_front) a.ctl->err = 2;
+        // deterministic order of discovery: sort slots by goal index
+        for (int i = 1; i < n; ++i) {
+            const int v = s_flag[i];
+            int j = i - 1;
+            while (j >= 0 && s_flag[j] > v) { s_flag[j + 1] = s_flag[j]; --j; }
+            s_flag[j + 1] = v;
         }
     }
-    a.ctl->n_front = n;
+    __syncthreads();
+    const int stride = a.S_max + 1;
+    for (int f = threadIdx.x; f < n; f += blockDim.x) {
+        a.front_ids[f] = a.goal_ids[s_flag[f]];
+        a.path_len[f] = path_of(a, a.front_ids[f], a.paths + (size_t)f * stride, stride);
+        s_ord[f] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // insertion sort of the front's indices (pop, then cost, then path)
+        for (int i = 1; i < n; ++i) {
+            const int v = s_ord[i];
+            int j = i - 1;
+            while (j >= 0 && front_less(a, v, s_ord[j])) { s_ord[j + 1] = s_ord[j]; --j; }
+            s_ord[j + 1] = v;
+        }
+    }
+    __syncthreads();
+    int id[(kMaxFront + 63) / 64];   // this thread's entries in the sorted order
+    for (int f = threadIdx.x, r = 0; f < n; f += blockDim.x, ++r) id[r] = a.front_ids[s_ord[f]];
+    __syncthreads();
+    for (int f = threadIdx.x, r = 0; f < n; f += blockDim.x, ++r) {
+        a.front_ids[f] = id[r];
+        a.path_len[f] = path_of(a, id[r], a.paths + (size_t)f * stride, stride);
+    }
+    if (threadIdx.x == 0) a.ctl->n_front = n;
 }
 
 // Nominal tracking waypoints of path f (step 0 = the first node's position):

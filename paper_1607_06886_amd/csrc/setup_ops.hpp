@@ -735,21 +735,31 @@ __device__ __forceinline__ void graph_fill_dev(int n, const uint32_t* __restrict
                                                     const int32_t* __restrict__ row_ptr,
                                                     int32_t* __restrict__ col,
                                                     int32_t* __restrict__ esrc, int words) {
+    // one wave per row, one 32-bit word of the row per lane and pass: the
+    // lanes' bit counts scanned across the wave give each lane its first
+    // slot, and the lane writes its word's columns in ascending order
     const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (v >= n) return;
     int pos = row_ptr[v];
-    for (int base = 0; base < n; base += 64) {
-        uint32_t w = ebits[(size_t)v * words + base / 32 + (lane >> 5)];
-        bool e = (w >> (lane & 31)) & 1u;
-        unsigned long long b = __ballot(e);
-        if (e) {
-            unsigned long long below = lane ? (b & ((1ull << lane) - 1ull)) : 0ull;
-            int at = pos + (int)__popcll(below);
-            col[at] = base + lane;
-            esrc[at] = v;
+    for (int w0 = 0; w0 < words; w0 += 64) {
+        const int w = w0 + lane;
+        uint32_t bits = w < words ? ebits[(size_t)v * words + w] : 0u;
+        const int c = __popc(bits);
+        int x = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
         }
-        pos += (int)__popcll(b);
+        int at = pos + x - c;
+        while (bits) {
+            const int b = __ffs((int)bits) - 1;
+            bits &= bits - 1u;
+            col[at] = w * 32 + b;
+            esrc[at] = v;
+            ++at;
+        }
+        pos += __shfl(x, 63, 64);
     }
 }
 
