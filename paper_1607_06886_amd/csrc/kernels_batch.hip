@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_b_gw_near_col0(BatchQuery* qs) {
                  graph_work(Q));
 }
 
-__global__ __launch_bounds__(kBoxThreads, 2) void k_b_gw_boxes_rm(BatchQuery* qs) {
+__global__ __launch_bounds__(kBoxThreads, 3) void k_b_gw_boxes_rm(BatchQuery* qs) {
     __shared__ float s_obs[kMaxObs * 6];
     __shared__ uint32_t s_q[kBoxThreads / 64 * kBoxQueue];
     __shared__ int s_src[kBoxThreads], s_dst[kBoxThreads], s_blk[kBoxThreads];
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kNearThreads) void k_b_gw_near_rows(BatchQuery* qs)
                 s_cnt);
 }
 
-__global__ __launch_bounds__(kBoxThreads, 2) void k_b_gw_boxes(BatchQuery* qs) {
+__global__ __launch_bounds__(kBoxThreads, 3) void k_b_gw_boxes(BatchQuery* qs) {
     __shared__ float s_obs[kMaxObs * 6];
     __shared__ uint32_t s_q[kBoxThreads / 64 * kBoxQueue];
     __shared__ int s_src[kBoxThreads], s_dst[kBoxThreads], s_blk[kBoxThreads];

@@ -104,7 +104,10 @@ __global__ __launch_bounds__(256) void k_gw_near_col0(const float* __restrict__ 
 }
 
 // boxes over the near list (count on the device) or a cached list (count given)
-__global__ __launch_bounds__(kBoxThreads, 2) void k_gw_boxes(const float* __restrict__ X,
+// (three waves per SIMD: the compiler spills about 40 VGPRs there, which
+// measured faster than two waves without spills -- indoor query, pass 1
+// 7.36 -> 6.96 ms -- and than four waves with more spills)
+__global__ __launch_bounds__(kBoxThreads, 3) void k_gw_boxes(const float* __restrict__ X,
                                                           const uint8_t* __restrict__ valid,
                                                           const int32_t* __restrict__ src,
                                                           const int32_t* __restrict__ dst,
