@@ -40,8 +40,8 @@ __global__ __launch_bounds__(1024) void k_front(SelectArgs a) {
 }
 
 // Below this many plans (or when the count is not known on the host) one
-// workgroup gathers P_goal; above it the device-wide gather is faster.
-constexpr int32_t kGoalGatherWide = 1 << 16;
+// workgroup gathers P_goal; from it on the device-wide gather is faster.
+constexpr int32_t kGoalGatherWide = 1 << 14;
 
 void launch_select_front(hipStream_t s, const SelectArgs& a, int32_t* scratch, int32_t* blk) {
     if (a.n_plans < kGoalGatherWide) {

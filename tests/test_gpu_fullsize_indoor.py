@@ -129,3 +129,26 @@ def test_front_order_and_certification_counts(run):
         assert res["status"] == 1
     else:
         assert res["status"] == 0 and res["best"] == front.index(best)
+
+
+def test_front_is_the_pareto_front_of_the_goal_plans(run):
+    """P_goal and its Pareto front recomputed on the host from the plan
+    store: the goal plans are the plans not removed whose head is a goal
+    sample, and the front keeps those no other goal plan dominates (strictly
+    cheaper with cp_hat no larger).  At this size (2^14 plans or more) the
+    library gathers P_goal over the whole device; the smaller queries of the
+    other tests take the one-workgroup gather."""
+    sc, res, st = run["sc"], run["res"], run["st"]
+    ids, _ = run["front"]
+    n_plans = len(st["cost"])
+    assert n_plans == res["n_plans"] >= 1 << 14
+    V = np.concatenate([sc.x_init[None], sc.samples]).astype(np.float64)
+    gl = sc.goal.astype(np.float64)
+    valid = ~ogr.points_in_boxes(V[:, :3], sc.obstacles)
+    is_goal = np.all((V[:, :3] >= gl[:3]) & (V[:, :3] <= gl[3:]), axis=1) & valid
+    goal = np.nonzero((st["state"] != 2) & is_goal[st["head"]])[0]
+    assert res["n_goal_plans"] == len(goal)
+    c, k = st["cost"][goal], st["pop"][goal]
+    dominated = np.array([np.any((c < c[i]) & (k <= k[i])) for i in range(len(goal))])
+    assert sorted(goal[~dominated].tolist()) == sorted(int(i) for i in ids)
+
