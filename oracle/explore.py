@@ -262,7 +262,7 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
     goal = np.zeros(V.shape[0], bool)
     goal[np.asarray(goal_nodes, np.int64)] = True
     stats = dict(partial_plans=0, inserted=0, rounds=0, iterations=0,
-                 dropped_steps=0, flagged_particles=0)
+                 dropped_steps=0, flagged_particles=0, flagged_below_cut=0)
     hs_cache = {}
     rounds = []
     t_start = time.perf_counter()
@@ -301,6 +301,9 @@ def explore(V, graph, D, boxes, goal_nodes, alpha_min, alpha_max, lam, r_n, dt,
                 continue
             cp_hat = mask[q].sum() / N
             if cp_hat < alpha_max:                      # CP cutoff
+                # flagged decisions of the pairs that pass the cutoff (a
+                # diagnostic count only; the rest of the run ignores it)
+                stats["flagged_below_cut"] += int(flagged[q].sum())
                 pf = parents[q].fmask
                 plan = Plan(nodes=parents[q].nodes + (int(x[q]),), cost=float(cost[q]),
                             step=int(step[q]), mask=mask[q].copy(), parent=parent_ids[q],

@@ -357,7 +357,6 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
     const int Kj = max(1, (int)ceil(tj / a.dt));
     const int spj = tk.s_p;
     unsigned wm = tk.near;                         // non-zero for a queued pair
-    n_wp += __popc(wm);
     // loads that do not depend on the waypoint loop, issued first
     int k = __ffs((int)wm);
     float dc[PPL][3], dn[PPL][3];
@@ -393,6 +392,7 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
     uint32_t hm = 0u, dm = 0u, nm = 0u;           // per particle r: hit, deep, near a face
     // one marked waypoint k with its deviations d (the next one's are in flight)
     auto test_waypoint = [&](const float (&d)[PPL][3], int kk) {
+        ++n_wp;
         float nom32[3], lo3[3], hi3[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -464,19 +464,36 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
     // between dc and dn without copies
     // (the next load is issued unconditionally -- the last waypoint reloads
     // its own row -- so no branch has to wait for it before merging)
+    //
+    // Once the pair's count (the parent's bits and the hits so far) reaches
+    // c_cut the pair is cut whatever the remaining waypoints add, so the loop
+    // stops there: a cut pair's count is then some value >= c_cut rather than
+    // its full count.
+    uint32_t pml = 0u;   // the parent's bits of this lane's particles
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        if (w == lane / LPW) pml = (pm[w] >> ((lane * PPL) & 31)) & ((1u << PPL) - 1u);
+    if (!valid_lane) pml = 0u;
+    auto reached_cut = [&]() {
+        const uint32_t b = valid_lane ? (hm | pml) : 0u;
+        int cnt = 0;
+#pragma unroll
+        for (int r = 0; r < PPL; ++r) cnt += (int)__popcll(__ballot((b >> r) & 1u));
+        return cnt >= c_cut;
+    };
     for (;;) {
         unsigned rest = wm & (wm - 1u);
         int kn = rest ? __ffs((int)rest) : 0;
         load_deviations<N>(a.D, spj + (kn ? kn : k), lane, dn);
         test_waypoint(dc, k);
-        if (!kn) break;
+        if (!kn || reached_cut()) break;
         k = kn;
         wm = rest;
         rest = wm & (wm - 1u);
         kn = rest ? __ffs((int)rest) : 0;
         load_deviations<N>(a.D, spj + (kn ? kn : k), lane, dc);
         test_waypoint(dn, k);
-        if (!kn) break;
+        if (!kn || reached_cut()) break;
         k = kn;
         wm = rest;
     }
@@ -522,7 +539,7 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
             if (w == lane) v = words[w];
         a.c_mask[(size_t)qj * W + lane] = v;
     }
-    n_flag += flg;
+    if (popc < c_cut) n_flag += flg;   // flagged decisions of pairs below the cut
 }
 
 // Half-space model (Sec. III-B, eq. (7)) of the same step: per marked waypoint
@@ -621,7 +638,7 @@ __device__ __forceinline__ void simulate_pair_hsmc(const RoundArgs& a, int task,
             if (w == lane) v = words[w];
         a.c_mask[(size_t)qj * W + lane] = v;
     }
-    n_flag += flg;
+    if (popc < a.c_cut) n_flag += flg;   // flagged decisions of pairs below the cut
 }
 
 

@@ -57,7 +57,7 @@ def test_lqg_plan_end_to_end(kind, seed, mode):
     assert res["rounds"] == ref["stats"]["rounds"]
     assert res["final_i"] == ref["stats"]["final_i"]
     assert res["inserted"] == ref["stats"]["inserted"]
-    assert res["flagged"] == ref["stats"]["flagged_particles"]
+    assert res["flagged"] == ref["stats"]["flagged_below_cut"]
     st = gpu_plans(pl)
     alive = st["state"] != 2
     gpu_P = {st["paths"][p]: p for p in np.nonzero(alive)[0]}

@@ -474,7 +474,8 @@ def test_rows_on_demand_and_split_rounds_equal_the_whole_graph():
         assert [p.cost for p in other[0]] == [p.cost for p in ref[0]]
         assert all((a.mask == b.mask).all() for a, b in zip(other[0], ref[0]))
         assert other[1] == ref[1]
-        for k in ("partial_plans", "inserted", "rounds", "final_i", "flagged_particles"):
+        for k in ("partial_plans", "inserted", "rounds", "final_i", "flagged_particles",
+                  "flagged_below_cut"):
             assert other[2][k] == ref[2][k], k
     # the rows built on demand are the whole graph's rows
     for v in {p.head for p in ref[0]}:
