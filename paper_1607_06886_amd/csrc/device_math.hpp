@@ -225,8 +225,17 @@ struct Cubic {
     __device__ double at(double t) const { return c0 + t * (c1 + t * (c2 + t * c3)); }
 };
 
-__device__ __forceinline__ void hermite(const float* x0, const float* x1, double tau, Cubic* out) {
-    const double it = 1.0 / tau;   // one division for all six coefficients
+// 1 / b from the hardware reciprocal and two Newton steps: within an ulp or
+// two of the rounded quotient, for values that need no exact rounding.
+__device__ __forceinline__ double recip_fast(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, 1.0), r, r);
+    return fma(fma(-b, r, 1.0), r, r);
+}
+
+// The same coefficients with it = 1 / tau given.
+__device__ __forceinline__ void hermite_r(const float* x0, const float* x1, double tau, double it,
+                                          Cubic* out) {
     const double it2 = it * it, it3 = it2 * it;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -237,6 +246,10 @@ __device__ __forceinline__ void hermite(const float* x0, const float* x1, double
         out[a].c2 = (3.0 * P - (2.0 * v0 + v1) * tau) * it2;
         out[a].c3 = (-2.0 * P + (v0 + v1) * tau) * it3;
     }
+}
+
+__device__ __forceinline__ void hermite(const float* x0, const float* x1, double tau, Cubic* out) {
+    hermite_r(x0, x1, tau, 1.0 / tau, out);   // one division for all six coefficients
 }
 
 // Interior stationary points of a cubic on (0, tau), ascending; returns count.

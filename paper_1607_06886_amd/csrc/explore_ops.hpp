@@ -211,7 +211,7 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int lo, co
             for (int w = 0; w < W; ++w) a.c_mask[(size_t)sl * W + w] = a.p_mask[(size_t)p * W + w];
             return 1;
         }
-        tk = SimTask{sl, p, e, near, (uint32_t)head | ((uint32_t)x << 16), s_p, tau};
+        tk = SimTask{sl, p, K, near, (uint32_t)head | ((uint32_t)x << 16), s_p, tau};
         return 2;
     }
     // obstacles the cloud can reach anywhere along the edge
@@ -265,7 +265,7 @@ __device__ __forceinline__ int expand_pair(const RoundArgs& a, int q, int lo, co
         for (int w = 0; w < W; ++w) a.c_mask[(size_t)sl * W + w] = a.p_mask[(size_t)p * W + w];
         return 1;
     }
-    tk = SimTask{sl, p, e, near, (uint32_t)head | ((uint32_t)x << 16), s_p, tau};
+    tk = SimTask{sl, p, K, near, (uint32_t)head | ((uint32_t)x << 16), s_p, tau};
     return 2;
 }
 
@@ -301,29 +301,24 @@ __device__ __forceinline__ void queue_pairs_block(const RoundArgs& a, int st, co
 // the pair is cut if pop >= c_cut.  Counters are wave-uniform (n_wp:
 // waypoints tested, n_bt: waypoint-box tests, each over all particles).
 //
-// Lane l holds particles l*PPL .. l*PPL + PPL-1, so one waypoint's deviations
-// are one vector load per axis and lane.  The loads of the next marked
-// waypoint are issued before the current one is tested, and the parent's
-// bits, the pair's cost and the head's staircase entries are loaded before
-// the waypoint loop, so a pair costs about one memory latency per waypoint
-// instead of two, plus one at its start.
+// Lane l holds particles l, l + 64, ..., l + 64 (PPL-1), so the hit bits of
+// particle row r are one wave ballot (mask words 2r and 2r+1 as they stand)
+// and a waypoint's deviations are PPL coalesced loads per axis.  The loads of
+// the next marked waypoint are issued before the current one is tested, and
+// the parent's bits, the pair's cost and the head's staircase entries are
+// loaded before the waypoint loop, so a pair costs about one memory latency
+// per waypoint instead of two, plus one at its start.
 // ---------------------------------------------------------------------------
 template <int N>
 __device__ __forceinline__ void load_deviations(const float* __restrict__ D, int s, int lane,
                                                 float (&d)[(N >= 64 ? N / 64 : 1)][3]) {
     constexpr int PPL = N >= 64 ? N / 64 : 1;
+    const int j = N >= 64 ? lane : (lane & (N - 1));   // N = 32: lanes 32..63 repeat (ignored)
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        const float* row = D + ((size_t)s * 3 + ax) * N;
-        if constexpr (PPL == 4) {
-            const float4 v = *reinterpret_cast<const float4*>(row + lane * 4);
-            d[0][ax] = v.x; d[1][ax] = v.y; d[2][ax] = v.z; d[3][ax] = v.w;
-        } else if constexpr (PPL == 2) {
-            const float2 v = *reinterpret_cast<const float2*>(row + lane * 2);
-            d[0][ax] = v.x; d[1][ax] = v.y;
-        } else {
-            d[0][ax] = row[lane & (N - 1)];   // N = 32: lanes 32..63 repeat (ignored)
-        }
+        const float* row = D + ((size_t)s * 3 + ax) * N + j;
+#pragma unroll
+        for (int r = 0; r < PPL; ++r) d[r][ax] = row[r * 64];
     }
 }
 
@@ -346,7 +341,6 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
                                                   long long& n_wp, long long& n_bt) {
     constexpr int W = N / 32;                      // u32 mask words
     constexpr int PPL = N >= 64 ? N / 64 : 1;      // particles per lane
-    constexpr int LPW = 32 / PPL;                  // lanes per mask word
     const int n_obs = a.n_obs;
     const int lane = threadIdx.x & 63;
     const bool valid_lane = (N >= 64) || (lane < N);
@@ -354,7 +348,7 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
     const int qj = tk.q, pj = tk.p;
     const int hj = (int)(tk.nodes & 0xFFFFu), xj = (int)(tk.nodes >> 16);
     const double tj = tk.tau;
-    const int Kj = max(1, (int)ceil(tj / a.dt));
+    const int Kj = tk.K;
     const int spj = tk.s_p;
     unsigned wm = tk.near;                         // non-zero for a queued pair
     // loads that do not depend on the waypoint loop, issued first
@@ -375,10 +369,12 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
     double my_nom[3] = {0.0, 0.0, 0.0};
     float my_n32[3] = {0.f, 0.f, 0.f}, my_lo[3] = {0.f, 0.f, 0.f}, my_hi[3] = {0.f, 0.f, 0.f};
     {
+        // (reciprocals from the hardware estimate: the nominal points need
+        // no exactly rounded quotient, only FP64 accuracy)
         Cubic cs[3];
-        hermite(a.X + (size_t)hj * 6, a.X + (size_t)xj * 6, tj, cs);
+        hermite_r(a.X + (size_t)hj * 6, a.X + (size_t)xj * 6, tj, recip_fast(tj), cs);
         if (lane < Kj) {
-            const double t = (double)(lane + 1) * (tj / (double)Kj);
+            const double t = (double)(lane + 1) * (tj * recip_fast((double)Kj));
             const float* cl = a.cloud + (size_t)(spj + lane + 1) * 6;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
@@ -471,8 +467,12 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
     // its full count.
     uint32_t pml = 0u;   // the parent's bits of this lane's particles
 #pragma unroll
-    for (int w = 0; w < W; ++w)
-        if (w == lane / LPW) pml = (pm[w] >> ((lane * PPL) & 31)) & ((1u << PPL) - 1u);
+    for (int r = 0; r < PPL; ++r) {
+        // particle r * 64 + lane: bit lane of words 2r, 2r+1 taken as one 64-bit word
+        const unsigned long long wv =
+            N >= 64 ? ((unsigned long long)pm[(2 * r + 1) % W] << 32) | pm[(2 * r) % W] : pm[0];
+        pml |= (uint32_t)((wv >> lane) & 1ull) << r;
+    }
     if (!valid_lane) pml = 0u;
     auto reached_cut = [&]() {
         const uint32_t b = valid_lane ? (hm | pml) : 0u;
@@ -497,28 +497,26 @@ __device__ __forceinline__ void simulate_pair_box(const RoundArgs& a, int task, 
         k = kn;
         wm = rest;
     }
-    // this lane's PPL bits go to bit (lane * PPL) % 32 of word lane / LPW;
-    // OR them together across the LPW lanes of each word
-    uint32_t hv = valid_lane ? hm : 0u;
-    uint32_t fv = valid_lane ? (nm & ~dm) : 0u;
-    hv <<= (lane * PPL) & 31;
-    fv <<= (lane * PPL) & 31;
-#pragma unroll
-    for (int o = 1; o < LPW; o <<= 1) {
-        hv |= (uint32_t)__shfl_xor((int)hv, o, 64);
-        fv |= (uint32_t)__shfl_xor((int)fv, o, 64);
-    }
+    // particle row r's bits are ballot r: words 2r and 2r+1 (N = 32: word 0)
     uint32_t words[W];
     int popc = 0;
     long long flg = 0;
+    const uint32_t fm = nm & ~dm;                  // near a face and never deep
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        const uint32_t hw = (uint32_t)__builtin_amdgcn_readlane((int)hv, w * LPW);
-        const uint32_t fw = (uint32_t)__builtin_amdgcn_readlane((int)fv, w * LPW);
-        words[w] = pm[w] | hw;
-        flg += __popc(fw & ~pm[w]);
-        popc += __popc(words[w]);
+    for (int r = 0; r < PPL; ++r) {
+        const unsigned long long hb = __ballot(valid_lane && ((hm >> r) & 1u));
+        const unsigned long long fb = __ballot(valid_lane && ((fm >> r) & 1u));
+        if constexpr (N >= 64) {
+            words[2 * r] = pm[2 * r] | (uint32_t)hb;
+            words[2 * r + 1] = pm[2 * r + 1] | (uint32_t)(hb >> 32);
+            flg += __popc((uint32_t)fb & ~pm[2 * r]) + __popc((uint32_t)(fb >> 32) & ~pm[2 * r + 1]);
+        } else {
+            words[0] = pm[0] | (uint32_t)hb;
+            flg += __popc((uint32_t)fb & ~pm[0]);
+        }
     }
+#pragma unroll
+    for (int w = 0; w < W; ++w) popc += __popc(words[w]);
     bool keep = popc < c_cut;
     if (keep && pre) {
         const double m = popc < 64 ? readlane_f64(st_lane, popc)
@@ -557,7 +555,7 @@ __device__ __forceinline__ void simulate_pair_hsmc(const RoundArgs& a, int task,
     const int qj = tk.q, pj = tk.p;
     const int hj = (int)(tk.nodes & 0xFFFFu), xj = (int)(tk.nodes >> 16);
     const double tj = tk.tau, cj = a.c_cost[qj];
-    const int Kj = max(1, (int)ceil(tj / a.dt));
+    const int Kj = tk.K;
     const int spj = tk.s_p;
     const unsigned nj = tk.near;
     Cubic cs[3];

@@ -100,7 +100,7 @@ struct Ctl {
 struct SimTask {
     int32_t q;                 // pair index
     int32_t p;                 // parent plan
-    int32_t e;                 // edge
+    int32_t K;                 // waypoints on the edge, ceil(tau / dt) (at most 32)
     uint32_t near;             // waypoints whose cloud box meets an obstacle (bit k-1)
     uint32_t nodes;            // edge endpoints: head | x << 16 (node ids < 65536)
     int32_t s_p;               // parent's step count
