@@ -180,7 +180,7 @@ typedef struct pump_result {
     int64_t sim_waypoints;   /* (pair, waypoint) particle tests: each covers the N
                                 particles at a waypoint whose cloud meets a box;
                                 a pair stops at the waypoint where its count
-                                reaches c_cut (box model)                      */
+                                reaches c_cut                                  */
     int64_t sim_box_tests;   /* (pair, waypoint, box) tests, each over N particles */
     /* Smooth(p*, alpha) with cfg.smooth = 1 (else beta 0 and p*'s figures):  */
     double smooth_beta;      /* blend weight returned (0: p* kept)            */
@@ -251,10 +251,10 @@ int pump_get_plans(pump_ctx* ctx, int32_t* head, int32_t* parent, int32_t* edge,
                    uint8_t* state, uint32_t* mask, int64_t cap, int64_t* n_plans);
 /* Candidates of the last round, one per (plan, neighbour) pair in pair order:
  * flag (0 dropped, 1 kept and not dominated, 2 kept but dominated),
- * pop (-1 pre-pruned before simulation, -2 over S_max; with the box model a
- * cut pair's pop is some value >= c_cut, as its simulation stops once the
- * count reaches c_cut), and for kept ones parent plan, head, cost and
- * particle bits.  Any pointer may be NULL.
+ * pop (-1 pre-pruned before simulation, -2 over S_max; a cut pair's pop is
+ * some value >= c_cut, as its simulation stops once the count reaches c_cut),
+ * and for kept ones parent plan, head, cost and particle bits.  Any pointer
+ * may be NULL.
  * PUMP_E_STATE if that round ran in chunks (its candidates are not kept). */
 int pump_get_candidates(pump_ctx* ctx, uint8_t* flag, int32_t* pop, int32_t* parent,
                         int32_t* head, double* cost, uint32_t* mask, int64_t cap,

@@ -562,12 +562,19 @@ __device__ __forceinline__ void simulate_pair_hsmc(const RoundArgs& a, int task,
     hermite(a.X + (size_t)hj * 6, a.X + (size_t)xj * 6, tj, cs);
     bool hit[PPL], deep[PPL], nearp[PPL];
     for (int r = 0; r < PPL; ++r) { hit[r] = false; deep[r] = false; nearp[r] = false; }
+    // the parent's bit of each of this lane's particles (particle r * 64 + lane)
+    bool par[PPL];
+    for (int r = 0; r < PPL; ++r) {
+        const int j = valid_lane ? r * 64 + lane : 0;
+        par[r] = valid_lane && ((a.p_mask[(size_t)pj * W + (j >> 5)] >> (j & 31)) & 1u);
+    }
     unsigned wm = nj;
-    n_wp += __popc(wm);   // waypoints whose cloud box meets an obstacle (or a plane)
     {
         // at each marked waypoint, every plane of the local region against
-        // every particle's deviation, in FP64
+        // every particle's deviation, in FP64; as with the box model, the
+        // pair stops at the waypoint where its count reaches c_cut
         while (wm) {
+            ++n_wp;   // waypoints whose cloud box meets an obstacle (or a plane)
             const int k = __ffs((int)wm);
             wm &= wm - 1u;
             const int s = spj + k;
@@ -599,6 +606,9 @@ __device__ __forceinline__ void simulate_pair_hsmc(const RoundArgs& a, int task,
                     if (fabs(mg) < kFlagEps) nearp[r] = true;
                 }
             }
+            int cnt = 0;
+            for (int r = 0; r < PPL; ++r) cnt += (int)__popcll(__ballot(valid_lane && (hit[r] || par[r])));
+            if (cnt >= a.c_cut) break;
         }
     }
     // gather hits into the N-bit mask and OR with the parent's bits

@@ -202,10 +202,14 @@ static int part_grid(long long n, int per_block) {
 // simulated; k_expand_sim simulates them with one pair per wave.
 //
 // The queue records of a workgroup gather in LDS (one LDS atomic per wave)
-// and go out in one coalesced copy, behind one global atomic, whenever the
-// next pass could overfill the stage, and at the end.
+// and go out in one coalesced copy, behind one global atomic, after each
+// 256-pair pass that queued any.  The box-model pair stage runs six waves
+// per SIMD (80 VGPRs, a few values spilled; 20 KB of LDS per workgroup): on
+// the 20,000-sample indoor query it took 1.48 ms per query against 1.59 ms
+// at four waves (105 VGPRs, a 768-record stage) and 1.61 ms at eight.  The
+// half-space model's, with more live values, stays at four.
 // ---------------------------------------------------------------------------
-constexpr int kTaskStage = 768;   // records staged per workgroup (24 KB)
+constexpr int kTaskStage = 256;   // records staged per workgroup (8 KB): one pass
 
 __device__ __forceinline__ void flush_tasks(const RoundArgs& a, SimTask* s_tq, int* s_tn, int* s_tb) {
     const int n = *s_tn;   // (read after a barrier: the same in every thread)
@@ -220,7 +224,7 @@ __device__ __forceinline__ void flush_tasks(const RoundArgs& a, SimTask* s_tq, i
 }
 
 template <int N, int CP>
-__global__ __launch_bounds__(256) void k_expand_pairs(RoundArgs a) {
+__global__ __launch_bounds__(256, CP == 0 ? 6 : 4) void k_expand_pairs(RoundArgs a) {
     __shared__ float s_raw[kMaxObs * 6];
     __shared__ float s_out[kMaxObs * 6];
     __shared__ SimTask s_tq[kTaskStage];
