@@ -116,7 +116,9 @@ __global__ __launch_bounds__(256) void k_b_gw_near_col0(BatchQuery* qs) {
 
 __global__ __launch_bounds__(kBoxThreads, 3) void k_b_gw_boxes_rm(BatchQuery* qs) {
     __shared__ float s_obs[kMaxObs * 6];
-    __shared__ BoxLds s_box;
+    __shared__ uint32_t s_q[kBoxThreads / 64 * kBoxQueue];
+    __shared__ int s_src[kBoxThreads], s_dst[kBoxThreads], s_blk[kBoxThreads];
+    __shared__ double s_tau[kBoxThreads];
     __shared__ BoxBins s_bins;
     BatchQuery& Q = qs[blockIdx.y];
     if (!Q.use_rm) return;
@@ -125,7 +127,8 @@ __global__ __launch_bounds__(kBoxThreads, 3) void k_b_gw_boxes_rm(BatchQuery* qs
     __syncthreads();
     box_bins_build(s_obs, n_obs, &s_bins);
     gw_boxes(Q.X, Q.valid, Q.rm.esrc, Q.rm.col, Q.rm.tau, Q.rm.bbox, Q.rm.n_edges, false, true,
-             s_obs, n_obs, &s_bins, graph_work(Q), Q.ebits, Q.words, &s_box);
+             s_obs, n_obs, &s_bins, graph_work(Q), Q.ebits, Q.words, blockIdx.x * blockDim.x + threadIdx.x,
+             gridDim.x * blockDim.x, s_q, s_src, s_dst, s_tau, s_blk);
 }
 
 __global__ __launch_bounds__(kNearThreads) void k_b_gw_near_rows(BatchQuery* qs) {
@@ -139,7 +142,9 @@ __global__ __launch_bounds__(kNearThreads) void k_b_gw_near_rows(BatchQuery* qs)
 
 __global__ __launch_bounds__(kBoxThreads, 3) void k_b_gw_boxes(BatchQuery* qs) {
     __shared__ float s_obs[kMaxObs * 6];
-    __shared__ BoxLds s_box;
+    __shared__ uint32_t s_q[kBoxThreads / 64 * kBoxQueue];
+    __shared__ int s_src[kBoxThreads], s_dst[kBoxThreads], s_blk[kBoxThreads];
+    __shared__ double s_tau[kBoxThreads];
     __shared__ BoxBins s_bins;
     BatchQuery& Q = qs[blockIdx.y];
     const int n_obs = Q.ra[0].n_obs;
@@ -149,7 +154,8 @@ __global__ __launch_bounds__(kBoxThreads, 3) void k_b_gw_boxes(BatchQuery* qs) {
     const GraphWork gw = graph_work(Q);
     gw_boxes(Q.X, Q.valid, gw.near_src, gw.near_dst, gw.near_tau, nullptr,
              min(gw.counts[0], gw.near_cap), true, false, s_obs, n_obs, &s_bins, gw, Q.ebits, Q.words,
-             &s_box);
+             blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, s_q, s_src, s_dst,
+             s_tau, s_blk);
 }
 
 __global__ __launch_bounds__(256) void k_b_gw_exact(BatchQuery* qs) {

@@ -119,14 +119,17 @@ __global__ __launch_bounds__(kBoxThreads, 3) void k_gw_boxes(const float* __rest
                                                           uint32_t* __restrict__ ebits,
                                                           int words) {
     __shared__ float s_obs[kMaxObs * 6];
-    __shared__ BoxLds s_box;
+    __shared__ uint32_t s_q[kBoxThreads / 64 * kBoxQueue];
+    __shared__ int s_src[kBoxThreads], s_dst[kBoxThreads], s_blk[kBoxThreads];
+    __shared__ double s_tau[kBoxThreads];
     __shared__ BoxBins s_bins;
     for (int t = threadIdx.x; t < n_obs * 6; t += blockDim.x) s_obs[t] = obs[t];
     __syncthreads();
     box_bins_build(s_obs, n_obs, &s_bins);
     const int N = near_list ? min(gw.counts[0], gw.near_cap) : count;
     gw_boxes(X, valid, src, dst, tau, bbox, N, near_list != 0, near_list == 0, s_obs, n_obs, &s_bins, gw,
-             ebits, words, &s_box);
+             ebits, words, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, s_q,
+             s_src, s_dst, s_tau, s_blk);
 }
 
 __global__ __launch_bounds__(256) void k_gw_exact(const float* __restrict__ X,

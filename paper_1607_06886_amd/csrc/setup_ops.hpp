@@ -513,35 +513,17 @@ __device__ __forceinline__ bool pieces_vs_boxes(const Cubic* cs, double tau, con
 // roadmap list, < 0: -1 - index into the near list).  check_valid: skip
 // connections with an invalid end (the cached roadmap list).
 //
-// The workgroup takes kBoxThreads connections at a time.  (1) Thread t finds
-// the boxes connection t's range meets (candidates from the workspace
-// partition `bins`, then the range test); one that meets none sets its bit.
-// (2) The others are ordered by how many boxes they meet (a counting sort in
-// LDS), so that each wave of the piece test holds connections with about
-// the same number of boxes instead of waiting, box after box, for its
-// busiest lane.  (3) Thread t takes the t-th of them and runs
-// pieces_vs_boxes; the (connection, box) pairs that leaves open are spread
-// over all 64 lanes through an LDS queue per wave, so a connection with many
-// of them does not hold its wave either: each pair gets the quick test, a hit
-// blocks the connection, an unsure pair goes to the exact queue; connections
-// not blocked set their bit.  Whole workgroup of kBoxThreads threads.
+// Lane i of a wave takes connection i of the wave's 64 and finds the boxes
+// its range meets (candidates from the workspace partition `bins`, then the
+// range test), then runs pieces_vs_boxes over them.  The (connection, box)
+// pairs that leaves open are spread over all 64 lanes through an LDS queue
+// per wave, so a connection with many of them does not hold its wave: each
+// pair gets the quick test, a hit blocks the connection, an unsure pair goes
+// to the exact queue; connections not blocked set their bit.  Whole
+// workgroup of kBoxThreads; s_q/s_src/s_dst/s_tau/s_blk are per-wave LDS
+// arrays (kBoxQueue, 64, 64, 64, 64 entries per wave).
 constexpr int kBoxThreads = 256;
 constexpr int kBoxQueue = 256;
-constexpr int kBoxSortBins = 16;   // box-count buckets (the last: 16 and more)
-
-struct BoxConn {
-    double tau;
-    unsigned long long ov[kMaxObsWords];   // boxes the range meets
-    int i, src, dst, n_ov;                 // list index, ends, box count
-};
-
-struct BoxLds {
-    uint32_t q[kBoxThreads / 64 * kBoxQueue];   // per wave: open (lane, box) pairs
-    int src[kBoxThreads], dst[kBoxThreads], blk[kBoxThreads], idx[kBoxThreads];
-    double tau[kBoxThreads];
-    BoxConn conn[kBoxThreads];                  // ordered by box count
-    int start[kBoxSortBins + 1];                // bucket starts; [kBoxSortBins]: total
-};
 
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -557,18 +539,17 @@ __device__ __forceinline__ void gw_boxes(const float* __restrict__ X,
                                          bool check_valid, const float* s_obs, int n_obs,
                                          const BoxBins* bins,
                                          const GraphWork& gw, uint32_t* __restrict__ ebits,
-                                         int words, BoxLds* L) {
+                                         int words, int gid, int stride, uint32_t* s_q,
+                                         int* s_src, int* s_dst, double* s_tau, int* s_blk) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t* q = L->q + w * kBoxQueue;
-    int* qs = L->src + w * 64;
-    int* qd = L->dst + w * 64;
-    int* qi = L->idx + w * 64;
-    double* qt = L->tau + w * 64;
-    int* blk = L->blk + w * 64;
-    // all threads of the workgroup iterate together
-    for (int wbase = blockIdx.x * blockDim.x; wbase < count; wbase += gridDim.x * blockDim.x) {
-        // (1) range and the boxes it meets
-        const int i = wbase + threadIdx.x;
+    uint32_t* q = s_q + w * kBoxQueue;
+    int* qs = s_src + w * 64;
+    int* qd = s_dst + w * 64;
+    double* qt = s_tau + w * 64;
+    int* blk = s_blk + w * 64;
+    // all lanes of a wave iterate together (stride is a multiple of 64)
+    for (int base = gid - lane; base < count; base += stride) {
+        const int i = base + lane;
         bool keep = i < count;
         int src = 0, dst = 0;
         double tau = 0.0;
@@ -580,152 +561,108 @@ __device__ __forceinline__ void gw_boxes(const float* __restrict__ X,
         }
         unsigned long long ov[kMaxObsWords] = {0ull, 0ull, 0ull, 0ull};
         int n_ov = 0;
-        if (keep && n_obs > 0) {
-            double mn[3], mx[3];
-            if (bbox) {
-                for (int a = 0; a < 3; ++a) {
-                    mn[a] = bbox[(size_t)i * 6 + a];
-                    mx[a] = bbox[(size_t)i * 6 + 3 + a];
-                }
-            } else {
+        bool proved = false;
+        if (keep) {
+            if (n_obs > 0) {
+                double mn[3], mx[3];
                 Cubic cs[3];
-                hermite(X + (size_t)src * 6, X + (size_t)dst * 6, tau, cs);
-                for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
-            }
-            // the range rounded outwards to FP32: a box it misses in FP32
-            // the FP64 range misses too; the few it then meets that the
-            // FP64 range would not go to the piece and exact tests, which
-            // decide them the same way
-            float mnf[3], mxf[3];
-            for (int a = 0; a < 3; ++a) {
-                mnf[a] = __double2float_rd(mn[a]);
-                mxf[a] = __double2float_ru(mx[a]);
-            }
-            unsigned long long cand[kMaxObsWords];
-            box_bins_query(bins, mnf, mxf, cand);
-            for (int wd = 0; wd < kMaxObsWords; ++wd) {
-                unsigned long long m = cand[wd];
-                while (m) {
-                    const int o = wd * 64 + __ffsll((long long)m) - 1;
-                    m &= m - 1ull;
-                    const float* bx = s_obs + o * 6;
-                    const bool disjoint = (mxf[0] < bx[0]) | (mnf[0] > bx[3]) |
-                                          (mxf[1] < bx[1]) | (mnf[1] > bx[4]) |
-                                          (mxf[2] < bx[2]) | (mnf[2] > bx[5]);
-                    if (!disjoint) {
-                        ov[wd] |= 1ull << (o & 63);
-                        ++n_ov;
+                if (bbox) {
+                    for (int a = 0; a < 3; ++a) {
+                        mn[a] = bbox[(size_t)i * 6 + a];
+                        mx[a] = bbox[(size_t)i * 6 + 3 + a];
                     }
+                } else {
+                    hermite(X + (size_t)src * 6, X + (size_t)dst * 6, tau, cs);
+                    for (int a = 0; a < 3; ++a) cubic_range(cs[a], tau, mn[a], mx[a]);
                 }
-            }
-        }
-        if (keep && n_ov == 0) atomicOr(&ebits[(size_t)src * words + (dst >> 5)], 1u << (dst & 31));
-        // (2) the connections that meet a box, ordered by their box count
-        if (threadIdx.x <= kBoxSortBins) L->start[threadIdx.x] = 0;
-        __syncthreads();
-        const bool act = keep && n_ov > 0;
-        const int bkt = min(n_ov, kBoxSortBins) - 1;
-        int rank = 0;
-        if (act) rank = atomicAdd(&L->start[bkt], 1);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int b = 0; b < kBoxSortBins; ++b) {
-                const int c = L->start[b];
-                L->start[b] = tot;
-                tot += c;
-            }
-            L->start[kBoxSortBins] = tot;
-        }
-        __syncthreads();
-        if (act) {
-            BoxConn& C = L->conn[L->start[bkt] + rank];
-            C.tau = tau;
-            for (int wd = 0; wd < kMaxObsWords; ++wd) C.ov[wd] = ov[wd];
-            C.i = i;
-            C.src = src;
-            C.dst = dst;
-            C.n_ov = n_ov;
-        }
-        __syncthreads();
-        const int n_act = L->start[kBoxSortBins];
-        // (3) the piece test over them, then the quick tests of the open pairs
-        if (w * 64 < n_act) {   // wave-uniform: a wave with none of them skips
-            const bool has = (int)threadIdx.x < n_act;
-            int c_src = 0, c_dst = 0, c_i = 0, c_n = 0;
-            double c_tau = 0.0;
-            unsigned long long cov[kMaxObsWords] = {0ull, 0ull, 0ull, 0ull};
-            bool proved = false;
-            if (has) {
-                const BoxConn& C = L->conn[threadIdx.x];
-                c_src = C.src;
-                c_dst = C.dst;
-                c_i = C.i;
-                c_n = C.n_ov;
-                c_tau = C.tau;
-                for (int wd = 0; wd < kMaxObsWords; ++wd) cov[wd] = C.ov[wd];
-                Cubic cs[3];
-                hermite(X + (size_t)c_src * 6, X + (size_t)c_dst * 6, c_tau, cs);
-                proved = pieces_vs_boxes(cs, c_tau, s_obs, cov, c_n);
-                if (proved) c_n = 0;
-            }
-            qs[lane] = c_src;
-            qd[lane] = c_dst;
-            qt[lane] = c_tau;
-            qi[lane] = c_i;
-            blk[lane] = proved ? 1 : 0;
-            // this lane's first pair within the wave's list
-            int x = c_n;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(x, o, 64);
-                if (lane >= o) x += y;
-            }
-            const int total = __shfl(x, 63, 64);
-            const int first = x - c_n;
-            for (int seg = 0; seg < total; seg += kBoxQueue) {
-                // this lane's pairs that fall in [seg, seg + kBoxQueue)
-                if (c_n > 0 && first < seg + kBoxQueue && first + c_n > seg) {
-                    int k = first;
-                    for (int wd = 0; wd < kMaxObsWords; ++wd) {
-                        unsigned long long m = cov[wd];
-                        while (m) {
-                            const int o = wd * 64 + __ffsll((long long)m) - 1;
-                            m &= m - 1ull;
-                            if (k >= seg && k < seg + kBoxQueue) q[k - seg] = ((uint32_t)lane << 8) | (uint32_t)o;
-                            ++k;
+                // the range rounded outwards to FP32: a box it misses in FP32
+                // the FP64 range misses too; the few it then meets that the
+                // FP64 range would not go to the piece and exact tests, which
+                // decide them the same way
+                float mnf[3], mxf[3];
+                for (int a = 0; a < 3; ++a) {
+                    mnf[a] = __double2float_rd(mn[a]);
+                    mxf[a] = __double2float_ru(mx[a]);
+                }
+                unsigned long long cand[kMaxObsWords];
+                box_bins_query(bins, mnf, mxf, cand);
+                for (int w = 0; w < kMaxObsWords; ++w) {
+                    unsigned long long m = cand[w];
+                    while (m) {
+                        const int o = w * 64 + __ffsll((long long)m) - 1;
+                        m &= m - 1ull;
+                        const float* bx = s_obs + o * 6;
+                        const bool disjoint = (mxf[0] < bx[0]) | (mnf[0] > bx[3]) |
+                                              (mxf[1] < bx[1]) | (mnf[1] > bx[4]) |
+                                              (mxf[2] < bx[2]) | (mnf[2] > bx[5]);
+                        if (!disjoint) {
+                            ov[w] |= 1ull << (o & 63);
+                            ++n_ov;
                         }
                     }
                 }
-                wave_lds_sync();
-                const int m_seg = min(total - seg, kBoxQueue);
-                for (int j0 = 0; j0 < m_seg; j0 += 64) {
-                    const int j = j0 + lane;
-                    bool unsure = false;
-                    int who = 0, o = 0;
-                    if (j < m_seg) {
-                        who = (int)(q[j] >> 8);
-                        o = (int)(q[j] & 255u);
-                        const int cs_src = qs[who], cs_dst = qd[who];
-                        const double ct = qt[who];
-                        Cubic cs[3];
-                        hermite(X + (size_t)cs_src * 6, X + (size_t)cs_dst * 6, ct, cs);
-                        const int r = trajectory_box_quick(cs, ct, s_obs + o * 6);
-                        if (r == kBoxHit) blk[who] = 1;
-                        unsure = r == kBoxUnsure;
-                    }
-                    const int slot = wave_append(unsure, gw.counts + 1);
-                    if (unsure && slot < gw.xq_cap) {
-                        gw.xq_edge[slot] = near_list ? -1 - qi[who] : qi[who];
-                        gw.xq_box[slot] = o;
+                if (n_ov > 0) {
+                    if (bbox) hermite(X + (size_t)src * 6, X + (size_t)dst * 6, tau, cs);
+                    proved = pieces_vs_boxes(cs, tau, s_obs, ov, n_ov);
+                    if (proved) n_ov = 0;
+                }
+            }
+        }
+        qs[lane] = src;
+        qd[lane] = dst;
+        qt[lane] = tau;
+        blk[lane] = proved ? 1 : 0;
+        // this lane's first pair within the wave's list
+        int x = n_ov;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const int total = __shfl(x, 63, 64);
+        const int first = x - n_ov;
+        const int tag_base = near_list ? -1 - base : base;   // tag of lane 0's connection
+        for (int seg = 0; seg < total; seg += kBoxQueue) {
+            // this lane's pairs that fall in [seg, seg + kBoxQueue)
+            if (n_ov > 0 && first < seg + kBoxQueue && first + n_ov > seg) {
+                int k = first;
+                for (int wd = 0; wd < kMaxObs / 64; ++wd) {
+                    unsigned long long m = ov[wd];
+                    while (m) {
+                        const int o = wd * 64 + __ffsll((long long)m) - 1;
+                        m &= m - 1ull;
+                        if (k >= seg && k < seg + kBoxQueue) q[k - seg] = ((uint32_t)lane << 8) | (uint32_t)o;
+                        ++k;
                     }
                 }
-                wave_lds_sync();
             }
             wave_lds_sync();
-            if (has && !blk[lane])
-                atomicOr(&ebits[(size_t)c_src * words + (c_dst >> 5)], 1u << (c_dst & 31));
+            const int m_seg = min(total - seg, kBoxQueue);
+            for (int j0 = 0; j0 < m_seg; j0 += 64) {
+                const int j = j0 + lane;
+                bool unsure = false;
+                int who = 0, o = 0;
+                if (j < m_seg) {
+                    who = (int)(q[j] >> 8);
+                    o = (int)(q[j] & 255u);
+                    const int cs_src = qs[who], cs_dst = qd[who];
+                    const double ct = qt[who];
+                    Cubic cs[3];
+                    hermite(X + (size_t)cs_src * 6, X + (size_t)cs_dst * 6, ct, cs);
+                    const int r = trajectory_box_quick(cs, ct, s_obs + o * 6);
+                    if (r == kBoxHit) blk[who] = 1;
+                    unsure = r == kBoxUnsure;
+                }
+                const int slot = wave_append(unsure, gw.counts + 1);
+                if (unsure && slot < gw.xq_cap) {
+                    gw.xq_edge[slot] = near_list ? tag_base - who : tag_base + who;
+                    gw.xq_box[slot] = o;
+                }
+            }
+            wave_lds_sync();
         }
-        __syncthreads();   // the LDS arrays are reused
+        wave_lds_sync();
+        if (keep && !blk[lane]) atomicOr(&ebits[(size_t)src * words + (dst >> 5)], 1u << (dst & 31));
+        wave_lds_sync();
     }
 }
 
