@@ -17,7 +17,12 @@ struct BSums {
     double pp, pv, vv;
 };
 
+// boundary_sums and cost_of round every operation on its own (no fused
+// multiply-adds), so that each kernel that inlines them -- the near stage's
+// steering, the edge costs of pass 2, the batched engine's -- gets the same
+// bits from the same inputs.
 __device__ __forceinline__ BSums boundary_sums(const float* x0, const float* x1) {
+#pragma clang fp contract(off)
     BSums s{0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -32,6 +37,7 @@ __device__ __forceinline__ BSums boundary_sums(const float* x0, const float* x1)
 }
 
 __device__ __forceinline__ double cost_of(double t, const BSums& s, double r) {
+#pragma clang fp contract(off)
     const double it = 1.0 / t;
     return t + r * (it * (it * (12.0 * s.pp * it - 12.0 * s.pv) + 4.0 * s.vv));
 }

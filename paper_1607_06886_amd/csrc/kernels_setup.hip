@@ -164,6 +164,26 @@ __global__ __launch_bounds__(256) void k_edge_steer(const float* __restrict__ X,
     edge_steer_dev(X, n, r_steer, row_ptr, col, esrc, etau, ecost);
 }
 
+__global__ __launch_bounds__(256) void k_word_start(int n, const uint32_t* __restrict__ ebits,
+                                                    const int32_t* __restrict__ row_ptr,
+                                                    int32_t* __restrict__ wstart, int words) {
+    word_start_dev(n, ebits, row_ptr, wstart, words);
+}
+
+__global__ __launch_bounds__(256) void k_near_to_slot(GraphWork gw, const uint32_t* __restrict__ ebits,
+                                                      const int32_t* __restrict__ wstart, int words,
+                                                      double* __restrict__ slot_tau) {
+    near_to_slot_dev(gw, ebits, wstart, words, slot_tau);
+}
+
+__global__ __launch_bounds__(256) void k_edge_cost(const float* __restrict__ X, int n, double r_steer,
+                                                   const int32_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ esrc,
+                                                   double* __restrict__ etau, double* __restrict__ ecost) {
+    edge_cost_dev(X, n, r_steer, row_ptr, col, esrc, etau, ecost);
+}
+
 namespace {
 constexpr int kStageBlocks = 2048;   // grid of the grid-stride stages
 }
@@ -204,6 +224,21 @@ void launch_graph_pass1_roadmap(hipStream_t s, const float* X, const uint8_t* va
 void launch_graph_cols(hipStream_t s, int n_nodes, const uint32_t* ebits, const int32_t* row_ptr,
                        int32_t* col, int32_t* esrc, int words) {
     k_graph_fill<<<(n_nodes + 3) / 4, 256, 0, s>>>(n_nodes, ebits, row_ptr, col, esrc, words);
+}
+
+void launch_graph_fill_near(hipStream_t s, const float* X, int n_nodes, double r_steer,
+                            const uint32_t* ebits, const int32_t* row_ptr, int32_t* col,
+                            int32_t* esrc, double* etau, double* ecost, int32_t* wstart, int words,
+                            int n_edges, const GraphWork& gw) {
+    // the near list lives in esrc / col / etau: its tau* go to their slots
+    // (in ecost) before the CSR fill overwrites it
+    k_word_start<<<(n_nodes + 3) / 4, 256, 0, s>>>(n_nodes, ebits, row_ptr, wstart, words);
+    k_near_to_slot<<<kStageBlocks, 256, 0, s>>>(gw, ebits, wstart, words, ecost);
+    k_graph_fill<<<(n_nodes + 3) / 4, 256, 0, s>>>(n_nodes, ebits, row_ptr, col, esrc, words);
+    int blocks = (n_edges + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 8192) blocks = 8192;
+    k_edge_cost<<<blocks, 256, 0, s>>>(X, n_nodes, r_steer, row_ptr, col, esrc, etau, ecost);
 }
 
 void launch_graph_fill(hipStream_t s, const float* X, int n_nodes, double r_steer,

@@ -44,6 +44,7 @@ struct pump_ctx {
     int32_t* dev_ints = nullptr;  // [0] n_nodes, [1] bad-input flag
     // graph
     uint32_t* ebits = nullptr;
+    int32_t* wstart = nullptr;  // pass 2: CSR slot of each bit-matrix word's first edge
     int32_t* deg = nullptr;
     int32_t* row_ptr = nullptr;
     int32_t* col = nullptr;
@@ -328,7 +329,7 @@ int pump_destroy(pump_ctx* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     void* ptrs[] = {ctx->X, ctx->valid, ctx->goal, ctx->obs, ctx->noise_buf, ctx->noise_mc_buf,
                     ctx->noise_meas_buf, ctx->noise_mc_meas_buf,
-                    ctx->D, ctx->cloud, ctx->gcloud, ctx->dev_ints, ctx->ebits, ctx->deg,
+                    ctx->D, ctx->cloud, ctx->gcloud, ctx->dev_ints, ctx->ebits, ctx->wstart, ctx->deg,
                     ctx->row_ptr, ctx->col, ctx->esrc, ctx->etau, ctx->ecost, ctx->p_head, ctx->p_parent,
                     ctx->p_edge, ctx->p_step, ctx->p_pop, ctx->p_round, ctx->p_cost, ctx->p_mask,
                     ctx->p_state, ctx->stair, ctx->open_a, ctx->open_b, ctx->o_keep, ctx->o_inB,
@@ -411,6 +412,7 @@ int pump_create(const pump_config* cfg_in, void* hip_stream, pump_ctx** out) {
     A(dalloc(&ctx->gcloud, 8));
     A(dalloc(&ctx->dev_ints, 8));
     A(dalloc(&ctx->ebits, nn * ctx->words_per_row));
+    A(dalloc(&ctx->wstart, nn * ctx->words_per_row));
     A(dalloc(&ctx->deg, nn + 1));
     A(dalloc(&ctx->row_ptr, nn + 2));
     A(dalloc(&ctx->col, E));
@@ -646,9 +648,9 @@ int pump_setup(pump_ctx* ctx, const pump_problem* pr) {
         launch_rm_fill(ctx->stream, ctx->X, ctx->n_nodes, (double)cfg.r_steer, ctx->row_ptr, ctx->col,
                        ctx->esrc, ctx->rm->d, ctx->etau, ctx->ecost, ctx->n_edges);
     } else {
-        launch_graph_fill(ctx->stream, ctx->X, ctx->n_nodes, (double)cfg.r_steer, ctx->ebits,
-                          ctx->row_ptr, ctx->col, ctx->esrc, ctx->etau, ctx->ecost,
-                          ctx->words_per_row, ctx->n_edges);
+        launch_graph_fill_near(ctx->stream, ctx->X, ctx->n_nodes, (double)cfg.r_steer, ctx->ebits,
+                               ctx->row_ptr, ctx->col, ctx->esrc, ctx->etau, ctx->ecost, ctx->wstart,
+                               ctx->words_per_row, ctx->n_edges, gw);
     }
     tend(ctx);
     // no wait here: the setup time is read at the next synchronisation

@@ -258,6 +258,12 @@ void launch_graph_mark(hipStream_t s, const float* X, const uint8_t* valid, int 
 void launch_graph_fill(hipStream_t s, const float* X, int n_nodes, double r_steer,
                        const uint32_t* ebits, const int32_t* row_ptr, int32_t* col,
                        int32_t* esrc, double* etau, double* ecost, int words, int n_edges);
+// The same from the pass-1 near list (gw, which aliases esrc / col / etau),
+// without steering the edges again; wstart: n_nodes * words ints of scratch.
+void launch_graph_fill_near(hipStream_t s, const float* X, int n_nodes, double r_steer,
+                            const uint32_t* ebits, const int32_t* row_ptr, int32_t* col,
+                            int32_t* esrc, double* etau, double* ecost, int32_t* wstart, int words,
+                            int n_edges, const GraphWork& gw);
 
 // The total goes to *total_dev and, if given, also to *total2_dev.
 void scan_exclusive(hipStream_t s, const int32_t* in, int32_t* out, const int32_t* n_dev,

@@ -766,6 +766,64 @@ __device__ __forceinline__ void graph_fill_dev(int n, const uint32_t* __restrict
     }
 }
 
+// Pass 2 from the near list, without steering again.  The near list holds
+// each connection's tau* from pass 1 and every graph edge is one of its
+// entries whose bit survived the box and exact stages, so:
+//   word_start_dev: the CSR slot of the first edge of each 32-bit word of
+//     each row (one wave per row, the words' bit counts scanned);
+//   near_to_slot_dev: each surviving near entry's slot (its word's start
+//     plus the bits below it in the word) receives its tau* -- in ecost,
+//     since etau still holds the near list;
+//   edge_cost_dev (after graph_fill_dev): tau* to etau and c* = cost_of(tau*)
+//     to ecost, the very expression steer64 returns, so (tau*, c*) equal
+//     what a second steering would give, bit for bit.
+__device__ __forceinline__ void word_start_dev(int n, const uint32_t* __restrict__ ebits,
+                                               const int32_t* __restrict__ row_ptr,
+                                               int32_t* __restrict__ wstart, int words) {
+    const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (v >= n) return;
+    int pos = row_ptr[v];
+    for (int w0 = 0; w0 < words; w0 += 64) {
+        const int w = w0 + lane;
+        const int c = w < words ? __popc(ebits[(size_t)v * words + w]) : 0;
+        int x = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (w < words) wstart[(size_t)v * words + w] = pos + x - c;
+        pos += __shfl(x, 63, 64);
+    }
+}
+
+__device__ __forceinline__ void near_to_slot_dev(const GraphWork& gw, const uint32_t* __restrict__ ebits,
+                                                 const int32_t* __restrict__ wstart, int words,
+                                                 double* __restrict__ slot_tau) {
+    const int count = min(gw.counts[0], gw.near_cap);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const int v = gw.near_src[i], u = gw.near_dst[i];
+        const size_t wi = (size_t)v * words + (u >> 5);
+        const uint32_t word = ebits[wi];
+        const uint32_t bit = 1u << (u & 31);
+        if (word & bit) slot_tau[wstart[wi] + __popc(word & (bit - 1u))] = gw.near_tau[i];
+    }
+}
+
+__device__ __forceinline__ void edge_cost_dev(const float* __restrict__ X, int n, double r_steer,
+                                              const int32_t* __restrict__ row_ptr,
+                                              const int32_t* __restrict__ col,
+                                              const int32_t* __restrict__ esrc,
+                                              double* __restrict__ etau, double* __restrict__ ecost) {
+    const int E = row_ptr[n];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x) {
+        const double tau = ecost[e];
+        const BSums s = boundary_sums(X + (size_t)esrc[e] * 6, X + (size_t)col[e] * 6);
+        etau[e] = tau;
+        ecost[e] = cost_of(tau, s, r_steer);
+    }
+}
+
 // Edge controls, one lane per edge: the same FP64 steering as pass 1, so the
 // cached (tau*, c*) are bit-identical to the values that admitted the edge.
 __device__ __forceinline__ void edge_steer_dev(const float* __restrict__ X, int n,
