@@ -208,19 +208,34 @@ __global__ __launch_bounds__(1024) void k_b_row_scan(BatchQuery* qs) {
     }
 }
 
+// pass 2 without steering again (setup_ops.hpp): the near list's tau* go to
+// their CSR slots before the fill overwrites the list; a cached roadmap's
+// edges take theirs from the roadmap instead
+__global__ __launch_bounds__(256) void k_b_word_start(BatchQuery* qs) {
+    const BatchQuery& Q = qs[blockIdx.y];
+    if (Q.bad || Q.use_rm) return;
+    word_start_dev(Q.n_nodes, Q.ebits, Q.row_ptr, Q.wstart, Q.words);
+}
+
+__global__ __launch_bounds__(256) void k_b_near_to_slot(BatchQuery* qs) {
+    BatchQuery& Q = qs[blockIdx.y];
+    if (Q.bad || Q.use_rm) return;
+    near_to_slot_dev(graph_work(Q), Q.ebits, Q.wstart, Q.words, Q.ecost);
+}
+
 __global__ __launch_bounds__(256) void k_b_graph_fill(BatchQuery* qs) {
     const BatchQuery& Q = qs[blockIdx.y];
     if (Q.bad) return;
     graph_fill_dev(Q.n_nodes, Q.ebits, Q.row_ptr, Q.col, Q.esrc, Q.words);
 }
 
-__global__ __launch_bounds__(256) void k_b_edge_steer(BatchQuery* qs) {
+__global__ __launch_bounds__(256) void k_b_edge_cost(BatchQuery* qs) {
     const BatchQuery& Q = qs[blockIdx.y];
     if (Q.bad) return;
     if (Q.use_rm)
         rm_fill_dev(Q.X, Q.n_nodes, Q.r_steer, Q.row_ptr, Q.col, Q.esrc, Q.rm, Q.etau, Q.ecost);
     else
-        edge_steer_dev(Q.X, Q.n_nodes, Q.r_steer, Q.row_ptr, Q.col, Q.esrc, Q.etau, Q.ecost);
+        edge_cost_dev(Q.X, Q.n_nodes, Q.r_steer, Q.row_ptr, Q.col, Q.esrc, Q.etau, Q.ecost);
 }
 
 // ----------------------------- explore --------------------------------------
@@ -465,8 +480,10 @@ void launch_batch(hipStream_t s, BatchQuery* qs, int q, int N_max, int max_nodes
     k_b_gw_exact<<<dim3(64, q), 256, 0, s>>>(qs);
     k_b_row_deg<<<dim3((max_nodes + 3) / 4, q), 256, 0, s>>>(qs);
     k_b_row_scan<<<q, 1024, 0, s>>>(qs);
+    k_b_word_start<<<dim3((max_nodes + 3) / 4, q), 256, 0, s>>>(qs);
+    k_b_near_to_slot<<<dim3(256, q), 256, 0, s>>>(qs);
     k_b_graph_fill<<<dim3((max_nodes + 3) / 4, q), 256, 0, s>>>(qs);
-    k_b_edge_steer<<<dim3(256, q), 256, 0, s>>>(qs);
+    k_b_edge_cost<<<dim3(256, q), 256, 0, s>>>(qs);
     k_b_reset<<<q, 64, 0, s>>>(qs, counter);
     for (int g = 0; g < n_groups; ++g) {
         const BatchGroup& G = groups[g];

@@ -26,7 +26,7 @@ struct Slot {
     float *X, *obs, *D, *cloud, *gcloud;
     uint8_t *valid, *goal, *p_state, *o_inB, *c_flag;
     uint32_t *ebits, *p_mask, *c_mask;
-    int32_t *deg, *row_ptr, *col, *esrc, *p_head, *p_parent, *p_edge, *p_step, *p_pop, *p_round;
+    int32_t *wstart, *deg, *row_ptr, *col, *esrc, *p_head, *p_parent, *p_edge, *p_step, *p_pop, *p_round;
     int32_t *open_a, *open_b, *o_keep, *b_ids, *b_off, *b_deg;
     int32_t *c_head, *c_parent, *c_edge, *c_step, *c_pop, *c_pos;
     SimTask* tasks;
@@ -139,7 +139,7 @@ int pump_batch_create(const pump_config* cfg_in, int32_t max_queries, void* hip_
     take(&lay.X, nn * 6); take(&lay.obs, (size_t)kMaxObs * 6); take(&lay.D, (S + 1) * 3 * N);
     take(&lay.cloud, (S + 1) * 6);
     take(&lay.dev_scratch, (size_t)kDevScratchPer * ((S + 15) / 16) * 3 * N); take(&lay.gcloud, 8); take(&lay.valid, nn); take(&lay.goal, nn);
-    take(&lay.ebits, nn * b->words); take(&lay.deg, nn + 1); take(&lay.row_ptr, nn + 2);
+    take(&lay.ebits, nn * b->words); take(&lay.wstart, nn * b->words); take(&lay.deg, nn + 1); take(&lay.row_ptr, nn + 2);
     take(&lay.col, E); take(&lay.esrc, E); take(&lay.etau, E); take(&lay.ecost, E);
     take(&lay.p_head, P); take(&lay.p_parent, P); take(&lay.p_edge, P); take(&lay.p_step, P);
     take(&lay.p_pop, P); take(&lay.p_round, P); take(&lay.p_cost, P); take(&lay.p_mask, P * W);
@@ -264,7 +264,7 @@ int pump_batch_plan(pump_batch* b, const pump_problem* probs, const int32_t* n_p
             Q.rm = rm->d;
         }
         Q.X = s.X; Q.obs = s.obs; Q.valid = s.valid; Q.goal = s.goal; Q.ebits = s.ebits;
-        Q.deg = s.deg; Q.row_ptr = s.row_ptr; Q.col = s.col; Q.esrc = s.esrc; Q.etau = s.etau;
+        Q.wstart = s.wstart; Q.deg = s.deg; Q.row_ptr = s.row_ptr; Q.col = s.col; Q.esrc = s.esrc; Q.etau = s.etau;
         Q.ecost = s.ecost; Q.b_deg = s.b_deg; Q.open_a = s.open_a; Q.open_b = s.open_b;
         RoundArgs& a = Q.ra[0];
         a.X = s.X; a.goal = s.goal; a.obs = s.obs; a.n_obs = pr.n_obs; a.D = s.D; a.cloud = s.cloud;

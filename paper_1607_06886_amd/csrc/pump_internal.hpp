@@ -413,6 +413,7 @@ struct BatchQuery {
     uint8_t* valid;
     uint8_t* goal;
     uint32_t* ebits;
+    int32_t* wstart;           // pass 2: CSR slot of each bit-matrix word's first edge
     int32_t* deg;
     int32_t* row_ptr;
     int32_t* col;
