@@ -340,8 +340,9 @@ int pump_get_timing(pump_ctx* ctx, double* ms, int64_t* launches, int32_t n);
  * always does); mode 2 (the default where the single launch fits) chooses
  * per query from the graph's edge count: the single launch below 4 * 2^20
  * edges, per-phase launches from there on, where the particle simulation's
- * own kernel is faster.  All modes build the same plan store.  get reports
- * the configured mode and the workgroups of the single launch. */
+ * own kernel is faster, and per-phase launches at any size with the
+ * half-space model (cp_model 1).  All modes build the same plan store.  get
+ * reports the configured mode and the workgroups of the single launch. */
 int pump_set_explore_mode(pump_ctx* ctx, int32_t mode);
 int pump_get_explore_mode(pump_ctx* ctx, int32_t* mode, int32_t* blocks);
 

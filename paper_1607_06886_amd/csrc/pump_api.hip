@@ -866,11 +866,14 @@ static int explore_single_launch(pump_ctx* ctx) {
 // kernel, at four waves per SIMD with dynamically scheduled workgroups, is
 // faster than the single launch despite a host round trip per round
 // (indoor 20,000-sample query: 16.4 against 19.9 ms; 4,000-sample query:
-// 1.86 against 0.76 ms).
+// 1.86 against 0.76 ms).  The half-space model's particle work is heavy at
+// any size (4,000-sample query: 9.2 ms per phase against 11.3 ms in one
+// launch), so with it the per-phase kernels are taken throughout.
 constexpr long long kPerPhaseEdges = 4ll << 20;
 
 static int effective_mode(const pump_ctx* ctx) {
     if (ctx->explore_mode != 2) return ctx->explore_mode;
+    if (ctx->cfg.cp_model == 1) return 0;
     return (long long)ctx->n_edges >= kPerPhaseEdges ? 0 : 1;
 }
 
