@@ -542,6 +542,60 @@ __device__ __forceinline__ bool hs_next(const double* y, const float* boxes, int
     return true;
 }
 
+// hs_next for a wave whose lanes share y and rem (all 64 lanes call it, in
+// uniform control flow): lane l takes box w * 64 + l, the nearest box is the
+// wave minimum of the same squared distances, taken at its lowest box index
+// (as the loop above, which keeps the first strict minimum in box order), and
+// the boxes the new plane removes are one ballot per word.  Every value is
+// the same expression as in hs_next, so the planes and the boxes left are
+// identical.
+__device__ __forceinline__ bool hs_next_wave(const double* y, const float* boxes, int n_obs,
+                                             unsigned long long* rem, double* d) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    int best = -1;
+    double best_d2 = INFINITY;
+    for (int w = 0; w * 64 < n_obs; ++w) {
+        double d2 = INFINITY;
+        if ((rem[w] >> lane) & 1ull) {
+            const float* b = boxes + (w * 64 + lane) * 6;
+            double dv[3];
+            for (int a = 0; a < 3; ++a)
+                dv[a] = fmin(fmax(y[a], (double)b[a]), (double)b[3 + a]) - y[a];
+            d2 = (dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2];
+            if (!(d2 < INFINITY)) d2 = INFINITY;   // never chosen, as in the loop
+        }
+        double m = d2;
+        for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+        if (m < best_d2) {
+            best_d2 = m;
+            best = w * 64 + __ffsll((long long)__ballot(d2 == m)) - 1;
+        }
+    }
+    if (best < 0) return false;
+    double bd[3];
+    {
+        const float* b = boxes + best * 6;
+        for (int a = 0; a < 3; ++a) bd[a] = fmin(fmax(y[a], (double)b[a]), (double)b[3 + a]) - y[a];
+    }
+    d[0] = bd[0]; d[1] = bd[1]; d[2] = bd[2];
+    const double dd = (bd[0] * bd[0] + bd[1] * bd[1]) + bd[2] * bd[2];
+    const double dy = (bd[0] * y[0] + bd[1] * y[1]) + bd[2] * y[2];
+    for (int w = 0; w * 64 < n_obs; ++w) {
+        const int o = w * 64 + lane;
+        bool drop = false;
+        if ((rem[w] >> lane) & 1ull) {
+            const float* b = boxes + o * 6;
+            double lo_part = 0.0;
+            for (int a = 0; a < 3; ++a)
+                lo_part += fmin(bd[a] * (double)b[a], bd[a] * (double)b[3 + a]);
+            drop = o == best || lo_part - dy >= dd;
+        }
+        rem[w] &= ~__ballot(drop);
+    }
+    return true;
+}
+
 // eq. (7): the plane normal made perpendicular to the nominal velocity v
 // (unchanged at rest); b = a.a.
 __device__ __forceinline__ void hs_project(const double* d, const double* v, double* a, double& b) {

@@ -592,7 +592,7 @@ __device__ __forceinline__ void simulate_pair_hsmc(const RoundArgs& a, int task,
             unsigned long long rem[kMaxObsWords];
             all_boxes(n_obs, rem);
             double dd[3];
-            while (hs_next(y, s_raw, n_obs, rem, dd)) {
+            while (hs_next_wave(y, s_raw, n_obs, rem, dd)) {
                 double av[3], b;
                 hs_project(dd, v, av, b);
                 ++n_bt;
