@@ -481,3 +481,32 @@ def test_rows_on_demand_and_split_rounds_equal_the_whole_graph():
     for v in {p.head for p in ref[0]}:
         a, b = lazy.rows(v)
         np.testing.assert_array_equal(lazy["col"][a:b], g["col"][g["row_ptr"][v]:g["row_ptr"][v + 1]])
+
+
+def test_flagged_counters(monkeypatch):
+    """The flagged-decision count over the pairs that pass the CP cutoff is at
+    most the count over every formed pair, and equals it when no pair is cut
+    (alpha_max above 1) and none runs past S_max.  (The flag distance is
+    widened to 0.01 so that this small scene has flagged decisions at all.)"""
+    from oracle import graph as gr, pump as opump
+    monkeypatch.setattr(ex, "EPS_FLAG", 1e-2)
+    from paper_1607_06886_amd import scenes
+    sc = scenes.make_scene(dict(n=100, n_obs=8, side=(0.1, 0.3), N=32, sigma=0.05, alpha=0.05,
+                                indoor=False), 7, M=64, S_max=4096)
+    cfg = opump.Config()
+    V = np.concatenate([sc.x_init[None], sc.samples]).astype(np.float64)
+    A_cl, L, _ = dynamics.closed_loop(cfg.dt, sc.sigma, cfg.q_pos, cfg.q_vel, cfg.r_track)
+    D = dynamics.deviation_table(A_cl, L, sc.noise, sc.S_max)
+    g = gr.build_graph(V, sc.obstacles, cfg.r_conn, cfg.r_steer)
+    gl = sc.goal.astype(np.float64)
+    goal = np.nonzero(np.all((V[:, :3] >= gl[:3]) & (V[:, :3] <= gl[3:]), axis=1) & g["valid"])[0]
+    seen = []
+    for amax in (0.1, 2.0):
+        _, _, stats, _ = ex.explore(V, g, D, sc.obstacles, goal, 0.0, amax, cfg.lam, cfg.r_conn,
+                                    cfg.dt, sc.S_max)
+        assert 0 <= stats["flagged_below_cut"] <= stats["flagged_particles"]
+        seen.append(stats)
+    cut, uncut = seen
+    assert uncut["dropped_steps"] == 0
+    assert uncut["flagged_below_cut"] == uncut["flagged_particles"]
+    assert cut["flagged_particles"] > cut["flagged_below_cut"] > 0
