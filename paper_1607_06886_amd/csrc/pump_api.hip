@@ -865,8 +865,8 @@ static int explore_single_launch(pump_ctx* ctx) {
 // steps); on larger graphs the particle simulation dominates and its own
 // kernel, at four waves per SIMD with dynamically scheduled workgroups, is
 // faster than the single launch despite a host round trip per round
-// (indoor 20,000-sample query: 16.4 against 19.9 ms; 4,000-sample query:
-// 1.86 against 0.76 ms).  The half-space model's particle work is heavy at
+// (indoor 20,000-sample query: 13.3 against 19.3 ms; 4,000-sample query:
+// 1.38 against 1.24 ms).  The half-space model's particle work is heavy at
 // any size (4,000-sample query: 9.2 ms per phase against 11.3 ms in one
 // launch), so with it the per-phase kernels are taken throughout.
 constexpr long long kPerPhaseEdges = 4ll << 20;
