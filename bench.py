@@ -70,7 +70,7 @@ VALU_PEAK_TLANEOPS = 39.3          # 256 CU x 64 lanes x 2.4 GHz (one lane-op pe
 # The hot-path scope table's per-pair work of the expansion (A3-A7) at the
 # three single-query workloads (3 / 20 / 60 boxes; N = 32 / 128 / 256):
 # steer + K (18 + 12 n_obs) + K N (3 + 6 n_near) + K N / 64 with K ~ 10.
-SURVEY_OPS_PER_PAIR = {3: 1.9e3, 20: 8.2e3, 60: 31e3}
+SCOPE_OPS_PER_PAIR = {3: 1.9e3, 20: 8.2e3, 60: 31e3}
 
 # Executed lane-operations of the particle stage, per unit:
 OPS_SIM_PAIR = 50      # Hermite coefficients of the queued pair's edge
@@ -481,7 +481,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); "
-              "this build has no multi-GPU path", file=sys.stderr)
+              "the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     # the CPU oracle first: its worker processes are forked before this
     # process touches the GPU
@@ -527,12 +527,12 @@ def main():
                 "launches": launches, "work_per_launch": work_launch,
                 "algorithmic_hbm_bytes_per_launch": sim_bytes * args.steps / launches
                 if dom == "expand_sim" else None,
-                "survey_model": {
-                    "ops_per_pair": SURVEY_OPS_PER_PAIR[60],
+                "scope_model": {
+                    "ops_per_pair": SCOPE_OPS_PER_PAIR[60],
                     "pairs_per_query": r0["partial_plans"],
                     "expansion_kernel_ms_per_query": expl_ms,
-                    "achieved": SURVEY_OPS_PER_PAIR[60] * r0["partial_plans"] / (expl_ms / 1e3) / 1e12,
-                    "frac": SURVEY_OPS_PER_PAIR[60] * r0["partial_plans"] / (expl_ms / 1e3) / 1e12
+                    "achieved": SCOPE_OPS_PER_PAIR[60] * r0["partial_plans"] / (expl_ms / 1e3) / 1e12,
+                    "frac": SCOPE_OPS_PER_PAIR[60] * r0["partial_plans"] / (expl_ms / 1e3) / 1e12
                     / VALU_PEAK_TLANEOPS,
                     "note": "credits every (plan, neighbour) pair with the full per-pair particle work, "
                             "including the pairs settled by the staircase before simulation and those cut "
